@@ -1,0 +1,183 @@
+/*
+ * toeplitz.h - C ABI of the MI355X (gfx950) library that applies and solves the
+ * impedance matrix of an Nx x Ny array of identical, electrically connected
+ * elements (arXiv 2506.04710).
+ *
+ * The operator is Z = [[A, B^T], [B, C]] of eq. (matrixForm): A couples the
+ * N = Nx*Ny*b element basis functions and is two-level block Toeplitz
+ * (eq. submatrixAA), so it is fully described by the generator blocks Z_{m,n}
+ * for offsets m in (-Nx, Nx), n in (-Ny, Ny); B and C couple the Nr rim (margin)
+ * basis functions of Sec. II-B and are stored dense.  Nt = N + Nr.
+ *
+ * Vector ordering (Sec. II-C part order, x fastest): unknown (iy*Nx + ix)*b + p
+ * is basis p of element (ix, iy); unknown N + r is rim function r.
+ *
+ * Conventions for every entry point:
+ *   - complex numbers are interleaved (re, im); complex128 = 2 doubles,
+ *     complex64 = 2 floats;
+ *   - multi-vector arguments are column-major Nt x nrhs with a leading dimension
+ *     ld >= Nt (column r starts at element r*ld);
+ *   - a void* hip_stream is a hipStream_t (NULL = the default stream);
+ *   - arguments are validated before any device work; a bad argument returns
+ *     TP_E_INVAL and leaves every buffer untouched;
+ *   - no call throws, aborts or allocates device memory: the plan lives in a
+ *     device buffer the caller owns (e.g. a torch tensor);
+ *   - after a non-OK status, toeplitz_last_error() returns a message for the
+ *     calling thread.
+ */
+#ifndef TOEPLITZ_H
+#define TOEPLITZ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tp_plan_s *tp_plan; /* opaque; host-side metadata owned by the library */
+
+typedef enum {
+    TP_OK = 0,
+    TP_E_INVAL = 1,       /* invalid argument (shape, pointer, size, option) */
+    TP_E_NOMEM = 2,       /* the caller's device buffer is smaller than toeplitz_plan_bytes() */
+    TP_E_HIP = 3,         /* a HIP runtime call failed; the message names it */
+    TP_E_NOCONV = 4,      /* a solve column missed its tolerance within the iteration limits */
+    TP_E_BREAKDOWN = 5,   /* Krylov breakdown without convergence (e.g. singular operator) */
+    TP_E_UNSUPPORTED = 6  /* valid request this build does not handle (e.g. missing precision copy) */
+} tp_status;
+
+/* Which operator copies a plan holds, and which one a matvec uses. */
+typedef enum {
+    TP_FP64 = 0,   /* complex128 spectrum and rim, FP64 arithmetic */
+    TP_FP32 = 1,   /* complex64 spectrum and rim, FP32 arithmetic with FP32 accumulation */
+    TP_MIXED = 2   /* both copies (plans); for solves: FP32 operator inside FP64 refinement */
+} tp_prec;
+
+/* Plan layout facts, filled by toeplitz_plan_info. */
+typedef struct {
+    int Nx, Ny, b, Nr;
+    int Px, Py;              /* circulant grid, Px >= 2Nx-1, Py >= 2Ny-1 */
+    long N, Nt;
+    int max_rhs, restart;
+    tp_prec prec;
+    size_t spectrum_bytes;   /* per copy: Px*Py*b*b complex values */
+    size_t rim_bytes;        /* per copy: B (Nr x N), optional B_er^T (Nr x N), C (Nr x Nr) */
+    size_t workspace_bytes;  /* FFT grids, partial sums and the Krylov workspace */
+    size_t total_bytes;      /* == toeplitz_plan_bytes() */
+    int reciprocal;          /* 1 if the element-rim block is rim_re transposed */
+} tp_plan_desc;
+
+/*
+ * Device bytes a plan needs: the operator copies selected by prec (spectrum of
+ * the generators, Sec. I / eq. submatrixAA, plus the dense rim of eqs.
+ * submatrixBB..submatrixC456), FFT grids for up to max_rhs columns and the
+ * Krylov workspace of GMRES(restart) for max_rhs columns.  Use it for admission
+ * before creating a plan.  reciprocal = 1 when rim_er will be NULL (one dense
+ * rim block instead of two).  bytes receives the size; returns TP_E_INVAL for
+ * Nx, Ny, b < 1, Nr < 0, max_rhs < 1, restart < 1, Nx or Ny > 256, b > 256,
+ * Nr > 2048, restart > 512 or sizes that overflow.
+ */
+tp_status toeplitz_plan_bytes(int Nx, int Ny, int b, int Nr, int reciprocal, tp_prec prec,
+                              int max_rhs, int restart, size_t *bytes);
+
+/*
+ * Build a plan in the caller's device buffer (Sec. II-C structure; Sec. I FFT
+ * route): the generators are circulant-embedded in a Px x Py grid, transformed
+ * by a 2-D DFT (forward sign exp(-2 pi i k n / P)) and scaled by 1/(Px Py); the
+ * rim blocks are copied.  Every host input is copied; the caller may free them
+ * on return.  The call synchronises hip_stream before returning.
+ *
+ *   gen     host complex128 [2Ny-1][2Nx-1][b][b] with
+ *           gen[n+Ny-1][m+Nx-1][p][q] = Z_{m,n}[p][q], the block between basis p
+ *           of element (ix+m, iy+n) (row) and basis q of element (ix, iy).
+ *   rim_re  host complex128 [Nr][N]: rim row r, element column e (NULL iff Nr = 0).
+ *   rim_er  host complex128 [N][Nr]: element row e, rim column r; NULL means the
+ *           reciprocal case rim_er[e][r] = rim_re[r][e] (Sec. II-A symmetry).
+ *   rim_rr  host complex128 [Nr][Nr] (NULL iff Nr = 0).
+ *   dev_buf device buffer of dev_bytes >= toeplitz_plan_bytes(...) bytes, 256-byte
+ *           aligned; owned by the caller, who must keep it alive until
+ *           toeplitz_plan_destroy and free it afterwards.
+ *   out     receives the plan handle.
+ * Errors: TP_E_INVAL (shapes, NULL pointers, misaligned buffer), TP_E_NOMEM
+ * (dev_bytes too small), TP_E_HIP.
+ */
+tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
+                               const double *rim_re, const double *rim_er, const double *rim_rr,
+                               tp_prec prec, int max_rhs, int restart, void *dev_buf,
+                               size_t dev_bytes, void *hip_stream, tp_plan *out);
+
+/* Copy the plan's layout facts into *desc. */
+tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *desc);
+
+/*
+ * y = Z x for nrhs columns (eq. MoMMatrixEq operator): embed, forward 2-D DFT,
+ * per-frequency b x b block product with the stored spectrum, inverse DFT, crop,
+ * plus the dense rim terms y_A += B_er x_r, y_r = B x_A + C x_r.
+ * x, y: device, column-major Nt x nrhs, leading dimensions ldx, ldy >= Nt;
+ * complex128 if which == TP_FP64, complex64 if which == TP_FP32.  x and y must
+ * not overlap.  1 <= nrhs <= max_rhs.  Asynchronous on hip_stream; uses the
+ * plan's workspace, so calls on one plan must not run concurrently.
+ * Errors: TP_E_INVAL, TP_E_UNSUPPORTED (the plan lacks that precision copy),
+ * TP_E_HIP.
+ */
+tp_status toeplitz_matvec(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy,
+                          int nrhs, void *hip_stream);
+
+/* Solver options (all fields are read; see toeplitz_solve_opts_default). */
+typedef struct {
+    double tol;        /* stop when ||v - Z x||_2 / ||v||_2 <= tol, FP64 residual */
+    int restart;       /* GMRES restart length m (<= the plan's restart) */
+    int max_iter;      /* cap on Arnoldi steps (operator applications) per column */
+    int max_outer;     /* cap on refinement steps (TP_MIXED) or restarts (TP_FP64) */
+    tp_prec mode;      /* TP_FP64: GMRES on the FP64 operator; TP_MIXED: FP32 inner GMRES
+                          with FP64 residual refinement; TP_FP32 is not a solve mode */
+    int x0_given;      /* 1: x holds the initial guess; 0: start from zero */
+    double inner_tol;  /* TP_MIXED: relative residual target of each inner solve */
+} tp_solve_opts;
+
+/* Per-column result of toeplitz_solve. */
+typedef struct {
+    int iters;         /* Arnoldi steps (operator applications inside GMRES) */
+    int outer_iters;   /* FP64 residual evaluations after the first */
+    int status;        /* TP_OK, TP_E_NOCONV or TP_E_BREAKDOWN */
+    double relres;     /* final ||v - Z x||_2 / ||v||_2 from an FP64 matvec */
+} tp_solve_info;
+
+/* Defaults: tol 1e-8, restart = plan's, max_iter 2000, max_outer 50, TP_FP64, x0 zero, inner_tol 1e-4. */
+void toeplitz_solve_opts_default(tp_solve_opts *opts);
+
+/*
+ * Solve Z x = v (eq. MoMMatrixEq) for nrhs columns with restarted GMRES
+ * (Sec. II-D names GMRES on the second Toeplitz level; Arnoldi with classical
+ * Gram-Schmidt and one reorthogonalisation, Givens QR of the Hessenberg matrix,
+ * all in FP64 on the device).  Each column has its own Krylov space; columns
+ * converge independently and stop on their own FP64 residual.
+ * v, x: device complex128, column-major Nt x nrhs, ldv, ldx >= Nt, not
+ * overlapping.  info: host array of nrhs entries, filled on return.
+ * opts NULL = defaults.  The call synchronises hip_stream (the host reads the
+ * convergence scalars).  Returns TP_OK if every column met tol, TP_E_NOCONV /
+ * TP_E_BREAKDOWN otherwise (x then holds each column's best iterate and info is
+ * filled), TP_E_INVAL / TP_E_UNSUPPORTED / TP_E_HIP on errors.
+ */
+tp_status toeplitz_solve(tp_plan p, const void *v, long ldv, void *x, long ldx, int nrhs,
+                         const tp_solve_opts *opts, tp_solve_info *info, void *hip_stream);
+
+/*
+ * Copy one block of the stored spectrum to the host (the b x b matrix at
+ * frequency (kx, ky), row-major; complex128 for TP_FP64, complex64 for TP_FP32).
+ * It equals (1/(Px Py)) sum_{m,n} Z_{m,n} exp(-2 pi i (kx m / Px + ky n / Py)).
+ * Synchronous.  Errors: TP_E_INVAL, TP_E_UNSUPPORTED, TP_E_HIP.
+ */
+tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void *host_out);
+
+/* Release the plan's host metadata.  The caller frees dev_buf afterwards. NULL is ignored. */
+void toeplitz_plan_destroy(tp_plan p);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *toeplitz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOEPLITZ_H */

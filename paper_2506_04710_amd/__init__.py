@@ -1,0 +1,161 @@
+"""MI355X (gfx950) library for the two-level block-Toeplitz array impedance
+operator of arXiv 2506.04710: apply Z and solve Z x = v.
+
+The HIP kernels live in ``libtoeplitz.so`` behind the C ABI of
+``include/toeplitz.h``.  This module marshals torch device tensors (memory and
+streams only) and numpy host arrays into those calls.
+
+    plan = Plan.create(Nx, Ny, b, Nr, gen, rim_re, rim_rr, prec="mixed", max_rhs=R)
+    y = plan.matvec(x)                       # x: complex128 / complex64 cuda tensor (Nt,) or (R, Nt)
+    x, info = plan.solve(v, mode="mixed", tol=1e-8)
+
+Vectors are torch tensors of shape (R, Nt): row r is column r of the
+column-major Nt x R block that the C ABI takes (leading dimension = row stride).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import PREC, ToeplitzError, check  # noqa: F401
+
+__all__ = ["Plan", "plan_bytes", "ToeplitzError", "load"]
+
+
+def load():
+    """Load libtoeplitz.so (raises if it is missing)."""
+    return _lib.lib()
+
+
+def plan_bytes(Nx, Ny, b, Nr, prec="mixed", max_rhs=1, restart=40, reciprocal=True) -> int:
+    n = ctypes.c_size_t(0)
+    check(_lib.lib().toeplitz_plan_bytes(Nx, Ny, b, Nr, 1 if reciprocal else 0, PREC[prec], max_rhs, restart,
+                                         ctypes.byref(n)))
+    return n.value
+
+
+def _host_c128(a, shape):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if a.size != int(np.prod(shape)):
+        raise ValueError(f"expected {shape} elements, got {a.shape}")
+    return a
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A plan: the operator's spectrum and rim blocks resident in one device buffer."""
+
+    def __init__(self):
+        self._h = None
+
+    @classmethod
+    def create(cls, Nx, Ny, b, Nr, gen, rim_re=None, rim_rr=None, rim_er=None, prec="mixed", max_rhs=1,
+               restart=40, device="cuda:0", stream=None):
+        import torch
+        L = _lib.lib()
+        N = Nx * Ny * b
+        gen = _host_c128(gen, (2 * Ny - 1, 2 * Nx - 1, b, b))
+        rim_re = _host_c128(rim_re, (Nr, N)) if Nr else None
+        rim_rr = _host_c128(rim_rr, (Nr, Nr)) if Nr else None
+        rim_er = _host_c128(rim_er, (N, Nr)) if (Nr and rim_er is not None) else None
+        nbytes = plan_bytes(Nx, Ny, b, Nr, prec, max_rhs, restart, reciprocal=rim_er is None)
+        self = cls()
+        self.device = torch.device(device)
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.buf.data_ptr()
+        off = (-base) % 256
+        h = ctypes.c_void_p()
+        ptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        with torch.cuda.device(self.device):
+            check(L.toeplitz_plan_create(Nx, Ny, b, Nr, ptr(gen), ptr(rim_re), ptr(rim_er), ptr(rim_rr),
+                                         PREC[prec], max_rhs, restart, ctypes.c_void_p(base + off), nbytes,
+                                         _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.Nx, self.Ny, self.b, self.Nr = Nx, Ny, b, Nr
+        self.N, self.Nt = N, N + Nr
+        self.prec, self.max_rhs, self.restart = prec, max_rhs, restart
+        return self
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        return cls.create(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, **kw)
+
+    def info(self) -> dict:
+        d = _lib.PlanDesc()
+        check(_lib.lib().toeplitz_plan_info(self._h, ctypes.byref(d)))
+        return {f: getattr(d, f) for f, _ in _lib.PlanDesc._fields_}
+
+    def _cols(self, t, dtype):
+        import torch
+        if t.device.type != "cuda":
+            raise ValueError("vectors must be device tensors")
+        if t.dtype != dtype:
+            raise TypeError(f"expected {dtype}, got {t.dtype}")
+        if t.dim() == 1:
+            t = t.unsqueeze(0)
+        if t.dim() != 2 or t.shape[1] != self.Nt or t.stride(1) != 1:
+            raise ValueError("vectors must have shape (R, Nt) with unit stride along Nt")
+        return t, t.shape[0], t.stride(0) if t.shape[0] > 1 else self.Nt
+
+    def matvec(self, x, which=None, out=None, stream=None):
+        """y = Z x on the device (which: 'fp64' for complex128 x, 'fp32' for complex64)."""
+        import torch
+        if which is None:
+            which = "fp64" if x.dtype == torch.complex128 else "fp32"
+        dt = torch.complex128 if which == "fp64" else torch.complex64
+        x2, R, ldx = self._cols(x, dt)
+        y = torch.empty((R, self.Nt), dtype=dt, device=x.device) if out is None else out
+        y2, Ry, ldy = self._cols(y, dt)
+        if Ry != R:
+            raise ValueError("out has a different number of columns")
+        check(_lib.lib().toeplitz_matvec(self._h, PREC[which], ctypes.c_void_p(x2.data_ptr()), ldx,
+                                         ctypes.c_void_p(y2.data_ptr()), ldy, R, _stream_handle(stream)))
+        return y.reshape(x.shape) if out is None else out
+
+    def solve(self, v, mode="mixed", tol=1e-8, restart=0, max_iter=2000, max_outer=50, inner_tol=1e-4, x0=None,
+              stream=None, raise_on_noconv=False):
+        """Solve Z x = v for the columns of v (complex128 cuda tensor (Nt,) or (R, Nt))."""
+        import torch
+        v2, R, ldv = self._cols(v, torch.complex128)
+        if x0 is not None:
+            x = x0.clone().reshape(R, self.Nt)
+        else:
+            x = torch.empty((R, self.Nt), dtype=torch.complex128, device=v.device)
+        x2, _, ldx = self._cols(x, torch.complex128)
+        o = _lib.SolveOpts()
+        _lib.lib().toeplitz_solve_opts_default(ctypes.byref(o))
+        o.tol, o.restart, o.max_iter, o.max_outer = tol, restart, max_iter, max_outer
+        o.mode, o.x0_given, o.inner_tol = PREC[mode], 1 if x0 is not None else 0, inner_tol
+        info = (_lib.SolveInfo * R)()
+        st = _lib.lib().toeplitz_solve(self._h, ctypes.c_void_p(v2.data_ptr()), ldv, ctypes.c_void_p(x2.data_ptr()),
+                                       ldx, R, ctypes.byref(o), info, _stream_handle(stream))
+        if st not in (_lib.TP_OK, _lib.TP_E_NOCONV, _lib.TP_E_BREAKDOWN) or (raise_on_noconv and st != _lib.TP_OK):
+            check(st)
+        infos = [dict(iters=i.iters, outer_iters=i.outer_iters, status=i.status, relres=i.relres) for i in info]
+        return x.reshape(v.shape), infos
+
+    def spectrum(self, kx, ky, which="fp64") -> np.ndarray:
+        dt = np.complex128 if which == "fp64" else np.complex64
+        out = np.empty((self.b, self.b), dtype=dt)
+        check(_lib.lib().toeplitz_plan_spectrum(self._h, PREC[which], kx, ky, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def close(self):
+        if self._h is not None:
+            _lib.lib().toeplitz_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

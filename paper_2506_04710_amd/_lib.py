@@ -1,0 +1,87 @@
+"""ctypes binding of libtoeplitz.so (the C ABI in include/toeplitz.h).
+
+Argument marshalling only: every step of apply and solve runs in the library's
+HIP kernels.  Loading fails loudly if the library has not been built; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtoeplitz.so")
+
+TP_OK, TP_E_INVAL, TP_E_NOMEM, TP_E_HIP, TP_E_NOCONV, TP_E_BREAKDOWN, TP_E_UNSUPPORTED = range(7)
+TP_FP64, TP_FP32, TP_MIXED = 0, 1, 2
+STATUS_NAMES = {0: "TP_OK", 1: "TP_E_INVAL", 2: "TP_E_NOMEM", 3: "TP_E_HIP", 4: "TP_E_NOCONV",
+                5: "TP_E_BREAKDOWN", 6: "TP_E_UNSUPPORTED"}
+PREC = {"fp64": TP_FP64, "fp32": TP_FP32, "mixed": TP_MIXED}
+
+# every symbol the header declares
+EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", "toeplitz_matvec",
+           "toeplitz_solve_opts_default", "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_plan_destroy",
+           "toeplitz_last_error")
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("Nx", ctypes.c_int), ("Ny", ctypes.c_int), ("b", ctypes.c_int), ("Nr", ctypes.c_int),
+                ("Px", ctypes.c_int), ("Py", ctypes.c_int), ("N", ctypes.c_long), ("Nt", ctypes.c_long),
+                ("max_rhs", ctypes.c_int), ("restart", ctypes.c_int), ("prec", ctypes.c_int),
+                ("spectrum_bytes", ctypes.c_size_t), ("rim_bytes", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t), ("total_bytes", ctypes.c_size_t),
+                ("reciprocal", ctypes.c_int)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("max_outer", ctypes.c_int), ("mode", ctypes.c_int), ("x0_given", ctypes.c_int),
+                ("inner_tol", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
+                ("relres", ctypes.c_double)]
+
+
+class ToeplitzError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if libtoeplitz.so is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, ci, cl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_size_t
+        L.toeplitz_plan_bytes.argtypes = [ci, ci, ci, ci, ci, ci, ci, ci, ctypes.POINTER(sz)]
+        L.toeplitz_plan_create.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, ci, ci, ci, vp, sz, vp,
+                                           ctypes.POINTER(vp)]
+        L.toeplitz_plan_info.argtypes = [vp, ctypes.POINTER(PlanDesc)]
+        L.toeplitz_matvec.argtypes = [vp, ci, vp, cl, vp, cl, ci, vp]
+        L.toeplitz_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
+        L.toeplitz_solve_opts_default.restype = None
+        L.toeplitz_solve.argtypes = [vp, vp, cl, vp, cl, ci, ctypes.POINTER(SolveOpts),
+                                     ctypes.POINTER(SolveInfo), vp]
+        L.toeplitz_plan_spectrum.argtypes = [vp, ci, ci, ci, vp]
+        L.toeplitz_plan_destroy.argtypes = [vp]
+        L.toeplitz_plan_destroy.restype = None
+        L.toeplitz_last_error.restype = ctypes.c_char_p
+        for name in ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", "toeplitz_matvec",
+                     "toeplitz_solve", "toeplitz_plan_spectrum"):
+            getattr(L, name).restype = ci
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != TP_OK:
+        raise ToeplitzError(status, lib().toeplitz_last_error().decode())
+    return status

@@ -1,0 +1,382 @@
+// C ABI of the library: plan sizing and construction, operator application,
+// solve, spectrum export, errors.  Argument checks run before any device work.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tp_internal.h"
+
+namespace tp {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+tp_status fail(tp_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+tp_status hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return TP_E_HIP;
+}
+
+// ------------------------------------------------------------ transform sizes
+static bool smooth7(int n) {
+    for (int f : {2, 3, 5, 7})
+        while (n % f == 0) n /= f;
+    return n == 1;
+}
+
+int choose_grid(int n) {
+    int P = 2 * n - 1;
+    while (!smooth7(P)) ++P;
+    return P;
+}
+
+int fft_factor(int P, int *radix, int *L) {
+    int n = P, ns = 0;
+    std::vector<int> f;
+    while (n % 4 == 0) { f.push_back(4); n /= 4; }
+    for (int r : {2, 3, 5, 7})
+        while (n % r == 0) { f.push_back(r); n /= r; }
+    int len = 1;
+    for (int r : f) {
+        radix[ns] = r;
+        L[ns] = len;
+        len *= r;
+        ++ns;
+    }
+    return ns;
+}
+
+// Slot of natural input n: the last stage splits n by n mod r into blocks of
+// length P / r; recurse on n / r inside the block.
+void fft_perm(int P, int nst, const int *radix, int *perm) {
+    for (int n = 0; n < P; ++n) {
+        int pos = 0, len = P, m = n;
+        for (int s = nst - 1; s >= 0; --s) {
+            const int r = radix[s];
+            len /= r;
+            pos += (m % r) * len;
+            m /= r;
+        }
+        perm[n] = pos;
+    }
+}
+
+int rim_slab_width(long N) {
+    // widest slab (64, 128 or 256 columns) that still gives >= 512 workgroups
+    if (N >= 512L * 256) return 256;
+    if (N >= 512L * 128) return 128;
+    return 64;
+}
+
+// ------------------------------------------------------------ plan layout
+static size_t al(size_t n) { return (n + 255) & ~(size_t)255; }
+
+struct Layout {
+    int Px, Py;
+    size_t G64, G32, B64, BE64, C64, B32, BE32, C32;   // offsets (SIZE_MAX = absent)
+    size_t tab, ws, total;
+    size_t spec1, rim1;      // bytes per copy (complex128)
+    size_t grid_bytes, rimpart_bytes, solver_bytes, scratch_bytes, ws_bytes;
+    int rim_te, rim_nslab;
+};
+
+static bool overflow_mul(size_t a, size_t b, size_t *out) {
+    if (a && b > SIZE_MAX / a) return true;
+    *out = a * b;
+    return false;
+}
+
+static tp_status make_layout(int Nx, int Ny, int b, int Nr, int reciprocal, tp_prec prec, int max_rhs,
+                             int restart, Layout *L) {
+    if (Nx < 1 || Ny < 1 || b < 1 || Nr < 0 || max_rhs < 1 || restart < 1)
+        return fail(TP_E_INVAL, "Nx, Ny, b, max_rhs, restart must be >= 1 and Nr >= 0");
+    if (prec != TP_FP64 && prec != TP_FP32 && prec != TP_MIXED) return fail(TP_E_INVAL, "unknown precision");
+    if (Nx > 256 || Ny > 256) return fail(TP_E_INVAL, "Nx and Ny are limited to 256 (transform length <= 512)");
+    if (b > 256) return fail(TP_E_INVAL, "b is limited to 256");
+    if (Nr > 2048) return fail(TP_E_INVAL, "Nr is limited to 2048");
+    if (restart > 512) return fail(TP_E_INVAL, "restart is limited to 512");
+    L->Px = choose_grid(Nx);
+    L->Py = choose_grid(Ny);
+    if (L->Px > kMaxP || L->Py > kMaxP) return fail(TP_E_INVAL, "transform length exceeds 512");
+    const size_t N = (size_t)Nx * Ny * b, Nt = N + Nr, P = (size_t)L->Px * L->Py;
+    const size_t bb = (size_t)b * b;
+    size_t t;
+    if (overflow_mul(P, bb, &t) || overflow_mul(t, 16, &L->spec1)) return fail(TP_E_INVAL, "size overflow");
+    const size_t nrim = reciprocal ? 1 : 2;
+    L->rim1 = (nrim * (size_t)Nr * N + (size_t)Nr * Nr) * 16;
+    const bool f64 = prec != TP_FP32, f32 = prec != TP_FP64;
+    size_t off = 0;
+    auto take = [&](bool present, size_t bytes) -> size_t {
+        if (!present) return SIZE_MAX;
+        size_t o = off;
+        off += al(bytes);
+        return o;
+    };
+    L->G64 = take(f64, L->spec1);
+    L->G32 = take(f32, L->spec1 / 2);
+    L->B64 = take(f64 && Nr, (size_t)Nr * N * 16);
+    L->BE64 = take(f64 && Nr && !reciprocal, (size_t)Nr * N * 16);
+    L->C64 = take(f64 && Nr, (size_t)Nr * Nr * 16);
+    L->B32 = take(f32 && Nr, (size_t)Nr * N * 8);
+    L->BE32 = take(f32 && Nr && !reciprocal, (size_t)Nr * N * 8);
+    L->C32 = take(f32 && Nr, (size_t)Nr * Nr * 8);
+    const size_t tab_bytes = al((size_t)(L->Px + L->Py) * 4) + al((size_t)(L->Px + L->Py) * 16) +
+                             al((size_t)(L->Px + L->Py) * 8);
+    L->tab = take(true, tab_bytes);
+    // workspace: two transform grids, rim partial sums, Krylov storage
+    const size_t gpts = std::max((size_t)Ny * L->Px, P);
+    L->grid_bytes = al(gpts * (size_t)b * max_rhs * 16);
+    L->rim_te = rim_slab_width((long)N);
+    L->rim_nslab = (int)((N + L->rim_te - 1) / L->rim_te);
+    L->rimpart_bytes = al((size_t)L->rim_nslab * (Nr ? Nr : 1) * max_rhs * 16);
+    L->solver_bytes = al(solver_ws_bytes((long)Nt, restart, max_rhs));
+    // plan-time scratch: device copy of the generators + the x-transformed rows
+    L->scratch_bytes = al((size_t)(2 * Ny - 1) * (2 * Nx - 1) * bb * 16) + al((size_t)(2 * Ny - 1) * L->Px * bb * 16) +
+                       al((size_t)Nr * std::max(N, (size_t)Nr) * 16);
+    L->ws_bytes = std::max(2 * L->grid_bytes + L->rimpart_bytes + L->solver_bytes, L->scratch_bytes);
+    L->ws = take(true, L->ws_bytes);
+    L->total = off;
+    return TP_OK;
+}
+
+}  // namespace tp
+
+using namespace tp;
+
+extern "C" {
+
+const char *toeplitz_last_error(void) { return g_err.c_str(); }
+
+tp_status toeplitz_plan_bytes(int Nx, int Ny, int b, int Nr, int reciprocal, tp_prec prec, int max_rhs,
+                              int restart, size_t *bytes) {
+    if (!bytes) return fail(TP_E_INVAL, "bytes is NULL");
+    Layout L;
+    tp_status s = make_layout(Nx, Ny, b, Nr, reciprocal ? 1 : 0, prec, max_rhs, restart, &L);
+    if (s != TP_OK) return s;
+    *bytes = L.total;
+    return TP_OK;
+}
+
+tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen, const double *rim_re,
+                               const double *rim_er, const double *rim_rr, tp_prec prec, int max_rhs, int restart,
+                               void *dev_buf, size_t dev_bytes, void *hip_stream, tp_plan *out) {
+    if (!out) return fail(TP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!gen) return fail(TP_E_INVAL, "gen is NULL");
+    if (Nr > 0 && (!rim_re || !rim_rr)) return fail(TP_E_INVAL, "rim_re and rim_rr are required when Nr > 0");
+    if (!dev_buf) return fail(TP_E_INVAL, "dev_buf is NULL");
+    if (((uintptr_t)dev_buf) & 255) return fail(TP_E_INVAL, "dev_buf must be 256-byte aligned");
+    const int reciprocal = (rim_er == nullptr) ? 1 : 0;
+    Layout L;
+    tp_status s = make_layout(Nx, Ny, b, Nr, reciprocal, prec, max_rhs, restart, &L);
+    if (s != TP_OK) return s;
+    if (dev_bytes < L.total)
+        return fail(TP_E_NOMEM, "device buffer holds " + std::to_string(dev_bytes) + " bytes, plan needs " +
+                                    std::to_string(L.total));
+    hipStream_t st = (hipStream_t)hip_stream;
+    tp_plan_s *pl = new (std::nothrow) tp_plan_s();
+    if (!pl) return fail(TP_E_NOMEM, "host allocation failed");
+    char *base = (char *)dev_buf;
+    auto at = [&](size_t off) -> char * { return off == SIZE_MAX ? nullptr : base + off; };
+    pl->Nx = Nx; pl->Ny = Ny; pl->b = b; pl->Nr = Nr;
+    pl->Px = L.Px; pl->Py = L.Py;
+    pl->N = (long)Nx * Ny * b; pl->Nt = pl->N + Nr;
+    pl->max_rhs = max_rhs; pl->restart = restart; pl->prec = prec; pl->reciprocal = reciprocal;
+    pl->base = base; pl->total = L.total;
+    pl->G64 = (c128 *)at(L.G64); pl->G32 = (c64 *)at(L.G32);
+    pl->B64 = (c128 *)at(L.B64); pl->BE64 = (c128 *)at(L.BE64); pl->C64 = (c128 *)at(L.C64);
+    pl->B32 = (c64 *)at(L.B32); pl->BE32 = (c64 *)at(L.BE32); pl->C32 = (c64 *)at(L.C32);
+    pl->spectrum_bytes = L.spec1; pl->rim_bytes = L.rim1;
+    pl->ws = at(L.ws); pl->ws_bytes = L.ws_bytes; pl->workspace_bytes = L.ws_bytes;
+    pl->gridA = pl->ws;
+    pl->gridB = pl->ws + L.grid_bytes;
+    pl->rim_part = pl->ws + 2 * L.grid_bytes;
+    pl->rim_te = L.rim_te; pl->rim_nslab = L.rim_nslab;
+
+    // transform tables
+    const int Px = L.Px, Py = L.Py;
+    char *tab = at(L.tab);
+    int *perm_x = (int *)tab, *perm_y = perm_x + Px;
+    c128 *tw64_x = (c128 *)(tab + al((size_t)(Px + Py) * 4)), *tw64_y = tw64_x + Px;
+    c64 *tw32_x = (c64 *)(tab + al((size_t)(Px + Py) * 4) + al((size_t)(Px + Py) * 16)), *tw32_y = tw32_x + Px;
+    std::vector<int> hperm(Px + Py);
+    std::vector<c128> htw64(Px + Py);
+    std::vector<c64> htw32(Px + Py);
+    FFTDesc *descs[2] = {&pl->fx, &pl->fy};
+    const int Ps[2] = {Px, Py};
+    for (int d = 0; d < 2; ++d) {
+        FFTDesc &D = *descs[d];
+        D.P = Ps[d];
+        D.nst = fft_factor(D.P, D.radix, D.L);
+        const int o = d ? Px : 0;
+        fft_perm(D.P, D.nst, D.radix, hperm.data() + o);
+        for (int k = 0; k < D.P; ++k) {
+            const long double a = 2.0L * 3.141592653589793238462643383279503L * (long double)k / (long double)D.P;
+            htw64[o + k] = {(double)cosl(a), (double)-sinl(a)};
+            htw32[o + k] = {(float)htw64[o + k].x, (float)htw64[o + k].y};
+        }
+        D.perm = d ? perm_y : perm_x;
+        D.tw64 = d ? tw64_y : tw64_x;
+        D.tw32 = d ? tw32_y : tw32_x;
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(perm_x, hperm.data(), sizeof(int) * (Px + Py), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(tw64_x, htw64.data(), sizeof(c128) * (Px + Py), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(tw32_x, htw32.data(), sizeof(c64) * (Px + Py), hipMemcpyHostToDevice, st))) {
+        delete pl;
+        return hip_fail(e, "plan tables upload");
+    }
+    // spectrum: generators -> scratch, two transform passes -> G64 / G32
+    const size_t bb = (size_t)b * b;
+    const size_t gen_bytes = (size_t)(2 * Ny - 1) * (2 * Nx - 1) * bb * 16;
+    c128 *gen_dev = (c128 *)pl->ws;
+    c128 *tmp = (c128 *)(pl->ws + al(gen_bytes));
+    c128 *rim_tmp = (c128 *)(pl->ws + al(gen_bytes) + al((size_t)(2 * Ny - 1) * Px * bb * 16));
+    if ((e = hipMemcpyAsync(gen_dev, gen, gen_bytes, hipMemcpyHostToDevice, st))) {
+        delete pl;
+        return hip_fail(e, "generator upload");
+    }
+    if ((e = spectrum_build(pl, gen_dev, tmp, st))) {
+        delete pl;
+        return hip_fail(e, "spectrum build");
+    }
+    // rim blocks: complex128 copies and/or complex64 casts
+    if (Nr > 0) {
+        const size_t nN = (size_t)Nr * pl->N, nC = (size_t)Nr * Nr;
+        std::vector<c128> ber;
+        if (!reciprocal) {      // store B_er transposed, [Nr][N], like B
+            ber.resize(nN);
+            const c128 *src = (const c128 *)rim_er;
+            for (long ei = 0; ei < pl->N; ++ei)
+                for (int r = 0; r < Nr; ++r) ber[(size_t)r * pl->N + ei] = src[(size_t)ei * Nr + r];
+        }
+        struct Item { const void *src; size_t n; c128 *d64; c64 *d32; };
+        Item items[3] = {{rim_re, nN, pl->B64, pl->B32},
+                         {reciprocal ? nullptr : (const void *)ber.data(), nN, pl->BE64, pl->BE32},
+                         {rim_rr, nC, pl->C64, pl->C32}};
+        for (const Item &it : items) {
+            if (!it.src) continue;
+            c128 *stage = it.d64 ? it.d64 : rim_tmp;
+            if ((e = hipMemcpyAsync(stage, it.src, it.n * 16, hipMemcpyHostToDevice, st))) {
+                delete pl;
+                return hip_fail(e, "rim upload");
+            }
+            if (it.d32 && (e = cast_to_c64(stage, it.d32, (long)it.n, st))) {
+                delete pl;
+                return hip_fail(e, "rim cast");
+            }
+            if (!it.d64 && (e = hipStreamSynchronize(st))) {   // rim_tmp is reused by the next item
+                delete pl;
+                return hip_fail(e, "rim cast sync");
+            }
+        }
+    }
+    if ((e = hipStreamSynchronize(st))) {
+        delete pl;
+        return hip_fail(e, "plan create");
+    }
+    *out = pl;
+    return TP_OK;
+}
+
+tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *d) {
+    if (!p || !d) return fail(TP_E_INVAL, "NULL argument");
+    d->Nx = p->Nx; d->Ny = p->Ny; d->b = p->b; d->Nr = p->Nr;
+    d->Px = p->Px; d->Py = p->Py; d->N = p->N; d->Nt = p->Nt;
+    d->max_rhs = p->max_rhs; d->restart = p->restart; d->prec = p->prec;
+    d->spectrum_bytes = p->spectrum_bytes; d->rim_bytes = p->rim_bytes;
+    d->workspace_bytes = p->workspace_bytes; d->total_bytes = p->total;
+    d->reciprocal = p->reciprocal;
+    return TP_OK;
+}
+
+tp_status toeplitz_matvec(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int nrhs,
+                          void *hip_stream) {
+    if (!p) return fail(TP_E_INVAL, "plan is NULL");
+    if (!x || !y) return fail(TP_E_INVAL, "x or y is NULL");
+    if (nrhs < 1 || nrhs > p->max_rhs) return fail(TP_E_INVAL, "nrhs must be in [1, max_rhs]");
+    if (ldx < p->Nt || ldy < p->Nt) return fail(TP_E_INVAL, "leading dimension smaller than Nt");
+    const size_t es = which == TP_FP64 ? 16 : 8;
+    const char *xa = (const char *)x, *ya = (const char *)y;
+    const size_t xb = ((size_t)ldx * (nrhs - 1) + p->Nt) * es, yb = ((size_t)ldy * (nrhs - 1) + p->Nt) * es;
+    if (xa < ya + yb && ya < xa + xb) return fail(TP_E_INVAL, "x and y overlap");
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e;
+    if (which == TP_FP64) {
+        if (!p->G64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 operator");
+        e = matvec_fp64(p, Cols<const c128>{(const c128 *)x, ldx, nullptr}, Cols<c128>{(c128 *)y, ldy, nullptr},
+                        nrhs, st);
+    } else if (which == TP_FP32) {
+        if (!p->G32) return fail(TP_E_UNSUPPORTED, "plan holds no FP32 operator");
+        e = matvec_fp32(p, Cols<const c64>{(const c64 *)x, ldx, nullptr}, Cols<c64>{(c64 *)y, ldy, nullptr}, nrhs,
+                        st);
+    } else {
+        return fail(TP_E_INVAL, "matvec precision must be TP_FP64 or TP_FP32");
+    }
+    if (e != hipSuccess) return hip_fail(e, "matvec launch");
+    return TP_OK;
+}
+
+tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void *host_out) {
+    if (!p || !host_out) return fail(TP_E_INVAL, "NULL argument");
+    if (kx < 0 || kx >= p->Px || ky < 0 || ky >= p->Py) return fail(TP_E_INVAL, "frequency out of range");
+    const size_t bb = (size_t)p->b * p->b;
+    const size_t k = (size_t)kx * p->Py + ky;
+    hipError_t e;
+    if (which == TP_FP64) {
+        if (!p->G64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 operator");
+        e = hipMemcpy(host_out, p->G64 + k * bb, bb * 16, hipMemcpyDeviceToHost);
+    } else if (which == TP_FP32) {
+        if (!p->G32) return fail(TP_E_UNSUPPORTED, "plan holds no FP32 operator");
+        e = hipMemcpy(host_out, p->G32 + k * bb, bb * 8, hipMemcpyDeviceToHost);
+    } else {
+        return fail(TP_E_INVAL, "precision must be TP_FP64 or TP_FP32");
+    }
+    return e == hipSuccess ? TP_OK : hip_fail(e, "spectrum copy");
+}
+
+void toeplitz_solve_opts_default(tp_solve_opts *o) {
+    if (!o) return;
+    o->tol = 1e-8;
+    o->restart = 0;
+    o->max_iter = 2000;
+    o->max_outer = 50;
+    o->mode = TP_FP64;
+    o->x0_given = 0;
+    o->inner_tol = 1e-4;
+}
+
+tp_status toeplitz_solve(tp_plan p, const void *v, long ldv, void *x, long ldx, int nrhs, const tp_solve_opts *opts,
+                         tp_solve_info *info, void *hip_stream) {
+    if (!p) return fail(TP_E_INVAL, "plan is NULL");
+    if (!v || !x || !info) return fail(TP_E_INVAL, "v, x or info is NULL");
+    if (nrhs < 1 || nrhs > p->max_rhs) return fail(TP_E_INVAL, "nrhs must be in [1, max_rhs]");
+    if (ldv < p->Nt || ldx < p->Nt) return fail(TP_E_INVAL, "leading dimension smaller than Nt");
+    const char *va = (const char *)v, *xa = (const char *)x;
+    const size_t vb = ((size_t)ldv * (nrhs - 1) + p->Nt) * 16, xb = ((size_t)ldx * (nrhs - 1) + p->Nt) * 16;
+    if (va < xa + xb && xa < va + vb) return fail(TP_E_INVAL, "v and x overlap");
+    tp_solve_opts o;
+    toeplitz_solve_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.restart <= 0) o.restart = p->restart;
+    if (o.restart > p->restart) return fail(TP_E_INVAL, "restart exceeds the plan's restart");
+    if (!(o.tol > 0) || o.max_iter < 1 || o.max_outer < 1) return fail(TP_E_INVAL, "bad tol / max_iter / max_outer");
+    if (o.mode == TP_FP64) {
+        if (!p->G64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 operator");
+    } else if (o.mode == TP_MIXED) {
+        if (!p->G64 || !p->G32) return fail(TP_E_UNSUPPORTED, "mixed solves need a TP_MIXED plan");
+        if (!(o.inner_tol > 0 && o.inner_tol < 1)) return fail(TP_E_INVAL, "inner_tol must be in (0, 1)");
+    } else {
+        return fail(TP_E_INVAL, "solve mode must be TP_FP64 or TP_MIXED");
+    }
+    return solve_run(p, (const c128 *)v, ldv, (c128 *)x, ldx, nrhs, o, info, (hipStream_t)hip_stream);
+}
+
+void toeplitz_plan_destroy(tp_plan p) { delete p; }
+
+}  // extern "C"

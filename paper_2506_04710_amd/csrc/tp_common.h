@@ -1,0 +1,115 @@
+// Shared types for the gfx950 block-Toeplitz library: complex values, error
+// handling and the plan record.  Host and device code include it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/toeplitz.h"
+
+namespace tp {
+
+// Interleaved complex number; 8-byte (float) or 16-byte (double) aligned so
+// that one value is one vector load.
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    using value_type = T;
+    T x, y;
+};
+using c64 = cpx<float>;
+using c128 = cpx<double>;
+
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> mk(T a, T b) { return cpx<T>{a, b}; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> conjg(cpx<T> a) { return {a.x, -a.y}; }
+// acc + a * b with fused multiply-adds
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> cmac(cpx<T> acc, cpx<T> a, cpx<T> b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// acc + conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> cmac_conj(cpx<T> acc, cpx<T> a, cpx<T> b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+template <typename T, typename U>
+__host__ __device__ __forceinline__ cpx<T> cvt(cpx<U> a) { return {static_cast<T>(a.x), static_cast<T>(a.y)}; }
+
+// Column access for multi-vector operands: either base + r * ld, or a device
+// table of column pointers (used by the solver, whose columns live apart).
+template <typename V>
+struct Cols {
+    V *base;
+    long ld;
+    V *const *tab;
+    __device__ __forceinline__ V *col(int r) const { return tab ? tab[r] : base + (long)r * ld; }
+};
+
+// Radix plan of one transform length P (mixed radix, in-place decimation in
+// time): stage s combines sub-transforms of length L[s] with radix radix[s].
+// perm (device) maps natural input index n to its LDS slot; tw holds
+// exp(-2 pi i k / P), k < P.
+struct FFTDesc {
+    int P;
+    int nst;
+    int radix[12];
+    int L[12];
+    const int *perm;
+    const c128 *tw64;
+    const c64 *tw32;
+};
+
+constexpr int kMaxP = 512;
+
+}  // namespace tp
+
+// Plan record (host memory; every pointer is into the caller's device buffer).
+struct tp_plan_s {
+    int Nx, Ny, b, Nr;
+    int Px, Py;
+    long N, Nt;
+    int max_rhs, restart;
+    tp_prec prec;
+    int reciprocal;
+    char *base;
+    size_t total;
+    // operator copies
+    tp::c128 *G64;
+    tp::c64 *G32;
+    tp::c128 *B64, *BE64, *C64;   // B [Nr][N], B_er^T [Nr][N] (non-reciprocal), C [Nr][Nr]
+    tp::c64 *B32, *BE32, *C32;
+    size_t spectrum_bytes, rim_bytes;
+    // transform tables
+    tp::FFTDesc fx, fy;
+    // matvec workspace
+    void *gridA, *gridB;          // [max(Ny*Px, Px*Py)][b*max_rhs] complex128-sized each
+    void *rim_part;               // [nslab][Nr][max_rhs] complex128-sized
+    int rim_te;                   // rim columns per slab
+    int rim_nslab;
+    // solver workspace
+    char *ws;
+    size_t ws_bytes;
+    size_t workspace_bytes;
+};

@@ -1,0 +1,36 @@
+// Declarations shared between the library's translation units.
+#pragma once
+
+#include <string>
+
+#include "tp_common.h"
+
+namespace tp {
+
+// thread-local error message for toeplitz_last_error()
+void set_error(const std::string &msg);
+tp_status fail(tp_status s, const std::string &msg);
+tp_status hip_fail(hipError_t e, const char *what);
+
+// operator application (tp_matvec.hip)
+hipError_t matvec_fp64(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st);
+hipError_t matvec_fp32(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStream_t st);
+// FP32 operator on complex128 vectors (inner solves of the mixed scheme)
+hipError_t matvec_fp32_wide(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st);
+hipError_t spectrum_build(tp_plan pl, const c128 *gen_dev, c128 *tmp, hipStream_t st);
+hipError_t cast_to_c64(const c128 *in, c64 *out, long n, hipStream_t st);
+
+// plan-time transform tables (tp_plan.cpp side of tp_capi.hip)
+int choose_grid(int n);                     // smallest 2/3/5/7-smooth size >= 2n-1
+int fft_factor(int P, int *radix, int *L);  // stage radices and sub-lengths; returns stage count
+void fft_perm(int P, int nst, const int *radix, int *perm);
+
+// rim slab width chosen for N columns
+int rim_slab_width(long N);
+
+// solver (tp_gmres.hip)
+size_t solver_ws_bytes(long Nt, int restart, int max_rhs);
+tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int nrhs,
+                    const tp_solve_opts &o, tp_solve_info *info, hipStream_t st);
+
+}  // namespace tp

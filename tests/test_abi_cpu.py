@@ -1,0 +1,103 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "toeplitz.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2506_04710_amd import _lib
+    return _lib.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(toeplitz_\w+)\s*\(", src)))
+
+
+def test_header_declares_expected_api():
+    from paper_2506_04710_amd import _lib
+    assert declared_functions() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_plan_bytes_matches_layout_accounting(L):
+    from paper_2506_04710_amd import plan_bytes
+    # spectrum of config 2 at Px = Py = 63: 63*63*64*64 complex128 = 260 MB, and half for complex64
+    b64 = plan_bytes(32, 32, 64, 256, "fp64", 1, 40)
+    b32 = plan_bytes(32, 32, 64, 256, "fp32", 1, 40)
+    bm = plan_bytes(32, 32, 64, 256, "mixed", 1, 40)
+    spec = 63 * 63 * 64 * 64 * 16
+    rim = (256 * 65536 + 256 * 256) * 16
+    assert b64 >= spec + rim and b32 >= (spec + rim) // 2
+    assert bm - b64 >= (spec + rim) // 2 - 4096 * 8
+    # a non-reciprocal rim stores a second dense block per precision
+    nr = plan_bytes(32, 32, 64, 256, "fp64", 1, 40, reciprocal=False)
+    assert nr - b64 >= 256 * 65536 * 16
+    # more columns and longer restarts need more Krylov workspace (small array: the
+    # plan-time scratch does not dominate)
+    small = plan_bytes(8, 8, 16, 0, "mixed", 4, 40)
+    assert plan_bytes(8, 8, 16, 0, "mixed", 64, 40) > small
+    assert plan_bytes(8, 8, 16, 0, "mixed", 4, 200) > small
+
+
+@pytest.mark.parametrize("args", [
+    (0, 4, 16, 0), (4, 0, 16, 0), (4, 4, 0, 0), (4, 4, 16, -1), (257, 4, 4, 0), (4, 4, 257, 0)])
+def test_plan_bytes_rejects_bad_shapes(L, args):
+    n = ctypes.c_size_t(0)
+    assert L.toeplitz_plan_bytes(*args, 1, 2, 1, 40, ctypes.byref(n)) == 1
+    assert L.toeplitz_last_error()
+
+
+def test_plan_bytes_rejects_bad_options(L):
+    n = ctypes.c_size_t(0)
+    assert L.toeplitz_plan_bytes(4, 4, 16, 0, 1, 7, 1, 40, ctypes.byref(n)) == 1     # precision
+    assert L.toeplitz_plan_bytes(4, 4, 16, 0, 1, 0, 0, 40, ctypes.byref(n)) == 1     # max_rhs
+    assert L.toeplitz_plan_bytes(4, 4, 16, 0, 1, 0, 1, 0, ctypes.byref(n)) == 1      # restart
+    assert L.toeplitz_plan_bytes(4, 4, 16, 0, 1, 0, 1, 40, None) == 1
+
+
+def test_plan_create_validates_before_device_work(L):
+    from paper_2506_04710_amd import _lib
+    h = ctypes.c_void_p()
+    gen = (ctypes.c_double * (2 * 7 * 7 * 4))()
+    fake = ctypes.c_void_p(0x1000)          # never dereferenced: validation fails first
+    # NULL generators
+    assert L.toeplitz_plan_create(4, 4, 1, 0, None, None, None, None, 0, 1, 8, fake, 1 << 30, None,
+                                  ctypes.byref(h)) == _lib.TP_E_INVAL
+    # rim blocks missing with Nr > 0
+    assert L.toeplitz_plan_create(4, 4, 1, 3, gen, None, None, None, 0, 1, 8, fake, 1 << 30, None,
+                                  ctypes.byref(h)) == _lib.TP_E_INVAL
+    # misaligned device buffer
+    assert L.toeplitz_plan_create(4, 4, 1, 0, gen, None, None, None, 0, 1, 8, ctypes.c_void_p(0x1001),
+                                  1 << 30, None, ctypes.byref(h)) == _lib.TP_E_INVAL
+    # buffer too small
+    assert L.toeplitz_plan_create(4, 4, 1, 0, gen, None, None, None, 0, 1, 8, fake, 16, None,
+                                  ctypes.byref(h)) == _lib.TP_E_NOMEM
+    assert h.value is None
+
+
+def test_null_plan_calls_fail_cleanly(L):
+    from paper_2506_04710_amd import _lib
+    assert L.toeplitz_matvec(None, 0, None, 1, None, 1, 1, None) == _lib.TP_E_INVAL
+    assert L.toeplitz_solve(None, None, 1, None, 1, 1, None, None, None) == _lib.TP_E_INVAL
+    assert L.toeplitz_plan_info(None, None) == _lib.TP_E_INVAL
+    L.toeplitz_plan_destroy(None)
+
+
+def test_solve_defaults(L):
+    from paper_2506_04710_amd import _lib
+    o = _lib.SolveOpts()
+    L.toeplitz_solve_opts_default(ctypes.byref(o))
+    assert o.tol == 1e-8 and o.max_iter == 2000 and o.mode == _lib.TP_FP64 and o.x0_given == 0

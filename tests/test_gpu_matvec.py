@@ -1,0 +1,155 @@
+"""GPU parity of the operator application and of the plan-time spectrum,
+through the C ABI, against the plain FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import arrays as sa
+from helpers import banner, random_rim_er, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL64, TOL32 = 1e-10, 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2506_04710_amd as tp
+    tp.load()
+    return torch
+
+
+def _matvec_case(torch, prob, X, rim_er=None, which="fp64", ld_pad=0):
+    import paper_2506_04710_amd as tp
+    R = X.shape[0]
+    plan = tp.Plan.create(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, rim_er=rim_er,
+                          prec="mixed", max_rhs=R, restart=4)
+    dt = torch.complex128 if which == "fp64" else torch.complex64
+    xd = torch.zeros((R, prob.Nt + ld_pad), dtype=dt, device="cuda:0")
+    xd[:, :prob.Nt] = to_dev(X, dt)
+    yd = torch.zeros((R, prob.Nt + ld_pad), dtype=dt, device="cuda:0")
+    plan.matvec(xd[:, :prob.Nt], which=which, out=yd[:, :prob.Nt])
+    torch.cuda.synchronize()
+    return yd[:, :prob.Nt].cpu().numpy().astype(np.complex128), plan
+
+
+CASES = [  # (Nx, Ny, b, Nr, R): ragged b against the 64-lane rows, prime and padded grids
+    (4, 4, 16, 24, 1), (1, 1, 8, 0, 1), (1, 5, 4, 3, 2), (7, 2, 3, 0, 1), (5, 3, 33, 10, 3),
+    (3, 4, 70, 5, 2), (17, 9, 8, 20, 1), (2, 3, 100, 7, 5), (9, 9, 96, 72, 1)]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}b{c[2]}r{c[3]}R{c[4]}" for c in CASES])
+@pytest.mark.parametrize("which", ["fp64", "fp32"])
+def test_matvec_parity(torch_cuda, case, which):
+    Nx, Ny, b, Nr, R = case
+    banner(f"matvec {which} {case}")
+    prob = sa.make_problem(Nx, Ny, b, Nr, 3000 + Nx * 100 + Ny * 10 + b)
+    X = sa.rhs_random(prob, R)
+    if which == "fp32":
+        X = X.astype(np.complex64).astype(np.complex128)     # the exact input the kernel sees
+    Y, _ = _matvec_case(torch_cuda, prob, X, which=which, ld_pad=3 if R > 1 else 0)
+    ref = oracle.matvec(prob, X)
+    err = rel_err(Y, ref)
+    assert err <= (TOL64 if which == "fp64" else TOL32), err
+
+
+@pytest.mark.parametrize("which", ["fp64", "fp32"])
+def test_matvec_nonreciprocal_rim(torch_cuda, which):
+    banner(f"matvec non-reciprocal {which}")
+    prob = sa.make_problem(6, 5, 12, 9, 41)
+    rim_er = random_rim_er(prob, 5)
+    X = sa.rhs_random(prob, 2)
+    if which == "fp32":
+        X = X.astype(np.complex64).astype(np.complex128)
+    Y, _ = _matvec_case(torch_cuda, prob, X, rim_er=rim_er, which=which)
+    op = oracle.Operator(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, rim_er)
+    assert rel_err(Y, oracle.matvec(op, X)) <= (TOL64 if which == "fp64" else TOL32)
+
+
+def test_matvec_batch_invariant_bitwise(torch_cuda):
+    """Each column of a batched product equals the same column applied alone, bit for bit."""
+    banner("matvec batch invariance")
+    prob = sa.make_problem(5, 4, 24, 12, 42)
+    X = sa.rhs_random(prob, 5)
+    Yb, _ = _matvec_case(torch_cuda, prob, X)
+    for r in range(5):
+        Y1, _ = _matvec_case(torch_cuda, prob, X[r:r + 1])
+        assert np.array_equal(Y1[0], Yb[r])
+
+
+def test_matvec_repeat_bitwise(torch_cuda):
+    banner("matvec repeat determinism")
+    import paper_2506_04710_amd as tp
+    prob = sa.make_problem(6, 6, 20, 16, 43)
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=2, restart=4)
+    x = to_dev(sa.rhs_random(prob, 2))
+    y1 = plan.matvec(x).cpu().numpy()
+    y2 = plan.matvec(x).cpu().numpy()
+    assert np.array_equal(y1, y2)
+
+
+def test_embed_crop_identity(torch_cuda):
+    """Only Z_{0,0} = I: every stage (embed, transforms, product, crop) must return x."""
+    banner("embed/crop identity")
+    import paper_2506_04710_amd as tp
+    Nx, Ny, b = 5, 7, 6
+    gen = np.zeros((2 * Ny - 1, 2 * Nx - 1, b, b), dtype=complex)
+    gen[Ny - 1, Nx - 1] = np.eye(b)
+    plan = tp.Plan.create(Nx, Ny, b, 0, gen, prec="mixed", max_rhs=1, restart=4)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(Nx * Ny * b) + 1j * rng.standard_normal(Nx * Ny * b)
+    y = plan.matvec(to_dev(x)).cpu().numpy()
+    assert np.max(np.abs(y - x)) <= 1e-14 * np.max(np.abs(x))
+
+
+def test_spectrum_parity(torch_cuda):
+    banner("spectrum parity config 1")
+    import paper_2506_04710_amd as tp
+    prob, _ = sa.make_config(1)
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=1, restart=4)
+    info = plan.info()
+    Px, Py = info["Px"], info["Py"]
+    assert Px >= 2 * prob.Nx - 1 and Py >= 2 * prob.Ny - 1
+    kx, ky = np.meshgrid(np.arange(Px), np.arange(Py), indexing="ij")
+    ref = oracle.spectrum(prob, Px, Py, kx.ravel(), ky.ravel())
+    got64 = np.stack([plan.spectrum(int(a), int(c), "fp64") for a, c in zip(kx.ravel(), ky.ravel())])
+    got32 = np.stack([plan.spectrum(int(a), int(c), "fp32") for a, c in zip(kx.ravel(), ky.ravel())])
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(got64 - ref)) <= 1e-13 * scale
+    assert np.max(np.abs(got32 - ref)) <= 1e-6 * scale
+
+
+def test_spectrum_parity_config2_sampled(torch_cuda):
+    banner("spectrum parity config 2 sampled")
+    import paper_2506_04710_amd as tp
+    prob, _ = sa.make_config(2)
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=1, restart=4)
+    info = plan.info()
+    Px, Py = info["Px"], info["Py"]
+    assert (Px, Py) == (63, 63)
+    ks = [(0, 0), (1, 0), (0, 1), (Px - 1, Py - 1), (31, 17), (62, 5)]
+    ref = oracle.spectrum(prob, Px, Py, [k[0] for k in ks], [k[1] for k in ks])
+    got = np.stack([plan.spectrum(a, c, "fp64") for a, c in ks])
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("cfg", [2, 4])
+@pytest.mark.parametrize("which", ["fp64", "fp32"])
+def test_matvec_full_size_sampled(torch_cuda, cfg, which):
+    """Benchmark-size arrays: sampled output rows against the oracle's row sums."""
+    banner(f"matvec full size config {cfg} {which}")
+    import paper_2506_04710_amd as tp
+    torch = torch_cuda
+    prob, V = sa.make_config(cfg)
+    if which == "fp32":
+        V = V.astype(np.complex64).astype(np.complex128)
+    R = V.shape[0]
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=R, restart=4)
+    dt = torch.complex128 if which == "fp64" else torch.complex64
+    Y = plan.matvec(to_dev(V, dt)).cpu().numpy().astype(np.complex128).reshape(R, prob.Nt)
+    rng = np.random.default_rng(cfg)
+    rows = np.unique(np.concatenate([[0, prob.N - 1, prob.Nt - 1], rng.integers(0, prob.Nt, 40),
+                                     prob.N + np.arange(min(prob.Nr, 4))]))
+    ref = oracle.matvec(prob, V, rows=rows)
+    assert rel_err(Y[:, rows], ref) <= (TOL64 if which == "fp64" else TOL32)

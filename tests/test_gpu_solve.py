@@ -1,0 +1,135 @@
+"""GPU solves (plain FP64 GMRES and mixed-precision refinement) checked by the
+oracle's FP64 residual, and against the oracle's dense LU where it fits."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import arrays as sa
+from helpers import banner, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tp():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2506_04710_amd as tp
+    tp.load()
+    return tp
+
+
+def _solve(tp, prob, V, mode, tol=1e-8, restart=40, **kw):
+    R = V.shape[0]
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=R, restart=restart)
+    x, info = plan.solve(to_dev(V), mode=mode, tol=tol, **kw)
+    return x.cpu().numpy().reshape(R, prob.Nt), info, plan
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_solve_config1_vs_lu(tp, mode):
+    banner(f"solve config 1 {mode}")
+    prob, V = sa.make_config(1)
+    X, info, _ = _solve(tp, prob, V, mode)
+    rr = oracle.relres(prob, X, V)
+    assert info[0]["status"] == 0 and rr[0] <= 1e-8, (info, rr)
+    assert abs(info[0]["relres"] - rr[0]) <= 1e-12 + 1e-3 * rr[0]       # library's own FP64 residual
+    Xlu = oracle.lu_solve(oracle.assemble(prob), V)
+    assert rel_err(X, Xlu) <= 1e-6
+    print(f"config1 {mode}: iters={info[0]['iters']} outer={info[0]['outer_iters']} relres={rr[0]:.2e} "
+          f"fwd_err={rel_err(X, Xlu):.2e}")
+
+
+def test_solve_scaled_identity_one_step(tp):
+    """Z = alpha I: the first Krylov vector is the solution (one Arnoldi step)."""
+    banner("solve scaled identity")
+    Nx, Ny, b = 3, 2, 4
+    gen = np.zeros((2 * Ny - 1, 2 * Nx - 1, b, b), dtype=complex)
+    gen[Ny - 1, Nx - 1] = (2 - 1j) * np.eye(b)
+    plan = tp.Plan.create(Nx, Ny, b, 0, gen, prec="mixed", max_rhs=1, restart=10)
+    v = np.random.default_rng(1).standard_normal(Nx * Ny * b) + 0j
+    x, info = plan.solve(to_dev(v), mode="fp64", tol=1e-12)
+    assert info[0]["iters"] == 1 and info[0]["status"] == 0
+    assert np.allclose(x.cpu().numpy(), v / (2 - 1j), rtol=1e-13, atol=0)
+
+
+def test_solve_block_diagonal_minimal_polynomial(tp):
+    """Only Z_{0,0} != 0: Z = I (x) Z00, so GMRES ends within b steps."""
+    banner("solve block diagonal")
+    Nx, Ny, b = 4, 3, 6
+    rng = np.random.default_rng(2)
+    gen = np.zeros((2 * Ny - 1, 2 * Nx - 1, b, b), dtype=complex)
+    gen[Ny - 1, Nx - 1] = rng.standard_normal((b, b)) + 1j * rng.standard_normal((b, b)) + 6 * np.eye(b)
+    plan = tp.Plan.create(Nx, Ny, b, 0, gen, prec="mixed", max_rhs=1, restart=20)
+    v = rng.standard_normal(Nx * Ny * b) + 1j * rng.standard_normal(Nx * Ny * b)
+    x, info = plan.solve(to_dev(v), mode="fp64", tol=1e-12)
+    assert info[0]["status"] == 0 and info[0]["iters"] <= b
+    op = oracle.Operator(Nx, Ny, b, 0, gen)
+    assert oracle.relres(op, x.cpu().numpy()[None], v[None])[0] <= 1e-12
+
+
+def test_solve_x0_exact_needs_no_iterations(tp):
+    banner("solve with exact x0")
+    prob, V = sa.make_config(1)
+    Xlu = oracle.lu_solve(oracle.assemble(prob), V)
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=1, restart=40)
+    x, info = plan.solve(to_dev(V), mode="fp64", tol=1e-8, x0=to_dev(Xlu))
+    assert info[0]["iters"] == 0 and info[0]["status"] == 0
+
+
+def test_solve_noconv_reports(tp):
+    banner("solve no-convergence path")
+    prob, V = sa.make_config(1)
+    _, info, _ = _solve(tp, prob, V, "fp64", tol=1e-14, max_iter=2)
+    assert info[0]["status"] == 4 and info[0]["iters"] <= 2 and info[0]["relres"] > 1e-14
+
+
+def test_solve_rejects_bad_requests(tp):
+    banner("solve argument errors")
+    import torch
+    prob, V = sa.make_config(1)
+    plan = tp.Plan.from_problem(prob, prec="fp64", max_rhs=1, restart=10)
+    with pytest.raises(tp.ToeplitzError) as e:
+        plan.solve(to_dev(V), mode="mixed")           # no FP32 copy in this plan
+    assert e.value.status == 6
+    with pytest.raises(tp.ToeplitzError):
+        plan.solve(to_dev(np.vstack([V, V])), mode="fp64")   # more columns than max_rhs
+    with pytest.raises(tp.ToeplitzError):
+        plan.solve(to_dev(V), mode="fp64", restart=11)        # beyond the plan's restart
+    with pytest.raises(tp.ToeplitzError):
+        plan.matvec(to_dev(V, torch.complex64), which="fp32")  # no FP32 copy
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_solve_batch_matches_single(tp, mode):
+    """Independent Krylov spaces: a column solved in a batch matches it solved alone."""
+    banner(f"solve batch vs single {mode}")
+    prob = sa.make_problem(6, 5, 16, 20, 77)
+    V = sa.rhs_random(prob, 4)
+    Xb, ib, _ = _solve(tp, prob, V, mode)
+    for r in (0, 3):
+        X1, i1, _ = _solve(tp, prob, V[r:r + 1], mode)
+        assert i1[0]["iters"] == ib[r]["iters"]
+        assert rel_err(X1[0], Xb[r]) <= 1e-12
+    assert np.all(oracle.relres(prob, Xb, V) <= 1e-8)
+
+
+def test_solve_config3_ports_batched(tp):
+    """81 port excitations solved together (mixed precision), residual by the oracle."""
+    banner("solve config 3 batched ports")
+    prob, V = sa.make_config(3)
+    X, info, _ = _solve(tp, prob, V, "mixed")
+    rr = oracle.relres(prob, X, V)
+    assert all(i["status"] == 0 for i in info)
+    assert np.max(rr) <= 1e-8, np.max(rr)
+    print(f"config3: iters max={max(i['iters'] for i in info)} outer max={max(i['outer_iters'] for i in info)}")
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_solve_config2_full_size(tp, mode):
+    banner(f"solve config 2 full size {mode}")
+    prob, V = sa.make_config(2)
+    X, info, _ = _solve(tp, prob, V, mode)
+    rr = oracle.relres(prob, X, V)
+    assert info[0]["status"] == 0 and rr[0] <= 1e-8, (info, rr)
+    print(f"config2 {mode}: iters={info[0]['iters']} outer={info[0]['outer_iters']} relres={rr[0]:.2e}")
