@@ -123,6 +123,18 @@ tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *desc);
 tp_status toeplitz_matvec(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy,
                           int nrhs, void *hip_stream);
 
+/*
+ * Instrumentation: run the operator application of toeplitz_matvec `reps`
+ * times on hip_stream with HIP events between its kernels and write the mean
+ * duration in milliseconds of each stage to stage_ms[7]: 0 rim pass over B,
+ * 1 embed + x transform, 2 y transform, 3 per-frequency block product,
+ * 4 inverse y transform, 5 inverse x transform + crop, 6 rim finish (C x_r).
+ * Stages a plan does not run (no rim) report 0.  Same arguments and errors as
+ * toeplitz_matvec; synchronises hip_stream.
+ */
+tp_status toeplitz_matvec_profile(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy,
+                                  int nrhs, int reps, void *hip_stream, double *stage_ms);
+
 /* Solver options (all fields are read; see toeplitz_solve_opts_default). */
 typedef struct {
     double tol;        /* stop when ||v - Z x||_2 / ||v||_2 <= tol, FP64 residual */

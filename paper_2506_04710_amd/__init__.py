@@ -121,6 +121,22 @@ class Plan:
                                          ctypes.c_void_p(y2.data_ptr()), ldy, R, _stream_handle(stream)))
         return y.reshape(x.shape) if out is None else out
 
+    STAGES = ("rim_main", "fwd_x", "fwd_y", "prod", "inv_y", "inv_x", "rim_finish")
+
+    def matvec_profile(self, x, which=None, reps=20, stream=None) -> dict:
+        """Mean per-stage milliseconds of the operator application (HIP events)."""
+        import torch
+        if which is None:
+            which = "fp64" if x.dtype == torch.complex128 else "fp32"
+        dt = torch.complex128 if which == "fp64" else torch.complex64
+        x2, R, ldx = self._cols(x, dt)
+        y = torch.empty((R, self.Nt), dtype=dt, device=x.device)
+        ms = (ctypes.c_double * 7)()
+        check(_lib.lib().toeplitz_matvec_profile(self._h, PREC[which], ctypes.c_void_p(x2.data_ptr()), ldx,
+                                                 ctypes.c_void_p(y.data_ptr()), self.Nt, R, reps,
+                                                 _stream_handle(stream), ms))
+        return dict(zip(self.STAGES, list(ms)))
+
     def solve(self, v, mode="mixed", tol=1e-8, restart=0, max_iter=2000, max_outer=50, inner_tol=1e-4, x0=None,
               stream=None, raise_on_noconv=False):
         """Solve Z x = v for the columns of v (complex128 cuda tensor (Nt,) or (R, Nt))."""

@@ -20,6 +20,7 @@ PREC = {"fp64": TP_FP64, "fp32": TP_FP32, "mixed": TP_MIXED}
 
 # every symbol the header declares
 EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", "toeplitz_matvec",
+           "toeplitz_matvec_profile",
            "toeplitz_solve_opts_default", "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_plan_destroy",
            "toeplitz_last_error")
 
@@ -66,6 +67,7 @@ def lib():
                                            ctypes.POINTER(vp)]
         L.toeplitz_plan_info.argtypes = [vp, ctypes.POINTER(PlanDesc)]
         L.toeplitz_matvec.argtypes = [vp, ci, vp, cl, vp, cl, ci, vp]
+        L.toeplitz_matvec_profile.argtypes = [vp, ci, vp, cl, vp, cl, ci, ci, vp, ctypes.POINTER(ctypes.c_double)]
         L.toeplitz_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
         L.toeplitz_solve_opts_default.restype = None
         L.toeplitz_solve.argtypes = [vp, vp, cl, vp, cl, ci, ctypes.POINTER(SolveOpts),
@@ -75,6 +77,7 @@ def lib():
         L.toeplitz_plan_destroy.restype = None
         L.toeplitz_last_error.restype = ctypes.c_char_p
         for name in ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", "toeplitz_matvec",
+                     "toeplitz_matvec_profile",
                      "toeplitz_solve", "toeplitz_plan_spectrum"):
             getattr(L, name).restype = ci
         _lib = L

@@ -322,6 +322,39 @@ tp_status toeplitz_matvec(tp_plan p, tp_prec which, const void *x, long ldx, voi
     return TP_OK;
 }
 
+tp_status toeplitz_matvec_profile(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int nrhs,
+                                  int reps, void *hip_stream, double *stage_ms) {
+    if (!stage_ms || reps < 1) return fail(TP_E_INVAL, "stage_ms is NULL or reps < 1");
+    // same checks as a plain application
+    tp_status s = toeplitz_matvec(p, which, x, ldx, y, ldy, nrhs, hip_stream);
+    if (s != TP_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t ev[kMatvecStages + 1];
+    for (int i = 0; i <= kMatvecStages; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) {
+            for (int k = 0; k < i; ++k) hipEventDestroy(ev[k]);
+            return fail(TP_E_HIP, "event create");
+        }
+    for (int i = 0; i < kMatvecStages; ++i) stage_ms[i] = 0.0;
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        if (which == TP_FP64)
+            e = matvec_fp64_timed(p, Cols<const c128>{(const c128 *)x, ldx, nullptr}, Cols<c128>{(c128 *)y, ldy, nullptr},
+                                  nrhs, st, ev);
+        else
+            e = matvec_fp32_timed(p, Cols<const c64>{(const c64 *)x, ldx, nullptr}, Cols<c64>{(c64 *)y, ldy, nullptr},
+                                  nrhs, st, ev);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[kMatvecStages]);
+        for (int i = 0; i < kMatvecStages && e == hipSuccess; ++i) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            stage_ms[i] += ms / reps;
+        }
+    }
+    for (int i = 0; i <= kMatvecStages; ++i) hipEventDestroy(ev[i]);
+    return e == hipSuccess ? TP_OK : hip_fail(e, "matvec profile");
+}
+
 tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void *host_out) {
     if (!p || !host_out) return fail(TP_E_INVAL, "NULL argument");
     if (kx < 0 || kx >= p->Px || ky < 0 || ky >= p->Py) return fail(TP_E_INVAL, "frequency out of range");
@@ -377,6 +410,10 @@ tp_status toeplitz_solve(tp_plan p, const void *v, long ldv, void *x, long ldx, 
     return solve_run(p, (const c128 *)v, ldv, (c128 *)x, ldx, nrhs, o, info, (hipStream_t)hip_stream);
 }
 
-void toeplitz_plan_destroy(tp_plan p) { delete p; }
+void toeplitz_plan_destroy(tp_plan p) {
+    if (!p) return;
+    solver_release(p);
+    delete p;
+}
 
 }  // extern "C"

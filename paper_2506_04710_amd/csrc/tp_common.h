@@ -112,4 +112,17 @@ struct tp_plan_s {
     char *ws;
     size_t ws_bytes;
     size_t workspace_bytes;
+    // solver launch resources, created on the first solve and released by
+    // toeplitz_plan_destroy: a stream for graph capture and replay (default
+    // priority), events ordering it against the caller's stream, pinned host
+    // buffers for status polling, and captured super-step graphs.
+    hipStream_t cs = nullptr;
+    hipEvent_t ev[4] = {};
+    void *host_status = nullptr;
+    struct GraphEntry {
+        int mode, nslots, m, steps;
+        hipGraphExec_t exec;
+    };
+    GraphEntry graphs[8] = {};
+    int ngraphs = 0;
 };

@@ -1,27 +1,31 @@
 // Restarted GMRES for Z x = v (eq. MoMMatrixEq), one independent Krylov space
-// per right-hand side, driven by a per-column state machine that lives in
-// device memory.
+// per right-hand side, driven by a per-column state machine in device memory.
 //
-// A "super-step" is a fixed sequence of launches:
-//   advance  -> operator application(s) -> CGS2 (dots, update, dots, update+norm)
-//   -> finish (Hessenberg column, Givens rotation, residual estimate)
-//   -> x update (triangular solve + x += V y) -> true residual -> normalise.
-// Every kernel reads each column's phase and Arnoldi index from device memory
-// and does nothing for columns in other phases, so the same launch sequence
-// serves every column at every step and the host only polls for completion.
+// A super-step is a fixed sequence of launches, captured once as a HIP graph
+// and replayed:
+//   commit   apply last step's decisions: next phase, Arnoldi index, operator
+//            input/output tables; scale a fresh residual into V_0
+//   operator w = Z V_j (Arnoldi columns), W = Z x (residual columns)
+//   dots     partial h1 = V^H w                      (per element range)
+//   orth1    h1; w' = w - V h1; partial h2 = V^H w', ||w'||^2
+//   orth2    h2; w'' = w' - V h2; V_{j+1} = w'' / ||w''|| with
+//            ||w''||^2 = ||w'||^2 - ||h2||^2; Hessenberg column, Givens
+//            rotation and residual estimate (first block of each column)
+//   tail     columns whose cycle ended: R y = g, x += V y;
+//            residual columns: r = v - W into V_0, partial ||r||^2, ||v||^2
+// Classical Gram-Schmidt with one reorthogonalisation (CGS2) in FP64.
 //
-// Column phases:
-//   ARN      Arnoldi step j: w = Z V_j is orthogonalised into V_{j+1}
-//   UPD      cycle over (estimate below threshold, j + 1 == m, breakdown or
-//            iteration cap): solve R y = g, x += V y
-//   PRE_RES  x updated; its operator application happens next super-step
-//   RES      r = v - Z x (FP64): stop, or start a cycle with V_0 = r / ||r||
-//   DONE     final
-// Plain mode (TP_FP64) applies the FP64 operator both in ARN and RES.  Mixed
-// mode (TP_MIXED, iterative refinement) applies the FP32 operator in ARN, the
-// FP64 one in RES, and each inner cycle stops at inner_tol * ||r||.  All
-// Krylov vectors, inner products, norms and the Hessenberg least-squares
-// problem are FP64.
+// Every kernel reads the column states committed at the start of its
+// super-step (state[parity]) and the decisions of earlier kernels; the commit
+// kernel writes state[parity] from state[parity ^ 1].  No kernel reads a
+// field that another block of the same kernel writes, and every reduction
+// sums fixed partial slots in a fixed order (deterministic, batch-invariant).
+//
+// Plain mode (TP_FP64) applies the FP64 operator for both column kinds.  Mixed
+// mode applies the FP32 operator to Arnoldi columns and the FP64 operator to
+// residual columns (iterative refinement); each inner cycle stops when the
+// estimate drops below inner_tol * ||r||.  Krylov vectors, inner products,
+// norms and the small least-squares problem are FP64 throughout.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -30,65 +34,79 @@
 
 namespace tp {
 
-enum : int { PH_IDLE = 0, PH_ARN = 1, PH_UPD = 2, PH_PRE_RES = 3, PH_RES = 4, PH_DONE = 5 };
+enum : int { PH_IDLE = 0, PH_INIT = 1, PH_ARN = 2, PH_RES = 3, PH_DONE = 4 };
 
-struct SlotDev {
+// committed per-column state (two copies, by super-step parity)
+struct SlotState {
+    int phase, j, xzero, iters;
+    int outer, status, first, pad;
+    double thr, beta, vnorm, relres;
+};
+// fixed per-solve column data
+struct SlotConst {
     const c128 *v;
     c128 *x;
     double tol, inner_tol;
     int max_iter, max_outer;
-    int phase, xzero, j, k;
-    int iters, outer, status, needs_norm;
-    int first, pad0;
-    double nrm, beta, vnorm, relres, thr, est;
+};
+// decision of the Arnoldi step of the current super-step (orth2, first block)
+struct SlotDec {
+    int end, k, breakdown, pad;
+    double est, nrm;
 };
 
 constexpr int kThreads = 256;
-constexpr int kEPT = 4;                       // vector elements per thread
-constexpr int kChunk = kThreads * kEPT;       // elements per workgroup
+constexpr int kMaxBlocks = 256;        // element ranges per column
 constexpr int kMaxRestart = 512;
+constexpr int kG = 4;                  // basis vectors handled together
 
 struct Eng {
     long Nt;
-    int m, nch, mixed;
-    SlotDev *slots;
-    c128 *V, *W, *H, *sn, *g, *h1, *h2, *part;
-    double *cs, *pn;
-    unsigned *cnt;
-    const c128 **tin;   // operator input per column (ARN, and RES in plain mode)
+    int m, nb, mixed;
+    long span;                         // elements per range
+    SlotState *st;                     // [2][nslots]
+    SlotConst *sc;
+    SlotDec *dec;
+    c128 *V, *W, *H, *sn, *g, *h1, *y;
+    c128 *P1, *P2;                     // [slot][m + 1][nb] partial inner products
+    double *cs, *PN, *PR;              // [slot][nb] ||w'||^2; [slot][2][nb] ||r||^2, ||v||^2
+    const c128 **tin;                  // operator tables (Arnoldi; plain: both kinds)
     c128 **tout;
-    const c128 **rin;   // FP64 residual input per column (mixed mode)
+    const c128 **rin;                  // FP64 residual tables (mixed)
     c128 **rout;
+    int nslots;
     __device__ c128 *vec(int s, int i) const { return V + ((long)s * (m + 1) + i) * Nt; }
 };
 
 static size_t a256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 struct EngLayout {
-    size_t slots, V, W, H, sn, g, h1, h2, part, cs, pn, cnt, tabs, total;
+    size_t st, sc, dec, V, W, H, sn, g, h1, y, P1, P2, cs, PN, PR, tabs, total;
 };
 
 static EngLayout eng_layout(long Nt, int m, int R) {
     EngLayout L;
-    const size_t nch = (size_t)((Nt + kChunk - 1) / kChunk);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
         off += a256(bytes);
         return o;
     };
-    L.slots = take(sizeof(SlotDev) * R);
+    L.st = take(2 * sizeof(SlotState) * R);
+    L.sc = take(sizeof(SlotConst) * R);
+    L.dec = take(sizeof(SlotDec) * R);
     L.V = take((size_t)R * (m + 1) * Nt * 16);
     L.W = take((size_t)R * Nt * 16);
     L.H = take((size_t)R * (m + 1) * m * 16);
     L.sn = take((size_t)R * m * 16);
     L.g = take((size_t)R * (m + 1) * 16);
     L.h1 = take((size_t)R * (m + 1) * 16);
-    L.h2 = take((size_t)R * (m + 1) * 16);
-    L.part = take((size_t)R * (m + 1) * nch * 16);
+    L.y = take((size_t)R * (m + 1) * 16);
+    L.P1 = take((size_t)R * (m + 1) * kMaxBlocks * 16);
+    L.P2 = take((size_t)R * (m + 1) * kMaxBlocks * 16);
     L.cs = take((size_t)R * m * 8);
-    L.pn = take((size_t)R * nch * 16);
-    L.cnt = take((size_t)R * 8 * 4);
+    L.PN = take((size_t)R * kMaxBlocks * 8);
+    L.PR = take((size_t)R * 2 * kMaxBlocks * 8);
     L.tabs = take((size_t)R * 4 * sizeof(void *));
     L.total = off;
     return L;
@@ -100,175 +118,266 @@ size_t solver_ws_bytes(long Nt, int restart, int max_rhs) { return eng_layout(Nt
 __device__ __forceinline__ c128 shfl_xor_c(c128 v, int mk_) {
     return c128{__shfl_xor(v.x, mk_, 64), __shfl_xor(v.y, mk_, 64)};
 }
-__device__ __forceinline__ double shfl_xor_d(double v, int mk_) { return __shfl_xor(v, mk_, 64); }
+__device__ __forceinline__ double cabs2(c128 a) { return a.x * a.x + a.y * a.y; }
 
-// Sum over the 256 threads of the block; the result is valid in thread 0.
-__device__ __forceinline__ c128 block_sum(c128 v) {
-    __shared__ c128 red[kThreads / 64];
+// Sums of G values over the block (valid in every thread afterwards).
+template <int G>
+__device__ __forceinline__ void block_sum_g(c128 (&v)[G], c128 *red /* [4][G] LDS */) {
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = v + shfl_xor_c(v, m);
+    for (int msk = 32; msk >= 1; msk >>= 1)
+#pragma unroll
+        for (int q = 0; q < G; ++q) v[q] = v[q] + shfl_xor_c(v[q], msk);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < G; ++q) red[w * G + q] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < G; ++q) v[q] = red[q] + red[G + q] + red[2 * G + q] + red[3 * G + q];
+}
+__device__ __forceinline__ double block_sum_d(double v, double *red /* [4] LDS */) {
+#pragma unroll
+    for (int msk = 32; msk >= 1; msk >>= 1) v += __shfl_xor(v, msk, 64);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
-    c128 s = c128{0, 0};
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kThreads / 64; ++i) s = s + red[i];
-    return s;
-}
-__device__ __forceinline__ double block_sum_d(double v) {
-    __shared__ double redd[kThreads / 64];
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
-    const int w = threadIdx.x >> 6;
+    const double t = red[0] + red[1] + red[2] + red[3];
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) redd[w] = v;
-    __syncthreads();
-    double s = 0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kThreads / 64; ++i) s += redd[i];
-    return s;
+    return t;
 }
 
-// Block-completion counter: returns true in every thread of the last block
-// to finish (of `total` participating blocks) and resets the counter.
-__device__ __forceinline__ bool last_block(unsigned *cnt, unsigned total) {
-    __shared__ int am_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned t = atomicAdd(cnt, 1u);
-        am_last = (t + 1 == total);
-        if (am_last) *cnt = 0;
+// h[i] = sum_b P[i][b], i <= j, for every i in parallel: groups of 8 threads
+// share one i and sum a strided slice of the nb partials, then combine.
+__device__ __forceinline__ void reduce_partials(const c128 *P, int j, int nb, c128 *h /* LDS */) {
+    const int sub = threadIdx.x & 7, grp = threadIdx.x >> 3;   // 32 groups
+    for (int i0 = 0; i0 <= j; i0 += 32) {
+        const int i = i0 + grp;
+        c128 t = c128{0, 0};
+        if (i <= j)
+            for (int b = sub; b < nb; b += 8) t = t + P[(long)i * nb + b];
+#pragma unroll
+        for (int msk = 4; msk >= 1; msk >>= 1) t = t + shfl_xor_c(t, msk);
+        if (sub == 0 && i <= j) h[i] = t;
     }
     __syncthreads();
-    if (am_last) __threadfence();
-    return am_last != 0;
+}
+// sum of nb partials by the whole block (fixed order: strided per thread,
+// then the block reduction); every thread gets the result
+__device__ __forceinline__ double reduce_d(const double *P, int nb, double *red) {
+    double t = 0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) t += P[b];
+    return block_sum_d(t, red);
 }
 
-__device__ __forceinline__ double cabs2(c128 a) { return a.x * a.x + a.y * a.y; }
-
-// ------------------------------------------------------------ kernels
-__global__ void k_advance(Eng E, int nslots) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nslots) return;
-    SlotDev &S = E.slots[s];
-    S.needs_norm = 0;
-    if (S.phase == PH_PRE_RES) S.phase = PH_RES;
-}
-
-// part[s][i][chunk] = sum_{n in chunk} conj(V_i[n]) w[n], w = V_{j+1}; the last
-// block sums the chunks in order into h (pass 0 -> h1, pass 1 -> h2).
-__global__ void __launch_bounds__(kThreads) k_dots(Eng E, int pass) {
-    const int s = blockIdx.z, i = blockIdx.y, ch = blockIdx.x;
-    const SlotDev &S = E.slots[s];
-    if (S.phase != PH_ARN) return;
-    const int j = S.j;
-    if (i > j) return;
-    const c128 *vi = E.vec(s, i), *w = E.vec(s, j + 1);
-    c128 acc = c128{0, 0};
+// partial inner products of V_0..V_j with w over this block's element range
+__device__ __forceinline__ void partial_dots(const Eng &E, int s, int j, const c128 *w, long n0, long n1,
+                                            c128 *P, c128 *red) {
+    for (int i0 = 0; i0 <= j; i0 += kG) {
+        c128 acc[kG];
 #pragma unroll
-    for (int t = 0; t < kEPT; ++t) {
-        const long n = (long)ch * kChunk + t * kThreads + threadIdx.x;
-        if (n < E.Nt) acc = cmac_conj(acc, vi[n], w[n]);
-    }
-    acc = block_sum(acc);
-    c128 *part = E.part + (long)s * (E.m + 1) * E.nch;
-    if (threadIdx.x == 0) part[(long)i * E.nch + ch] = acc;
-    if (last_block(E.cnt + s * 8 + pass, (unsigned)((j + 1) * E.nch))) {
-        c128 *h = (pass == 0 ? E.h1 : E.h2) + (long)s * (E.m + 1);
-        for (int ii = threadIdx.x; ii <= j; ii += blockDim.x) {
-            c128 t = c128{0, 0};
-            for (int c = 0; c < E.nch; ++c) t = t + part[(long)ii * E.nch + c];
-            h[ii] = t;
+        for (int q = 0; q < kG; ++q) acc[q] = c128{0, 0};
+        for (long n = n0 + threadIdx.x; n < n1; n += kThreads) {
+            const c128 wn = w[n];
+#pragma unroll
+            for (int q = 0; q < kG; ++q)
+                if (i0 + q <= j) acc[q] = cmac_conj(acc[q], E.vec(s, i0 + q)[n], wn);
         }
+        block_sum_g<kG>(acc, red);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int q = 0; q < kG; ++q)
+                if (i0 + q <= j) P[(long)(i0 + q) * E.nb + blockIdx.x] = acc[q];
+        __syncthreads();
     }
 }
 
-// w -= sum_i V_i h_i (h = h1 or h2); on the second pass also ||w||^2 -> nrm.
-__global__ void __launch_bounds__(kThreads) k_update(Eng E, int pass) {
-    __shared__ c128 hs[kMaxRestart + 1];
-    const int s = blockIdx.y, ch = blockIdx.x;
-    SlotDev &S = E.slots[s];
-    if (S.phase != PH_ARN) return;
-    const int j = S.j;
-    const c128 *h = (pass == 0 ? E.h1 : E.h2) + (long)s * (E.m + 1);
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) hs[i] = h[i];
-    __syncthreads();
-    c128 *w = E.vec(s, j + 1);
-    c128 wv[kEPT];
-    long idx[kEPT];
-#pragma unroll
-    for (int t = 0; t < kEPT; ++t) {
-        idx[t] = (long)ch * kChunk + t * kThreads + threadIdx.x;
-        wv[t] = idx[t] < E.Nt ? w[idx[t]] : c128{0, 0};
-    }
-    for (int i = 0; i <= j; ++i) {
-        const c128 *vi = E.vec(s, i);
-        const c128 hn = c128{-hs[i].x, -hs[i].y};
-#pragma unroll
-        for (int t = 0; t < kEPT; ++t)
-            if (idx[t] < E.Nt) wv[t] = cmac(wv[t], vi[idx[t]], hn);
-    }
+// w[n] -= sum_i V_i[n] h[i] over the range, four basis vectors per pass;
+// returns this thread's share of ||w_new||^2.
+__device__ __forceinline__ double range_update(const Eng &E, int s, int j, c128 *w, long n0, long n1,
+                                               const c128 *h) {
     double nn = 0;
-#pragma unroll
-    for (int t = 0; t < kEPT; ++t)
-        if (idx[t] < E.Nt) {
-            w[idx[t]] = wv[t];
-            nn += cabs2(wv[t]);
+    for (long n = n0 + threadIdx.x; n < n1; n += kThreads) {
+        c128 acc = w[n];
+        int i = 0;
+        for (; i + 3 <= j; i += 4) {
+            const c128 a0 = E.vec(s, i)[n], a1 = E.vec(s, i + 1)[n], a2 = E.vec(s, i + 2)[n], a3 = E.vec(s, i + 3)[n];
+            acc = acc - a0 * h[i];
+            acc = acc - a1 * h[i + 1];
+            acc = acc - a2 * h[i + 2];
+            acc = acc - a3 * h[i + 3];
         }
-    if (pass == 1) {
-        nn = block_sum_d(nn);
-        double *pn = E.pn + (long)s * E.nch * 2;
-        if (threadIdx.x == 0) pn[ch] = nn;
-        if (last_block(E.cnt + s * 8 + 2, (unsigned)E.nch)) {
-            if (threadIdx.x == 0) {
-                double t = 0;
-                for (int c = 0; c < E.nch; ++c) t += pn[c];
-                S.nrm = sqrt(t);
-            }
+        for (; i <= j; ++i) acc = acc - E.vec(s, i)[n] * h[i];
+        w[n] = acc;
+        nn += cabs2(acc);
+    }
+    return nn;
+}
+
+// ---------------------------------------------------------------- commit
+// Transition of one column from the previous super-step's state and results.
+struct Next {
+    SlotState S;
+    int restart;        // a new cycle starts: V_0 = r / beta
+    double scale;       // 1 / beta
+};
+
+// Called by every thread of a block (the residual case reduces cooperatively).
+__device__ __forceinline__ Next transition(const Eng &E, int s, const SlotState &P, double *red) {
+    Next nx;
+    nx.S = P;
+    nx.restart = 0;
+    nx.scale = 0;
+    const SlotConst &C = E.sc[s];
+    if (P.phase == PH_INIT) {
+        nx.S.phase = PH_RES;
+    } else if (P.phase == PH_ARN) {
+        const SlotDec &D = E.dec[s];
+        nx.S.iters = P.iters + 1;
+        if (D.end) {
+            nx.S.phase = PH_RES;
+            nx.S.xzero = 0;
+        } else {
+            nx.S.j = P.j + 1;
         }
+    } else if (P.phase == PH_RES) {
+        const double *pr = E.PR + (long)s * 2 * E.nb;
+        const double rr = reduce_d(pr, E.nb, red), vv = reduce_d(pr + E.nb, E.nb, red);
+        const double beta = sqrt(rr), vn = sqrt(vv);
+        const double rel = vn > 0 ? beta / vn : (beta > 0 ? INFINITY : 0.0);
+        nx.S.vnorm = vn;
+        nx.S.relres = rel;
+        if (!P.first) nx.S.outer = P.outer + 1;
+        nx.S.first = 0;
+        if (rel <= C.tol) {
+            nx.S.phase = PH_DONE;
+            nx.S.status = TP_OK;
+        } else if (!(rel == rel) || rel == INFINITY) {
+            nx.S.phase = PH_DONE;
+            nx.S.status = TP_E_BREAKDOWN;
+        } else if (P.iters >= C.max_iter || nx.S.outer >= C.max_outer) {
+            nx.S.phase = PH_DONE;
+            nx.S.status = TP_E_NOCONV;
+        } else {
+            nx.S.phase = PH_ARN;
+            nx.S.j = 0;
+            nx.S.beta = beta;
+            const double plain_thr = 0.5 * C.tol * vn;
+            nx.S.thr = E.mixed ? fmax(C.inner_tol * beta, plain_thr) : plain_thr;
+            nx.restart = 1;
+            nx.scale = 1.0 / beta;
+        }
+    }
+    return nx;
+}
+
+__global__ void __launch_bounds__(kThreads) k_commit(Eng E, int par) {
+    __shared__ double redd[4];
+    const int s = blockIdx.y;
+    const SlotState P = E.st[(par ^ 1) * E.nslots + s];
+    const Next nx = transition(E, s, P, redd);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        E.st[par * E.nslots + s] = nx.S;
+        const SlotConst &C = E.sc[s];
+        const c128 *in = nullptr, *rin = nullptr;
+        c128 *out = nullptr, *rout = nullptr;
+        if (nx.S.phase == PH_ARN) {
+            in = E.vec(s, nx.S.j);
+            out = E.vec(s, nx.S.j + 1);
+        } else if (nx.S.phase == PH_RES && !nx.S.xzero) {
+            rin = C.x;
+            rout = E.W + (long)s * E.Nt;
+        }
+        if (E.mixed) {
+            E.tin[s] = in;
+            E.tout[s] = out;
+            E.rin[s] = rin;
+            E.rout[s] = rout;
+        } else {
+            E.tin[s] = in ? in : rin;
+            E.tout[s] = in ? out : rout;
+        }
+        if (nx.restart) E.g[(long)s * (E.m + 1)] = c128{nx.S.beta, 0};
+    }
+    if (nx.restart) {     // every block scales its range of the new V_0
+        c128 *v0 = E.vec(s, 0);
+        const long n0 = (long)blockIdx.x * E.span, n1 = min(E.Nt, n0 + E.span);
+        for (long n = n0 + threadIdx.x; n < n1; n += kThreads) v0[n] = scale(v0[n], nx.scale);
     }
 }
 
-// Hessenberg column j, previous Givens rotations, new rotation, residual
-// estimate |g_{j+1}|, and the phase decision.  One lane per column: the work
-// is O(j).
-__global__ void k_finish(Eng E, int nslots) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nslots) return;
-    SlotDev &S = E.slots[s];
+// ------------------------------------------------------------------ CGS2
+__global__ void __launch_bounds__(kThreads) k_dots(Eng E, int par) {
+    __shared__ c128 red[4 * kG];
+    const int s = blockIdx.y;
+    const SlotState S = E.st[par * E.nslots + s];
     if (S.phase != PH_ARN) return;
-    const int m = E.m, j = S.j;
-    const c128 *h1 = E.h1 + (long)s * (m + 1), *h2 = E.h2 + (long)s * (m + 1);
+    const long n0 = (long)blockIdx.x * E.span, n1 = min(E.Nt, n0 + E.span);
+    partial_dots(E, s, S.j, E.vec(s, S.j + 1), n0, n1, E.P1 + (long)s * (E.m + 1) * E.nb, red);
+}
+
+__global__ void __launch_bounds__(kThreads) k_orth1(Eng E, int par) {
+    __shared__ c128 h[kMaxRestart + 1];
+    __shared__ c128 red[4 * kG];
+    __shared__ double redd[4];
+    const int s = blockIdx.y;
+    const SlotState S = E.st[par * E.nslots + s];
+    if (S.phase != PH_ARN) return;
+    const int j = S.j;
+    reduce_partials(E.P1 + (long)s * (E.m + 1) * E.nb, j, E.nb, h);
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i <= j; i += kThreads) E.h1[(long)s * (E.m + 1) + i] = h[i];
+    const long n0 = (long)blockIdx.x * E.span, n1 = min(E.Nt, n0 + E.span);
+    c128 *w = E.vec(s, j + 1);
+    double nn = range_update(E, s, j, w, n0, n1, h);
+    nn = block_sum_d(nn, redd);
+    if (threadIdx.x == 0) E.PN[(long)s * E.nb + blockIdx.x] = nn;
+    partial_dots(E, s, j, w, n0, n1, E.P2 + (long)s * (E.m + 1) * E.nb, red);
+}
+
+__global__ void __launch_bounds__(kThreads) k_orth2(Eng E, int par) {
+    __shared__ c128 h[kMaxRestart + 1];
+    __shared__ double redd[4];
+    const int s = blockIdx.y;
+    const SlotState S = E.st[par * E.nslots + s];
+    if (S.phase != PH_ARN) return;
+    const int j = S.j, m = E.m;
+    reduce_partials(E.P2 + (long)s * (m + 1) * E.nb, j, E.nb, h);
+    // ||w''||^2 = ||w'||^2 - ||h2||^2 (the second correction is tiny next to w')
+    double hh = 0;
+    for (int i = 0; i <= j; ++i) hh += cabs2(h[i]);
+    const double ww = reduce_d(E.PN + (long)s * E.nb, E.nb, redd);
+    const double nrm = sqrt(fmax(ww - hh, 0.0));
+    const long n0 = (long)blockIdx.x * E.span, n1 = min(E.Nt, n0 + E.span);
+    c128 *w = E.vec(s, j + 1);
+    range_update(E, s, j, w, n0, n1, h);
+    const double sc = nrm > 1e-300 ? 1.0 / nrm : 0.0;
+    for (long n = n0 + threadIdx.x; n < n1; n += kThreads) w[n] = scale(w[n], sc);
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    // Hessenberg column j: h1 + h2, then the previous rotations and a new one
+    const c128 *h1 = E.h1 + (long)s * (m + 1);
     c128 *H = E.H + (long)s * (m + 1) * m, *sn = E.sn + (long)s * m, *g = E.g + (long)s * (m + 1);
     double *cs = E.cs + (long)s * m;
     c128 *Hj = H + (long)j * (m + 1);
-    for (int i = 0; i <= j; ++i) Hj[i] = h1[i] + h2[i];
-    const double nrm = S.nrm;
-    const c128 below = c128{nrm, 0};
-    for (int i = 0; i < j; ++i) {   // apply rotation i to rows i, i+1
+    for (int i = 0; i <= j; ++i) Hj[i] = h1[i] + h[i];
+    for (int i = 0; i < j; ++i) {
         const c128 a = Hj[i], b = Hj[i + 1];
-        const c128 sv = sn[i];
-        const c128 t = c128{cs[i] * a.x, cs[i] * a.y} + sv * b;
-        const c128 u = c128{cs[i] * b.x, cs[i] * b.y} - conjg(sv) * a;
-        Hj[i] = t;
-        Hj[i + 1] = u;
+        Hj[i] = c128{cs[i] * a.x, cs[i] * a.y} + sn[i] * b;
+        Hj[i + 1] = c128{cs[i] * b.x, cs[i] * b.y} - conjg(sn[i]) * a;
     }
-    // new rotation zeroing the subdiagonal entry (real, >= 0)
     const c128 a = Hj[j];
     const double aa = sqrt(cabs2(a));
     double c;
-    c128 sv;
-    c128 diag;
+    c128 sv, diag;
     if (aa == 0.0) {
         c = 0.0;
         sv = c128{1, 0};
-        diag = below;
+        diag = c128{nrm, 0};
     } else {
         const double rho = sqrt(aa * aa + nrm * nrm);
         c = aa / rho;
-        sv = c128{a.x / aa * nrm / rho, a.y / aa * nrm / rho};    // (a/|a|) b / rho, b real
+        sv = c128{a.x / aa * nrm / rho, a.y / aa * nrm / rho};
         diag = c128{a.x / aa * rho, a.y / aa * rho};
     }
     cs[j] = c;
@@ -278,153 +387,70 @@ __global__ void k_finish(Eng E, int nslots) {
     g[j + 1] = c128{0, 0} - conjg(sv) * gj;
     g[j] = c128{c * gj.x, c * gj.y};
     const double est = sqrt(cabs2(g[j + 1]));
-    S.est = est;
-    S.k = j + 1;
-    S.iters += 1;
-    const bool converged = est <= S.thr;
-    const bool dead = !(nrm > 1e-300) || !(est == est);
-    if (!converged && !dead && j + 1 < m && S.iters < S.max_iter) {
-        S.j = j + 1;
-        S.needs_norm = 1;
-        E.tin[s] = E.vec(s, j + 1);
-        E.tout[s] = E.vec(s, j + 2);
-    } else {
-        S.phase = PH_UPD;
-        E.tin[s] = nullptr;
-        E.tout[s] = nullptr;
-    }
+    const SlotConst &C = E.sc[s];
+    SlotDec D;
+    D.est = est;
+    D.nrm = nrm;
+    D.k = j + 1;
+    D.breakdown = !(nrm > 1e-300) || !(est == est);
+    D.end = (est <= S.thr) || D.breakdown || (j + 1 >= m) || (S.iters + 1 >= C.max_iter);
+    D.pad = 0;
+    E.dec[s] = D;
 }
 
-// Back substitution R y = g (k x k upper triangular, R in H after the
-// rotations), then x += sum_i V_i y_i.  Every block solves the small system
-// itself; the last block moves the column to PRE_RES.
-__global__ void __launch_bounds__(kThreads) k_xupdate(Eng E) {
+// ------------------------------------------------------------------ tail
+// Cycle end (x update) for Arnoldi columns whose step decided to stop, and
+// the true residual r = v - W for residual columns.
+__global__ void __launch_bounds__(kThreads) k_tail(Eng E, int par) {
     __shared__ c128 ys[kMaxRestart];
-    const int s = blockIdx.y, ch = blockIdx.x;
-    SlotDev &S = E.slots[s];
-    if (S.phase != PH_UPD) return;
-    const int m = E.m, k = S.k;
-    const c128 *H = E.H + (long)s * (m + 1) * m, *g = E.g + (long)s * (m + 1);
-    for (int i = threadIdx.x; i < k; i += blockDim.x) ys[i] = g[i];
-    __syncthreads();
-    for (int i = k - 1; i >= 0; --i) {
-        if (threadIdx.x == 0) {
-            const c128 d = H[(long)i * (m + 1) + i];
-            const double dd = cabs2(d);
+    __shared__ double redd[4];
+    const int s = blockIdx.y;
+    const SlotState S = E.st[par * E.nslots + s];
+    const long n0 = (long)blockIdx.x * E.span, n1 = min(E.Nt, n0 + E.span);
+    const SlotConst &C = E.sc[s];
+    if (S.phase == PH_ARN) {
+        const SlotDec &D = E.dec[s];
+        if (!D.end) return;
+        const int m = E.m, k = D.k;
+        const c128 *H = E.H + (long)s * (m + 1) * m, *g = E.g + (long)s * (m + 1);
+        // back substitution R y = g, column-oriented
+        for (int i = threadIdx.x; i < k; i += kThreads) ys[i] = g[i];
+        __syncthreads();
+        for (int i = k - 1; i >= 0; --i) {
+            if (threadIdx.x == 0) {
+                const c128 d = H[(long)i * (m + 1) + i];
+                const double dd = cabs2(d);
+                const c128 yi = ys[i];
+                ys[i] = dd > 0 ? c128{(yi.x * d.x + yi.y * d.y) / dd, (yi.y * d.x - yi.x * d.y) / dd} : c128{0, 0};
+            }
+            __syncthreads();
             const c128 yi = ys[i];
-            ys[i] = dd > 0 ? c128{(yi.x * d.x + yi.y * d.y) / dd, (yi.y * d.x - yi.x * d.y) / dd} : c128{0, 0};
+            for (int l = threadIdx.x; l < i; l += kThreads) ys[l] = ys[l] - H[(long)i * (m + 1) + l] * yi;
+            __syncthreads();
         }
-        __syncthreads();
-        const c128 yi = ys[i];
-        for (int l = threadIdx.x; l < i; l += blockDim.x) ys[l] = ys[l] - H[(long)i * (m + 1) + l] * yi;
-        __syncthreads();
-    }
-    c128 *x = S.x;
-#pragma unroll
-    for (int t = 0; t < kEPT; ++t) {
-        const long n = (long)ch * kChunk + t * kThreads + threadIdx.x;
-        if (n < E.Nt) {
+        c128 *x = C.x;
+        for (long n = n0 + threadIdx.x; n < n1; n += kThreads) {
             c128 acc = x[n];
             for (int i = 0; i < k; ++i) acc = cmac(acc, E.vec(s, i)[n], ys[i]);
             x[n] = acc;
         }
-    }
-    if (last_block(E.cnt + s * 8 + 3, (unsigned)E.nch)) {
-        if (threadIdx.x == 0) {
-            S.phase = PH_PRE_RES;
-            S.xzero = 0;
-            if (E.mixed) {
-                E.rin[s] = x;
-                E.rout[s] = E.W + (long)s * E.Nt;
-            } else {
-                E.tin[s] = x;
-                E.tout[s] = E.W + (long)s * E.Nt;
-            }
-        }
-    }
-}
-
-// r = v - Z x (Z x in W, or x == 0), stored in V_0; ||r||, ||v||; decision.
-__global__ void __launch_bounds__(kThreads) k_residual(Eng E) {
-    const int s = blockIdx.y, ch = blockIdx.x;
-    SlotDev &S = E.slots[s];
-    if (S.phase != PH_RES) return;
-    const c128 *v = S.v, *Wz = E.W + (long)s * E.Nt;
-    c128 *r = E.vec(s, 0);
-    const bool xz = S.xzero != 0;
-    double rr = 0, vv = 0;
-#pragma unroll
-    for (int t = 0; t < kEPT; ++t) {
-        const long n = (long)ch * kChunk + t * kThreads + threadIdx.x;
-        if (n < E.Nt) {
+    } else if (S.phase == PH_RES) {
+        const c128 *v = C.v, *Wz = E.W + (long)s * E.Nt;
+        c128 *r = E.vec(s, 0);
+        double rr = 0, vv = 0;
+        for (long n = n0 + threadIdx.x; n < n1; n += kThreads) {
             const c128 vn = v[n];
-            const c128 rn = xz ? vn : vn - Wz[n];
+            const c128 rn = S.xzero ? vn : vn - Wz[n];
             r[n] = rn;
             rr += cabs2(rn);
             vv += cabs2(vn);
         }
-    }
-    rr = block_sum_d(rr);
-    vv = block_sum_d(vv);
-    double *pn = E.pn + (long)s * E.nch * 2;
-    if (threadIdx.x == 0) {
-        pn[ch] = rr;
-        pn[E.nch + ch] = vv;
-    }
-    if (last_block(E.cnt + s * 8 + 4, (unsigned)E.nch) && threadIdx.x == 0) {
-        double tr = 0, tv = 0;
-        for (int c = 0; c < E.nch; ++c) {
-            tr += pn[c];
-            tv += pn[E.nch + c];
+        rr = block_sum_d(rr, redd);
+        vv = block_sum_d(vv, redd);
+        if (threadIdx.x == 0) {
+            E.PR[(long)s * 2 * E.nb + blockIdx.x] = rr;
+            E.PR[(long)s * 2 * E.nb + E.nb + blockIdx.x] = vv;
         }
-        const double beta = sqrt(tr), vn = sqrt(tv);
-        S.vnorm = vn;
-        const double rel = vn > 0 ? beta / vn : (beta > 0 ? INFINITY : 0.0);
-        S.relres = rel;
-        if (!S.first) S.outer += 1;
-        S.first = 0;
-        E.tin[s] = nullptr;
-        E.tout[s] = nullptr;
-        if (E.mixed) {
-            E.rin[s] = nullptr;
-            E.rout[s] = nullptr;
-        }
-        if (rel <= S.tol) {
-            S.phase = PH_DONE;
-            S.status = TP_OK;
-        } else if (!(rel == rel) || rel == INFINITY) {
-            S.phase = PH_DONE;
-            S.status = TP_E_BREAKDOWN;
-        } else if (S.iters >= S.max_iter || S.outer >= S.max_outer) {
-            S.phase = PH_DONE;
-            S.status = TP_E_NOCONV;
-        } else {
-            S.phase = PH_ARN;
-            S.j = 0;
-            S.k = 0;
-            S.beta = beta;
-            S.nrm = beta;
-            S.needs_norm = 1;
-            const double plain_thr = 0.5 * S.tol * vn;
-            S.thr = E.mixed ? fmax(S.inner_tol * beta, plain_thr) : plain_thr;
-            E.g[(long)s * (E.m + 1)] = c128{beta, 0};
-            E.tin[s] = E.vec(s, 0);
-            E.tout[s] = E.vec(s, 1);
-        }
-    }
-}
-
-// V_j *= 1 / nrm for columns that start or continue a cycle.
-__global__ void __launch_bounds__(kThreads) k_normalize(Eng E) {
-    const int s = blockIdx.y, ch = blockIdx.x;
-    const SlotDev &S = E.slots[s];
-    if (!S.needs_norm || S.phase != PH_ARN) return;
-    c128 *vj = E.vec(s, S.j);
-    const double sc = S.nrm > 0 ? 1.0 / S.nrm : 0.0;
-#pragma unroll
-    for (int t = 0; t < kEPT; ++t) {
-        const long n = (long)ch * kChunk + t * kThreads + threadIdx.x;
-        if (n < E.Nt) vj[n] = c128{vj[n].x * sc, vj[n].y * sc};
     }
 }
 
@@ -434,126 +460,184 @@ __global__ void k_zero_cols(c128 *x, long ld, long Nt) {
         x[(long)r * ld + n] = c128{0, 0};
 }
 
-__global__ void k_clear_u32(unsigned *p, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
 // --------------------------------------------------------------- driver
-static hipError_t super_step(tp_plan pl, const Eng &E, int nslots, hipStream_t st) {
-    const int m = E.m;
-    hipLaunchKernelGGL(k_advance, dim3((nslots + 63) / 64), dim3(64), 0, st, E, nslots);
+static hipError_t super_step(tp_plan pl, const Eng &E, int par, hipStream_t st) {
+    const dim3 gv(E.nb, E.nslots), blk(kThreads);
+    hipLaunchKernelGGL(k_commit, gv, blk, 0, st, E, par);
     hipError_t e;
     if (E.mixed) {
-        e = matvec_fp32_wide(pl, Cols<const c128>{nullptr, 0, E.tin}, Cols<c128>{nullptr, 0, E.tout}, nslots, st);
+        e = matvec_fp32_wide(pl, Cols<const c128>{nullptr, 0, E.tin}, Cols<c128>{nullptr, 0, E.tout}, E.nslots, st);
         if (e) return e;
-        e = matvec_fp64(pl, Cols<const c128>{nullptr, 0, E.rin}, Cols<c128>{nullptr, 0, E.rout}, nslots, st);
+        e = matvec_fp64(pl, Cols<const c128>{nullptr, 0, E.rin}, Cols<c128>{nullptr, 0, E.rout}, E.nslots, st);
     } else {
-        e = matvec_fp64(pl, Cols<const c128>{nullptr, 0, E.tin}, Cols<c128>{nullptr, 0, E.tout}, nslots, st);
+        e = matvec_fp64(pl, Cols<const c128>{nullptr, 0, E.tin}, Cols<c128>{nullptr, 0, E.tout}, E.nslots, st);
     }
     if (e) return e;
-    const dim3 gd(E.nch, m + 1, nslots), gv(E.nch, nslots), blk(kThreads);
-    hipLaunchKernelGGL(k_dots, gd, blk, 0, st, E, 0);
-    hipLaunchKernelGGL(k_update, gv, blk, 0, st, E, 0);
-    hipLaunchKernelGGL(k_dots, gd, blk, 0, st, E, 1);
-    hipLaunchKernelGGL(k_update, gv, blk, 0, st, E, 1);
-    hipLaunchKernelGGL(k_finish, dim3((nslots + 63) / 64), dim3(64), 0, st, E, nslots);
-    hipLaunchKernelGGL(k_xupdate, gv, blk, 0, st, E);
-    hipLaunchKernelGGL(k_residual, gv, blk, 0, st, E);
-    hipLaunchKernelGGL(k_normalize, gv, blk, 0, st, E);
+    hipLaunchKernelGGL(k_dots, gv, blk, 0, st, E, par);
+    hipLaunchKernelGGL(k_orth1, gv, blk, 0, st, E, par);
+    hipLaunchKernelGGL(k_orth2, gv, blk, 0, st, E, par);
+    hipLaunchKernelGGL(k_tail, gv, blk, 0, st, E, par);
     return hipGetLastError();
+}
+
+constexpr int kStepsPerGraph = 2;     // one super-step per state parity
+
+void solver_release(tp_plan pl) {
+    for (int i = 0; i < pl->ngraphs; ++i) hipGraphExecDestroy(pl->graphs[i].exec);
+    pl->ngraphs = 0;
+    for (hipEvent_t &e : pl->ev)
+        if (e) {
+            hipEventDestroy(e);
+            e = nullptr;
+        }
+    if (pl->cs) {
+        hipStreamDestroy(pl->cs);
+        pl->cs = nullptr;
+    }
+    if (pl->host_status) {
+        hipHostFree(pl->host_status);
+        pl->host_status = nullptr;
+    }
+}
+
+static hipError_t solver_resources(tp_plan pl) {
+    hipError_t e = hipSuccess;
+    if (!pl->cs && (e = hipStreamCreateWithFlags(&pl->cs, hipStreamNonBlocking))) return e;
+    for (hipEvent_t &ev : pl->ev)
+        if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming))) return e;
+    if (!pl->host_status && (e = hipHostMalloc(&pl->host_status, 2 * sizeof(SlotState) * pl->max_rhs)))
+        return e;
+    return e;
+}
+
+// Graph of two super-steps (parities 0 and 1) for this (mode, columns,
+// restart); every kernel argument is fixed by the plan, so the graph is
+// captured once and replayed by every later solve of the same shape.
+static hipError_t step_graph(tp_plan pl, const Eng &E, hipGraphExec_t *out) {
+    for (int i = 0; i < pl->ngraphs; ++i) {
+        const auto &g = pl->graphs[i];
+        if (g.mode == E.mixed && g.nslots == E.nslots && g.m == E.m && g.steps == kStepsPerGraph) {
+            *out = g.exec;
+            return hipSuccess;
+        }
+    }
+    hipError_t e;
+    if ((e = hipStreamBeginCapture(pl->cs, hipStreamCaptureModeThreadLocal))) return e;
+    hipError_t le = hipSuccess;
+    for (int t = 0; t < kStepsPerGraph && le == hipSuccess; ++t) le = super_step(pl, E, t & 1, pl->cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(pl->cs, &g);
+    if (le) {
+        if (g) hipGraphDestroy(g);
+        return le;
+    }
+    if (e) return e;
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e) return e;
+    if (pl->ngraphs == 8) {
+        hipGraphExecDestroy(pl->graphs[0].exec);
+        for (int i = 1; i < 8; ++i) pl->graphs[i - 1] = pl->graphs[i];
+        pl->ngraphs = 7;
+    }
+    pl->graphs[pl->ngraphs++] = {E.mixed, E.nslots, E.m, kStepsPerGraph, ex};
+    *out = ex;
+    return hipSuccess;
 }
 
 tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int nrhs, const tp_solve_opts &o,
                     tp_solve_info *info, hipStream_t st) {
     const long Nt = pl->Nt;
-    const int m = o.restart;
-    // the engine is carved for the plan's restart; a shorter o.restart uses a prefix
     EngLayout L = eng_layout(Nt, pl->restart, pl->max_rhs);
     char *wsb = (char *)pl->rim_part + a256((size_t)pl->rim_nslab * (pl->Nr ? pl->Nr : 1) * pl->max_rhs * 16);
     Eng E;
     E.Nt = Nt;
-    E.m = pl->restart;
-    E.nch = (int)((Nt + kChunk - 1) / kChunk);
+    E.m = o.restart;        // a shorter restart than the plan's uses a prefix of each region
+    E.nb = (int)std::min<long>(kMaxBlocks, (Nt + kThreads - 1) / kThreads);
+    E.span = (Nt + E.nb - 1) / E.nb;
     E.mixed = o.mode == TP_MIXED;
-    E.slots = (SlotDev *)(wsb + L.slots);
+    E.nslots = nrhs;
+    E.st = (SlotState *)(wsb + L.st);
+    E.sc = (SlotConst *)(wsb + L.sc);
+    E.dec = (SlotDec *)(wsb + L.dec);
     E.V = (c128 *)(wsb + L.V);
     E.W = (c128 *)(wsb + L.W);
     E.H = (c128 *)(wsb + L.H);
     E.sn = (c128 *)(wsb + L.sn);
     E.g = (c128 *)(wsb + L.g);
     E.h1 = (c128 *)(wsb + L.h1);
-    E.h2 = (c128 *)(wsb + L.h2);
-    E.part = (c128 *)(wsb + L.part);
+    E.y = (c128 *)(wsb + L.y);
+    E.P1 = (c128 *)(wsb + L.P1);
+    E.P2 = (c128 *)(wsb + L.P2);
     E.cs = (double *)(wsb + L.cs);
-    E.pn = (double *)(wsb + L.pn);
-    E.cnt = (unsigned *)(wsb + L.cnt);
+    E.PN = (double *)(wsb + L.PN);
+    E.PR = (double *)(wsb + L.PR);
     void **tabs = (void **)(wsb + L.tabs);
     E.tin = (const c128 **)tabs;
     E.tout = (c128 **)(tabs + pl->max_rhs);
     E.rin = (const c128 **)(tabs + 2 * pl->max_rhs);
     E.rout = (c128 **)(tabs + 3 * pl->max_rhs);
 
-    // host-side initial state, copied once
-    std::vector<SlotDev> hs(nrhs);
-    for (int r = 0; r < nrhs; ++r) {
-        SlotDev &S = hs[r];
-        std::memset(&S, 0, sizeof(S));
-        S.v = v + (long)r * ldv;
-        S.x = x + (long)r * ldx;
-        S.tol = o.tol;
-        S.inner_tol = o.inner_tol;
-        S.max_iter = o.max_iter;
-        S.max_outer = o.max_outer;
-        S.first = 1;
-        if (o.x0_given) {
-            S.phase = PH_PRE_RES;   // true residual of x0 first
-            S.xzero = 0;
-        } else {
-            S.phase = PH_RES;
-            S.xzero = 1;
-        }
-    }
-    // a shorter restart than the plan's uses a prefix of each per-column region
-    E.m = m;
-    std::vector<void *> htab(4 * (size_t)pl->max_rhs, nullptr);
-    for (int r = 0; r < nrhs; ++r)
-        if (o.x0_given) {
-            if (E.mixed) {
-                htab[2 * pl->max_rhs + r] = hs[r].x;
-                htab[3 * pl->max_rhs + r] = E.W + (long)r * Nt;
-            } else {
-                htab[r] = hs[r].x;
-                htab[pl->max_rhs + r] = E.W + (long)r * Nt;
-            }
-        }
     hipError_t e;
-    if ((e = hipMemcpyAsync(E.slots, hs.data(), sizeof(SlotDev) * nrhs, hipMemcpyHostToDevice, st)) ||
-        (e = hipMemcpyAsync(tabs, htab.data(), sizeof(void *) * htab.size(), hipMemcpyHostToDevice, st)))
-        return hip_fail(e, "solver state upload");
-    hipLaunchKernelGGL(k_clear_u32, dim3((nrhs * 8 + 255) / 256), dim3(256), 0, st, E.cnt, nrhs * 8);
-    if (!o.x0_given)
-        hipLaunchKernelGGL(k_zero_cols, dim3(256, nrhs), dim3(256), 0, st, x, ldx, Nt);
-    if ((e = hipGetLastError())) return hip_fail(e, "solver init");
+    if ((e = solver_resources(pl))) return hip_fail(e, "solver resources");
+    hipStream_t cs = pl->cs;
+    SlotState *hstat = (SlotState *)pl->host_status;     // [2][max_rhs], pinned
 
-    std::vector<SlotDev> snap(nrhs);
-    const long max_steps = (long)o.max_iter * 2 + (long)o.max_outer * 4 + 16;
-    long step = 0;
-    bool done = false;
-    while (!done) {
-        for (int t = 0; t < 4 && step < max_steps; ++t, ++step)
-            if ((e = super_step(pl, E, nrhs, st))) return hip_fail(e, "solver step");
-        if ((e = hipMemcpyAsync(snap.data(), E.slots, sizeof(SlotDev) * nrhs, hipMemcpyDeviceToHost, st)) ||
-            (e = hipStreamSynchronize(st)))
-            return hip_fail(e, "solver poll");
-        done = true;
-        for (int r = 0; r < nrhs; ++r)
-            if (snap[r].phase != PH_DONE) done = false;
-        if (step >= max_steps) break;
+    // the first super-step (parity 0) commits from the parity-1 copy
+    std::vector<SlotState> hs(2 * (size_t)nrhs);
+    std::vector<SlotConst> hc(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        SlotState S;
+        std::memset(&S, 0, sizeof(S));
+        S.phase = PH_INIT;
+        S.xzero = o.x0_given ? 0 : 1;
+        S.first = 1;
+        hs[r] = S;
+        hs[nrhs + r] = S;
+        hc[r] = SlotConst{v + (long)r * ldv, x + (long)r * ldx, o.tol, o.inner_tol, o.max_iter, o.max_outer};
     }
+    if ((e = hipEventRecord(pl->ev[0], st)) || (e = hipStreamWaitEvent(cs, pl->ev[0], 0)))
+        return hip_fail(e, "solver stream ordering");
+    if ((e = hipMemcpyAsync(E.st, hs.data(), sizeof(SlotState) * hs.size(), hipMemcpyHostToDevice, cs)) ||
+        (e = hipMemcpyAsync(E.sc, hc.data(), sizeof(SlotConst) * hc.size(), hipMemcpyHostToDevice, cs)))
+        return hip_fail(e, "solver state upload");
+    if (!o.x0_given) hipLaunchKernelGGL(k_zero_cols, dim3(256, nrhs), dim3(256), 0, cs, x, ldx, Nt);
+    if ((e = hipGetLastError())) return hip_fail(e, "solver init");
+    if ((e = hipStreamSynchronize(cs))) return hip_fail(e, "solver init sync");
+
+    hipGraphExec_t gexec = nullptr;
+    if ((e = step_graph(pl, E, &gexec))) return hip_fail(e, "solver graph capture");
+
+    // replay with one graph of lookahead; the state after a graph is the
+    // parity-1 copy (the second super-step's commit)
+    const long max_launch = ((long)o.max_iter * 2 + (long)o.max_outer * 4 + 16) / kStepsPerGraph + 2;
+    const size_t sbytes = sizeof(SlotState) * nrhs;
+    const SlotState *dev_last = E.st + nrhs;
+    long k = 0;
+    bool done = false;
+    while (!done && k < max_launch) {
+        const int buf = (int)(k & 1);
+        if ((e = hipGraphLaunch(gexec, cs)) ||
+            (e = hipMemcpyAsync(hstat + buf * pl->max_rhs, dev_last, sbytes, hipMemcpyDeviceToHost, cs)) ||
+            (e = hipEventRecord(pl->ev[1 + buf], cs)))
+            return hip_fail(e, "solver replay");
+        if (k > 0) {
+            const int pb = 1 - buf;
+            if ((e = hipEventSynchronize(pl->ev[1 + pb]))) return hip_fail(e, "solver poll");
+            done = true;
+            for (int r = 0; r < nrhs; ++r)
+                if (hstat[pb * pl->max_rhs + r].phase != PH_DONE) done = false;
+        }
+        ++k;
+    }
+    if ((e = hipStreamSynchronize(cs))) return hip_fail(e, "solver sync");
+    const int last = (int)((k - 1) & 1);
+    if ((e = hipEventRecord(pl->ev[3], cs)) || (e = hipStreamWaitEvent(st, pl->ev[3], 0)))
+        return hip_fail(e, "solver stream ordering");
     tp_status ret = TP_OK;
     for (int r = 0; r < nrhs; ++r) {
-        const SlotDev &S = snap[r];
+        const SlotState &S = hstat[last * pl->max_rhs + r];
         info[r].iters = S.iters;
         info[r].outer_iters = S.outer;
         info[r].relres = S.relres;

@@ -8,14 +8,19 @@
 // Channel c = r*b + p (right-hand side r, basis p) is the contiguous axis of
 // every grid, so every transform pass reads and writes whole channel runs.
 //
-// Stages (one kernel each):
-//   k_fwd_x   embed + DFT along x, rows iy < Ny only      x      -> [Ny][Px][C]
-//   k_fwd_y   DFT along y (inputs iy < Ny)                      -> [Px][Py][C]
-//   k_prod    per-frequency b x b block times b x R block        -> [Px][Py][C]
-//   k_inv_y   inverse DFT along y, keep iy < Ny                  -> [Ny][Px][C]
-//   k_inv_x   inverse DFT along x, keep ix < Nx, add rim term    -> y_A
-//   k_rim_main  one pass over B: y_A = B_er x_r, partial B x_A
-//   k_rim_finish  y_r = sum of partials + C x_r
+// Kernels:
+//   k_fwd_x      embed + DFT along x, rows iy < Ny only     x -> [Ny][Px][C]
+//   k_fwd_y      DFT along y (inputs iy < Ny)                 -> [Px][Py][C]
+//   k_prod       per-frequency b x b block times b x R block  -> [Px][Py][C]
+//   k_inv_y      inverse DFT along y, keep iy < Ny            -> [Ny][Px][C]
+//   k_rim_main   one pass over B: y_A = B_er x_r, partial B x_A per slab
+//   k_inv_x_fin  inverse DFT along x, keep ix < Nx, add the rim term -> y_A;
+//                and y_r = sum of the slab partials + C x_r
+//   k_spec_rim   single-column path: y transform, product and inverse y
+//                transform fused per spectrum column, with the rim pass as
+//                extra workgroups of the same launch
+// A single column runs k_fwd_x -> k_spec_rim -> k_inv_x_fin; several columns
+// run k_rim_main, k_fwd_x, k_fwd_y, k_prod, k_inv_y, k_inv_x_fin.
 #include "tp_fft.h"
 #include "tp_internal.h"
 
@@ -124,36 +129,6 @@ __global__ void __launch_bounds__(256) k_inv_y(const cpx<T> *__restrict__ in, in
     }
 }
 
-template <typename T, typename Out>
-__global__ void __launch_bounds__(256) k_inv_x(const cpx<T> *__restrict__ in, int R, int Nx, int b,
-                                               FFTDesc fx, int lgCC, Cols<Out> y, int accumulate) {
-    extern __shared__ char smem_raw[];
-    cpx<T> *twl = reinterpret_cast<cpx<T> *>(smem_raw);
-    cpx<T> *buf = twl + fx.P;
-    const int CC = 1 << lgCC, C = b * R, P = fx.P;
-    const int c0 = blockIdx.x * CC, iy = blockIdx.y;
-    if (!cols_live((const void *const *)y.tab, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
-    load_twiddles<T>(twl, fx);
-    for (int i = threadIdx.x; i < P * CC; i += blockDim.x) {
-        const int kx = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
-        buf[(fx.perm[kx] << lgCC) + cl] = (c < C) ? in[((long)iy * P + kx) * C + c] : mk<T>(0, 0);
-    }
-    __syncthreads();
-    lds_fft<T, true>(buf, lgCC, fx, twl);
-    for (int i = threadIdx.x; i < Nx * CC; i += blockDim.x) {
-        const int ix = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
-        if (c < C) {
-            const int r = c / b, p = c - r * b;
-            Out *yc = y.col(r);
-            if (!yc) continue;
-            Out *dst = yc + (long)(iy * Nx + ix) * b + p;
-            cpx<T> v = buf[i];
-            if (accumulate) v = v + cvt<T>(*dst);
-            *dst = cvt<typename Out::value_type>(v);
-        }
-    }
-}
-
 // ---------------------------------------------------- per-frequency product
 // Workgroup = one frequency k, four waves.  Wave w streams rows p = w, w+4, ...
 // of the b x b spectrum block: lane l reads G[k][p][q] for q = l, l+64, ...
@@ -209,21 +184,22 @@ __global__ void __launch_bounds__(256) k_prod(const cpx<T> *__restrict__ G, cons
 }
 
 // ------------------------------------------------------------------- rim
-// Workgroup = one slab of TE = 64*E element columns and all Nr rim rows.  Lane
-// l of wave w owns columns e0 + l + 64 i and rows w, w + nw, ...:
-//   uA[e]   = sum_row BE[row][e] x_r[row]   (BE = B when reciprocal)  -> y_A
-//   part[slab][row] = sum_{e in slab} B[row][e] x_A[e]                -> y_r partials
-template <typename T, typename In, typename Out, int E, int RB>
-__global__ void __launch_bounds__(256) k_rim_main(const cpx<T> *__restrict__ B, const cpx<T> *__restrict__ BE,
-                                                  Cols<const In> x, Cols<Out> y, int R, long N, int Nr,
-                                                  cpx<T> *__restrict__ part) {
-    extern __shared__ char smem_raw[];
+// One slab = TE = 64*E element columns x all Nr rim rows.  Lane l of wave w
+// owns columns e0 + l + 64 i; wave w takes rows in groups of UR consecutive
+// rows (w*UR, w*UR + nw*UR, ...), issuing all UR*E loads of a group before
+// using any, so UR*E independent loads are in flight per lane:
+//   uA[e]            = sum_row BE[row][e] x_r[row]   (BE = B when reciprocal) -> y_A
+//   part[slab][row]  = sum_{e in slab} B[row][e] x_A[e]                      -> y_r partials
+template <typename T, typename In, typename Out, int E, int RB, int UR, bool NBE>
+__device__ __forceinline__ void rim_block(const cpx<T> *__restrict__ B, const cpx<T> *__restrict__ BE,
+                                          Cols<const In> x, Cols<Out> y, int R, long N, int Nr,
+                                          cpx<T> *__restrict__ part, int slab, int rbk, char *smem) {
     const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int TE = 64 * E, slab = blockIdx.x, rb = blockIdx.y * RB;
+    const int TE = 64 * E, rb = rbk * RB;
     const long e0 = (long)slab * TE;
     if (!cols_live((const void *const *)x.tab, rb, min(rb + RB, R) - 1)) return;
-    cpx<T> *xr = reinterpret_cast<cpx<T> *>(smem_raw);            // [RB][Nr]
-    cpx<T> *ua = xr + RB * Nr;                                       // [nw][TE][RB]
+    cpx<T> *xr = reinterpret_cast<cpx<T> *>(smem);   // [RB][Nr]
+    cpx<T> *ua = xr + RB * Nr;                          // [nw][TE][RB]
     for (int i = threadIdx.x; i < RB * Nr; i += blockDim.x) {
         const int c = i / Nr, t = i - c * Nr;
         const In *xc = (rb + c < R) ? x.col(rb + c) : nullptr;
@@ -241,28 +217,36 @@ __global__ void __launch_bounds__(256) k_rim_main(const cpx<T> *__restrict__ B, 
         }
     }
     __syncthreads();
-    const cpx<T> *BEm = BE ? BE : B;
-    for (int row = w; row < Nr; row += nw) {
-        cpx<T> s[RB];
+    for (int r0 = w * UR; r0 < Nr; r0 += nw * UR) {
+        cpx<T> g[UR][E], ge[NBE ? UR : 1][E];
 #pragma unroll
-        for (int c = 0; c < RB; ++c) s[c] = mk<T>(0, 0);
+        for (int u = 0; u < UR; ++u)
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const long e = e0 + lane + 64 * i;
-            if (e < N) {
-                const cpx<T> g = B[(long)row * N + e];
-                const cpx<T> ge = BE ? BEm[(long)row * N + e] : g;
+            for (int i = 0; i < E; ++i) {
+                const long e = e0 + lane + 64 * i;
+                const int row = r0 + u;
+                const bool ok = row < Nr && e < N;
+                g[u][i] = ok ? B[(long)row * N + e] : mk<T>(0, 0);
+                if constexpr (NBE) ge[u][i] = ok ? BE[(long)row * N + e] : mk<T>(0, 0);
+            }
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            const int row = r0 + u;
+            cpx<T> sr[RB];
+#pragma unroll
+            for (int c = 0; c < RB; ++c) sr[c] = mk<T>(0, 0);
+#pragma unroll
+            for (int i = 0; i < E; ++i)
 #pragma unroll
                 for (int c = 0; c < RB; ++c) {
-                    s[c] = cmac(s[c], g, xa[i][c]);
-                    acc[i][c] = cmac(acc[i][c], ge, xr[c * Nr + row]);
+                    sr[c] = cmac(sr[c], g[u][i], xa[i][c]);
+                    if (row < Nr) acc[i][c] = cmac(acc[i][c], NBE ? ge[NBE ? u : 0][i] : g[u][i], xr[c * Nr + row]);
                 }
-            }
-        }
 #pragma unroll
-        for (int c = 0; c < RB; ++c) {
-            cpx<T> t = wave_sum(s[c]);
-            if (lane == 0 && rb + c < R) part[((long)slab * Nr + row) * R + rb + c] = t;
+            for (int c = 0; c < RB; ++c) {
+                const cpx<T> t = wave_sum(sr[c]);
+                if (lane == 0 && row < Nr && rb + c < R) part[((long)slab * Nr + row) * R + rb + c] = t;
+            }
         }
     }
 #pragma unroll
@@ -282,10 +266,21 @@ __global__ void __launch_bounds__(256) k_rim_main(const cpx<T> *__restrict__ B, 
     }
 }
 
+template <typename T, typename In, typename Out, int E, int RB, int UR, bool NBE>
+__global__ void __launch_bounds__(256) k_rim_main(const cpx<T> *__restrict__ B, const cpx<T> *__restrict__ BE,
+                                                  Cols<const In> x, Cols<Out> y, int R, long N, int Nr,
+                                                  cpx<T> *__restrict__ part) {
+    extern __shared__ char smem_raw[];
+    rim_block<T, In, Out, E, RB, UR, NBE>(B, BE, x, y, R, N, Nr, part, blockIdx.x, blockIdx.y, smem_raw);
+}
+
+// y_r = sum over slabs of the partials + C x_r; one wave per (rim row, column).
 template <typename T, typename In, typename Out>
-__global__ void __launch_bounds__(64) k_rim_finish(const cpx<T> *__restrict__ part, const cpx<T> *__restrict__ Cm,
-                                                   Cols<const In> x, Cols<Out> y, int R, long N, int Nr, int nslab) {
-    const int row = blockIdx.x, c = blockIdx.y, lane = threadIdx.x;
+__device__ __forceinline__ void rim_finish_wave(const cpx<T> *__restrict__ part, const cpx<T> *__restrict__ Cm,
+                                                Cols<const In> x, Cols<Out> y, int R, long N, int Nr, int nslab,
+                                                int row, int c) {
+    const int lane = threadIdx.x & 63;
+    if (row >= Nr) return;
     const In *xcol = x.col(c);
     Out *ycol = y.col(c);
     if (!xcol || !ycol) return;
@@ -297,10 +292,158 @@ __global__ void __launch_bounds__(64) k_rim_finish(const cpx<T> *__restrict__ pa
     if (lane == 0) ycol[N + row] = cvt<typename Out::value_type>(s);
 }
 
+// ------------------------------------------------ fused single-column path
+// Workgroup = (frequency column kx, TP spectrum rows p0..p0+TP-1).  It
+//   1. loads the x-transformed column X1[iy][kx][0..b) (iy < Ny) into LDS and
+//      transforms it along y (all Py frequencies, all b channels);
+//   2. streams the TP x b row panels of the Py spectrum blocks G[kx][ky]:
+//      lane q multiplies G[..][p][q] by xhat[ky][q] and the wave sums the row;
+//      U rows are loaded before any is used (U independent loads per lane);
+//   3. inverse-transforms the TP output channels along y in LDS and writes the
+//      rows iy < Ny of Y1.
+// The y transform of the input column is repeated by the b / TP workgroups of
+// a column; it is small next to the spectrum stream.
+template <typename T, int TP, int QL>
+__device__ __forceinline__ void spec_block(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ X1,
+                                           cpx<T> *__restrict__ Y1, int b, int Ny, int Px, const FFTDesc &fy,
+                                           int lgCC, int blk, char *smem) {
+    constexpr int U = 16 / QL;
+    constexpr int lgTP = TP == 4 ? 2 : TP == 8 ? 3 : 4;
+    const int P = fy.P, CC = 1 << lgCC;
+    const int nchunk = (b + TP - 1) / TP;
+    const int kx = blk / nchunk, p0 = (blk - kx * nchunk) * TP;
+    cpx<T> *twl = reinterpret_cast<cpx<T> *>(smem);
+    cpx<T> *xs = twl + P;          // [Py][CC]
+    cpx<T> *ys = xs + P * CC;      // [Py][TP]
+    load_twiddles<T>(twl, fy);
+    zero_lds<T>(xs, P * CC);
+    __syncthreads();
+    for (int i = threadIdx.x; i < Ny * CC; i += blockDim.x) {
+        const int iy = i >> lgCC, c = i & (CC - 1);
+        if (c < b) xs[(fy.perm[iy] << lgCC) + c] = X1[((long)iy * Px + kx) * b + c];
+    }
+    __syncthreads();
+    lds_fft<T, false>(xs, lgCC, fy, twl);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int nrows = P * TP;
+    const cpx<T> *Gk = G + (long)kx * P * b * b;
+    for (int base = w * U; base < nrows; base += nw * U) {
+        cpx<T> g[U][QL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int row = base + u;
+            const int ky = row >> lgTP, p = p0 + (row & (TP - 1));
+#pragma unroll
+            for (int t = 0; t < QL; ++t) {
+                const int q = lane + 64 * t;
+                g[u][t] = (row < nrows && p < b && q < b) ? Gk[((long)ky * b + p) * b + q] : mk<T>(0, 0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int row = base + u;
+            const int ky = row >> lgTP;
+            cpx<T> acc = mk<T>(0, 0);
+#pragma unroll
+            for (int t = 0; t < QL; ++t) {
+                const int q = lane + 64 * t;
+                if (q < b && row < nrows) acc = cmac(acc, g[u][t], xs[(ky << lgCC) + q]);
+            }
+            acc = wave_sum(acc);
+            // the inverse transform takes its input in digit-reversed slots
+            if (lane == 0 && row < nrows) ys[(fy.perm[ky] << lgTP) + (row & (TP - 1))] = acc;
+        }
+    }
+    __syncthreads();
+    lds_fft<T, true>(ys, lgTP, fy, twl);
+    for (int i = threadIdx.x; i < Ny * TP; i += blockDim.x) {
+        const int iy = i >> lgTP, pl = i & (TP - 1), p = p0 + pl;
+        if (p < b) Y1[((long)iy * Px + kx) * b + p] = ys[i];
+    }
+}
+
+// Spectrum workgroups and rim workgroups share one launch so that both HBM
+// streams (the spectrum and the dense rim) run together; the two kinds are
+// interleaved in block order.
+template <typename T, typename In, typename Out, int TP, int QL, int E, bool NBE>
+__global__ void __launch_bounds__(256) k_spec_rim(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ X1,
+                                                  cpx<T> *__restrict__ Y1, int b, int Ny, int Px, FFTDesc fy,
+                                                  int lgCC, int nspec, const cpx<T> *__restrict__ B,
+                                                  const cpx<T> *__restrict__ BE, Cols<const In> x, Cols<Out> y,
+                                                  long N, int Nr, cpx<T> *__restrict__ part, int nrim) {
+    extern __shared__ char smem_raw[];
+    const int i = blockIdx.x, both = 2 * min(nspec, nrim);
+    int spec_id, rim_id;
+    if (i < both) {
+        spec_id = (i & 1) ? -1 : (i >> 1);
+        rim_id = (i & 1) ? (i >> 1) : -1;
+    } else if (nspec > nrim) {
+        spec_id = i - both + nrim;
+        rim_id = -1;
+    } else {
+        spec_id = -1;
+        rim_id = i - both + nspec;
+    }
+    if (spec_id >= 0) {
+        if (!cols_live((const void *const *)x.tab, 0, 0)) return;
+        spec_block<T, TP, QL>(G, X1, Y1, b, Ny, Px, fy, lgCC, spec_id, smem_raw);
+    } else if constexpr (E > 0) {
+        rim_block<T, In, Out, E, 1, (E >= 4 ? 2 : 8 / E), NBE>(B, BE, x, y, 1, N, Nr, part, rim_id, 0, smem_raw);
+    }
+}
+
+// Inverse x transform + crop (+ rim term already in y), and the rim finish
+// waves, in one launch: blocks [0, ninv) transform, the rest finish rim rows.
+template <typename T, typename In, typename Out>
+__global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in, int R, int Nx, int b, FFTDesc fx,
+                                                   int lgCC, int nchunk, Cols<Out> y, int accumulate, int ninv,
+                                                   const cpx<T> *__restrict__ part, const cpx<T> *__restrict__ Cm,
+                                                   Cols<const In> x, long N, int Nr, int nslab) {
+    extern __shared__ char smem_raw[];
+    const int blk = blockIdx.x;
+    if (blk >= ninv) {
+        const int f = blk - ninv, w = threadIdx.x >> 6;
+        const int nrowblk = (Nr + 3) >> 2;
+        const int c = f / nrowblk, row = (f - c * nrowblk) * 4 + w;
+        rim_finish_wave<T, In, Out>(part, Cm, x, y, R, N, Nr, nslab, row, c);
+        return;
+    }
+    cpx<T> *twl = reinterpret_cast<cpx<T> *>(smem_raw);
+    cpx<T> *buf = twl + fx.P;
+    const int CC = 1 << lgCC, C = b * R, P = fx.P;
+    const int iy = blk / nchunk, c0 = (blk - iy * nchunk) * CC;
+    if (!cols_live((const void *const *)y.tab, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
+    load_twiddles<T>(twl, fx);
+    for (int i = threadIdx.x; i < P * CC; i += blockDim.x) {
+        const int kx = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
+        buf[(fx.perm[kx] << lgCC) + cl] = (c < C) ? in[((long)iy * P + kx) * C + c] : mk<T>(0, 0);
+    }
+    __syncthreads();
+    lds_fft<T, true>(buf, lgCC, fx, twl);
+    for (int i = threadIdx.x; i < Nx * CC; i += blockDim.x) {
+        const int ix = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
+        if (c < C) {
+            const int r = c / b, p = c - r * b;
+            Out *yc = y.col(r);
+            if (!yc) continue;
+            Out *dst = yc + (long)(iy * Nx + ix) * b + p;
+            cpx<T> v = buf[i];
+            if (accumulate) v = v + cvt<T>(*dst);
+            *dst = cvt<typename Out::value_type>(v);
+        }
+    }
+}
+
 // --------------------------------------------------------------- launcher
-static int fft_lgcc(int P, int C, size_t elem) {
-    // channels per workgroup: a power of two, at most 64, LDS tile <= 48 KB
-    int lg = 6;
+static int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+static int fft_lgcc(int P, int C, size_t elem, int max_cc = 64) {
+    // channels per workgroup: a power of two, at most max_cc, LDS tile <= 48 KB
+    int lg = ilog2(max_cc);
     while (lg > 0 && ((size_t)P * ((size_t)1 << lg) + P) * elem > 48 * 1024) --lg;
     while (lg > 0 && (1 << (lg - 1)) >= C) --lg;
     return lg;
@@ -323,8 +466,85 @@ struct OpPtrs<float> {
     static const c64 *C(tp_plan p) { return p->C32; }
 };
 
+static int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Fused single-column path: rows per workgroup and LDS bytes.
+static int spec_tp(int b) { return b >= 8 ? 8 : 4; }
+static size_t spec_lds(tp_plan pl, size_t es) {
+    const int P = pl->Py, CC = next_pow2(pl->b);
+    return ((size_t)P + (size_t)P * CC + (size_t)P * spec_tp(pl->b)) * es;
+}
+static size_t rim_lds(tp_plan pl, int RB, size_t es) { return ((size_t)RB * pl->Nr + 4 * (size_t)pl->rim_te * RB) * es; }
+constexpr size_t kLdsLimit = 160 * 1024;
+
+template <typename T, typename In, typename Out, int TP, int QL, int E, bool NBE>
+static void launch_spec_rim(tp_plan pl, Cols<const In> x, Cols<Out> y, cpx<T> *gA, cpx<T> *gB, size_t sh,
+                            hipStream_t st) {
+    const int nchunk = (pl->b + TP - 1) / TP, nspec = pl->Px * nchunk;
+    const int nrim = pl->Nr > 0 ? pl->rim_nslab : 0;
+    const int lgCC = ilog2(next_pow2(pl->b));
+    hipLaunchKernelGGL((k_spec_rim<T, In, Out, TP, QL, E, NBE>), dim3(nspec + nrim), dim3(256), sh, st, OpPtrs<T>::G(pl),
+                       gA, gB, pl->b, pl->Ny, pl->Px, pl->fy, lgCC, nspec, OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl), x, y,
+                       pl->N, pl->Nr, reinterpret_cast<cpx<T> *>(pl->rim_part), nrim);
+}
+
+template <typename T, typename In, typename Out, int TP, int QL>
+static void launch_spec_rim_e(tp_plan pl, Cols<const In> x, Cols<Out> y, cpx<T> *gA, cpx<T> *gB, size_t sh,
+                              hipStream_t st) {
+    if (pl->Nr == 0) {
+        launch_spec_rim<T, In, Out, TP, QL, 0, false>(pl, x, y, gA, gB, sh, st);
+        return;
+    }
+    const bool nbe = OpPtrs<T>::BE(pl) != nullptr;
+    switch ((pl->rim_te / 64) * 2 + (nbe ? 1 : 0)) {
+        case 2: launch_spec_rim<T, In, Out, TP, QL, 1, false>(pl, x, y, gA, gB, sh, st); break;
+        case 3: launch_spec_rim<T, In, Out, TP, QL, 1, true>(pl, x, y, gA, gB, sh, st); break;
+        case 4: launch_spec_rim<T, In, Out, TP, QL, 2, false>(pl, x, y, gA, gB, sh, st); break;
+        case 5: launch_spec_rim<T, In, Out, TP, QL, 2, true>(pl, x, y, gA, gB, sh, st); break;
+        case 8: launch_spec_rim<T, In, Out, TP, QL, 4, false>(pl, x, y, gA, gB, sh, st); break;
+        default: launch_spec_rim<T, In, Out, TP, QL, 4, true>(pl, x, y, gA, gB, sh, st); break;
+    }
+}
+
+// Rows per group (UR) depend only on the slab width, in the fused and the
+// general path alike: which rows a wave sums, and in which order, must not
+// depend on the number of columns, so a column's result is the same alone or
+// in a batch, bit for bit.
 template <typename T, typename In, typename Out>
-hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipStream_t st) {
+static void launch_rim_general(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipStream_t st) {
+    const size_t es = sizeof(cpx<T>);
+    cpx<T> *part = reinterpret_cast<cpx<T> *>(pl->rim_part);
+    const int E = pl->rim_te / 64;
+    const int RB = 8 / E;
+    dim3 grid(pl->rim_nslab, (R + RB - 1) / RB);
+    const size_t sh = rim_lds(pl, RB, es);
+    const cpx<T> *B = OpPtrs<T>::B(pl), *BE = OpPtrs<T>::BE(pl);
+    switch (E * 2 + (BE ? 1 : 0)) {
+        case 2: hipLaunchKernelGGL((k_rim_main<T, In, Out, 1, 8, 8, false>), grid, dim3(256), sh, st, B, BE, x, y, R,
+                                   pl->N, pl->Nr, part); break;
+        case 3: hipLaunchKernelGGL((k_rim_main<T, In, Out, 1, 8, 8, true>), grid, dim3(256), sh, st, B, BE, x, y, R,
+                                   pl->N, pl->Nr, part); break;
+        case 4: hipLaunchKernelGGL((k_rim_main<T, In, Out, 2, 4, 4, false>), grid, dim3(256), sh, st, B, BE, x, y, R,
+                                   pl->N, pl->Nr, part); break;
+        case 5: hipLaunchKernelGGL((k_rim_main<T, In, Out, 2, 4, 4, true>), grid, dim3(256), sh, st, B, BE, x, y, R,
+                                   pl->N, pl->Nr, part); break;
+        case 8: hipLaunchKernelGGL((k_rim_main<T, In, Out, 4, 2, 2, false>), grid, dim3(256), sh, st, B, BE, x, y, R,
+                                   pl->N, pl->Nr, part); break;
+        default: hipLaunchKernelGGL((k_rim_main<T, In, Out, 4, 2, 2, true>), grid, dim3(256), sh, st, B, BE, x, y, R,
+                                    pl->N, pl->Nr, part); break;
+    }
+}
+
+// ev (optional, kMatvecStages + 1 events): ev[0] before the first stage and
+// ev[i + 1] after stage i, for per-stage timing.  Stages that a path merges
+// into another are recorded as empty intervals.
+template <typename T, typename In, typename Out>
+hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipStream_t st,
+                         hipEvent_t *ev = nullptr) {
     const int Nx = pl->Nx, Ny = pl->Ny, b = pl->b, Nr = pl->Nr;
     const int Px = pl->Px, Py = pl->Py, C = b * R;
     cpx<T> *gA = reinterpret_cast<cpx<T> *>(pl->gridA);
@@ -332,38 +552,42 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     const size_t es = sizeof(cpx<T>);
     const dim3 blk(256);
     const void *const *act = (const void *const *)x.tab;
+    auto mark = [&](int i) {
+        if (ev) hipEventRecord(ev[i], st);
+    };
+    const int QL = b <= 64 ? 1 : b <= 128 ? 2 : 4;
+    const size_t sh_fused = std::max(spec_lds(pl, es), Nr > 0 ? rim_lds(pl, 1, es) : (size_t)0);
+    const bool fused = R == 1 && sh_fused <= kLdsLimit;
 
-    if (Nr > 0) {
-        constexpr int RB = 1;
-        const int E = pl->rim_te / 64;
-        const int nw = 4;
-        const size_t sh = ((size_t)RB * Nr + (size_t)nw * pl->rim_te * RB) * es;
-        dim3 grid(pl->rim_nslab, (R + RB - 1) / RB);
-        cpx<T> *part = reinterpret_cast<cpx<T> *>(pl->rim_part);
-        if (E == 1)
-            hipLaunchKernelGGL((k_rim_main<T, In, Out, 1, RB>), grid, dim3(64 * nw), sh, st, OpPtrs<T>::B(pl),
-                               OpPtrs<T>::BE(pl), x, y, R, pl->N, Nr, part);
-        else if (E == 2)
-            hipLaunchKernelGGL((k_rim_main<T, In, Out, 2, RB>), grid, dim3(64 * nw), sh, st, OpPtrs<T>::B(pl),
-                               OpPtrs<T>::BE(pl), x, y, R, pl->N, Nr, part);
-        else
-            hipLaunchKernelGGL((k_rim_main<T, In, Out, 4, RB>), grid, dim3(64 * nw), sh, st, OpPtrs<T>::B(pl),
-                               OpPtrs<T>::BE(pl), x, y, R, pl->N, Nr, part);
-    }
+    mark(0);
+    if (Nr > 0 && !fused) launch_rim_general<T, In, Out>(pl, x, y, R, st);
+    mark(1);
     {
-        const int lg = fft_lgcc(Px, C, es);
+        const int lg = fft_lgcc(Px, C, es, 8);
         const size_t sh = ((size_t)Px * (1 << lg) + Px) * es;
         dim3 grid((C + (1 << lg) - 1) >> lg, Ny);
         hipLaunchKernelGGL((k_fwd_x<T, In>), grid, blk, sh, st, x, R, Nx, b, pl->fx, lg, gA);
     }
-    {
-        const int lg = fft_lgcc(Py, C, es);
+    mark(2);
+    if (!fused) {
+        const int lg = fft_lgcc(Py, C, es, 16);
         const size_t sh = ((size_t)Py * (1 << lg) + Py) * es;
         dim3 grid((C + (1 << lg) - 1) >> lg, Px);
         hipLaunchKernelGGL((k_fwd_y<T>), grid, blk, sh, st, gA, C, Ny, Px, pl->fy, lg, gB, act, b);
     }
-    {
-        const int RBc = R >= 16 ? 16 : R >= 8 ? 8 : R >= 4 ? 4 : R >= 2 ? 2 : 1;
+    mark(3);
+    if (fused) {
+        const int TP = spec_tp(b);
+        if (TP == 8) {
+            if (QL == 1) launch_spec_rim_e<T, In, Out, 8, 1>(pl, x, y, gA, gB, sh_fused, st);
+            else if (QL == 2) launch_spec_rim_e<T, In, Out, 8, 2>(pl, x, y, gA, gB, sh_fused, st);
+            else launch_spec_rim_e<T, In, Out, 8, 4>(pl, x, y, gA, gB, sh_fused, st);
+        } else {
+            launch_spec_rim_e<T, In, Out, 4, 1>(pl, x, y, gA, gB, sh_fused, st);
+        }
+    } else {
+        int RBc = R >= 16 ? 16 : R >= 8 ? 8 : R >= 4 ? 4 : R >= 2 ? 2 : 1;
+        while (RBc > 1 && (size_t)RBc * b * es > 32768) RBc >>= 1;
         const size_t sh = (size_t)RBc * b * es;
         dim3 grid(Px * Py, (R + RBc - 1) / RBc);
         const cpx<T> *G = OpPtrs<T>::G(pl);
@@ -375,23 +599,28 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
             default: hipLaunchKernelGGL((k_prod<T, 16, 1>), grid, blk, sh, st, G, gB, b, R, gA, act); break;
         }
     }
-    {
-        const int lg = fft_lgcc(Py, C, es);
+    mark(4);
+    if (!fused) {
+        const int lg = fft_lgcc(Py, C, es, 16);
         const size_t sh = ((size_t)Py * (1 << lg) + Py) * es;
         dim3 grid((C + (1 << lg) - 1) >> lg, Px);
         hipLaunchKernelGGL((k_inv_y<T>), grid, blk, sh, st, gA, C, Ny, Px, pl->fy, lg, gB, act, b);
     }
+    mark(5);
     {
-        const int lg = fft_lgcc(Px, C, es);
+        // the fused path leaves Y1 in gB with channel count b (R = 1), the
+        // general path in gB with b * R channels: the same layout
+        const int lg = fft_lgcc(Px, C, es, 8);
         const size_t sh = ((size_t)Px * (1 << lg) + Px) * es;
-        dim3 grid((C + (1 << lg) - 1) >> lg, Ny);
-        hipLaunchKernelGGL((k_inv_x<T, Out>), grid, blk, sh, st, gB, R, Nx, b, pl->fx, lg, y, Nr > 0 ? 1 : 0);
+        const int nchunk = (C + (1 << lg) - 1) >> lg;
+        const int ninv = nchunk * Ny;
+        const int nfin = Nr > 0 ? ((Nr + 3) / 4) * R : 0;
+        hipLaunchKernelGGL((k_inv_x_fin<T, In, Out>), dim3(ninv + nfin), blk, sh, st, gB, R, Nx, b, pl->fx, lg,
+                           nchunk, y, Nr > 0 ? 1 : 0, ninv, reinterpret_cast<const cpx<T> *>(pl->rim_part),
+                           OpPtrs<T>::C(pl), x, pl->N, Nr, pl->rim_nslab);
     }
-    if (Nr > 0) {
-        hipLaunchKernelGGL((k_rim_finish<T, In, Out>), dim3(Nr, R), dim3(64), 0, st,
-                           reinterpret_cast<const cpx<T> *>(pl->rim_part), OpPtrs<T>::C(pl), x, y, R, pl->N, Nr,
-                           pl->rim_nslab);
-    }
+    mark(6);
+    mark(7);
     return hipGetLastError();
 }
 
@@ -403,6 +632,12 @@ hipError_t matvec_fp32(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStr
 }
 hipError_t matvec_fp32_wide(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st) {
     return matvec_launch<float, c128, c128>(pl, x, y, R, st);
+}
+hipError_t matvec_fp64_timed(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st, hipEvent_t *ev) {
+    return matvec_launch<double, c128, c128>(pl, x, y, R, st, ev);
+}
+hipError_t matvec_fp32_timed(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStream_t st, hipEvent_t *ev) {
+    return matvec_launch<float, c64, c64>(pl, x, y, R, st, ev);
 }
 
 // ------------------------------------------------------ plan-time spectrum

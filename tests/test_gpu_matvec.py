@@ -36,7 +36,9 @@ def _matvec_case(torch, prob, X, rim_er=None, which="fp64", ld_pad=0):
 
 CASES = [  # (Nx, Ny, b, Nr, R): ragged b against the 64-lane rows, prime and padded grids
     (4, 4, 16, 24, 1), (1, 1, 8, 0, 1), (1, 5, 4, 3, 2), (7, 2, 3, 0, 1), (5, 3, 33, 10, 3),
-    (3, 4, 70, 5, 2), (17, 9, 8, 20, 1), (2, 3, 100, 7, 5), (9, 9, 96, 72, 1)]
+    (3, 4, 70, 5, 2), (17, 9, 8, 20, 1), (2, 3, 100, 7, 5), (9, 9, 96, 72, 1),
+    # single columns take the fused path: multi-stage y lengths (18 = 2*3*3, 15, 9)
+    (9, 8, 8, 0, 1), (5, 9, 40, 6, 1), (8, 5, 130, 3, 1)]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}b{c[2]}r{c[3]}R{c[4]}" for c in CASES])

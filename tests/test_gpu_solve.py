@@ -133,3 +133,24 @@ def test_solve_config2_full_size(tp, mode):
     rr = oracle.relres(prob, X, V)
     assert info[0]["status"] == 0 and rr[0] <= 1e-8, (info, rr)
     print(f"config2 {mode}: iters={info[0]['iters']} outer={info[0]['outer_iters']} relres={rr[0]:.2e}")
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_solve_graph_replays_deterministic(tp, mode):
+    """Solves replay a captured graph: repeated solves on one plan, with eager
+    operator applications in between, give bit-identical results."""
+    banner(f"solve graph replay determinism {mode}")
+    import torch
+    prob = sa.make_problem(7, 6, 24, 30, 91)
+    V = sa.rhs_random(prob, 2)
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=2, restart=40)
+    v = to_dev(V)
+    ref, info0 = plan.solve(v, mode=mode)
+    ref = ref.cpu().numpy()
+    for rep in range(3):
+        plan.matvec(v)                                  # eager work between replays
+        torch.cuda.synchronize()
+        x, info = plan.solve(v, mode=mode)
+        assert np.array_equal(x.cpu().numpy(), ref), rep
+        assert [i["iters"] for i in info] == [i["iters"] for i in info0]
+    assert np.all(oracle.relres(prob, ref, V) <= 1e-8)
