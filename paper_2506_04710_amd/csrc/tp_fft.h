@@ -22,9 +22,50 @@ __device__ __forceinline__ cpx<T> twid(const cpx<T> *twl, int idx) {
     return w;
 }
 
-// Radix-R DFT of a[0..R) in registers; twl holds exp(-2 pi i k / P), Pr = P / R.
+// cos and sin of 2 pi m / R for m = 0..R-1 (odd R), to 40 digits
+template <int R>
+struct Roots;
+template <>
+struct Roots<3> {
+    static constexpr double c[3] = {1.0, -0.5, -0.5};
+    static constexpr double s[3] = {0.0, 0.8660254037844386467637231707529361834714,
+                                    -0.8660254037844386467637231707529361834714};
+};
+template <>
+struct Roots<5> {
+    static constexpr double c[5] = {1.0, 0.3090169943749474241022934171828190588602,
+                                    -0.8090169943749474241022934171828190588602,
+                                    -0.8090169943749474241022934171828190588602,
+                                    0.3090169943749474241022934171828190588602};
+    static constexpr double s[5] = {0.0, 0.9510565162951535721164393333793821434057,
+                                    0.5877852522924731291687059546390727685977,
+                                    -0.5877852522924731291687059546390727685977,
+                                    -0.9510565162951535721164393333793821434057};
+};
+template <>
+struct Roots<7> {
+    static constexpr double c[7] = {1.0, 0.6234898018587335305250048840042398106323,
+                                    -0.2225209339563144042889025644967947594664,
+                                    -0.9009688679024191262361023195074450511659,
+                                    -0.9009688679024191262361023195074450511659,
+                                    -0.2225209339563144042889025644967947594664,
+                                    0.6234898018587335305250048840042398106323};
+    static constexpr double s[7] = {0.0, 0.7818314824680298087084445266740577502323,
+                                    0.9749279121818236070181316829939312172328,
+                                    0.4338837391175581204757683328483587546100,
+                                    -0.4338837391175581204757683328483587546100,
+                                    -0.9749279121818236070181316829939312172328,
+                                    -0.7818314824680298087084445266740577502323};
+};
+
+// Radix-R DFT of a[0..R) in registers (forward: w = exp(-2 pi i / R)).
+// Odd R pairs inputs q and R - q: with s_q = a_q + a_{R-q}, d_q = a_q - a_{R-q}
+// and t = 2 pi q k / R,
+//   y_k     = a_0 + sum_q (cos t) s_q - i (sin t) d_q
+//   y_{R-k} = a_0 + sum_q (cos t) s_q + i (sin t) d_q
+// (signs of the sine terms swap for the inverse).
 template <typename T, int R, bool INV>
-__device__ __forceinline__ void small_dft(cpx<T> (&a)[R], const cpx<T> *twl, int Pr) {
+__device__ __forceinline__ void small_dft(cpx<T> (&a)[R]) {
     if constexpr (R == 2) {
         cpx<T> t = a[0] - a[1];
         a[0] = a[0] + a[1];
@@ -38,16 +79,39 @@ __device__ __forceinline__ void small_dft(cpx<T> (&a)[R], const cpx<T> *twl, int
         a[1] = t1 + u;
         a[3] = t1 - u;
     } else {
-        cpx<T> y[R];
+        constexpr int H = (R - 1) / 2;
+        cpx<T> sp[H + 1], dm[H + 1];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            cpx<T> s = a[0];
-#pragma unroll
-            for (int q = 1; q < R; ++q) s = cmac(s, twid<T, INV>(twl, ((q * k) % R) * Pr), a[q]);
-            y[k] = s;
+        for (int q = 1; q <= H; ++q) {
+            sp[q] = a[q] + a[R - q];
+            dm[q] = a[q] - a[R - q];
         }
+        cpx<T> y0 = a[0];
 #pragma unroll
-        for (int k = 0; k < R; ++k) a[k] = y[k];
+        for (int q = 1; q <= H; ++q) y0 = y0 + sp[q];
+        cpx<T> lo[H + 1], hi[H + 1];
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            cpx<T> re = a[0], im = mk<T>(0, 0);
+#pragma unroll
+            for (int q = 1; q <= H; ++q) {
+                const T c = (T)Roots<R>::c[(q * k) % R], sn = (T)Roots<R>::s[(q * k) % R];
+                re.x = fma(c, sp[q].x, re.x);
+                re.y = fma(c, sp[q].y, re.y);
+                im.x = fma(sn, dm[q].x, im.x);
+                im.y = fma(sn, dm[q].y, im.y);
+            }
+            // -i * im = (im.y, -im.x); +i * im = (-im.y, im.x)
+            const cpx<T> mi = mk<T>(im.y, -im.x), pi = mk<T>(-im.y, im.x);
+            lo[k] = re + (INV ? pi : mi);
+            hi[k] = re + (INV ? mi : pi);
+        }
+        a[0] = y0;
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            a[k] = lo[k];
+            a[R - k] = hi[k];
+        }
     }
 }
 
@@ -56,7 +120,6 @@ __device__ __forceinline__ void fft_stage(cpx<T> *buf, int lgCC, int P, int L, c
     const int CC = 1 << lgCC;
     const int nb = P / R;
     const int stride = P / (L * R);
-    const int Pr = P / R;
     const int total = nb << lgCC;
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
         const int ch = it & (CC - 1);
@@ -70,7 +133,7 @@ __device__ __forceinline__ void fft_stage(cpx<T> *buf, int lgCC, int P, int L, c
 #pragma unroll
             for (int q = 1; q < R; ++q) a[q] = a[q] * twid<T, INV>(twl, q * j * stride);
         }
-        small_dft<T, R, INV>(a, twl, Pr);
+        small_dft<T, R, INV>(a);
 #pragma unroll
         for (int q = 0; q < R; ++q) buf[((base + q * L) << lgCC) + ch] = a[q];
     }

@@ -58,7 +58,7 @@ struct SlotDec {
 constexpr int kThreads = 256;
 constexpr int kMaxBlocks = 256;        // element ranges per column
 constexpr int kMaxRestart = 512;
-constexpr int kG = 4;                  // basis vectors handled together
+constexpr int kG = 16;                 // basis vectors handled together
 
 struct Eng {
     long Nt;
@@ -120,22 +120,30 @@ __device__ __forceinline__ c128 shfl_xor_c(c128 v, int mk_) {
 }
 __device__ __forceinline__ double cabs2(c128 a) { return a.x * a.x + a.y * a.y; }
 
-// Sums of G values over the block (valid in every thread afterwards).
-template <int G>
-__device__ __forceinline__ void block_sum_g(c128 (&v)[G], c128 *red /* [4][G] LDS */) {
+// Sums over the 64 lanes of a wave of 16 values per lane, by a butterfly that
+// halves the values each lane keeps at every exchange (17 exchanges instead of
+// 16 x 6).  Lane l returns the total of value index (l >> 2) & 15.
+template <int HALF, int MSK>
+__device__ __forceinline__ void tsum_step(c128 (&v)[16], int lane) {
+    const bool hi = (lane & MSK) != 0;
 #pragma unroll
-    for (int msk = 32; msk >= 1; msk >>= 1)
-#pragma unroll
-        for (int q = 0; q < G; ++q) v[q] = v[q] + shfl_xor_c(v[q], msk);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int q = 0; q < G; ++q) red[w * G + q] = v[q];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < G; ++q) v[q] = red[q] + red[G + q] + red[2 * G + q] + red[3 * G + q];
+    for (int q = 0; q < HALF; ++q) {
+        const c128 mine = hi ? v[HALF + q] : v[q];
+        const c128 oth = hi ? v[q] : v[HALF + q];
+        v[q] = mine + shfl_xor_c(oth, MSK);
+    }
 }
+__device__ __forceinline__ c128 wave_tsum16(c128 (&v)[16]) {
+    const int lane = threadIdx.x & 63;
+    tsum_step<8, 32>(v, lane);
+    tsum_step<4, 16>(v, lane);
+    tsum_step<2, 8>(v, lane);
+    tsum_step<1, 4>(v, lane);
+    c128 t = v[0];
+    t = t + shfl_xor_c(t, 2);
+    return t + shfl_xor_c(t, 1);
+}
+
 __device__ __forceinline__ double block_sum_d(double v, double *red /* [4] LDS */) {
 #pragma unroll
     for (int msk = 32; msk >= 1; msk >>= 1) v += __shfl_xor(v, msk, 64);
@@ -171,9 +179,11 @@ __device__ __forceinline__ double reduce_d(const double *P, int nb, double *red)
     return block_sum_d(t, red);
 }
 
-// partial inner products of V_0..V_j with w over this block's element range
+// partial inner products of V_0..V_j with w over this block's element range,
+// 16 basis vectors per pass (16 independent loads per element in flight)
 __device__ __forceinline__ void partial_dots(const Eng &E, int s, int j, const c128 *w, long n0, long n1,
-                                            c128 *P, c128 *red) {
+                                            c128 *P, c128 *red /* [4][16] */) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int i0 = 0; i0 <= j; i0 += kG) {
         c128 acc[kG];
 #pragma unroll
@@ -184,16 +194,17 @@ __device__ __forceinline__ void partial_dots(const Eng &E, int s, int j, const c
             for (int q = 0; q < kG; ++q)
                 if (i0 + q <= j) acc[q] = cmac_conj(acc[q], E.vec(s, i0 + q)[n], wn);
         }
-        block_sum_g<kG>(acc, red);
-        if (threadIdx.x == 0)
-#pragma unroll
-            for (int q = 0; q < kG; ++q)
-                if (i0 + q <= j) P[(long)(i0 + q) * E.nb + blockIdx.x] = acc[q];
+        const c128 t = wave_tsum16(acc);
+        if ((lane & 3) == 0) red[wv * kG + (lane >> 2)] = t;
+        __syncthreads();
+        if (threadIdx.x < kG && i0 + (int)threadIdx.x <= j)
+            P[(long)(i0 + threadIdx.x) * E.nb + blockIdx.x] =
+                red[threadIdx.x] + red[kG + threadIdx.x] + red[2 * kG + threadIdx.x] + red[3 * kG + threadIdx.x];
         __syncthreads();
     }
 }
 
-// w[n] -= sum_i V_i[n] h[i] over the range, four basis vectors per pass;
+// w[n] -= sum_i V_i[n] h[i] over the range, eight basis vectors per pass;
 // returns this thread's share of ||w_new||^2.
 __device__ __forceinline__ double range_update(const Eng &E, int s, int j, c128 *w, long n0, long n1,
                                                const c128 *h) {
@@ -201,12 +212,12 @@ __device__ __forceinline__ double range_update(const Eng &E, int s, int j, c128 
     for (long n = n0 + threadIdx.x; n < n1; n += kThreads) {
         c128 acc = w[n];
         int i = 0;
-        for (; i + 3 <= j; i += 4) {
-            const c128 a0 = E.vec(s, i)[n], a1 = E.vec(s, i + 1)[n], a2 = E.vec(s, i + 2)[n], a3 = E.vec(s, i + 3)[n];
-            acc = acc - a0 * h[i];
-            acc = acc - a1 * h[i + 1];
-            acc = acc - a2 * h[i + 2];
-            acc = acc - a3 * h[i + 3];
+        for (; i + 7 <= j; i += 8) {
+            c128 a[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[q] = E.vec(s, i + q)[n];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc = acc - a[q] * h[i + q];
         }
         for (; i <= j; ++i) acc = acc - E.vec(s, i)[n] * h[i];
         w[n] = acc;

@@ -293,28 +293,56 @@ __device__ __forceinline__ void rim_finish_wave(const cpx<T> *__restrict__ part,
 }
 
 // ------------------------------------------------ fused single-column path
-// Workgroup = (frequency column kx, TP spectrum rows p0..p0+TP-1).  It
+// Workgroup = (frequency column kx, 8 spectrum rows p0..p0+7).  It
 //   1. loads the x-transformed column X1[iy][kx][0..b) (iy < Ny) into LDS and
 //      transforms it along y (all Py frequencies, all b channels);
-//   2. streams the TP x b row panels of the Py spectrum blocks G[kx][ky]:
-//      lane q multiplies G[..][p][q] by xhat[ky][q] and the wave sums the row;
-//      U rows are loaded before any is used (U independent loads per lane);
-//   3. inverse-transforms the TP output channels along y in LDS and writes the
+//   2. streams the 8 x b row panels of the Py spectrum blocks G[kx][ky]
+//      (one contiguous 8*b run per ky): lane l takes row l >> 3 and the VPL
+//      values q in [(l & 7) VPL, (l & 7) VPL + VPL), multiplies them with
+//      xhat[ky][q] and the 8 lanes of the row add up their parts; wave w takes
+//      ky = w, w + 4, ... and keeps the loads of the next U frequencies in
+//      flight while it reduces the current ones (the first group is issued
+//      before the y transform);
+//   3. inverse-transforms the 8 output channels along y in LDS and writes the
 //      rows iy < Ny of Y1.
-// The y transform of the input column is repeated by the b / TP workgroups of
+// The y transform of the input column is repeated by the b / 8 workgroups of
 // a column; it is small next to the spectrum stream.
-template <typename T, int TP, int QL>
+template <typename T>
+__device__ __forceinline__ cpx<T> sum8(cpx<T> v) {
+    v = v + shfl_xor_c(v, 1);
+    v = v + shfl_xor_c(v, 2);
+    return v + shfl_xor_c(v, 4);
+}
+
+template <typename T, int VPL, int U>
 __device__ __forceinline__ void spec_block(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ X1,
                                            cpx<T> *__restrict__ Y1, int b, int Ny, int Px, const FFTDesc &fy,
                                            int lgCC, int blk, char *smem) {
-    constexpr int U = 16 / QL;
-    constexpr int lgTP = TP == 4 ? 2 : TP == 8 ? 3 : 4;
+    constexpr int TP = 8;
     const int P = fy.P, CC = 1 << lgCC;
     const int nchunk = (b + TP - 1) / TP;
     const int kx = blk / nchunk, p0 = (blk - kx * nchunk) * TP;
     cpx<T> *twl = reinterpret_cast<cpx<T> *>(smem);
     cpx<T> *xs = twl + P;          // [Py][CC]
     cpx<T> *ys = xs + P * CC;      // [Py][TP]
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int pl = lane >> 3, qs = (lane & 7) * VPL, p = p0 + pl;
+    const bool prow = p < b;
+    const long kstride = (long)b * b;
+    const cpx<T> *Grow = G + (long)kx * P * kstride + (long)(prow ? p : 0) * b;
+    cpx<T> gc[U][VPL], gn[U][VPL];
+    auto load = [&](cpx<T>(&g)[U][VPL], int ky0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ky = ky0 + u * nw;
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+                const int q = qs + v;
+                g[u][v] = (ky < P && prow && q < b) ? Grow[ky * kstride + q] : mk<T>(0, 0);
+            }
+        }
+    };
+    load(gc, w);
     load_twiddles<T>(twl, fy);
     zero_lds<T>(xs, P * CC);
     __syncthreads();
@@ -324,48 +352,127 @@ __device__ __forceinline__ void spec_block(const cpx<T> *__restrict__ G, const c
     }
     __syncthreads();
     lds_fft<T, false>(xs, lgCC, fy, twl);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    const int nrows = P * TP;
-    const cpx<T> *Gk = G + (long)kx * P * b * b;
-    for (int base = w * U; base < nrows; base += nw * U) {
-        cpx<T> g[U][QL];
+    for (int ky0 = w; ky0 < P; ky0 += nw * U) {
+        const int nxt = ky0 + nw * U;
+        if (nxt < P) load(gn, nxt);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int row = base + u;
-            const int ky = row >> lgTP, p = p0 + (row & (TP - 1));
-#pragma unroll
-            for (int t = 0; t < QL; ++t) {
-                const int q = lane + 64 * t;
-                g[u][t] = (row < nrows && p < b && q < b) ? Gk[((long)ky * b + p) * b + q] : mk<T>(0, 0);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int row = base + u;
-            const int ky = row >> lgTP;
+            const int ky = ky0 + u * nw;
             cpx<T> acc = mk<T>(0, 0);
+            if (ky < P) {
+                const cpx<T> *xk = xs + (ky << lgCC) + qs;
 #pragma unroll
-            for (int t = 0; t < QL; ++t) {
-                const int q = lane + 64 * t;
-                if (q < b && row < nrows) acc = cmac(acc, g[u][t], xs[(ky << lgCC) + q]);
+                for (int v = 0; v < VPL; ++v)
+                    if (qs + v < b) acc = cmac(acc, gc[u][v], xk[v]);
             }
-            acc = wave_sum(acc);
+            acc = sum8(acc);
             // the inverse transform takes its input in digit-reversed slots
-            if (lane == 0 && row < nrows) ys[(fy.perm[ky] << lgTP) + (row & (TP - 1))] = acc;
+            if ((lane & 7) == 0 && ky < P) ys[(fy.perm[ky] << 3) + pl] = acc;
+        }
+        if (nxt < P) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int v = 0; v < VPL; ++v) gc[u][v] = gn[u][v];
         }
     }
     __syncthreads();
-    lds_fft<T, true>(ys, lgTP, fy, twl);
+    lds_fft<T, true>(ys, 3, fy, twl);
     for (int i = threadIdx.x; i < Ny * TP; i += blockDim.x) {
-        const int iy = i >> lgTP, pl = i & (TP - 1), p = p0 + pl;
-        if (p < b) Y1[((long)iy * Px + kx) * b + p] = ys[i];
+        const int iy = i >> 3, pr = i & 7, pp = p0 + pr;
+        if (pp < b) Y1[((long)iy * Px + kx) * b + pp] = ys[i];
+    }
+}
+
+// Rim pass for a single column.  Slab = TE = 64 E element columns x all Nr
+// rows; 16 lanes per row: lane l takes row offset l >> 4 of each group of 4
+// rows and the VE = 4 E columns [(l & 15) VE, (l & 15) VE + VE) of the slab,
+// so a group of 4 rows is 4 contiguous TE-column runs.  Per row the 16 lanes
+// add up sum_e B[row][e] x_A[e] (-> slab partial of y_r); every lane keeps
+// sum_row BE[row][e] x_r[row] for its columns, and those are summed over the
+// row lanes and the waves at the end (-> y_A).  The next group's loads are
+// issued before the current group is used.
+template <typename T, typename In, typename Out, int E, bool NBE>
+__device__ __forceinline__ void rim_block1(const cpx<T> *__restrict__ B, const cpx<T> *__restrict__ BE,
+                                           Cols<const In> x, Cols<Out> y, long N, int Nr,
+                                           cpx<T> *__restrict__ part, int slab, char *smem) {
+    constexpr int VE = 4 * E, TE = 64 * E;
+    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ro = lane >> 4, cs = (lane & 15) * VE;
+    const long e0 = (long)slab * TE;
+    const In *xc = x.col(0);
+    Out *yc = y.col(0);
+    if (!xc || !yc) return;
+    cpx<T> *xr = reinterpret_cast<cpx<T> *>(smem);   // [Nr]
+    cpx<T> *ua = xr + Nr;                               // [nw][TE]
+    for (int i = threadIdx.x; i < Nr; i += blockDim.x) xr[i] = cvt<T>(xc[N + i]);
+    cpx<T> xa[VE], acc[VE];
+#pragma unroll
+    for (int v = 0; v < VE; ++v) {
+        const long e = e0 + cs + v;
+        xa[v] = e < N ? cvt<T>(xc[e]) : mk<T>(0, 0);
+        acc[v] = mk<T>(0, 0);
+    }
+    __syncthreads();
+    cpx<T> gc[VE], gn[VE], ec[NBE ? VE : 1], en[NBE ? VE : 1];
+    auto load = [&](cpx<T>(&g)[VE], cpx<T>(&ge)[NBE ? VE : 1], int row) {
+#pragma unroll
+        for (int v = 0; v < VE; ++v) {
+            const long e = e0 + cs + v;
+            const bool ok = row < Nr && e < N;
+            g[v] = ok ? B[(long)row * N + e] : mk<T>(0, 0);
+            if constexpr (NBE) ge[v] = ok ? BE[(long)row * N + e] : mk<T>(0, 0);
+        }
+    };
+    int row = w * 4 + ro;
+    load(gc, ec, row);
+    for (int g0 = w * 4; g0 < Nr; g0 += nw * 4) {
+        const int nrow = row + nw * 4;
+        const bool more = g0 + nw * 4 < Nr;
+        if (more) load(gn, en, nrow);
+        cpx<T> sr = mk<T>(0, 0);
+        const cpx<T> xrow = row < Nr ? xr[row] : mk<T>(0, 0);
+#pragma unroll
+        for (int v = 0; v < VE; ++v) {
+            sr = cmac(sr, gc[v], xa[v]);
+            acc[v] = cmac(acc[v], NBE ? ec[NBE ? v : 0] : gc[v], xrow);
+        }
+        sr = sr + shfl_xor_c(sr, 8);
+        sr = sum8(sr);
+        if ((lane & 15) == 0 && row < Nr) part[(long)slab * Nr + row] = sr;
+        if (more) {
+#pragma unroll
+            for (int v = 0; v < VE; ++v) {
+                gc[v] = gn[v];
+                if constexpr (NBE) ec[v] = en[v];
+            }
+        }
+        row = nrow;
+    }
+    // sum the four row lanes of each column, then the waves
+#pragma unroll
+    for (int v = 0; v < VE; ++v) {
+        acc[v] = acc[v] + shfl_xor_c(acc[v], 16);
+        acc[v] = acc[v] + shfl_xor_c(acc[v], 32);
+    }
+    if (ro == 0)
+#pragma unroll
+        for (int v = 0; v < VE; ++v) ua[w * TE + cs + v] = acc[v];
+    __syncthreads();
+    for (int el = threadIdx.x; el < TE; el += blockDim.x) {
+        const long e = e0 + el;
+        if (e < N) {
+            cpx<T> t = mk<T>(0, 0);
+            for (int v = 0; v < nw; ++v) t = t + ua[v * TE + el];
+            yc[e] = cvt<typename Out::value_type>(t);
+        }
     }
 }
 
 // Spectrum workgroups and rim workgroups share one launch so that both HBM
 // streams (the spectrum and the dense rim) run together; the two kinds are
 // interleaved in block order.
-template <typename T, typename In, typename Out, int TP, int QL, int E, bool NBE>
+template <typename T, typename In, typename Out, int VPL, int U, int E, bool NBE>
 __global__ void __launch_bounds__(256) k_spec_rim(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ X1,
                                                   cpx<T> *__restrict__ Y1, int b, int Ny, int Px, FFTDesc fy,
                                                   int lgCC, int nspec, const cpx<T> *__restrict__ B,
@@ -386,9 +493,9 @@ __global__ void __launch_bounds__(256) k_spec_rim(const cpx<T> *__restrict__ G, 
     }
     if (spec_id >= 0) {
         if (!cols_live((const void *const *)x.tab, 0, 0)) return;
-        spec_block<T, TP, QL>(G, X1, Y1, b, Ny, Px, fy, lgCC, spec_id, smem_raw);
+        spec_block<T, VPL, U>(G, X1, Y1, b, Ny, Px, fy, lgCC, spec_id, smem_raw);
     } else if constexpr (E > 0) {
-        rim_block<T, In, Out, E, 1, (E >= 4 ? 2 : 8 / E), NBE>(B, BE, x, y, 1, N, Nr, part, rim_id, 0, smem_raw);
+        rim_block1<T, In, Out, E, NBE>(B, BE, x, y, N, Nr, part, rim_id, smem_raw);
     }
 }
 
@@ -472,41 +579,42 @@ static int next_pow2(int v) {
     return p;
 }
 
-// Fused single-column path: rows per workgroup and LDS bytes.
-static int spec_tp(int b) { return b >= 8 ? 8 : 4; }
+// Fused single-column path: LDS bytes.
 static size_t spec_lds(tp_plan pl, size_t es) {
     const int P = pl->Py, CC = next_pow2(pl->b);
-    return ((size_t)P + (size_t)P * CC + (size_t)P * spec_tp(pl->b)) * es;
+    return ((size_t)P + (size_t)P * CC + (size_t)P * 8) * es;
 }
 static size_t rim_lds(tp_plan pl, int RB, size_t es) { return ((size_t)RB * pl->Nr + 4 * (size_t)pl->rim_te * RB) * es; }
 constexpr size_t kLdsLimit = 160 * 1024;
 
-template <typename T, typename In, typename Out, int TP, int QL, int E, bool NBE>
+template <typename T, typename In, typename Out, int VPL, int E, bool NBE>
 static void launch_spec_rim(tp_plan pl, Cols<const In> x, Cols<Out> y, cpx<T> *gA, cpx<T> *gB, size_t sh,
                             hipStream_t st) {
-    const int nchunk = (pl->b + TP - 1) / TP, nspec = pl->Px * nchunk;
+    // rounds kept in flight per wave: fewer for wide rows and for FP64
+    constexpr int U = (sizeof(T) == 8 || VPL > 8) ? 1 : 2;
+    const int nchunk = (pl->b + 7) / 8, nspec = pl->Px * nchunk;
     const int nrim = pl->Nr > 0 ? pl->rim_nslab : 0;
     const int lgCC = ilog2(next_pow2(pl->b));
-    hipLaunchKernelGGL((k_spec_rim<T, In, Out, TP, QL, E, NBE>), dim3(nspec + nrim), dim3(256), sh, st, OpPtrs<T>::G(pl),
-                       gA, gB, pl->b, pl->Ny, pl->Px, pl->fy, lgCC, nspec, OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl), x, y,
-                       pl->N, pl->Nr, reinterpret_cast<cpx<T> *>(pl->rim_part), nrim);
+    hipLaunchKernelGGL((k_spec_rim<T, In, Out, VPL, U, E, NBE>), dim3(nspec + nrim), dim3(256), sh, st,
+                       OpPtrs<T>::G(pl), gA, gB, pl->b, pl->Ny, pl->Px, pl->fy, lgCC, nspec, OpPtrs<T>::B(pl),
+                       OpPtrs<T>::BE(pl), x, y, pl->N, pl->Nr, reinterpret_cast<cpx<T> *>(pl->rim_part), nrim);
 }
 
-template <typename T, typename In, typename Out, int TP, int QL>
+template <typename T, typename In, typename Out, int VPL>
 static void launch_spec_rim_e(tp_plan pl, Cols<const In> x, Cols<Out> y, cpx<T> *gA, cpx<T> *gB, size_t sh,
                               hipStream_t st) {
     if (pl->Nr == 0) {
-        launch_spec_rim<T, In, Out, TP, QL, 0, false>(pl, x, y, gA, gB, sh, st);
+        launch_spec_rim<T, In, Out, VPL, 0, false>(pl, x, y, gA, gB, sh, st);
         return;
     }
     const bool nbe = OpPtrs<T>::BE(pl) != nullptr;
     switch ((pl->rim_te / 64) * 2 + (nbe ? 1 : 0)) {
-        case 2: launch_spec_rim<T, In, Out, TP, QL, 1, false>(pl, x, y, gA, gB, sh, st); break;
-        case 3: launch_spec_rim<T, In, Out, TP, QL, 1, true>(pl, x, y, gA, gB, sh, st); break;
-        case 4: launch_spec_rim<T, In, Out, TP, QL, 2, false>(pl, x, y, gA, gB, sh, st); break;
-        case 5: launch_spec_rim<T, In, Out, TP, QL, 2, true>(pl, x, y, gA, gB, sh, st); break;
-        case 8: launch_spec_rim<T, In, Out, TP, QL, 4, false>(pl, x, y, gA, gB, sh, st); break;
-        default: launch_spec_rim<T, In, Out, TP, QL, 4, true>(pl, x, y, gA, gB, sh, st); break;
+        case 2: launch_spec_rim<T, In, Out, VPL, 1, false>(pl, x, y, gA, gB, sh, st); break;
+        case 3: launch_spec_rim<T, In, Out, VPL, 1, true>(pl, x, y, gA, gB, sh, st); break;
+        case 4: launch_spec_rim<T, In, Out, VPL, 2, false>(pl, x, y, gA, gB, sh, st); break;
+        case 5: launch_spec_rim<T, In, Out, VPL, 2, true>(pl, x, y, gA, gB, sh, st); break;
+        case 8: launch_spec_rim<T, In, Out, VPL, 4, false>(pl, x, y, gA, gB, sh, st); break;
+        default: launch_spec_rim<T, In, Out, VPL, 4, true>(pl, x, y, gA, gB, sh, st); break;
     }
 }
 
@@ -555,7 +663,6 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     auto mark = [&](int i) {
         if (ev) hipEventRecord(ev[i], st);
     };
-    const int QL = b <= 64 ? 1 : b <= 128 ? 2 : 4;
     const size_t sh_fused = std::max(spec_lds(pl, es), Nr > 0 ? rim_lds(pl, 1, es) : (size_t)0);
     const bool fused = R == 1 && sh_fused <= kLdsLimit;
 
@@ -577,14 +684,14 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     }
     mark(3);
     if (fused) {
-        const int TP = spec_tp(b);
-        if (TP == 8) {
-            if (QL == 1) launch_spec_rim_e<T, In, Out, 8, 1>(pl, x, y, gA, gB, sh_fused, st);
-            else if (QL == 2) launch_spec_rim_e<T, In, Out, 8, 2>(pl, x, y, gA, gB, sh_fused, st);
-            else launch_spec_rim_e<T, In, Out, 8, 4>(pl, x, y, gA, gB, sh_fused, st);
-        } else {
-            launch_spec_rim_e<T, In, Out, 4, 1>(pl, x, y, gA, gB, sh_fused, st);
-        }
+        const int vpl = (b + 7) / 8;
+        if (vpl <= 2) launch_spec_rim_e<T, In, Out, 2>(pl, x, y, gA, gB, sh_fused, st);
+        else if (vpl <= 4) launch_spec_rim_e<T, In, Out, 4>(pl, x, y, gA, gB, sh_fused, st);
+        else if (vpl <= 6) launch_spec_rim_e<T, In, Out, 6>(pl, x, y, gA, gB, sh_fused, st);
+        else if (vpl <= 8) launch_spec_rim_e<T, In, Out, 8>(pl, x, y, gA, gB, sh_fused, st);
+        else if (vpl <= 12) launch_spec_rim_e<T, In, Out, 12>(pl, x, y, gA, gB, sh_fused, st);
+        else if (vpl <= 16) launch_spec_rim_e<T, In, Out, 16>(pl, x, y, gA, gB, sh_fused, st);
+        else launch_spec_rim_e<T, In, Out, 32>(pl, x, y, gA, gB, sh_fused, st);
     } else {
         int RBc = R >= 16 ? 16 : R >= 8 ? 8 : R >= 4 ? 4 : R >= 2 ? 2 : 1;
         while (RBc > 1 && (size_t)RBc * b * es > 32768) RBc >>= 1;
