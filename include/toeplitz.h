@@ -169,7 +169,8 @@ void toeplitz_solve_opts_default(tp_solve_opts *opts);
  * opts NULL = defaults.  The call synchronises hip_stream (the host reads the
  * convergence scalars).  Returns TP_OK if every column met tol, TP_E_NOCONV /
  * TP_E_BREAKDOWN otherwise (x then holds each column's best iterate and info is
- * filled), TP_E_INVAL / TP_E_UNSUPPORTED / TP_E_HIP on errors.
+ * filled), TP_E_INVAL / TP_E_UNSUPPORTED / TP_E_HIP on errors.  Solves are
+ * limited to Nt <= 262144 unknowns (TP_E_UNSUPPORTED beyond).
  */
 tp_status toeplitz_solve(tp_plan p, const void *v, long ldv, void *x, long ldx, int nrhs,
                          const tp_solve_opts *opts, tp_solve_info *info, void *hip_stream);

@@ -55,10 +55,17 @@ struct SlotDec {
     double est, nrm;
 };
 
-constexpr int kThreads = 256;
-constexpr int kMaxBlocks = 256;        // element ranges per column
+// Vector kernels use 1024-thread blocks: 256 element lanes x 4 groups of
+// basis vectors (group g takes V_i with i = g mod 4), so one pass issues up to
+// 16 independent loads per thread and needs a single round of memory latency.
+constexpr int kThreads = 1024;
+constexpr int kLanes = 256;
+constexpr int kGroups = 4;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxBlocks = 512;        // element ranges per column
 constexpr int kMaxRestart = 512;
-constexpr int kG = 16;                 // basis vectors handled together
+constexpr int kG = 16;                 // basis vectors per group and pass
+constexpr int kMaxEPT = 2;             // element rounds of 256 per block (Nt <= 262144)
 
 struct Eng {
     long Nt;
@@ -144,30 +151,41 @@ __device__ __forceinline__ c128 wave_tsum16(c128 (&v)[16]) {
     return t + shfl_xor_c(t, 1);
 }
 
-__device__ __forceinline__ double block_sum_d(double v, double *red /* [4] LDS */) {
+__device__ __forceinline__ double block_sum_d(double v, double *red /* [kWaves] LDS */) {
 #pragma unroll
     for (int msk = 32; msk >= 1; msk >>= 1) v += __shfl_xor(v, msk, 64);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
-    const double t = red[0] + red[1] + red[2] + red[3];
+    double t = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += red[i];
     __syncthreads();
     return t;
 }
 
-// h[i] = sum_b P[i][b], i <= j, for every i in parallel: groups of 8 threads
-// share one i and sum a strided slice of the nb partials, then combine.
+// h[i] = sum_b P[i][b], i <= j: 32 threads per i (32 i per pass of 1024
+// threads); thread k of an i loads partials b = k, k + 32, ... (at most 16,
+// all issued before any is added) and the 32 threads combine by shuffles, so
+// a pass costs one round of memory latency.  Fixed order: deterministic.
 __device__ __forceinline__ void reduce_partials(const c128 *P, int j, int nb, c128 *h /* LDS */) {
-    const int sub = threadIdx.x & 7, grp = threadIdx.x >> 3;   // 32 groups
-    for (int i0 = 0; i0 <= j; i0 += 32) {
-        const int i = i0 + grp;
-        c128 t = c128{0, 0};
-        if (i <= j)
-            for (int b = sub; b < nb; b += 8) t = t + P[(long)i * nb + b];
+    constexpr int TPI = 32, MAXL = kMaxBlocks / TPI;
+    const int k = threadIdx.x & (TPI - 1), ii = threadIdx.x / TPI;
+    for (int i0 = 0; i0 <= j; i0 += kThreads / TPI) {
+        const int i = i0 + ii;
+        c128 v[MAXL];
 #pragma unroll
-        for (int msk = 4; msk >= 1; msk >>= 1) t = t + shfl_xor_c(t, msk);
-        if (sub == 0 && i <= j) h[i] = t;
+        for (int u = 0; u < MAXL; ++u) {
+            const int bb = k + TPI * u;
+            v[u] = (i <= j && bb < nb) ? P[(long)i * nb + bb] : c128{0, 0};
+        }
+        c128 t = v[0];
+#pragma unroll
+        for (int u = 1; u < MAXL; ++u) t = t + v[u];
+#pragma unroll
+        for (int msk = TPI / 2; msk >= 1; msk >>= 1) t = t + shfl_xor_c(t, msk);
+        if (k == 0 && i <= j) h[i] = t;
     }
     __syncthreads();
 }
@@ -179,49 +197,102 @@ __device__ __forceinline__ double reduce_d(const double *P, int nb, double *red)
     return block_sum_d(t, red);
 }
 
-// partial inner products of V_0..V_j with w over this block's element range,
-// 16 basis vectors per pass (16 independent loads per element in flight)
-__device__ __forceinline__ void partial_dots(const Eng &E, int s, int j, const c128 *w, long n0, long n1,
-                                            c128 *P, c128 *red /* [4][16] */) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i0 = 0; i0 <= j; i0 += kG) {
+// Element n of this block's range for lane l and round e (rounds of 256).
+__device__ __forceinline__ long elem(const Eng &E, int e) {
+    return (long)blockIdx.x * E.span + (long)e * kLanes + (threadIdx.x & (kLanes - 1));
+}
+__device__ __forceinline__ int rounds(const Eng &E) { return (int)((E.span + kLanes - 1) / kLanes); }
+
+// partial inner products P[i][block] = sum_{n in range} conj(V_i[n]) w[n],
+// i <= j; group g takes i = g, g + 4, ... (16 per pass, one load each).
+// wv[e] holds w at this thread's element of round e (0 outside the range).
+__device__ __forceinline__ void partial_dots(const Eng &E, int s, int j, const c128 (&wv)[kMaxEPT], long n1, c128 *P,
+                                            c128 *red /* [kWaves][kG] */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = threadIdx.x >> 8;
+    const int nr = rounds(E);
+    for (int i0 = 0; i0 <= j; i0 += kGroups * kG) {
         c128 acc[kG];
 #pragma unroll
         for (int q = 0; q < kG; ++q) acc[q] = c128{0, 0};
-        for (long n = n0 + threadIdx.x; n < n1; n += kThreads) {
-            const c128 wn = w[n];
 #pragma unroll
-            for (int q = 0; q < kG; ++q)
-                if (i0 + q <= j) acc[q] = cmac_conj(acc[q], E.vec(s, i0 + q)[n], wn);
+        for (int e = 0; e < kMaxEPT; ++e) {
+            const long n = elem(E, e);
+            if (e >= nr || n >= n1) break;
+            const c128 wn = wv[e];
+#pragma unroll
+            for (int q = 0; q < kG; ++q) {
+                const int i = i0 + g + kGroups * q;
+                if (i <= j) acc[q] = cmac_conj(acc[q], E.vec(s, i)[n], wn);
+            }
         }
         const c128 t = wave_tsum16(acc);
-        if ((lane & 3) == 0) red[wv * kG + (lane >> 2)] = t;
+        if ((lane & 3) == 0) red[wave * kG + (lane >> 2)] = t;
         __syncthreads();
-        if (threadIdx.x < kG && i0 + (int)threadIdx.x <= j)
-            P[(long)(i0 + threadIdx.x) * E.nb + blockIdx.x] =
-                red[threadIdx.x] + red[kG + threadIdx.x] + red[2 * kG + threadIdx.x] + red[3 * kG + threadIdx.x];
+        if (threadIdx.x < kGroups * kG) {
+            const int gg = threadIdx.x / kG, q = threadIdx.x - gg * kG, i = i0 + gg + kGroups * q;
+            if (i <= j) {
+                const int w0 = gg * (kLanes / 64);
+                c128 tt = red[w0 * kG + q];
+#pragma unroll
+                for (int k = 1; k < kLanes / 64; ++k) tt = tt + red[(w0 + k) * kG + q];
+                P[(long)i * E.nb + blockIdx.x] = tt;
+            }
+        }
         __syncthreads();
     }
 }
 
-// w[n] -= sum_i V_i[n] h[i] over the range, eight basis vectors per pass;
-// returns this thread's share of ||w_new||^2.
-__device__ __forceinline__ double range_update(const Eng &E, int s, int j, c128 *w, long n0, long n1,
-                                               const c128 *h) {
-    double nn = 0;
-    for (long n = n0 + threadIdx.x; n < n1; n += kThreads) {
-        c128 acc = w[n];
-        int i = 0;
-        for (; i + 7 <= j; i += 8) {
-            c128 a[8];
+// sum_i V_i[n] c[i] over i <= j at this thread's element of round e: each
+// group adds its basis vectors, the four group partials meet in LDS.  Every
+// thread of group 0 returns the total for its element; other groups get 0.
+__device__ __forceinline__ c128 basis_combo(const Eng &E, int s, int j, long n, long n1, const c128 *c,
+                                           c128 *part /* [kGroups][kLanes] */) {
+    const int g = threadIdx.x >> 8, l = threadIdx.x & (kLanes - 1);
+    c128 acc = c128{0, 0};
+    if (n < n1) {
+        int i = g;
+        for (; i + kGroups * 3 <= j; i += kGroups * 4) {
+            c128 a[4];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[q] = E.vec(s, i + q)[n];
+            for (int q = 0; q < 4; ++q) a[q] = E.vec(s, i + kGroups * q)[n];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc = acc - a[q] * h[i + q];
+            for (int q = 0; q < 4; ++q) acc = cmac(acc, a[q], c[i + kGroups * q]);
         }
-        for (; i <= j; ++i) acc = acc - E.vec(s, i)[n] * h[i];
-        w[n] = acc;
-        nn += cabs2(acc);
+        for (; i <= j; i += kGroups) acc = cmac(acc, E.vec(s, i)[n], c[i]);
+    }
+    part[g * kLanes + l] = acc;
+    __syncthreads();
+    c128 t = c128{0, 0};
+    if (g == 0) t = part[l] + part[kLanes + l] + part[2 * kLanes + l] + part[3 * kLanes + l];
+    __syncthreads();
+    return t;
+}
+
+// w -= sum_i V_i h_i over the range; wv[e] receives the new w at this
+// thread's elements (all groups, through LDS); returns this thread's share of
+// ||w_new||^2 (group 0 only).
+// The stored w is the new w times out_scale.
+__device__ __forceinline__ double range_update(const Eng &E, int s, int j, c128 *w, long n1, const c128 *h,
+                                               c128 (&wv)[kMaxEPT], c128 *part, c128 *wl /* [kLanes] */,
+                                               double out_scale) {
+    const int g = threadIdx.x >> 8, l = threadIdx.x & (kLanes - 1);
+    const int nr = rounds(E);
+    double nn = 0;
+#pragma unroll
+    for (int e = 0; e < kMaxEPT; ++e) {
+        wv[e] = c128{0, 0};
+        if (e >= nr) continue;
+        const long n = elem(E, e);
+        const c128 sum = basis_combo(E, s, j, n, n1, h, part);
+        if (g == 0 && n < n1) {
+            const c128 wn = w[n] - sum;
+            w[n] = scale(wn, out_scale);
+            wl[l] = wn;
+            nn += cabs2(wn);
+        }
+        __syncthreads();
+        wv[e] = (n < n1) ? wl[l] : c128{0, 0};
+        __syncthreads();
     }
     return nn;
 }
@@ -284,7 +355,7 @@ __device__ __forceinline__ Next transition(const Eng &E, int s, const SlotState 
 }
 
 __global__ void __launch_bounds__(kThreads) k_commit(Eng E, int par) {
-    __shared__ double redd[4];
+    __shared__ double redd[kWaves];
     const int s = blockIdx.y;
     const SlotState P = E.st[(par ^ 1) * E.nslots + s];
     const Next nx = transition(E, s, P, redd);
@@ -320,18 +391,27 @@ __global__ void __launch_bounds__(kThreads) k_commit(Eng E, int par) {
 
 // ------------------------------------------------------------------ CGS2
 __global__ void __launch_bounds__(kThreads) k_dots(Eng E, int par) {
-    __shared__ c128 red[4 * kG];
+    __shared__ c128 red[kWaves * kG];
     const int s = blockIdx.y;
     const SlotState S = E.st[par * E.nslots + s];
     if (S.phase != PH_ARN) return;
-    const long n0 = (long)blockIdx.x * E.span, n1 = min(E.Nt, n0 + E.span);
-    partial_dots(E, s, S.j, E.vec(s, S.j + 1), n0, n1, E.P1 + (long)s * (E.m + 1) * E.nb, red);
+    const c128 *w = E.vec(s, S.j + 1);
+    c128 wv[kMaxEPT];
+    const int nr = rounds(E);
+#pragma unroll
+    for (int e = 0; e < kMaxEPT; ++e) {
+        const long n = elem(E, e);
+        wv[e] = (e < nr && n < E.Nt) ? w[n] : c128{0, 0};
+    }
+    partial_dots(E, s, S.j, wv, E.Nt, E.P1 + (long)s * (E.m + 1) * E.nb, red);
 }
 
 __global__ void __launch_bounds__(kThreads) k_orth1(Eng E, int par) {
     __shared__ c128 h[kMaxRestart + 1];
-    __shared__ c128 red[4 * kG];
-    __shared__ double redd[4];
+    __shared__ c128 red[kWaves * kG];
+    __shared__ c128 part[kGroups * kLanes];
+    __shared__ c128 wl[kLanes];
+    __shared__ double redd[kWaves];
     const int s = blockIdx.y;
     const SlotState S = E.st[par * E.nslots + s];
     if (S.phase != PH_ARN) return;
@@ -339,17 +419,19 @@ __global__ void __launch_bounds__(kThreads) k_orth1(Eng E, int par) {
     reduce_partials(E.P1 + (long)s * (E.m + 1) * E.nb, j, E.nb, h);
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i <= j; i += kThreads) E.h1[(long)s * (E.m + 1) + i] = h[i];
-    const long n0 = (long)blockIdx.x * E.span, n1 = min(E.Nt, n0 + E.span);
     c128 *w = E.vec(s, j + 1);
-    double nn = range_update(E, s, j, w, n0, n1, h);
+    c128 wv[kMaxEPT];
+    double nn = range_update(E, s, j, w, E.Nt, h, wv, part, wl, 1.0);
     nn = block_sum_d(nn, redd);
     if (threadIdx.x == 0) E.PN[(long)s * E.nb + blockIdx.x] = nn;
-    partial_dots(E, s, j, w, n0, n1, E.P2 + (long)s * (E.m + 1) * E.nb, red);
+    partial_dots(E, s, j, wv, E.Nt, E.P2 + (long)s * (E.m + 1) * E.nb, red);
 }
 
 __global__ void __launch_bounds__(kThreads) k_orth2(Eng E, int par) {
     __shared__ c128 h[kMaxRestart + 1];
-    __shared__ double redd[4];
+    __shared__ c128 part[kGroups * kLanes];
+    __shared__ c128 wl[kLanes];
+    __shared__ double redd[kWaves];
     const int s = blockIdx.y;
     const SlotState S = E.st[par * E.nslots + s];
     if (S.phase != PH_ARN) return;
@@ -360,11 +442,10 @@ __global__ void __launch_bounds__(kThreads) k_orth2(Eng E, int par) {
     for (int i = 0; i <= j; ++i) hh += cabs2(h[i]);
     const double ww = reduce_d(E.PN + (long)s * E.nb, E.nb, redd);
     const double nrm = sqrt(fmax(ww - hh, 0.0));
-    const long n0 = (long)blockIdx.x * E.span, n1 = min(E.Nt, n0 + E.span);
-    c128 *w = E.vec(s, j + 1);
-    range_update(E, s, j, w, n0, n1, h);
     const double sc = nrm > 1e-300 ? 1.0 / nrm : 0.0;
-    for (long n = n0 + threadIdx.x; n < n1; n += kThreads) w[n] = scale(w[n], sc);
+    c128 *w = E.vec(s, j + 1);
+    c128 wv[kMaxEPT];
+    range_update(E, s, j, w, E.Nt, h, wv, part, wl, sc);
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     // Hessenberg column j: h1 + h2, then the previous rotations and a new one
     const c128 *h1 = E.h1 + (long)s * (m + 1);
@@ -414,7 +495,8 @@ __global__ void __launch_bounds__(kThreads) k_orth2(Eng E, int par) {
 // the true residual r = v - W for residual columns.
 __global__ void __launch_bounds__(kThreads) k_tail(Eng E, int par) {
     __shared__ c128 ys[kMaxRestart];
-    __shared__ double redd[4];
+    __shared__ c128 part[kGroups * kLanes];
+    __shared__ double redd[kWaves];
     const int s = blockIdx.y;
     const SlotState S = E.st[par * E.nslots + s];
     const long n0 = (long)blockIdx.x * E.span, n1 = min(E.Nt, n0 + E.span);
@@ -440,10 +522,13 @@ __global__ void __launch_bounds__(kThreads) k_tail(Eng E, int par) {
             __syncthreads();
         }
         c128 *x = C.x;
-        for (long n = n0 + threadIdx.x; n < n1; n += kThreads) {
-            c128 acc = x[n];
-            for (int i = 0; i < k; ++i) acc = cmac(acc, E.vec(s, i)[n], ys[i]);
-            x[n] = acc;
+        const int g0 = threadIdx.x >> 8, nr = rounds(E);
+#pragma unroll
+        for (int e = 0; e < kMaxEPT; ++e) {
+            if (e >= nr) break;
+            const long n = elem(E, e);
+            const c128 sum = basis_combo(E, s, k - 1, n, E.Nt, ys, part);
+            if (g0 == 0 && n < E.Nt) x[n] = x[n] + sum;
         }
     } else if (S.phase == PH_RES) {
         const c128 *v = C.v, *Wz = E.W + (long)s * E.Nt;
@@ -557,16 +642,23 @@ static hipError_t step_graph(tp_plan pl, const Eng &E, hipGraphExec_t *out) {
     return hipSuccess;
 }
 
+long solver_max_nt() { return (long)kLanes * kMaxEPT * kMaxBlocks; }
+
 tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int nrhs, const tp_solve_opts &o,
                     tp_solve_info *info, hipStream_t st) {
     const long Nt = pl->Nt;
+    if (Nt > solver_max_nt())
+        return fail(TP_E_UNSUPPORTED, "solves are limited to Nt <= " + std::to_string(solver_max_nt()));
     EngLayout L = eng_layout(Nt, pl->restart, pl->max_rhs);
     char *wsb = (char *)pl->rim_part + a256((size_t)pl->rim_nslab * (pl->Nr ? pl->Nr : 1) * pl->max_rhs * 16);
     Eng E;
     E.Nt = Nt;
     E.m = o.restart;        // a shorter restart than the plan's uses a prefix of each region
-    E.nb = (int)std::min<long>(kMaxBlocks, (Nt + kThreads - 1) / kThreads);
-    E.span = (Nt + E.nb - 1) / E.nb;
+    {
+        const long ept = (Nt + (long)kLanes * kMaxBlocks - 1) / ((long)kLanes * kMaxBlocks);
+        E.span = (long)kLanes * ept;
+        E.nb = (int)((Nt + E.span - 1) / E.span);
+    }
     E.mixed = o.mode == TP_MIXED;
     E.nslots = nrhs;
     E.st = (SlotState *)(wsb + L.st);
