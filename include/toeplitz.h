@@ -176,6 +176,42 @@ tp_status toeplitz_solve(tp_plan p, const void *v, long ldv, void *x, long ldx, 
                          const tp_solve_opts *opts, tp_solve_info *info, void *hip_stream);
 
 /*
+ * Continuous batching (serving): a plan runs one GMRES engine with max_rhs
+ * slots.  Each slot solves one column Z x = v independently (same method and
+ * options as toeplitz_solve); columns are admitted into free slots and
+ * released after they finish while the other slots keep iterating, so
+ * requests that arrive while others are running join the running batch.
+ * All work runs on the plan's own stream (default priority); the calls below
+ * only enqueue work, except batch_poll with wait = 1 and batch_end.
+ *
+ * toeplitz_batch_begin: start the engine (opts as for toeplitz_solve; NULL =
+ *   defaults); every slot starts idle.  Errors as toeplitz_solve.
+ * toeplitz_batch_admit: put column v (device complex128, Nt contiguous values)
+ *   into an idle or released slot; x (device complex128, Nt values) receives
+ *   the solution (x0_given = 1: x holds the initial guess).  The engine waits
+ *   for work already enqueued on hip_stream (so v may be written there).  v and
+ *   x must stay valid until the slot is released.
+ * toeplitz_batch_release: return a slot to idle (after it finished, or to
+ *   cancel it).
+ * toeplitz_batch_step: enqueue ngraphs rounds of two GMRES super-steps for
+ *   all slots, then an asynchronous copy of the slot states.
+ * toeplitz_batch_poll: slot states after the latest (lag = 0) or the previous
+ *   (lag = 1) batch_step: phases[max_rhs] = 0 idle, 1 running, 2 finished, and
+ *   info[max_rhs] (status/iters/relres, final once finished); with wait = 0
+ *   returns TP_E_NOCONV if that step has not completed yet (no error).  Once a
+ *   slot reads finished, its x is complete in device memory.
+ * toeplitz_batch_end: wait for the engine's stream and stop the batch
+ *   (toeplitz_solve is refused on the plan while a batch is active).
+ */
+tp_status toeplitz_batch_begin(tp_plan p, const tp_solve_opts *opts);
+tp_status toeplitz_batch_admit(tp_plan p, int slot, const void *v, void *x, double tol, int x0_given,
+                               void *hip_stream);
+tp_status toeplitz_batch_release(tp_plan p, int slot);
+tp_status toeplitz_batch_step(tp_plan p, int ngraphs);
+tp_status toeplitz_batch_poll(tp_plan p, int lag, int wait, int *phases, tp_solve_info *info);
+tp_status toeplitz_batch_end(tp_plan p);
+
+/*
  * Copy one block of the stored spectrum to the host (the b x b matrix at
  * frequency (kx, ky), row-major; complex128 for TP_FP64, complex64 for TP_FP32).
  * It equals (1/(Px Py)) sum_{m,n} Z_{m,n} exp(-2 pi i (kx m / Px + ky n / Py)).

@@ -22,7 +22,8 @@ PREC = {"fp64": TP_FP64, "fp32": TP_FP32, "mixed": TP_MIXED}
 EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", "toeplitz_matvec",
            "toeplitz_matvec_profile",
            "toeplitz_solve_opts_default", "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_plan_destroy",
-           "toeplitz_last_error")
+           "toeplitz_last_error", "toeplitz_batch_begin", "toeplitz_batch_admit", "toeplitz_batch_release",
+           "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end")
 
 
 class PlanDesc(ctypes.Structure):
@@ -73,12 +74,19 @@ def lib():
         L.toeplitz_solve.argtypes = [vp, vp, cl, vp, cl, ci, ctypes.POINTER(SolveOpts),
                                      ctypes.POINTER(SolveInfo), vp]
         L.toeplitz_plan_spectrum.argtypes = [vp, ci, ci, ci, vp]
+        L.toeplitz_batch_begin.argtypes = [vp, ctypes.POINTER(SolveOpts)]
+        L.toeplitz_batch_admit.argtypes = [vp, ci, vp, vp, ctypes.c_double, ci, vp]
+        L.toeplitz_batch_release.argtypes = [vp, ci]
+        L.toeplitz_batch_step.argtypes = [vp, ci]
+        L.toeplitz_batch_poll.argtypes = [vp, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(SolveInfo)]
+        L.toeplitz_batch_end.argtypes = [vp]
         L.toeplitz_plan_destroy.argtypes = [vp]
         L.toeplitz_plan_destroy.restype = None
         L.toeplitz_last_error.restype = ctypes.c_char_p
         for name in ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", "toeplitz_matvec",
                      "toeplitz_matvec_profile",
-                     "toeplitz_solve", "toeplitz_plan_spectrum"):
+                     "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_batch_begin", "toeplitz_batch_admit",
+                     "toeplitz_batch_release", "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib

@@ -410,6 +410,63 @@ tp_status toeplitz_solve(tp_plan p, const void *v, long ldv, void *x, long ldx, 
     return solve_run(p, (const c128 *)v, ldv, (c128 *)x, ldx, nrhs, o, info, (hipStream_t)hip_stream);
 }
 
+static tp_status check_batch_opts(tp_plan p, tp_solve_opts &o, const tp_solve_opts *opts) {
+    toeplitz_solve_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.restart <= 0) o.restart = p->restart;
+    if (o.restart > p->restart) return fail(TP_E_INVAL, "restart exceeds the plan's restart");
+    if (!(o.tol > 0) || o.max_iter < 1 || o.max_outer < 1) return fail(TP_E_INVAL, "bad tol / max_iter / max_outer");
+    if (o.mode == TP_FP64) {
+        if (!p->G64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 operator");
+    } else if (o.mode == TP_MIXED) {
+        if (!p->G64 || !p->G32) return fail(TP_E_UNSUPPORTED, "mixed solves need a TP_MIXED plan");
+        if (!(o.inner_tol > 0 && o.inner_tol < 1)) return fail(TP_E_INVAL, "inner_tol must be in (0, 1)");
+    } else {
+        return fail(TP_E_INVAL, "solve mode must be TP_FP64 or TP_MIXED");
+    }
+    return TP_OK;
+}
+
+tp_status toeplitz_batch_begin(tp_plan p, const tp_solve_opts *opts) {
+    if (!p) return fail(TP_E_INVAL, "plan is NULL");
+    tp_solve_opts o;
+    tp_status s = check_batch_opts(p, o, opts);
+    if (s != TP_OK) return s;
+    return batch_begin(p, o);
+}
+
+tp_status toeplitz_batch_admit(tp_plan p, int slot, const void *v, void *x, double tol, int x0_given,
+                               void *hip_stream) {
+    if (!p) return fail(TP_E_INVAL, "plan is NULL");
+    hipStream_t cs = solver_stream(p);
+    if (!cs) return fail(TP_E_INVAL, "no active batch on this plan");
+    hipError_t e;
+    // the engine stream waits for the caller's pending writes of v (and x0)
+    if ((e = hipEventRecord(p->ev[0], (hipStream_t)hip_stream)) || (e = hipStreamWaitEvent(cs, p->ev[0], 0)))
+        return hip_fail(e, "batch admit ordering");
+    return batch_admit(p, slot, (const c128 *)v, (c128 *)x, tol, x0_given);
+}
+
+tp_status toeplitz_batch_release(tp_plan p, int slot) {
+    if (!p) return fail(TP_E_INVAL, "plan is NULL");
+    return batch_release(p, slot);
+}
+
+tp_status toeplitz_batch_step(tp_plan p, int ngraphs) {
+    if (!p) return fail(TP_E_INVAL, "plan is NULL");
+    return batch_step(p, ngraphs);
+}
+
+tp_status toeplitz_batch_poll(tp_plan p, int lag, int wait, int *phases, tp_solve_info *info) {
+    if (!p) return fail(TP_E_INVAL, "plan is NULL");
+    return batch_poll(p, lag, wait, phases, info);
+}
+
+tp_status toeplitz_batch_end(tp_plan p) {
+    if (!p) return fail(TP_E_INVAL, "plan is NULL");
+    return batch_end(p);
+}
+
 void toeplitz_plan_destroy(tp_plan p) {
     if (!p) return;
     solver_release(p);

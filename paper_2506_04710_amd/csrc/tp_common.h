@@ -125,4 +125,8 @@ struct tp_plan_s {
     };
     GraphEntry graphs[8] = {};
     int ngraphs = 0;
+    // continuous batching: host record of the engine and pinned staging for
+    // slot admission / release copies
+    void *batch = nullptr;
+    void *host_stage = nullptr;
 };

@@ -578,6 +578,16 @@ static hipError_t super_step(tp_plan pl, const Eng &E, int par, hipStream_t st) 
 
 constexpr int kStepsPerGraph = 2;     // one super-step per state parity
 
+// Host-side record of the continuous-batching engine of a plan.
+struct BatchEngine {
+    Eng E;
+    int active = 0;
+    std::vector<SlotConst> cst;      // per-slot constants (host copy)
+    hipGraphExec_t gexec = nullptr;
+    int pending = 0;
+    long nstep = 0;                  // batch_step calls since batch_begin
+};
+
 void solver_release(tp_plan pl) {
     for (int i = 0; i < pl->ngraphs; ++i) hipGraphExecDestroy(pl->graphs[i].exec);
     pl->ngraphs = 0;
@@ -594,6 +604,12 @@ void solver_release(tp_plan pl) {
         hipHostFree(pl->host_status);
         pl->host_status = nullptr;
     }
+    if (pl->host_stage) {
+        hipHostFree(pl->host_stage);
+        pl->host_stage = nullptr;
+    }
+    delete static_cast<BatchEngine *>(pl->batch);
+    pl->batch = nullptr;
 }
 
 static hipError_t solver_resources(tp_plan pl) {
@@ -644,23 +660,21 @@ static hipError_t step_graph(tp_plan pl, const Eng &E, hipGraphExec_t *out) {
 
 long solver_max_nt() { return (long)kLanes * kMaxEPT * kMaxBlocks; }
 
-tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int nrhs, const tp_solve_opts &o,
-                    tp_solve_info *info, hipStream_t st) {
+// The engine's device regions for `nslots` columns, restart m and a mode.
+static Eng engine_make(tp_plan pl, int m, int mixed, int nslots) {
     const long Nt = pl->Nt;
-    if (Nt > solver_max_nt())
-        return fail(TP_E_UNSUPPORTED, "solves are limited to Nt <= " + std::to_string(solver_max_nt()));
     EngLayout L = eng_layout(Nt, pl->restart, pl->max_rhs);
     char *wsb = (char *)pl->rim_part + a256((size_t)pl->rim_nslab * (pl->Nr ? pl->Nr : 1) * pl->max_rhs * 16);
     Eng E;
     E.Nt = Nt;
-    E.m = o.restart;        // a shorter restart than the plan's uses a prefix of each region
+    E.m = m;        // a shorter restart than the plan's uses a prefix of each region
     {
         const long ept = (Nt + (long)kLanes * kMaxBlocks - 1) / ((long)kLanes * kMaxBlocks);
         E.span = (long)kLanes * ept;
         E.nb = (int)((Nt + E.span - 1) / E.span);
     }
-    E.mixed = o.mode == TP_MIXED;
-    E.nslots = nrhs;
+    E.mixed = mixed;
+    E.nslots = nslots;
     E.st = (SlotState *)(wsb + L.st);
     E.sc = (SlotConst *)(wsb + L.sc);
     E.dec = (SlotDec *)(wsb + L.dec);
@@ -681,25 +695,43 @@ tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int 
     E.tout = (c128 **)(tabs + pl->max_rhs);
     E.rin = (const c128 **)(tabs + 2 * pl->max_rhs);
     E.rout = (c128 **)(tabs + 3 * pl->max_rhs);
+    return E;
+}
 
+static SlotState initial_state(int x0_given) {
+    SlotState S;
+    std::memset(&S, 0, sizeof(S));
+    S.phase = PH_INIT;
+    S.xzero = x0_given ? 0 : 1;
+    S.first = 1;
+    return S;
+}
+
+static void fill_info(const SlotState &S, tp_solve_info *info) {
+    info->iters = S.iters;
+    info->outer_iters = S.outer;
+    info->relres = S.relres;
+    info->status = S.phase == PH_DONE ? S.status : TP_E_NOCONV;
+}
+
+tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int nrhs, const tp_solve_opts &o,
+                    tp_solve_info *info, hipStream_t st) {
+    const long Nt = pl->Nt;
+    if (Nt > solver_max_nt())
+        return fail(TP_E_UNSUPPORTED, "solves are limited to Nt <= " + std::to_string(solver_max_nt()));
+    if (pl->batch && static_cast<BatchEngine *>(pl->batch)->active)
+        return fail(TP_E_INVAL, "a continuous batch is active on this plan");
+    const Eng E = engine_make(pl, o.restart, o.mode == TP_MIXED, nrhs);
     hipError_t e;
     if ((e = solver_resources(pl))) return hip_fail(e, "solver resources");
     hipStream_t cs = pl->cs;
     SlotState *hstat = (SlotState *)pl->host_status;     // [2][max_rhs], pinned
 
     // the first super-step (parity 0) commits from the parity-1 copy
-    std::vector<SlotState> hs(2 * (size_t)nrhs);
+    std::vector<SlotState> hs(2 * (size_t)nrhs, initial_state(o.x0_given));
     std::vector<SlotConst> hc(nrhs);
-    for (int r = 0; r < nrhs; ++r) {
-        SlotState S;
-        std::memset(&S, 0, sizeof(S));
-        S.phase = PH_INIT;
-        S.xzero = o.x0_given ? 0 : 1;
-        S.first = 1;
-        hs[r] = S;
-        hs[nrhs + r] = S;
+    for (int r = 0; r < nrhs; ++r)
         hc[r] = SlotConst{v + (long)r * ldv, x + (long)r * ldx, o.tol, o.inner_tol, o.max_iter, o.max_outer};
-    }
     if ((e = hipEventRecord(pl->ev[0], st)) || (e = hipStreamWaitEvent(cs, pl->ev[0], 0)))
         return hip_fail(e, "solver stream ordering");
     if ((e = hipMemcpyAsync(E.st, hs.data(), sizeof(SlotState) * hs.size(), hipMemcpyHostToDevice, cs)) ||
@@ -740,16 +772,158 @@ tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int 
         return hip_fail(e, "solver stream ordering");
     tp_status ret = TP_OK;
     for (int r = 0; r < nrhs; ++r) {
-        const SlotState &S = hstat[last * pl->max_rhs + r];
-        info[r].iters = S.iters;
-        info[r].outer_iters = S.outer;
-        info[r].relres = S.relres;
-        info[r].status = S.phase == PH_DONE ? S.status : TP_E_NOCONV;
+        fill_info(hstat[last * pl->max_rhs + r], &info[r]);
         if (info[r].status != TP_OK && ret == TP_OK) ret = (tp_status)info[r].status;
     }
     if (ret == TP_E_NOCONV) set_error("at least one column missed the tolerance");
     if (ret == TP_E_BREAKDOWN) set_error("Krylov breakdown or non-finite residual");
     return ret;
 }
+
+// ------------------------------------------------------ continuous batching
+// One engine per plan with max_rhs slots; a slot holds one column from
+// admission to retirement.  Admission and release are stream-ordered copies
+// (from pinned per-slot staging) into the state that the next commit reads,
+// so columns join and leave a running batch without stopping it: the host
+// never waits for the device except when it polls.
+
+struct SlotStage {
+    SlotConst c;
+    SlotState admit, idle;
+};
+
+tp_status batch_begin(tp_plan pl, const tp_solve_opts &o) {
+    if (pl->Nt > solver_max_nt())
+        return fail(TP_E_UNSUPPORTED, "solves are limited to Nt <= " + std::to_string(solver_max_nt()));
+    hipError_t e;
+    if ((e = solver_resources(pl))) return hip_fail(e, "solver resources");
+    if (!pl->host_stage && (e = hipHostMalloc(&pl->host_stage, sizeof(SlotStage) * pl->max_rhs)))
+        return hip_fail(e, "batch staging");
+    BatchEngine *B = static_cast<BatchEngine *>(pl->batch);
+    if (!B) {
+        B = new BatchEngine();
+        pl->batch = B;
+    }
+    if ((e = hipStreamSynchronize(pl->cs))) return hip_fail(e, "batch begin sync");
+    B->E = engine_make(pl, o.restart, o.mode == TP_MIXED, pl->max_rhs);
+    B->cst.assign(pl->max_rhs, SlotConst{nullptr, nullptr, o.tol, o.inner_tol, o.max_iter, o.max_outer});
+    B->pending = 0;
+    B->nstep = 0;
+    SlotState idle;
+    std::memset(&idle, 0, sizeof(idle));
+    idle.phase = PH_IDLE;
+    std::vector<SlotState> hs(2 * (size_t)pl->max_rhs, idle);
+    std::vector<void *> ht(4 * (size_t)pl->max_rhs, nullptr);
+    if ((e = hipMemcpyAsync(B->E.st, hs.data(), sizeof(SlotState) * hs.size(), hipMemcpyHostToDevice, pl->cs)) ||
+        (e = hipMemcpyAsync(B->E.sc, B->cst.data(), sizeof(SlotConst) * B->cst.size(), hipMemcpyHostToDevice,
+                            pl->cs)) ||
+        (e = hipMemcpyAsync((void *)B->E.tin, ht.data(), sizeof(void *) * ht.size(), hipMemcpyHostToDevice, pl->cs)) ||
+        (e = hipStreamSynchronize(pl->cs)))
+        return hip_fail(e, "batch state upload");
+    if ((e = step_graph(pl, B->E, &B->gexec))) return hip_fail(e, "batch graph capture");
+    B->active = 1;
+    return TP_OK;
+}
+
+static BatchEngine *active_batch(tp_plan pl) {
+    BatchEngine *B = static_cast<BatchEngine *>(pl->batch);
+    return (B && B->active) ? B : nullptr;
+}
+
+// A slot is only re-admitted after the host saw it finish and released it,
+// so its staging record is never rewritten while a copy from it is pending.
+tp_status batch_admit(tp_plan pl, int slot, const c128 *v, c128 *x, double tol, int x0_given) {
+    BatchEngine *B = active_batch(pl);
+    if (!B) return fail(TP_E_INVAL, "no active batch on this plan");
+    if (slot < 0 || slot >= pl->max_rhs) return fail(TP_E_INVAL, "slot out of range");
+    if (!v || !x) return fail(TP_E_INVAL, "v or x is NULL");
+    if (!(tol > 0)) return fail(TP_E_INVAL, "tol must be > 0");
+    SlotStage *stg = static_cast<SlotStage *>(pl->host_stage) + slot;
+    stg->c = B->cst[slot];
+    stg->c.v = v;
+    stg->c.x = x;
+    stg->c.tol = tol;
+    stg->admit = initial_state(x0_given);
+    hipError_t e;
+    // the next graph's first commit reads parity 1
+    if ((e = hipMemcpyAsync(B->E.sc + slot, &stg->c, sizeof(SlotConst), hipMemcpyHostToDevice, pl->cs)) ||
+        (e = hipMemcpyAsync(B->E.st + B->E.nslots + slot, &stg->admit, sizeof(SlotState), hipMemcpyHostToDevice,
+                            pl->cs)))
+        return hip_fail(e, "batch admit");
+    if (!x0_given) hipLaunchKernelGGL(k_zero_cols, dim3(256, 1), dim3(256), 0, pl->cs, x, pl->Nt, pl->Nt);
+    if ((e = hipGetLastError())) return hip_fail(e, "batch admit");
+    return TP_OK;
+}
+
+tp_status batch_release(tp_plan pl, int slot) {
+    BatchEngine *B = active_batch(pl);
+    if (!B) return fail(TP_E_INVAL, "no active batch on this plan");
+    if (slot < 0 || slot >= pl->max_rhs) return fail(TP_E_INVAL, "slot out of range");
+    SlotStage *stg = static_cast<SlotStage *>(pl->host_stage) + slot;
+    std::memset(&stg->idle, 0, sizeof(stg->idle));
+    stg->idle.phase = PH_IDLE;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(B->E.st + B->E.nslots + slot, &stg->idle, sizeof(SlotState), hipMemcpyHostToDevice,
+                            pl->cs)))
+        return hip_fail(e, "batch release");
+    return TP_OK;
+}
+
+// Enqueue ngraphs graph replays (2 super-steps each) and an asynchronous
+// copy of the slot states after them (status buffer nstep & 1).
+tp_status batch_step(tp_plan pl, int ngraphs) {
+    BatchEngine *B = active_batch(pl);
+    if (!B) return fail(TP_E_INVAL, "no active batch on this plan");
+    if (ngraphs < 1) return fail(TP_E_INVAL, "ngraphs must be >= 1");
+    hipError_t e;
+    for (int i = 0; i < ngraphs; ++i)
+        if ((e = hipGraphLaunch(B->gexec, pl->cs))) return hip_fail(e, "batch step");
+    const int buf = (int)(B->nstep & 1);
+    const size_t sbytes = sizeof(SlotState) * pl->max_rhs;
+    SlotState *hs = static_cast<SlotState *>(pl->host_status) + (size_t)buf * pl->max_rhs;
+    if ((e = hipMemcpyAsync(hs, B->E.st + B->E.nslots, sbytes, hipMemcpyDeviceToHost, pl->cs)) ||
+        (e = hipEventRecord(pl->ev[1 + buf], pl->cs)))
+        return hip_fail(e, "batch step status");
+    B->nstep += 1;
+    B->pending = 1;
+    return TP_OK;
+}
+
+// Slot status after the step `lag` calls before the latest batch_step (lag 0
+// or 1): phases[s] = 0 idle, 1 running, 2 finished; info[s].  wait = 0
+// returns TP_E_NOCONV (not an error) if that step is still running.
+tp_status batch_poll(tp_plan pl, int lag, int wait, int *phases, tp_solve_info *info) {
+    BatchEngine *B = active_batch(pl);
+    if (!B) return fail(TP_E_INVAL, "no active batch on this plan");
+    if (lag < 0 || lag > 1 || B->nstep <= lag) return fail(TP_E_INVAL, "no such step to poll");
+    const int buf = (int)((B->nstep - 1 - lag) & 1);
+    hipError_t e;
+    if (wait) {
+        if ((e = hipEventSynchronize(pl->ev[1 + buf]))) return hip_fail(e, "batch poll");
+    } else {
+        e = hipEventQuery(pl->ev[1 + buf]);
+        if (e == hipErrorNotReady) return TP_E_NOCONV;
+        if (e) return hip_fail(e, "batch poll");
+    }
+    const SlotState *hs = static_cast<const SlotState *>(pl->host_status) + (size_t)buf * pl->max_rhs;
+    for (int s = 0; s < pl->max_rhs; ++s) {
+        const int ph = hs[s].phase;
+        if (phases) phases[s] = ph == PH_IDLE ? 0 : ph == PH_DONE ? 2 : 1;
+        if (info) fill_info(hs[s], &info[s]);
+    }
+    return TP_OK;
+}
+
+tp_status batch_end(tp_plan pl) {
+    BatchEngine *B = static_cast<BatchEngine *>(pl->batch);
+    if (pl->cs) {
+        hipError_t e = hipStreamSynchronize(pl->cs);
+        if (e) return hip_fail(e, "batch end");
+    }
+    if (B) B->active = 0;
+    return TP_OK;
+}
+
+hipStream_t solver_stream(tp_plan pl) { return pl->cs; }
 
 }  // namespace tp

@@ -36,5 +36,13 @@ size_t solver_ws_bytes(long Nt, int restart, int max_rhs);
 void solver_release(tp_plan pl);
 tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int nrhs,
                     const tp_solve_opts &o, tp_solve_info *info, hipStream_t st);
+long solver_max_nt();
+tp_status batch_begin(tp_plan pl, const tp_solve_opts &o);
+tp_status batch_admit(tp_plan pl, int slot, const c128 *v, c128 *x, double tol, int x0_given);
+tp_status batch_release(tp_plan pl, int slot);
+tp_status batch_step(tp_plan pl, int ngraphs);
+tp_status batch_poll(tp_plan pl, int lag, int wait, int *phases, tp_solve_info *info);
+tp_status batch_end(tp_plan pl);
+hipStream_t solver_stream(tp_plan pl);
 
 }  // namespace tp

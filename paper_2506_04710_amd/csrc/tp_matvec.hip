@@ -130,55 +130,68 @@ __global__ void __launch_bounds__(256) k_inv_y(const cpx<T> *__restrict__ in, in
 }
 
 // ---------------------------------------------------- per-frequency product
-// Workgroup = one frequency k, four waves.  Wave w streams rows p = w, w+4, ...
-// of the b x b spectrum block: lane l reads G[k][p][q] for q = l, l+64, ...
-// (one contiguous row segment per wave instruction), multiplies it with the
-// input columns staged in LDS and the wave sums the row.  Rows are unrolled by
-// U so that U independent loads are in flight per lane.  RB right-hand sides
-// share each spectrum load; blockIdx.y selects the RB-column block.
-template <typename T, int RB, int U>
+// Several columns.  Workgroup = one frequency k and a block of RC columns.
+// The RC input columns xhat[k][r][0..b) sit in LDS; the b x b spectrum block
+// is streamed in 8-row panels with 8 lanes per row (lane l: row l >> 3 of the
+// panel, values q in [(l & 7) VPL, (l & 7) VPL + VPL)), each lane forms its
+// part of the RC row products and the 8 lanes of a row add them up.  Wave w
+// takes panels w, w + 4, ... with the next panel's loads issued first.
+template <typename T, int VPL, int RC>
 __global__ void __launch_bounds__(256) k_prod(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ in,
                                               int b, int R, cpx<T> *__restrict__ out, const void *const *act) {
     extern __shared__ char smem_raw[];
-    cpx<T> *xs = reinterpret_cast<cpx<T> *>(smem_raw);   // [RB][b]
-    const int C = b * R, rb = blockIdx.y * RB;
+    cpx<T> *xs = reinterpret_cast<cpx<T> *>(smem_raw);   // [RC][b]
+    const int C = b * R, r0 = blockIdx.y * RC;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     const long k = blockIdx.x;
-    if (!cols_live(act, rb, min(rb + RB, R) - 1)) return;
+    const int rn = min(RC, R - r0);
+    if (!cols_live(act, r0, r0 + rn - 1)) return;
+    const int pl = lane >> 3, qs = (lane & 7) * VPL;
     const cpx<T> *Gk = G + k * (long)b * b;
-    for (int i = threadIdx.x; i < RB * b; i += blockDim.x) {
+    const int npanel = (b + 7) >> 3;
+    cpx<T> gc[VPL], gn[VPL];
+    auto load = [&](cpx<T>(&g)[VPL], int panel) {
+        const int p = panel * 8 + pl;
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+            const int q = qs + v;
+            g[v] = (panel < npanel && p < b && q < b) ? Gk[(long)p * b + q] : mk<T>(0, 0);
+        }
+    };
+    load(gc, w);
+    for (int i = threadIdx.x; i < RC * b; i += blockDim.x) {
         const int c = i / b, q = i - c * b;
-        xs[i] = (rb + c < R) ? in[k * C + (long)(rb + c) * b + q] : mk<T>(0, 0);
+        xs[i] = (c < rn) ? in[k * C + (long)(r0 + c) * b + q] : mk<T>(0, 0);
     }
     __syncthreads();
-    for (int p0 = w; p0 < b; p0 += nw * U) {
-        cpx<T> acc[U][RB];
+    for (int panel = w; panel < npanel; panel += nw) {
+        const int nxt = panel + nw;
+        if (nxt < npanel) load(gn, nxt);
+        const int p = panel * 8 + pl;
+        cpx<T> acc[RC];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int c = 0; c < RC; ++c) acc[c] = mk<T>(0, 0);
 #pragma unroll
-            for (int c = 0; c < RB; ++c) acc[u][c] = mk<T>(0, 0);
-        for (int q = lane; q < b; q += 64) {
-            cpx<T> g[U];
+        for (int v = 0; v < VPL; ++v) {
+            if (qs + v < b) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int p = p0 + u * nw;
-                g[u] = (p < b) ? Gk[(long)p * b + q] : mk<T>(0, 0);
-            }
-#pragma unroll
-            for (int c = 0; c < RB; ++c) {
-                const cpx<T> xv = xs[c * b + q];
-#pragma unroll
-                for (int u = 0; u < U; ++u) acc[u][c] = cmac(acc[u][c], g[u], xv);
+                for (int c = 0; c < RC; ++c) acc[c] = cmac(acc[c], gc[v], xs[c * b + qs + v]);
             }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = p0 + u * nw;
+        for (int c = 0; c < RC; ++c) {
+            acc[c] = acc[c] + shfl_xor_c(acc[c], 1);
+            acc[c] = acc[c] + shfl_xor_c(acc[c], 2);
+            acc[c] = acc[c] + shfl_xor_c(acc[c], 4);
+        }
+        if ((lane & 7) == 0 && p < b) {
 #pragma unroll
-            for (int c = 0; c < RB; ++c) {
-                const cpx<T> s = wave_sum(acc[u][c]);
-                if (lane == 0 && p < b && rb + c < R) out[k * C + (long)(rb + c) * b + p] = s;
-            }
+            for (int c = 0; c < RC; ++c)
+                if (c < rn) out[k * C + (long)(r0 + c) * b + p] = acc[c];
+        }
+        if (nxt < npanel) {
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) gc[v] = gn[v];
         }
     }
 }
@@ -618,6 +631,28 @@ static void launch_spec_rim_e(tp_plan pl, Cols<const In> x, Cols<Out> y, cpx<T> 
     }
 }
 
+template <typename T, int VPL>
+static void launch_prod_v(int RC, dim3 grid, size_t sh, hipStream_t st, const cpx<T> *G, const cpx<T> *in, int b,
+                          int R, cpx<T> *out, const void *const *act) {
+    switch (RC) {
+        case 2: hipLaunchKernelGGL((k_prod<T, VPL, 2>), grid, dim3(256), sh, st, G, in, b, R, out, act); break;
+        case 4: hipLaunchKernelGGL((k_prod<T, VPL, 4>), grid, dim3(256), sh, st, G, in, b, R, out, act); break;
+        case 8: hipLaunchKernelGGL((k_prod<T, VPL, 8>), grid, dim3(256), sh, st, G, in, b, R, out, act); break;
+        default: hipLaunchKernelGGL((k_prod<T, VPL, 16>), grid, dim3(256), sh, st, G, in, b, R, out, act); break;
+    }
+}
+template <typename T>
+static void launch_prod(int vpl, int RC, dim3 grid, size_t sh, hipStream_t st, const cpx<T> *G, const cpx<T> *in,
+                        int b, int R, cpx<T> *out, const void *const *act) {
+    if (vpl <= 2) launch_prod_v<T, 2>(RC, grid, sh, st, G, in, b, R, out, act);
+    else if (vpl <= 4) launch_prod_v<T, 4>(RC, grid, sh, st, G, in, b, R, out, act);
+    else if (vpl <= 6) launch_prod_v<T, 6>(RC, grid, sh, st, G, in, b, R, out, act);
+    else if (vpl <= 8) launch_prod_v<T, 8>(RC, grid, sh, st, G, in, b, R, out, act);
+    else if (vpl <= 12) launch_prod_v<T, 12>(RC, grid, sh, st, G, in, b, R, out, act);
+    else if (vpl <= 16) launch_prod_v<T, 16>(RC, grid, sh, st, G, in, b, R, out, act);
+    else launch_prod_v<T, 32>(RC, grid, sh, st, G, in, b, R, out, act);
+}
+
 // Rows per group (UR) depend only on the slab width, in the fused and the
 // general path alike: which rows a wave sums, and in which order, must not
 // depend on the number of columns, so a column's result is the same alone or
@@ -693,18 +728,13 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         else if (vpl <= 16) launch_spec_rim_e<T, In, Out, 16>(pl, x, y, gA, gB, sh_fused, st);
         else launch_spec_rim_e<T, In, Out, 32>(pl, x, y, gA, gB, sh_fused, st);
     } else {
-        int RBc = R >= 16 ? 16 : R >= 8 ? 8 : R >= 4 ? 4 : R >= 2 ? 2 : 1;
-        while (RBc > 1 && (size_t)RBc * b * es > 32768) RBc >>= 1;
-        const size_t sh = (size_t)RBc * b * es;
-        dim3 grid(Px * Py, (R + RBc - 1) / RBc);
-        const cpx<T> *G = OpPtrs<T>::G(pl);
-        switch (RBc) {
-            case 1: hipLaunchKernelGGL((k_prod<T, 1, 4>), grid, blk, sh, st, G, gB, b, R, gA, act); break;
-            case 2: hipLaunchKernelGGL((k_prod<T, 2, 4>), grid, blk, sh, st, G, gB, b, R, gA, act); break;
-            case 4: hipLaunchKernelGGL((k_prod<T, 4, 2>), grid, blk, sh, st, G, gB, b, R, gA, act); break;
-            case 8: hipLaunchKernelGGL((k_prod<T, 8, 1>), grid, blk, sh, st, G, gB, b, R, gA, act); break;
-            default: hipLaunchKernelGGL((k_prod<T, 16, 1>), grid, blk, sh, st, G, gB, b, R, gA, act); break;
-        }
+        // columns per workgroup: up to 16 (the spectrum block is re-read from
+        // cache by each column block of a frequency)
+        const int RC = R >= 16 ? 16 : R >= 8 ? 8 : R >= 4 ? 4 : 2;
+        const size_t sh = (size_t)RC * b * es;
+        dim3 grid(Px * Py, (R + RC - 1) / RC);
+        const int vpl = (b + 7) / 8;
+        launch_prod<T>(vpl, RC, grid, sh, st, OpPtrs<T>::G(pl), gB, b, R, gA, act);
     }
     mark(4);
     if (!fused) {
