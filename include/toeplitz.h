@@ -219,6 +219,47 @@ tp_status toeplitz_batch_end(tp_plan p);
  */
 tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void *host_out);
 
+/*
+ * Post-steps on solved currents (Sec. III; they need no plan).
+ *
+ * toeplitz_port_smatrix: scattering matrix of p ports from the p solutions of
+ * the port excitations (Sec. III-B): column j of X (device complex128, Nt
+ * values per column, ld ldx >= Nt) is the current vector for a unit excitation
+ * at port j; port_rows (host int64 [p], each in [0, Nt)) are the unknowns of
+ * the ports, edge_len (host double [p], each > 0; NULL = all 1) their edge
+ * lengths.  With I_hat[i][j] = X[port_rows[i], j], L = diag(1 / edge_len),
+ * Y = L I_hat L and Z_port = Y^-1, the result is
+ * S = (Z_port - Z0 I)(Z_port + Z0 I)^-1 (equal real reference impedance Z0 > 0
+ * on every port), written column-major p x p to S (device complex128,
+ * ld lds >= p).  It is computed as S = (I + Z0 Y)^-1 (I - Z0 Y), which equals
+ * the definition whenever Y is invertible (both factors are functions of Y),
+ * by Gaussian elimination with partial pivoting; no inverse is formed.
+ * work: device scratch of work_bytes >= 32 p^2 + 16 p + 256 bytes, 8-byte
+ * aligned.
+ * 1 <= p <= 1024.  Synchronises hip_stream.  A zero pivot (I + Z0 Y singular)
+ * returns TP_E_BREAKDOWN (S undefined).
+ *
+ * toeplitz_far_field: far field of nrhs current vectors by the per-part
+ * contraction of eqs. (farfieldBasis) and (tensorProd), for point-dipole basis
+ * functions: element basis n sits at u_n + (ix dx, iy dy, 0) with unit tangent
+ * t_n (elem_pos, elem_tan: device double [b][3]); rim function r at c_r with
+ * tangent t_r (rim_pos, rim_tan: device double [Nr][3], NULL if Nr = 0).  For
+ * direction m (dirs: device double [nang][2] = (theta, phi) in radians),
+ *   F_tau = -j k eta [ sum_e exp(j k rhat.d_e) sum_n I[e b + n] (e_tau.t_n) exp(j k rhat.u_n)
+ *                      + sum_r I[N + r] (e_tau.t_r) exp(j k rhat.c_r) ],
+ * e_theta = (cos th cos ph, cos th sin ph, -sin th), e_phi = (-sin ph, cos ph, 0).
+ * I: device complex128, column-major Nt x nrhs (ld ldi).  F: device complex128
+ * [nrhs][nang][2] (tau = theta, phi).  1 <= Nx, Ny, b <= 1024, Nr >= 0,
+ * 1 <= nrhs <= 65535, nang >= 1.  Asynchronous on hip_stream.
+ */
+tp_status toeplitz_port_smatrix(int p, long Nt, const void *X, long ldx, const long *port_rows,
+                                const double *edge_len, double Z0, void *S, long lds, void *work, size_t work_bytes,
+                                void *hip_stream);
+tp_status toeplitz_far_field(int Nx, int Ny, int b, int Nr, double dx, double dy, const double *elem_pos,
+                             const double *elem_tan, const double *rim_pos, const double *rim_tan, const void *I,
+                             long ldi, int nrhs, const double *dirs, int nang, double k, double eta, void *F,
+                             void *hip_stream);
+
 /* Release the plan's host metadata.  The caller frees dev_buf afterwards. NULL is ignored. */
 void toeplitz_plan_destroy(tp_plan p);
 

@@ -21,7 +21,7 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ToeplitzError, check  # noqa: F401
 
-__all__ = ["Plan", "plan_bytes", "ToeplitzError", "load"]
+__all__ = ["Plan", "plan_bytes", "port_smatrix", "far_field", "ToeplitzError", "load"]
 
 
 def load():
@@ -175,3 +175,69 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def port_smatrix(X, port_rows, Z0=50.0, edge_len=None, stream=None):
+    """Scattering matrix (p x p complex128 cuda tensor, S[i, j]) from the port
+    solutions X (complex128 cuda tensor (p, Nt): row j solves the excitation of
+    port j) and the port unknowns port_rows (length p)."""
+    import torch
+    x2 = X if X.dim() == 2 else X.reshape(1, -1)
+    if x2.dtype != torch.complex128 or not x2.is_cuda or x2.stride(1) != 1:
+        raise ValueError("X must be a complex128 cuda tensor with contiguous rows")
+    p, Nt = x2.shape[0], x2.shape[1]
+    rows = np.ascontiguousarray(port_rows, dtype=np.int64)
+    if rows.shape != (p,):
+        raise ValueError(f"port_rows must have {p} entries")
+    lens = None if edge_len is None else np.ascontiguousarray(edge_len, dtype=np.float64)
+    if lens is not None and lens.shape != (p,):
+        raise ValueError(f"edge_len must have {p} entries")
+    wbytes = 32 * p * p + 16 * p + 256
+    work = torch.empty(wbytes // 8 + 1, dtype=torch.float64, device=x2.device)
+    St = torch.empty((p, p), dtype=torch.complex128, device=x2.device)   # St[j, i] = S[i, j] (column-major S)
+    check(_lib.lib().toeplitz_port_smatrix(
+        p, Nt, ctypes.c_void_p(x2.data_ptr()), x2.stride(0), rows.ctypes.data_as(ctypes.c_void_p),
+        None if lens is None else lens.ctypes.data_as(ctypes.c_void_p), float(Z0), ctypes.c_void_p(St.data_ptr()), p,
+        ctypes.c_void_p(work.data_ptr()), work.numel() * 8, _stream_handle(stream)))
+    return St.t()
+
+
+def far_field(I, Nx, Ny, b, Nr, dx, dy, elem_pos, elem_tan, rim_pos, rim_tan, theta, phi, k, eta, stream=None):
+    """Far field of the current vectors I (complex128 cuda tensor (R, Nt) or (Nt,))
+    in the directions (theta[m], phi[m]) (radians).  Geometry arrays are numpy
+    float64: elem_pos / elem_tan [b, 3] (basis offsets in the element and unit
+    tangents), rim_pos / rim_tan [Nr, 3].  Returns a complex128 cuda tensor
+    (R, nang, 2) of (F_theta, F_phi)."""
+    import torch
+    i2 = I if I.dim() == 2 else I.reshape(1, -1)
+    if i2.dtype != torch.complex128 or not i2.is_cuda or i2.stride(1) != 1:
+        raise ValueError("I must be a complex128 cuda tensor with contiguous rows")
+    dev = i2.device
+    R = i2.shape[0]
+    th = np.asarray(theta, dtype=np.float64).reshape(-1)
+    ph = np.asarray(phi, dtype=np.float64).reshape(-1)
+    if th.shape != ph.shape:
+        raise ValueError("theta and phi must pair up")
+
+    def d(a, shape):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if a.shape != shape:
+            raise ValueError(f"expected shape {shape}, got {a.shape}")
+        return torch.from_numpy(a).to(dev)
+
+    up, ut = d(elem_pos, (b, 3)), d(elem_tan, (b, 3))
+    rp = d(rim_pos, (Nr, 3)) if Nr else None
+    rt = d(rim_tan, (Nr, 3)) if Nr else None
+    dirs = torch.from_numpy(np.stack([th, ph], axis=1).copy()).to(dev)
+    F = torch.empty((R, th.size, 2), dtype=torch.complex128, device=dev)
+    if stream is not None:
+        # the staging tensors were filled on the current stream and are read on `stream`
+        stream.wait_stream(torch.cuda.current_stream(dev))
+        for t in (up, ut, rp, rt, dirs, F):
+            if t is not None:
+                t.record_stream(stream)
+    ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+    check(_lib.lib().toeplitz_far_field(Nx, Ny, b, Nr, float(dx), float(dy), ptr(up), ptr(ut), ptr(rp), ptr(rt),
+                                        ptr(i2), i2.stride(0), R, ptr(dirs), th.size, float(k), float(eta), ptr(F),
+                                        _stream_handle(stream)))
+    return F

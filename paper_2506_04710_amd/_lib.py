@@ -23,7 +23,8 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_matvec_profile",
            "toeplitz_solve_opts_default", "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_plan_destroy",
            "toeplitz_last_error", "toeplitz_batch_begin", "toeplitz_batch_admit", "toeplitz_batch_release",
-           "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end")
+           "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end", "toeplitz_port_smatrix",
+           "toeplitz_far_field")
 
 
 class PlanDesc(ctypes.Structure):
@@ -80,13 +81,17 @@ def lib():
         L.toeplitz_batch_step.argtypes = [vp, ci]
         L.toeplitz_batch_poll.argtypes = [vp, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(SolveInfo)]
         L.toeplitz_batch_end.argtypes = [vp]
+        cd = ctypes.c_double
+        L.toeplitz_port_smatrix.argtypes = [ci, cl, vp, cl, vp, vp, cd, vp, cl, vp, sz, vp]
+        L.toeplitz_far_field.argtypes = [ci, ci, ci, ci, cd, cd, vp, vp, vp, vp, vp, cl, ci, vp, ci, cd, cd, vp, vp]
         L.toeplitz_plan_destroy.argtypes = [vp]
         L.toeplitz_plan_destroy.restype = None
         L.toeplitz_last_error.restype = ctypes.c_char_p
         for name in ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", "toeplitz_matvec",
                      "toeplitz_matvec_profile",
                      "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_batch_begin", "toeplitz_batch_admit",
-                     "toeplitz_batch_release", "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end"):
+                     "toeplitz_batch_release", "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end",
+                     "toeplitz_port_smatrix", "toeplitz_far_field"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib

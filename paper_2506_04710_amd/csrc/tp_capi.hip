@@ -1,6 +1,7 @@
 // C ABI of the library: plan sizing and construction, operator application,
 // solve, spectrum export, errors.  Argument checks run before any device work.
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -465,6 +466,41 @@ tp_status toeplitz_batch_poll(tp_plan p, int lag, int wait, int *phases, tp_solv
 tp_status toeplitz_batch_end(tp_plan p) {
     if (!p) return fail(TP_E_INVAL, "plan is NULL");
     return batch_end(p);
+}
+
+tp_status toeplitz_port_smatrix(int p, long Nt, const void *X, long ldx, const long *port_rows,
+                                const double *edge_len, double Z0, void *S, long lds, void *work, size_t work_bytes,
+                                void *hip_stream) {
+    if (p < 1 || p > 1024) return fail(TP_E_INVAL, "p must be in [1, 1024]");
+    if (Nt < 1 || ldx < Nt || lds < p) return fail(TP_E_INVAL, "need Nt >= 1, ldx >= Nt and lds >= p");
+    if (!X || !port_rows || !S || !work) return fail(TP_E_INVAL, "X, port_rows, S or work is NULL");
+    if ((reinterpret_cast<uintptr_t>(work) & 7) != 0) return fail(TP_E_INVAL, "work must be 8-byte aligned");
+    if (work_bytes < smatrix_work_bytes(p)) return fail(TP_E_INVAL, "work buffer too small");
+    if (!(Z0 > 0) || !std::isfinite(Z0)) return fail(TP_E_INVAL, "Z0 must be a positive finite number");
+    for (int i = 0; i < p; ++i)
+        if (port_rows[i] < 0 || port_rows[i] >= Nt) return fail(TP_E_INVAL, "port row outside [0, Nt)");
+    if (edge_len)
+        for (int i = 0; i < p; ++i)
+            if (!(edge_len[i] > 0) || !std::isfinite(edge_len[i])) return fail(TP_E_INVAL, "edge lengths must be > 0");
+    return port_smatrix(p, (const c128 *)X, ldx, port_rows, edge_len, Z0, (c128 *)S, lds, work,
+                        (hipStream_t)hip_stream);
+}
+
+tp_status toeplitz_far_field(int Nx, int Ny, int b, int Nr, double dx, double dy, const double *elem_pos,
+                             const double *elem_tan, const double *rim_pos, const double *rim_tan, const void *I,
+                             long ldi, int nrhs, const double *dirs, int nang, double k, double eta, void *F,
+                             void *hip_stream) {
+    if (Nx < 1 || Ny < 1 || b < 1 || Nr < 0 || Nx > 1024 || Ny > 1024 || b > 1024)
+        return fail(TP_E_INVAL, "need 1 <= Nx, Ny, b <= 1024 and Nr >= 0");
+    if (nrhs < 1 || nrhs > 65535 || nang < 1) return fail(TP_E_INVAL, "nrhs must be in [1, 65535] and nang >= 1");
+    const long Nt = (long)Nx * Ny * b + Nr;
+    if (ldi < Nt) return fail(TP_E_INVAL, "ldi smaller than Nt");
+    if (!elem_pos || !elem_tan || !I || !dirs || !F) return fail(TP_E_INVAL, "a required pointer is NULL");
+    if (Nr > 0 && (!rim_pos || !rim_tan)) return fail(TP_E_INVAL, "rim_pos / rim_tan are NULL with Nr > 0");
+    if (!std::isfinite(dx) || !std::isfinite(dy) || !std::isfinite(k) || !std::isfinite(eta))
+        return fail(TP_E_INVAL, "dx, dy, k and eta must be finite");
+    return far_field(Nx, Ny, b, Nr, dx, dy, elem_pos, elem_tan, rim_pos, rim_tan, (const c128 *)I, ldi, nrhs, dirs,
+                     nang, k, eta, (c128 *)F, (hipStream_t)hip_stream);
 }
 
 void toeplitz_plan_destroy(tp_plan p) {

@@ -45,4 +45,12 @@ tp_status batch_poll(tp_plan pl, int lag, int wait, int *phases, tp_solve_info *
 tp_status batch_end(tp_plan pl);
 hipStream_t solver_stream(tp_plan pl);
 
+// post-steps (tp_post.hip)
+size_t smatrix_work_bytes(int p);
+tp_status port_smatrix(int p, const c128 *X, long ldx, const long *rows_h, const double *len_h, double Z0, c128 *S,
+                       long lds, void *work, hipStream_t st);
+tp_status far_field(int Nx, int Ny, int b, int Nr, double dx, double dy, const double *upos, const double *utan,
+                    const double *rpos, const double *rtan, const c128 *I, long ldi, int nrhs, const double *dirs,
+                    int nang, double k, double eta, c128 *F, hipStream_t st);
+
 }  // namespace tp

@@ -101,3 +101,44 @@ def test_solve_defaults(L):
     o = _lib.SolveOpts()
     L.toeplitz_solve_opts_default(ctypes.byref(o))
     assert o.tol == 1e-8 and o.max_iter == 2000 and o.mode == _lib.TP_FP64 and o.x0_given == 0
+
+
+def test_port_smatrix_validates_before_device_work(L):
+    import numpy as np
+    vp = ctypes.c_void_p
+    fake = vp(0x100000)          # never dereferenced: every case fails validation first
+    rows = np.array([0, 3, 5], dtype=np.int64)
+    lens = np.array([1.0, 0.5, 2.0])
+    rp = rows.ctypes.data_as(vp)
+    need = 32 * 9 + 16 * 3 + 256
+
+    def call(p=3, Nt=10, X=fake, ldx=10, r=rp, ln=None, Z0=50.0, S=fake, lds=3, work=fake, wb=need):
+        return L.toeplitz_port_smatrix(p, Nt, X, ldx, r, ln, Z0, S, lds, work, wb, None)
+
+    assert call(p=0) == 1 and call(p=1025) == 1
+    assert call(Nt=0) == 1 and call(ldx=9) == 1 and call(lds=2) == 1
+    assert call(X=None) == 1 and call(r=None) == 1 and call(S=None) == 1 and call(work=None) == 1
+    assert call(work=vp(0x100004)) == 1            # misaligned
+    assert call(wb=need - 1) == 1
+    assert call(Z0=0.0) == 1 and call(Z0=float("inf")) == 1
+    bad = np.array([0, 3, 10], dtype=np.int64)
+    assert call(r=bad.ctypes.data_as(vp)) == 1     # row outside [0, Nt)
+    neg = np.array([1.0, 0.0, 2.0])
+    assert call(ln=neg.ctypes.data_as(vp)) == 1
+    assert b"edge" in L.toeplitz_last_error()
+
+
+def test_far_field_validates_before_device_work(L):
+    vp = ctypes.c_void_p
+    fake = vp(0x100000)
+
+    def call(Nx=4, Ny=4, b=8, Nr=2, up=fake, ut=fake, rp=fake, rt=fake, I=fake, ldi=130, R=1, dirs=fake, nang=3,
+             F=fake, k=6.28):
+        return L.toeplitz_far_field(Nx, Ny, b, Nr, 0.5, 0.5, up, ut, rp, rt, I, ldi, R, dirs, nang, k, 376.7, F,
+                                    None)
+
+    assert call(Nx=0) == 1 and call(b=0) == 1 and call(Nr=-1) == 1
+    assert call(R=0) == 1 and call(nang=0) == 1 and call(ldi=129) == 1
+    assert call(up=None) == 1 and call(I=None) == 1 and call(F=None) == 1 and call(dirs=None) == 1
+    assert call(rp=None) == 1                      # Nr > 0 needs rim geometry
+    assert call(k=float("nan")) == 1
