@@ -29,7 +29,8 @@ METRIC = "solves/s at rel-residual 1e-8 (32x32,b=64) vs FP64 plain; matvec GB/s;
 # HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the same counters on a plain copy of known size),
 # valid only for the kernel source it was measured on.
-TRAFFIC = {"source_sha256": None, "bytes": None}
+TRAFFIC = {"source_sha256": "50e96c6e1a46084d0c28c706aa8404f6680c1a778f5bc2bff5cee6e48b215de1",
+           "bytes": 274440474, "fetch_factor": 0.500009, "write_factor": 1.0}
 
 
 def parse():
@@ -38,7 +39,22 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device-to-device copies of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """Plain copies of known size: the reference for scaling the HBM byte
+    counters (FETCH_SIZE, WRITE_SIZE) read on the operator's kernels."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.neg(src, out=dst)       # an elementwise kernel: reads n bytes, writes n bytes
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n, "copies": 5}), flush=True)
 
 
 def kernel_source_sha():
@@ -101,6 +117,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
               f"documented but not built", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
     import paper_2506_04710_amd as tp

@@ -157,3 +157,30 @@ def test_solve_graph_replays_deterministic(tp, mode):
         assert np.array_equal(x.cpu().numpy(), ref), rep
         assert [i["iters"] for i in info] == [i["iters"] for i in info0]
     assert np.all(oracle.relres(prob, ref, V) <= 1e-8)
+
+
+def test_config4_mixed_to_1e10_against_fp64():
+    """64 x 64 array, b = 48, 8 scan-angle plane waves: the mixed solve reaches
+    relative residual 1e-10 per column; its error against the plain FP64 solve
+    is reported and bounded; the oracle's rows agree on a row sample."""
+    banner("config 4 mixed 1e-10, 8 RHS")
+    import torch
+    import paper_2506_04710_amd as tp
+    prob, V = sa.make_config(4)
+    R = V.shape[0]
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=R, restart=40, device=torch.device("cuda:0"))
+    v = to_dev(V)
+    x, info = plan.solve(v, mode="mixed", tol=1e-10)
+    assert all(i["status"] == 0 and i["relres"] <= 1e-10 for i in info), info
+    x64, info64 = plan.solve(v, mode="fp64", tol=1e-10)
+    assert all(i["status"] == 0 for i in info64), info64
+    X, X64 = x.cpu().numpy(), x64.cpu().numpy()
+    errs = [rel_err(X[r], X64[r]) for r in range(R)]
+    print(f"config 4: mixed iters {[i['iters'] for i in info]} outer {[i['outer_iters'] for i in info]}, "
+          f"fp64 iters {[i['iters'] for i in info64]}, max rel diff mixed vs fp64 {max(errs):.2e}")
+    assert max(errs) <= 1e-8
+    rows = np.linspace(0, prob.Nt - 1, 64).astype(np.int64)
+    Y = oracle.matvec(prob, X, rows=rows)
+    for r in range(R):
+        assert np.max(np.abs(V[r, rows] - Y[r])) <= 1e-10 * np.linalg.norm(V[r])
+    plan.close()
