@@ -10,7 +10,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtoeplitz.so")
+# TOEPLITZ_LIBRARY may name another build of the same library (e.g. one
+# compiled with different tuning flags); the default is the in-tree build.
+LIB_PATH = os.environ.get("TOEPLITZ_LIBRARY") or os.path.join(_HERE, "libtoeplitz.so")
 
 TP_OK, TP_E_INVAL, TP_E_NOMEM, TP_E_HIP, TP_E_NOCONV, TP_E_BREAKDOWN, TP_E_UNSUPPORTED = range(7)
 TP_FP64, TP_FP32, TP_MIXED = 0, 1, 2

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libtoeplitz.so")
-SOURCES = ["tp_capi.hip", "tp_matvec.hip", "tp_gmres.hip", "tp_post.hip"]
+SOURCES = ["tp_capi.hip", "tp_matvec.hip", "tp_gmres.hip", "tp_post.hip", "tp_mfma.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # keep the compiler from forming packed FP32 instructions
@@ -17,9 +17,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include")]
 
 
-def _compile(src, verbose):
+def _compile(src, verbose, extra):
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -28,10 +28,12 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, extra=()) -> str:
+    """Compile every source and link libtoeplitz.so; `extra` holds additional
+    hipcc flags (e.g. -DTP_MFMA_MIN_R=8 to move the matrix-core threshold)."""
     os.makedirs(OBJ, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, list(extra)), SOURCES))
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", OUT + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)

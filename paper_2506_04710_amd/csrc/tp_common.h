@@ -67,6 +67,15 @@ struct Cols {
     __device__ __forceinline__ V *col(int r) const { return tab ? tab[r] : base + (long)r * ld; }
 };
 
+// Column activity: a NULL entry in a column-pointer table marks an idle column
+// (the solver masks columns this way).  Without a table every column is live.
+__device__ __forceinline__ bool cols_live(const void *const *tab, int r0, int r1) {
+    if (!tab) return true;
+    for (int r = r0; r <= r1; ++r)
+        if (tab[r]) return true;
+    return false;
+}
+
 // Radix plan of one transform length P (mixed radix, in-place decimation in
 // time): stage s combines sub-transforms of length L[s] with radix radix[s].
 // perm (device) maps natural input index n to its LDS slot; tw holds

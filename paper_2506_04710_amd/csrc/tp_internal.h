@@ -45,6 +45,16 @@ tp_status batch_poll(tp_plan pl, int lag, int wait, int *phases, tp_solve_info *
 tp_status batch_end(tp_plan pl);
 hipStream_t solver_stream(tp_plan pl);
 
+// matrix-core kernels for many right-hand sides (tp_mfma.hip)
+template <typename T>
+hipError_t prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, long P, cpx<T> *out, const void *const *act,
+                     hipStream_t st);
+template <typename T, typename In, typename Out>
+hipError_t rim_mfma(const cpx<T> *B, const cpx<T> *BE, Cols<const In> x, Cols<Out> y, int R, long N, int Nr,
+                    int nslab, cpx<T> *part, hipStream_t st);
+template <typename T>
+size_t rim_mfma_lds(bool nbe);
+
 // post-steps (tp_post.hip)
 size_t smatrix_work_bytes(int p);
 tp_status port_smatrix(int p, const c128 *X, long ldx, const long *rows_h, const double *len_h, double Z0, c128 *S,

@@ -38,15 +38,6 @@ __device__ __forceinline__ cpx<T> wave_sum(cpx<T> v) {
     return v;
 }
 
-// Column activity: a NULL entry in a column-pointer table marks an idle column
-// (the solver masks columns this way).  Without a table every column is live.
-__device__ __forceinline__ bool cols_live(const void *const *tab, int r0, int r1) {
-    if (!tab) return true;
-    for (int r = r0; r <= r1; ++r)
-        if (tab[r]) return true;
-    return false;
-}
-
 template <typename T>
 __device__ __forceinline__ void zero_lds(cpx<T> *buf, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = mk<T>(0, 0);
@@ -599,6 +590,12 @@ static size_t spec_lds(tp_plan pl, size_t es) {
 }
 static size_t rim_lds(tp_plan pl, int RB, size_t es) { return ((size_t)RB * pl->Nr + 4 * (size_t)pl->rim_te * RB) * es; }
 constexpr size_t kLdsLimit = 160 * 1024;
+// From this many columns on, the per-frequency product and the rim pass use
+// the MFMA kernels (a column block of 16 or 32 fills the matrix-core tiles).
+#ifndef TP_MFMA_MIN_R
+#define TP_MFMA_MIN_R 16
+#endif
+constexpr int kMfmaMinR = TP_MFMA_MIN_R;
 
 template <typename T, typename In, typename Out, int VPL, int E, bool NBE>
 static void launch_spec_rim(tp_plan pl, Cols<const In> x, Cols<Out> y, cpx<T> *gA, cpx<T> *gB, size_t sh,
@@ -701,8 +698,18 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     const size_t sh_fused = std::max(spec_lds(pl, es), Nr > 0 ? rim_lds(pl, 1, es) : (size_t)0);
     const bool fused = R == 1 && sh_fused <= kLdsLimit;
 
+    // many columns: the product and the rim run on the matrix cores
+    const bool mfma = !fused && R >= kMfmaMinR;
+    const bool rim_mma = mfma && Nr > 0 && pl->rim_te == 64 && rim_mfma_lds<T>(OpPtrs<T>::BE(pl) != nullptr) <= kLdsLimit;
+
     mark(0);
-    if (Nr > 0 && !fused) launch_rim_general<T, In, Out>(pl, x, y, R, st);
+    if (Nr > 0 && !fused) {
+        if (rim_mma)
+            rim_mfma<T, In, Out>(OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl), x, y, R, pl->N, Nr, pl->rim_nslab,
+                                 reinterpret_cast<cpx<T> *>(pl->rim_part), st);
+        else
+            launch_rim_general<T, In, Out>(pl, x, y, R, st);
+    }
     mark(1);
     {
         const int lg = fft_lgcc(Px, C, es, 8);
@@ -727,6 +734,8 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         else if (vpl <= 12) launch_spec_rim_e<T, In, Out, 12>(pl, x, y, gA, gB, sh_fused, st);
         else if (vpl <= 16) launch_spec_rim_e<T, In, Out, 16>(pl, x, y, gA, gB, sh_fused, st);
         else launch_spec_rim_e<T, In, Out, 32>(pl, x, y, gA, gB, sh_fused, st);
+    } else if (mfma) {
+        prod_mfma<T>(OpPtrs<T>::G(pl), gB, b, R, (long)Px * Py, gA, act, st);
     } else {
         // columns per workgroup: up to 16 (the spectrum block is re-read from
         // cache by each column block of a frequency)

@@ -38,7 +38,11 @@ CASES = [  # (Nx, Ny, b, Nr, R): ragged b against the 64-lane rows, prime and pa
     (4, 4, 16, 24, 1), (1, 1, 8, 0, 1), (1, 5, 4, 3, 2), (7, 2, 3, 0, 1), (5, 3, 33, 10, 3),
     (3, 4, 70, 5, 2), (17, 9, 8, 20, 1), (2, 3, 100, 7, 5), (9, 9, 96, 72, 1),
     # single columns take the fused path: multi-stage y lengths (18 = 2*3*3, 15, 9)
-    (9, 8, 8, 0, 1), (5, 9, 40, 6, 1), (8, 5, 130, 3, 1)]
+    (9, 8, 8, 0, 1), (5, 9, 40, 6, 1), (8, 5, 130, 3, 1),
+    # 16 or more columns run on the matrix cores: ragged column blocks, b not a
+    # multiple of 16 or 4, rim rows in several chunks, ragged 64-column slabs
+    (4, 4, 16, 24, 16), (3, 4, 70, 5, 17), (5, 3, 33, 10, 33), (2, 3, 100, 70, 20), (9, 9, 96, 72, 40),
+    (6, 4, 7, 0, 18)]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}b{c[2]}r{c[3]}R{c[4]}" for c in CASES])
@@ -83,6 +87,33 @@ def test_matvec_batch_invariant(torch_cuda):
     for r in range(5):
         Y1, _ = _matvec_case(torch_cuda, prob, X[r:r + 1])
         assert rel_err(Y1[0], Yb[r]) <= 1e-14
+
+
+def test_matvec_batch_invariant_mfma(torch_cuda):
+    """From 16 columns on (matrix-core kernels) a column's product is the same
+    bit for bit whatever its position in the batch and the batch's size."""
+    banner("matvec batch invariance (MFMA)")
+    prob = sa.make_problem(5, 4, 24, 12, 44)
+    X = sa.rhs_random(prob, 21)
+    for which in ("fp64", "fp32"):
+        Xw = X if which == "fp64" else X.astype(np.complex64).astype(np.complex128)
+        Ya, _ = _matvec_case(torch_cuda, prob, Xw, which=which)
+        Yb, _ = _matvec_case(torch_cuda, prob, Xw[3:21], which=which)
+        Yc, _ = _matvec_case(torch_cuda, prob, Xw[5:21], which=which)
+        assert np.array_equal(Yb, Ya[3:21]) and np.array_equal(Yc, Ya[5:21]), which
+
+
+@pytest.mark.parametrize("which", ["fp64", "fp32"])
+def test_matvec_nonreciprocal_rim_mfma(torch_cuda, which):
+    banner(f"matvec non-reciprocal MFMA {which}")
+    prob = sa.make_problem(6, 5, 12, 40, 45)
+    rim_er = random_rim_er(prob, 6)
+    X = sa.rhs_random(prob, 19)
+    if which == "fp32":
+        X = X.astype(np.complex64).astype(np.complex128)
+    Y, _ = _matvec_case(torch_cuda, prob, X, rim_er=rim_er, which=which)
+    op = oracle.Operator(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, rim_er)
+    assert rel_err(Y, oracle.matvec(op, X)) <= (TOL64 if which == "fp64" else TOL32)
 
 
 def test_matvec_repeat_bitwise(torch_cuda):
@@ -141,7 +172,7 @@ def test_spectrum_parity_config2_sampled(torch_cuda):
     assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("cfg", [2, 4])
+@pytest.mark.parametrize("cfg", [2, 3, 4])
 @pytest.mark.parametrize("which", ["fp64", "fp32"])
 def test_matvec_full_size_sampled(torch_cuda, cfg, which):
     """Benchmark-size arrays: sampled output rows against the oracle's row sums."""
