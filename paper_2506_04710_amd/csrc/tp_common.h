@@ -76,6 +76,54 @@ __device__ __forceinline__ bool cols_live(const void *const *tab, int r0, int r1
     return false;
 }
 
+// Load or store through a pointer known to address global memory (device
+// buffers), so that the access is a global instruction rather than a flat one
+// (a pointer read from a table is otherwise generic).
+// (Member-wise: a whole-struct copy through the cast pointer loses the
+// address space again.)
+template <typename T>
+__device__ __forceinline__ cpx<T> ldg(const cpx<T> *p) {
+    const __attribute__((address_space(1))) cpx<T> *g = (const __attribute__((address_space(1))) cpx<T> *)p;
+    return cpx<T>{g->x, g->y};
+}
+template <typename T>
+__device__ __forceinline__ void stg(cpx<T> *p, cpx<T> v) {
+    __attribute__((address_space(1))) cpx<T> *g = (__attribute__((address_space(1))) cpx<T> *)p;
+    g->x = v.x;
+    g->y = v.y;
+}
+
+// Keep a value in registers at this point: an empty asm statement that reads
+// it, so a load producing it completes here and is not moved into the code
+// that consumes it.
+template <typename T>
+__device__ __forceinline__ void pin(const cpx<T> &v) {
+    asm volatile("" : : "v"(v.x), "v"(v.y));
+}
+
+// Threads per workgroup of the transform, product and rim kernels.  Loops use
+// this constant rather than blockDim.x: the latter is read from the dispatch
+// packet in memory, and a barrier between two uses forces a fresh read.
+constexpr int kBlock = 256;
+
+// Loop over i < n with U independent loads in flight per thread: ld(i) (which
+// must be safe to call for every i < n) is issued U times, the values are
+// pinned, and only then does use(i, v) consume them, so a round costs one
+// memory latency instead of U.
+template <int U, typename V, typename Ld, typename Use>
+__device__ __forceinline__ void batched(int n, Ld ld, Use use, int nt = kBlock) {
+    for (int base = threadIdx.x; base < n; base += U * nt) {
+        V v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = ld(min(base + u * nt, n - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u) pin(v[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + u * nt < n) use(base + u * nt, v[u]);
+    }
+}
+
 // Radix plan of one transform length P (mixed radix, in-place decimation in
 // time): stage s combines sub-transforms of length L[s] with radix radix[s].
 // perm (device) maps natural input index n to its LDS slot; tw holds

@@ -115,29 +115,61 @@ __device__ __forceinline__ void small_dft(cpx<T> (&a)[R]) {
     }
 }
 
+// Quotient and remainder of n by d for 0 <= n < 2^22, 1 <= d < 2^12, from the
+// single-precision reciprocal rd = 1/d: the estimate is off by at most one
+// and is corrected with one compare each way.
+__device__ __forceinline__ int small_divmod(int n, int d, float rd, int &rem) {
+    int q = (int)((float)n * rd);
+    int r = n - q * d;
+    if (r >= d) {
+        ++q;
+        r -= d;
+    }
+    if (r < 0) {
+        --q;
+        r += d;
+    }
+    rem = r;
+    return q;
+}
+
+// One radix-R stage over nout transforms (transform o starts at o * so; point
+// n of it sits at n * sp), each over the CC contiguous channels.  Every
+// butterfly applies its twiddles (w^0 = 1 for j = 0), so the data and twiddle
+// reads of an item issue together.
 template <typename T, int R, bool INV>
-__device__ __forceinline__ void fft_stage(cpx<T> *buf, int lgCC, int P, int L, const cpx<T> *twl) {
+__device__ __forceinline__ void fft_stage_axis(cpx<T> *buf, int lgCC, int P, int L, int sp, int nout, int so,
+                                               const cpx<T> *twl) {
     const int CC = 1 << lgCC;
     const int nb = P / R;
     const int stride = P / (L * R);
-    const int total = nb << lgCC;
-    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+    const int total = (nout * nb) << lgCC;
+    const float rnb = 1.0f / (float)nb, rL = 1.0f / (float)L;
+    for (int it = threadIdx.x; it < total; it += kBlock) {
         const int ch = it & (CC - 1);
-        const int bf = it >> lgCC;
-        const int j = bf % L;
-        const int base = (bf - j) * R + j;      // (bf / L) * L * R + j
-        cpx<T> a[R];
+        const int rest = it >> lgCC;
+        int bf, j;
+        const int o = small_divmod(rest, nb, rnb, bf);
+        const int grp = small_divmod(bf, L, rL, j);
+        const int base = grp * L * R + j;
+        cpx<T> *b0 = buf + o * so + ch;
+        cpx<T> a[R], w[R];
 #pragma unroll
-        for (int q = 0; q < R; ++q) a[q] = buf[((base + q * L) << lgCC) + ch];
-        if (j != 0) {
+        for (int q = 0; q < R; ++q) a[q] = b0[(base + q * L) * sp];
 #pragma unroll
-            for (int q = 1; q < R; ++q) a[q] = a[q] * twid<T, INV>(twl, q * j * stride);
-        }
+        for (int q = 1; q < R; ++q) w[q] = twid<T, INV>(twl, q * j * stride);
+#pragma unroll
+        for (int q = 1; q < R; ++q) a[q] = a[q] * w[q];
         small_dft<T, R, INV>(a);
 #pragma unroll
-        for (int q = 0; q < R; ++q) buf[((base + q * L) << lgCC) + ch] = a[q];
+        for (int q = 0; q < R; ++q) b0[(base + q * L) * sp] = a[q];
     }
     __syncthreads();
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void fft_stage(cpx<T> *buf, int lgCC, int P, int L, const cpx<T> *twl) {
+    fft_stage_axis<T, R, INV>(buf, lgCC, P, L, 1 << lgCC, 1, 0, twl);
 }
 
 // Transform all CC = 2^lgCC channels of buf (loaded in perm order, barrier done).
@@ -155,6 +187,25 @@ __device__ void lds_fft(cpx<T> *buf, int lgCC, const FFTDesc &d, const cpx<T> *t
     }
 }
 
+// Two-dimensional tiles: nout transforms of length P along one axis of an LDS
+// array whose point stride is sp and whose transforms start so apart (both in
+// values), each over the CC = 2^lgCC contiguous channels.  Input in
+// digit-reversed order along the axis, output natural.
+template <typename T, bool INV>
+__device__ void lds_fft_axis(cpx<T> *buf, int lgCC, const FFTDesc &d, int sp, int nout, int so,
+                             const cpx<T> *twl) {
+    for (int s = 0; s < d.nst; ++s) {
+        switch (d.radix[s]) {
+            case 2: fft_stage_axis<T, 2, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
+            case 3: fft_stage_axis<T, 3, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
+            case 4: fft_stage_axis<T, 4, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
+            case 5: fft_stage_axis<T, 5, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
+            case 7: fft_stage_axis<T, 7, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
+            default: break;
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ const cpx<T> *tw_of(const FFTDesc &d);
 template <>
@@ -166,7 +217,7 @@ __device__ __forceinline__ const c64 *tw_of<float>(const FFTDesc &d) { return d.
 template <typename T>
 __device__ __forceinline__ void load_twiddles(cpx<T> *twl, const FFTDesc &d) {
     const cpx<T> *tw = tw_of<T>(d);
-    for (int k = threadIdx.x; k < d.P; k += blockDim.x) twl[k] = tw[k];
+    for (int k = threadIdx.x; k < d.P; k += kBlock) twl[k] = tw[k];
 }
 
 }  // namespace tp

@@ -40,7 +40,7 @@ __device__ __forceinline__ cpx<T> wave_sum(cpx<T> v) {
 
 template <typename T>
 __device__ __forceinline__ void zero_lds(cpx<T> *buf, int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = mk<T>(0, 0);
+    for (int i = threadIdx.x; i < n; i += kBlock) buf[i] = mk<T>(0, 0);
 }
 
 // ------------------------------------------------------------ FFT passes
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256) k_fwd_x(Cols<const In> x, int R, int Nx, 
     load_twiddles<T>(twl, fx);
     zero_lds<T>(buf, P * CC);
     __syncthreads();
-    for (int i = threadIdx.x; i < Nx * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < Nx * CC; i += kBlock) {
         const int ix = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
         if (c < C) {
             const int r = c / b, p = c - r * b;
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) k_fwd_x(Cols<const In> x, int R, int Nx, 
     }
     __syncthreads();
     lds_fft<T, false>(buf, lgCC, fx, twl);
-    for (int i = threadIdx.x; i < P * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < P * CC; i += kBlock) {
         const int k = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
         if (c < C) out[((long)iy * P + k) * C + c] = buf[i];
     }
@@ -85,13 +85,13 @@ __global__ void __launch_bounds__(256) k_fwd_y(const cpx<T> *__restrict__ in, in
     load_twiddles<T>(twl, fy);
     zero_lds<T>(buf, P * CC);
     __syncthreads();
-    for (int i = threadIdx.x; i < Ny * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < Ny * CC; i += kBlock) {
         const int iy = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
         if (c < C) buf[(fy.perm[iy] << lgCC) + cl] = in[((long)iy * Px + kx) * C + c];
     }
     __syncthreads();
     lds_fft<T, false>(buf, lgCC, fy, twl);
-    for (int i = threadIdx.x; i < P * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < P * CC; i += kBlock) {
         const int ky = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
         if (c < C) out[((long)kx * P + ky) * C + c] = buf[i];
     }
@@ -108,13 +108,13 @@ __global__ void __launch_bounds__(256) k_inv_y(const cpx<T> *__restrict__ in, in
     const int c0 = blockIdx.x * CC, kx = blockIdx.y;
     if (!cols_live(act, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
     load_twiddles<T>(twl, fy);
-    for (int i = threadIdx.x; i < P * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < P * CC; i += kBlock) {
         const int ky = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
         buf[(fy.perm[ky] << lgCC) + cl] = (c < C) ? in[((long)kx * P + ky) * C + c] : mk<T>(0, 0);
     }
     __syncthreads();
     lds_fft<T, true>(buf, lgCC, fy, twl);
-    for (int i = threadIdx.x; i < Ny * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < Ny * CC; i += kBlock) {
         const int iy = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
         if (c < C) out[((long)iy * Px + kx) * C + c] = buf[i];
     }
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_prod(const cpx<T> *__restrict__ G, cons
     extern __shared__ char smem_raw[];
     cpx<T> *xs = reinterpret_cast<cpx<T> *>(smem_raw);   // [RC][b]
     const int C = b * R, r0 = blockIdx.y * RC;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = kBlock >> 6;
     const long k = blockIdx.x;
     const int rn = min(RC, R - r0);
     if (!cols_live(act, r0, r0 + rn - 1)) return;
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(256) k_prod(const cpx<T> *__restrict__ G, cons
         }
     };
     load(gc, w);
-    for (int i = threadIdx.x; i < RC * b; i += blockDim.x) {
+    for (int i = threadIdx.x; i < RC * b; i += kBlock) {
         const int c = i / b, q = i - c * b;
         xs[i] = (c < rn) ? in[k * C + (long)(r0 + c) * b + q] : mk<T>(0, 0);
     }
@@ -198,13 +198,13 @@ template <typename T, typename In, typename Out, int E, int RB, int UR, bool NBE
 __device__ __forceinline__ void rim_block(const cpx<T> *__restrict__ B, const cpx<T> *__restrict__ BE,
                                           Cols<const In> x, Cols<Out> y, int R, long N, int Nr,
                                           cpx<T> *__restrict__ part, int slab, int rbk, char *smem) {
-    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = kBlock >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int TE = 64 * E, rb = rbk * RB;
     const long e0 = (long)slab * TE;
     if (!cols_live((const void *const *)x.tab, rb, min(rb + RB, R) - 1)) return;
     cpx<T> *xr = reinterpret_cast<cpx<T> *>(smem);   // [RB][Nr]
     cpx<T> *ua = xr + RB * Nr;                          // [nw][TE][RB]
-    for (int i = threadIdx.x; i < RB * Nr; i += blockDim.x) {
+    for (int i = threadIdx.x; i < RB * Nr; i += kBlock) {
         const int c = i / Nr, t = i - c * Nr;
         const In *xc = (rb + c < R) ? x.col(rb + c) : nullptr;
         xr[i] = xc ? cvt<T>(xc[N + t]) : mk<T>(0, 0);
@@ -258,7 +258,7 @@ __device__ __forceinline__ void rim_block(const cpx<T> *__restrict__ B, const cp
 #pragma unroll
         for (int c = 0; c < RB; ++c) ua[((long)w * TE + lane + 64 * i) * RB + c] = acc[i][c];
     __syncthreads();
-    for (int idx = threadIdx.x; idx < TE * RB; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < TE * RB; idx += kBlock) {
         const int el = idx / RB, c = idx - el * RB;
         const long e = e0 + el;
         Out *yc = (e < N && rb + c < R) ? y.col(rb + c) : nullptr;
@@ -329,7 +329,7 @@ __device__ __forceinline__ void spec_block(const cpx<T> *__restrict__ G, const c
     cpx<T> *twl = reinterpret_cast<cpx<T> *>(smem);
     cpx<T> *xs = twl + P;          // [Py][CC]
     cpx<T> *ys = xs + P * CC;      // [Py][TP]
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = kBlock >> 6;
     const int pl = lane >> 3, qs = (lane & 7) * VPL, p = p0 + pl;
     const bool prow = p < b;
     const long kstride = (long)b * b;
@@ -350,7 +350,7 @@ __device__ __forceinline__ void spec_block(const cpx<T> *__restrict__ G, const c
     load_twiddles<T>(twl, fy);
     zero_lds<T>(xs, P * CC);
     __syncthreads();
-    for (int i = threadIdx.x; i < Ny * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < Ny * CC; i += kBlock) {
         const int iy = i >> lgCC, c = i & (CC - 1);
         if (c < b) xs[(fy.perm[iy] << lgCC) + c] = X1[((long)iy * Px + kx) * b + c];
     }
@@ -382,7 +382,7 @@ __device__ __forceinline__ void spec_block(const cpx<T> *__restrict__ G, const c
     }
     __syncthreads();
     lds_fft<T, true>(ys, 3, fy, twl);
-    for (int i = threadIdx.x; i < Ny * TP; i += blockDim.x) {
+    for (int i = threadIdx.x; i < Ny * TP; i += kBlock) {
         const int iy = i >> 3, pr = i & 7, pp = p0 + pr;
         if (pp < b) Y1[((long)iy * Px + kx) * b + pp] = ys[i];
     }
@@ -401,7 +401,7 @@ __device__ __forceinline__ void rim_block1(const cpx<T> *__restrict__ B, const c
                                            Cols<const In> x, Cols<Out> y, long N, int Nr,
                                            cpx<T> *__restrict__ part, int slab, char *smem) {
     constexpr int VE = 4 * E, TE = 64 * E;
-    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = kBlock >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ro = lane >> 4, cs = (lane & 15) * VE;
     const long e0 = (long)slab * TE;
     const In *xc = x.col(0);
@@ -409,7 +409,7 @@ __device__ __forceinline__ void rim_block1(const cpx<T> *__restrict__ B, const c
     if (!xc || !yc) return;
     cpx<T> *xr = reinterpret_cast<cpx<T> *>(smem);   // [Nr]
     cpx<T> *ua = xr + Nr;                               // [nw][TE]
-    for (int i = threadIdx.x; i < Nr; i += blockDim.x) xr[i] = cvt<T>(xc[N + i]);
+    for (int i = threadIdx.x; i < Nr; i += kBlock) xr[i] = cvt<T>(xc[N + i]);
     cpx<T> xa[VE], acc[VE];
 #pragma unroll
     for (int v = 0; v < VE; ++v) {
@@ -463,7 +463,7 @@ __device__ __forceinline__ void rim_block1(const cpx<T> *__restrict__ B, const c
 #pragma unroll
         for (int v = 0; v < VE; ++v) ua[w * TE + cs + v] = acc[v];
     __syncthreads();
-    for (int el = threadIdx.x; el < TE; el += blockDim.x) {
+    for (int el = threadIdx.x; el < TE; el += kBlock) {
         const long e = e0 + el;
         if (e < N) {
             cpx<T> t = mk<T>(0, 0);
@@ -525,13 +525,13 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
     const int iy = blk / nchunk, c0 = (blk - iy * nchunk) * CC;
     if (!cols_live((const void *const *)y.tab, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
     load_twiddles<T>(twl, fx);
-    for (int i = threadIdx.x; i < P * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < P * CC; i += kBlock) {
         const int kx = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
         buf[(fx.perm[kx] << lgCC) + cl] = (c < C) ? in[((long)iy * P + kx) * C + c] : mk<T>(0, 0);
     }
     __syncthreads();
     lds_fft<T, true>(buf, lgCC, fx, twl);
-    for (int i = threadIdx.x; i < Nx * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < Nx * CC; i += kBlock) {
         const int ix = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
         if (c < C) {
             const int r = c / b, p = c - r * b;
@@ -545,11 +545,160 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
     }
 }
 
+// ------------------------------------------------- small grids: 2-D tiles
+// When the whole Px x Py grid of CC channels fits in LDS, one workgroup does
+// both transform directions: the forward kernel embeds x_A (rows and columns
+// in digit-reversed slots), transforms along y and then x, and writes the
+// channel block of every frequency; the inverse kernel loads the frequencies,
+// transforms along y and then x (x only for the Ny rows kept), crops to the
+// elements, adds the rim term and, in extra workgroups, finishes y_r.
+// Tile layout: value (x, y, channel) at (x Py + y) CC + channel.
+template <typename T, typename In>
+__global__ void __launch_bounds__(256) k_fft2_fwd(Cols<const In> x, int R, int Nx, int Ny, int b, FFTDesc fx,
+                                                  FFTDesc fy, int lgCC, int XS, cpx<T> *__restrict__ out) {
+    extern __shared__ char smem_raw[];
+    cpx<T> *twx = reinterpret_cast<cpx<T> *>(smem_raw);
+    cpx<T> *twy = twx + fx.P;
+    cpx<T> *buf = twy + fy.P;
+    int *px = reinterpret_cast<int *>(buf + fx.P * XS);   // digit-reversal tables
+    int *py = px + fx.P;
+    const int CC = 1 << lgCC, C = b * R, Px = fx.P, Py = fy.P;
+    const int c0 = blockIdx.x * CC;
+    if (!cols_live((const void *const *)x.tab, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
+    load_twiddles<T>(twx, fx);
+    load_twiddles<T>(twy, fy);
+    for (int i = threadIdx.x; i < Px + Py; i += kBlock) px[i] = i < Px ? fx.perm[i] : fy.perm[i - Px];
+    zero_lds<T>(buf, Px * XS);
+    // kBlock is a multiple of CC, so a thread keeps one channel (and one
+    // column pointer) for the whole loop and walks the elements
+    {
+        const int cl = threadIdx.x & (CC - 1), c = c0 + cl;
+        const In *xc = c < C ? x.col(c / b) : nullptr;
+        __syncthreads();
+        if (xc) {
+            xc += c % b;
+            const int es = kBlock >> lgCC, ne = Nx * Ny;
+            for (int eb = threadIdx.x >> lgCC; eb < ne; eb += 8 * es) {
+                In v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = ldg(xc + (long)min(eb + u * es, ne - 1) * b);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) pin(v[u]);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = eb + u * es;
+                    if (e < ne) {
+                        const int iy = e / Nx, ix = e - iy * Nx;
+                        buf[px[ix] * XS + (py[iy] << lgCC) + cl] = cvt<T>(v[u]);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft_axis<T, false>(buf, lgCC, fy, CC, Px, XS, twy);
+    lds_fft_axis<T, false>(buf, lgCC, fx, XS, Py, CC, twx);
+    for (int i = threadIdx.x; i < Px * Py * CC; i += kBlock) {
+        const int k = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
+        const int kx = k / Py, ky = k - kx * Py;
+        if (c < C) out[(long)k * C + c] = buf[kx * XS + (ky << lgCC) + cl];
+    }
+}
+
+template <typename T, typename In, typename Out>
+__global__ void __launch_bounds__(256) k_fft2_inv_fin(const cpx<T> *__restrict__ in, int R, int Nx, int Ny, int b,
+                                                      FFTDesc fx, FFTDesc fy, int lgCC, int XS, Cols<Out> y,
+                                                      int accumulate,
+                                                      int ninv, const cpx<T> *__restrict__ part,
+                                                      const cpx<T> *__restrict__ Cm, Cols<const In> x, long N,
+                                                      int Nr, int nslab) {
+    extern __shared__ char smem_raw[];
+    const int blk = blockIdx.x;
+    if (blk >= ninv) {
+        const int f = blk - ninv, w = threadIdx.x >> 6;
+        const int nrowblk = (Nr + 3) >> 2;
+        const int c = f / nrowblk, row = (f - c * nrowblk) * 4 + w;
+        rim_finish_wave<T, In, Out>(part, Cm, x, y, R, N, Nr, nslab, row, c);
+        return;
+    }
+    cpx<T> *twx = reinterpret_cast<cpx<T> *>(smem_raw);
+    cpx<T> *twy = twx + fx.P;
+    cpx<T> *buf = twy + fy.P;
+    int *px = reinterpret_cast<int *>(buf + fx.P * XS);
+    int *py = px + fx.P;
+    const int CC = 1 << lgCC, C = b * R, Px = fx.P, Py = fy.P;
+    const int c0 = blk * CC;
+    if (!cols_live((const void *const *)y.tab, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
+    load_twiddles<T>(twx, fx);
+    load_twiddles<T>(twy, fy);
+    for (int i = threadIdx.x; i < Px + Py; i += kBlock) px[i] = i < Px ? fx.perm[i] : fy.perm[i - Px];
+    __syncthreads();
+    batched<8, cpx<T>>(
+        Px * Py * CC, [&](int i) { return in[(long)(i >> lgCC) * C + min(c0 + (i & (CC - 1)), C - 1)]; },
+        [&](int i, cpx<T> v) {
+            const int k = i >> lgCC, cl = i & (CC - 1);
+            const int kx = k / Py, ky = k - kx * Py;
+            buf[px[kx] * XS + (py[ky] << lgCC) + cl] = c0 + cl < C ? v : mk<T>(0, 0);
+        });
+    __syncthreads();
+    lds_fft_axis<T, true>(buf, lgCC, fy, CC, Px, XS, twy);
+    lds_fft_axis<T, true>(buf, lgCC, fx, XS, Ny, CC, twx);
+    const int cl = threadIdx.x & (CC - 1), c = c0 + cl;
+    Out *yc = c < C ? y.col(c / b) : nullptr;
+    if (!yc) return;
+    yc += c % b;
+    const int es = kBlock >> lgCC, ne = Nx * Ny;
+    for (int eb = threadIdx.x >> lgCC; eb < ne; eb += 8 * es) {
+        Out old[8];
+        if (accumulate) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) old[u] = ldg(yc + (long)min(eb + u * es, ne - 1) * b);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) pin(old[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = eb + u * es;
+            if (e < ne) {
+                const int iy = e / Nx, ix = e - iy * Nx;
+                cpx<T> v = buf[ix * XS + (iy << lgCC) + cl];
+                if (accumulate) v = v + cvt<T>(old[u]);
+                stg(yc + (long)e * b, cvt<typename Out::value_type>(v));
+            }
+        }
+    }
+}
+
 // --------------------------------------------------------------- launcher
 static int ilog2(int v) {
     int l = 0;
     while ((1 << l) < v) ++l;
     return l;
+}
+
+// Values between consecutive x rows of a 2-D tile: Py CC, padded so that the
+// row stride in bytes is an odd multiple of 128; the channel runs of a wave's
+// x-direction butterflies then fall in alternate halves of the 64 LDS banks.
+static int fft2_xstride(int Py, int lgCC, size_t elem) {
+    int xs = Py << lgCC;
+    while ((xs * elem) % 256 != 128) ++xs;
+    return xs;
+}
+
+// Channels per workgroup of the 2-D tile kernels (log2), or -1 when a tile of
+// at least 4 channels does not fit in 48 KB of LDS.
+#ifndef TP_FFT2_MAXLG
+#define TP_FFT2_MAXLG 4
+#endif
+static int fft2_lgcc(int Px, int Py, int C, size_t elem) {
+    auto bytes = [&](int lg) {
+        return ((size_t)Px * fft2_xstride(Py, lg, elem) + Px + Py) * elem + (size_t)(Px + Py) * sizeof(int);
+    };
+    int lg = TP_FFT2_MAXLG;
+    while (lg >= 2 && bytes(lg) > 48 * 1024) --lg;
+    if (lg < 2) return -1;
+    while (lg > 2 && (1 << (lg - 1)) >= C) --lg;
+    return lg;
 }
 
 static int fft_lgcc(int P, int C, size_t elem, int max_cc = 64) {
@@ -711,14 +860,21 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
             launch_rim_general<T, In, Out>(pl, x, y, R, st);
     }
     mark(1);
-    {
+    // small grids with several columns: both transform directions per launch
+    const int lg2 = fused ? -1 : fft2_lgcc(Px, Py, C, es);
+    const int xs2 = lg2 >= 0 ? fft2_xstride(Py, lg2, es) : 0;
+    const size_t sh2 = ((size_t)Px * xs2 + Px + Py) * es + (size_t)(Px + Py) * sizeof(int);
+    if (lg2 >= 0) {
+        hipLaunchKernelGGL((k_fft2_fwd<T, In>), dim3((C + (1 << lg2) - 1) >> lg2), blk, sh2, st, x, R, Nx, Ny, b,
+                           pl->fx, pl->fy, lg2, xs2, gB);
+    } else {
         const int lg = fft_lgcc(Px, C, es, 8);
         const size_t sh = ((size_t)Px * (1 << lg) + Px) * es;
         dim3 grid((C + (1 << lg) - 1) >> lg, Ny);
         hipLaunchKernelGGL((k_fwd_x<T, In>), grid, blk, sh, st, x, R, Nx, b, pl->fx, lg, gA);
     }
     mark(2);
-    if (!fused) {
+    if (!fused && lg2 < 0) {
         const int lg = fft_lgcc(Py, C, es, 16);
         const size_t sh = ((size_t)Py * (1 << lg) + Py) * es;
         dim3 grid((C + (1 << lg) - 1) >> lg, Px);
@@ -746,14 +902,20 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         launch_prod<T>(vpl, RC, grid, sh, st, OpPtrs<T>::G(pl), gB, b, R, gA, act);
     }
     mark(4);
-    if (!fused) {
+    if (!fused && lg2 < 0) {
         const int lg = fft_lgcc(Py, C, es, 16);
         const size_t sh = ((size_t)Py * (1 << lg) + Py) * es;
         dim3 grid((C + (1 << lg) - 1) >> lg, Px);
         hipLaunchKernelGGL((k_inv_y<T>), grid, blk, sh, st, gA, C, Ny, Px, pl->fy, lg, gB, act, b);
     }
     mark(5);
-    {
+    if (lg2 >= 0) {
+        const int ninv = (C + (1 << lg2) - 1) >> lg2;
+        const int nfin = Nr > 0 ? ((Nr + 3) / 4) * R : 0;
+        hipLaunchKernelGGL((k_fft2_inv_fin<T, In, Out>), dim3(ninv + nfin), blk, sh2, st, gA, R, Nx, Ny, b, pl->fx,
+                           pl->fy, lg2, xs2, y, Nr > 0 ? 1 : 0, ninv, reinterpret_cast<const cpx<T> *>(pl->rim_part),
+                           OpPtrs<T>::C(pl), x, pl->N, Nr, pl->rim_nslab);
+    } else {
         // the fused path leaves Y1 in gB with channel count b (R = 1), the
         // general path in gB with b * R channels: the same layout
         const int lg = fft_lgcc(Px, C, es, 8);
@@ -800,7 +962,7 @@ __global__ void __launch_bounds__(256) k_gen_fwd_x(const c128 *__restrict__ gen,
     load_twiddles<double>(twl, fx);
     zero_lds<double>(buf, P * CC);
     __syncthreads();
-    for (int i = threadIdx.x; i < W * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < W * CC; i += kBlock) {
         const int mi = i >> lgCC, cl = i & (CC - 1);
         const long c = c0 + cl;
         if (c < bb) {
@@ -811,7 +973,7 @@ __global__ void __launch_bounds__(256) k_gen_fwd_x(const c128 *__restrict__ gen,
     }
     __syncthreads();
     lds_fft<double, false>(buf, lgCC, fx, twl);
-    for (int i = threadIdx.x; i < P * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < P * CC; i += kBlock) {
         const int k = i >> lgCC, cl = i & (CC - 1);
         const long c = c0 + cl;
         if (c < bb) out[((long)ni * P + k) * bb + c] = buf[i];
@@ -832,7 +994,7 @@ __global__ void __launch_bounds__(256) k_gen_fwd_y(const c128 *__restrict__ in, 
     load_twiddles<double>(twl, fy);
     zero_lds<double>(buf, P * CC);
     __syncthreads();
-    for (int i = threadIdx.x; i < H * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < H * CC; i += kBlock) {
         const int ni = i >> lgCC, cl = i & (CC - 1);
         const long c = c0 + cl;
         if (c < bb) {
@@ -843,7 +1005,7 @@ __global__ void __launch_bounds__(256) k_gen_fwd_y(const c128 *__restrict__ in, 
     }
     __syncthreads();
     lds_fft<double, false>(buf, lgCC, fy, twl);
-    for (int i = threadIdx.x; i < P * CC; i += blockDim.x) {
+    for (int i = threadIdx.x; i < P * CC; i += kBlock) {
         const int ky = i >> lgCC, cl = i & (CC - 1);
         const long c = c0 + cl;
         if (c < bb) {

@@ -51,8 +51,7 @@ __device__ __forceinline__ c128 keep(c128 v, bool c) {
 // clamped to n - 1 for the store as well: such a thread writes the same value
 // to the same slot as the thread that owns it, and no branch forms.
 template <int U, typename V, typename Load, typename Store>
-__device__ __forceinline__ void stage(int n, Load ld, Store st) {
-    const int nt = blockDim.x;
+__device__ __forceinline__ void stage(int n, Load ld, Store st, int nt = kBlock) {
     for (int base = threadIdx.x; base < n; base += U * nt) {
         V v[U];
 #pragma unroll
@@ -113,6 +112,7 @@ __global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G
     const int r0 = (int)(item - k * ncb) * 16 * NT, rn = min(16 * NT, R - r0);
     if (!cols_live(act, r0, r0 + rn - 1)) return;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, i = l & 15;
+    const int nthr = blockDim.x;   // 64 per 16-row tile of the output
     stage<4, cpx<T>>(
         16 * NT * W,
         [&](int idx) {
@@ -122,7 +122,8 @@ __global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G
         [&](int idx, cpx<T> v) {
             const int j = idx / W, q = idx - j * W;
             xs[j * bs + q] = keep(v, j < rn && q < b);
-        });
+        },
+        nthr);
     const int p = 16 * w + i;
     const bool prow = p < b;
     // loads use clamped addresses, so they issue without branches; values
