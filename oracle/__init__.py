@@ -17,6 +17,9 @@ What it computes, each by its plain definition:
 * ``circulant_product`` / ``spectrum``: the brute-force cyclic convolution and
   the placed-generator DFT that the FFT route computes (Sec. I: Toeplitz
   structure gives FFT-based products).
+* ``circulant_matrix`` / ``precond_apply``: the dense block circulant of the
+  placed generators and the block-circulant preconditioner built from it
+  (solved by the same elimination as ``lu_solve``).
 * ``s_matrix``: port currents -> admittance -> port impedance -> scattering
   matrix (Sec. III-B; Kurokawa's definition for a real, equal reference
   impedance), ``tarc`` (eq. TARC).
@@ -173,6 +176,60 @@ def spectrum(op, Px, Py, kx, ky, nthreads: int = 0) -> np.ndarray:
     _lib().orc_spectrum(op.Nx, op.Ny, op.b, _ptr(op.gen), Px, Py, _ptr(kx), _ptr(ky), len(kx),
                         _ptr(out), nthreads)
     return out
+
+
+def circulant_matrix(op, Px, Py) -> np.ndarray:
+    """Dense block-circulant matrix C_P of the generators placed on the Px x Py
+    torus (Z_{m,n} at grid point (m mod Px, n mod Py), zero elsewhere; the
+    embedding behind the FFT route of Sec. I).  Grid point (gx, gy) has index
+    gx + gy Px; the block between points i (row) and j (column) is the placed
+    block at ((ix - jx) mod Px, (iy - jy) mod Py).  [Px Py b, Px Py b]."""
+    op = _op(op)
+    Nx, Ny, b = op.Nx, op.Ny, op.b
+    assert Px >= 2 * Nx - 1 and Py >= 2 * Ny - 1
+    placed = np.zeros((Px, Py, b, b), dtype=np.complex128)
+    for n in range(-(Ny - 1), Ny):
+        for m in range(-(Nx - 1), Nx):
+            placed[m % Px, n % Py] = op.gen[n + Ny - 1, m + Nx - 1]
+    P = Px * Py
+    C = np.empty((P * b, P * b), dtype=np.complex128)
+    for iy in range(Py):
+        for ix in range(Px):
+            i = ix + iy * Px
+            for jy in range(Py):
+                for jx in range(Px):
+                    j = jx + jy * Px
+                    C[i * b:(i + 1) * b, j * b:(j + 1) * b] = placed[(ix - jx) % Px, (iy - jy) % Py]
+    return C
+
+
+def precond_apply(op, X, Px, Py) -> np.ndarray:
+    """Block-circulant preconditioner M^-1 (the paper names no preconditioner;
+    this is the library's reading, an approximate inverse from the same
+    embedding): the element part is crop(C_P^-1 pad(x_A)), with the
+    Px x Py circulant system solved by Gaussian elimination with partial
+    pivoting on the assembled C_P; the rim part is x_r / diag(C)."""
+    op = _op(op)
+    X = _c128(np.atleast_2d(X))
+    R = X.shape[0]
+    Nx, Ny, b, N = op.Nx, op.Ny, op.b, op.N
+    P = Px * Py
+    rhs = np.zeros((R, P * b), dtype=np.complex128)
+    for iy in range(Ny):
+        for ix in range(Nx):
+            e = iy * Nx + ix
+            g = ix + iy * Px
+            rhs[:, g * b:(g + 1) * b] = X[:, e * b:(e + 1) * b]
+    Zg = lu_solve(circulant_matrix(op, Px, Py), rhs)
+    Y = np.empty_like(X)
+    for iy in range(Ny):
+        for ix in range(Nx):
+            e = iy * Nx + ix
+            g = ix + iy * Px
+            Y[:, e * b:(e + 1) * b] = Zg[:, g * b:(g + 1) * b]
+    if op.Nr:
+        Y[:, N:] = X[:, N:] / np.diag(op.rim_rr)[None, :]
+    return Y
 
 
 def max_threads() -> int:

@@ -332,3 +332,58 @@ def test_far_field_single_dipole_and_array_factor(orc):
     F1 = orc.far_field(cs[:1], ts[:1], [1.0], [0.0], [90.0])[0]
     Fn = orc.far_field(cs, ts, np.ones(n), [0.0], [90.0])[0]
     assert np.isclose(Fn[0], n * F1[0], rtol=1e-13)
+
+
+# ------------------------------------------------------------- preconditioner
+def test_circulant_matrix_cropped_is_the_operator(orc):
+    """C_P applied to the zero-padded x_A and cropped is A x_A (P >= 2N - 1)."""
+    prob = sa.make_problem(3, 2, 4, 0, 71)
+    Px, Py = 5, 4
+    C = orc.circulant_matrix(prob, Px, Py)
+    x = sa.rhs_random(prob, 1)[0]
+    w = np.zeros(Px * Py * prob.b, dtype=complex)
+    for iy in range(prob.Ny):
+        for ix in range(prob.Nx):
+            g, e = ix + iy * Px, iy * prob.Nx + ix
+            w[g * prob.b:(g + 1) * prob.b] = x[e * prob.b:(e + 1) * prob.b]
+    u = C @ w
+    y = np.concatenate([u[(ix + iy * Px) * prob.b:(ix + iy * Px + 1) * prob.b]
+                        for iy in range(prob.Ny) for ix in range(prob.Nx)])
+    assert np.allclose(y, orc.matvec(prob, x)[0], rtol=0, atol=1e-13 * np.abs(y).max())
+    # block-circulant: shifting both points by one grid step leaves the block unchanged
+    b = prob.b
+    assert np.array_equal(C[0:b, b:2 * b], C[b:2 * b, 2 * b:3 * b])
+
+
+def test_precond_inverts_block_diagonal_operator(orc):
+    """With only Z_{0,0} nonzero and a diagonal C the preconditioner is the exact inverse."""
+    rng = np.random.default_rng(9)
+    Nx, Ny, b, Nr = 3, 3, 5, 4
+    gen = np.zeros((2 * Ny - 1, 2 * Nx - 1, b, b), dtype=complex)
+    gen[Ny - 1, Nx - 1] = rng.standard_normal((b, b)) + 1j * rng.standard_normal((b, b)) + 4 * np.eye(b)
+    op = orc.Operator(Nx, Ny, b, Nr, gen, np.zeros((Nr, Nx * Ny * b)), np.diag(rng.uniform(1, 2, Nr) + 1j))
+    x = rng.standard_normal((2, op.Nt)) + 1j * rng.standard_normal((2, op.Nt))
+    y = orc.precond_apply(op, orc.matvec(op, x), 5, 6)
+    assert np.allclose(y, x, rtol=0, atol=1e-12)
+
+
+def test_precond_matches_fft_circulant_solve(orc):
+    """Element part equals the circulant solve done by numpy FFT and per-frequency inverses."""
+    prob = sa.make_problem(3, 2, 4, 5, 72)
+    Px, Py = 6, 3
+    x = sa.rhs_random(prob, 2)
+    y = orc.precond_apply(prob, x, Px, Py)
+    b, Nx, Ny = prob.b, prob.Nx, prob.Ny
+    placed = np.zeros((Px, Py, b, b), dtype=complex)
+    for n in range(-(Ny - 1), Ny):
+        for m in range(-(Nx - 1), Nx):
+            placed[m % Px, n % Py] = prob.gen[n + Ny - 1, m + Nx - 1]
+    Ch = np.fft.fft2(placed, axes=(0, 1))
+    for r in range(2):
+        w = np.zeros((Px, Py, b), dtype=complex)
+        w[:Nx, :Ny] = x[r, :prob.N].reshape(Ny, Nx, b).transpose(1, 0, 2)
+        Wh = np.fft.fft2(w, axes=(0, 1))
+        z = np.fft.ifft2(np.linalg.solve(Ch, Wh[..., None])[..., 0], axes=(0, 1))
+        ref = z[:Nx, :Ny].transpose(1, 0, 2).reshape(-1)
+        assert np.allclose(y[r, :prob.N], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+        assert np.allclose(y[r, prob.N:], x[r, prob.N:] / np.diag(prob.rim_rr), rtol=1e-14)
