@@ -145,6 +145,8 @@ typedef struct {
                           with FP64 residual refinement; TP_FP32 is not a solve mode */
     int x0_given;      /* 1: x holds the initial guess; 0: start from zero */
     double inner_tol;  /* TP_MIXED: relative residual target of each inner solve */
+    int precond;       /* 1: right-precondition with the plan's block-circulant preconditioner
+                          (toeplitz_precond_create); 0: none */
 } tp_solve_opts;
 
 /* Per-column result of toeplitz_solve. */
@@ -155,7 +157,8 @@ typedef struct {
     double relres;     /* final ||v - Z x||_2 / ||v||_2 from an FP64 matvec */
 } tp_solve_info;
 
-/* Defaults: tol 1e-8, restart = plan's, max_iter 2000, max_outer 50, TP_FP64, x0 zero, inner_tol 1e-4. */
+/* Defaults: tol 1e-8, restart = plan's, max_iter 2000, max_outer 50, TP_FP64, x0 zero, inner_tol 1e-4,
+   no preconditioner. */
 void toeplitz_solve_opts_default(tp_solve_opts *opts);
 
 /*
@@ -218,6 +221,33 @@ tp_status toeplitz_batch_end(tp_plan p);
  * Synchronous.  Errors: TP_E_INVAL, TP_E_UNSUPPORTED, TP_E_HIP.
  */
 tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void *host_out);
+
+/*
+ * Block-circulant preconditioner (the paper gives none; Sec. II-D leaves the
+ * solver's details to another reference).  With C_P the block circulant of the
+ * generators placed on the plan's Px x Py grid (the embedding the operator uses),
+ *   M^-1 x = [ crop(C_P^-1 pad(x_A)) ; x_r / diag(C) ],
+ * applied as an inverse DFT of S(k) DFT(pad x_A) with S(k) = (sum of the
+ * placed generators times exp(-2 pi i (kx m / Px + ky n / Py)))^-1 per
+ * frequency.  GMRES then solves Z M^-1 u = v and returns x = M^-1 u (right
+ * preconditioning: the residual it tests is the true one).
+ *
+ * toeplitz_precond_bytes: device bytes the preconditioner of this plan needs
+ *   (S per precision the plan holds, 1/diag(C), a status word).
+ * toeplitz_precond_create: build it into dev_buf (caller-owned, >= that many
+ *   bytes, 256-byte aligned, kept until toeplitz_plan_destroy) by inverting
+ *   every b x b frequency block in FP64 (Gauss-Jordan, partial pivoting).
+ *   Needs a plan with the FP64 copy (TP_FP64 or TP_MIXED; else
+ *   TP_E_UNSUPPORTED).  Synchronises hip_stream; a singular block or a zero
+ *   diagonal entry of C returns TP_E_BREAKDOWN.  A second call rebuilds.
+ * toeplitz_precond_apply: y = M^-1 x for nrhs columns (same conventions as
+ *   toeplitz_matvec; x and y must not overlap).  TP_E_INVAL without a
+ *   preconditioner.  Asynchronous on hip_stream.
+ */
+tp_status toeplitz_precond_bytes(tp_plan p, size_t *bytes);
+tp_status toeplitz_precond_create(tp_plan p, void *dev_buf, size_t dev_bytes, void *hip_stream);
+tp_status toeplitz_precond_apply(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int nrhs,
+                                 void *hip_stream);
 
 /*
  * Post-steps on solved currents (Sec. III; they need no plan).

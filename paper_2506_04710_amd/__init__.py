@@ -121,6 +121,32 @@ class Plan:
                                          ctypes.c_void_p(y2.data_ptr()), ldy, R, _stream_handle(stream)))
         return y.reshape(x.shape) if out is None else out
 
+    def precond_create(self, stream=None):
+        """Build the block-circulant preconditioner into a second device buffer
+        owned by this plan object (needs an FP64 or mixed plan)."""
+        import torch
+        L = _lib.lib()
+        n = ctypes.c_size_t(0)
+        check(L.toeplitz_precond_bytes(self._h, ctypes.byref(n)))
+        self.pbuf = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.pbuf.data_ptr()
+        off = (-base) % 256
+        with torch.cuda.device(self.device):
+            check(L.toeplitz_precond_create(self._h, ctypes.c_void_p(base + off), n.value, _stream_handle(stream)))
+        return self
+
+    def precond_apply(self, x, which=None, stream=None):
+        """y = M^-1 x with the plan's preconditioner (complex128 'fp64' or complex64 'fp32')."""
+        import torch
+        if which is None:
+            which = "fp64" if x.dtype == torch.complex128 else "fp32"
+        dt = torch.complex128 if which == "fp64" else torch.complex64
+        x2, R, ldx = self._cols(x, dt)
+        y = torch.empty((R, self.Nt), dtype=dt, device=x.device)
+        check(_lib.lib().toeplitz_precond_apply(self._h, PREC[which], ctypes.c_void_p(x2.data_ptr()), ldx,
+                                                ctypes.c_void_p(y.data_ptr()), self.Nt, R, _stream_handle(stream)))
+        return y.reshape(x.shape)
+
     STAGES = ("rim_main", "fwd_x", "fwd_y", "prod", "inv_y", "inv_x", "rim_finish")
 
     def matvec_profile(self, x, which=None, reps=20, stream=None) -> dict:
@@ -138,7 +164,7 @@ class Plan:
         return dict(zip(self.STAGES, list(ms)))
 
     def solve(self, v, mode="mixed", tol=1e-8, restart=0, max_iter=2000, max_outer=50, inner_tol=1e-4, x0=None,
-              stream=None, raise_on_noconv=False):
+              stream=None, raise_on_noconv=False, precond=False):
         """Solve Z x = v for the columns of v (complex128 cuda tensor (Nt,) or (R, Nt))."""
         import torch
         v2, R, ldv = self._cols(v, torch.complex128)
@@ -151,6 +177,7 @@ class Plan:
         _lib.lib().toeplitz_solve_opts_default(ctypes.byref(o))
         o.tol, o.restart, o.max_iter, o.max_outer = tol, restart, max_iter, max_outer
         o.mode, o.x0_given, o.inner_tol = PREC[mode], 1 if x0 is not None else 0, inner_tol
+        o.precond = 1 if precond else 0
         info = (_lib.SolveInfo * R)()
         st = _lib.lib().toeplitz_solve(self._h, ctypes.c_void_p(v2.data_ptr()), ldv, ctypes.c_void_p(x2.data_ptr()),
                                        ldx, R, ctypes.byref(o), info, _stream_handle(stream))

@@ -26,7 +26,7 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_solve_opts_default", "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_plan_destroy",
            "toeplitz_last_error", "toeplitz_batch_begin", "toeplitz_batch_admit", "toeplitz_batch_release",
            "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end", "toeplitz_port_smatrix",
-           "toeplitz_far_field")
+           "toeplitz_far_field", "toeplitz_precond_bytes", "toeplitz_precond_create", "toeplitz_precond_apply")
 
 
 class PlanDesc(ctypes.Structure):
@@ -41,7 +41,7 @@ class PlanDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("mode", ctypes.c_int), ("x0_given", ctypes.c_int),
-                ("inner_tol", ctypes.c_double)]
+                ("inner_tol", ctypes.c_double), ("precond", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -86,6 +86,9 @@ def lib():
         cd = ctypes.c_double
         L.toeplitz_port_smatrix.argtypes = [ci, cl, vp, cl, vp, vp, cd, vp, cl, vp, sz, vp]
         L.toeplitz_far_field.argtypes = [ci, ci, ci, ci, cd, cd, vp, vp, vp, vp, vp, cl, ci, vp, ci, cd, cd, vp, vp]
+        L.toeplitz_precond_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.toeplitz_precond_create.argtypes = [vp, vp, sz, vp]
+        L.toeplitz_precond_apply.argtypes = [vp, ci, vp, cl, vp, cl, ci, vp]
         L.toeplitz_plan_destroy.argtypes = [vp]
         L.toeplitz_plan_destroy.restype = None
         L.toeplitz_last_error.restype = ctypes.c_char_p
@@ -93,7 +96,8 @@ def lib():
                      "toeplitz_matvec_profile",
                      "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_batch_begin", "toeplitz_batch_admit",
                      "toeplitz_batch_release", "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end",
-                     "toeplitz_port_smatrix", "toeplitz_far_field"):
+                     "toeplitz_port_smatrix", "toeplitz_far_field", "toeplitz_precond_bytes",
+                     "toeplitz_precond_create", "toeplitz_precond_apply"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib

@@ -374,6 +374,89 @@ tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void 
     return e == hipSuccess ? TP_OK : hip_fail(e, "spectrum copy");
 }
 
+static size_t precond_layout(tp_plan p, size_t *s64, size_t *s32, size_t *d64, size_t *d32, size_t *flag) {
+    const size_t P = (size_t)p->Px * p->Py, bb = (size_t)p->b * p->b;
+    size_t off = 0;
+    auto take = [&](bool on, size_t bytes) {
+        const size_t o = off;
+        if (on) off += al(bytes);
+        return on ? o : (size_t)-1;
+    };
+    *s64 = take(p->G64 != nullptr, P * bb * 16);
+    *s32 = take(p->G32 != nullptr, P * bb * 8);
+    *d64 = take(p->G64 != nullptr && p->Nr > 0, (size_t)p->Nr * 16);
+    *d32 = take(p->G32 != nullptr && p->Nr > 0, (size_t)p->Nr * 8);
+    *flag = take(true, 256);
+    return off;
+}
+
+tp_status toeplitz_precond_bytes(tp_plan p, size_t *bytes) {
+    if (!p || !bytes) return fail(TP_E_INVAL, "plan or bytes is NULL");
+    size_t a, b, c, d, f;
+    *bytes = precond_layout(p, &a, &b, &c, &d, &f);
+    return TP_OK;
+}
+
+tp_status toeplitz_precond_create(tp_plan p, void *dev_buf, size_t dev_bytes, void *hip_stream) {
+    if (!p || !dev_buf) return fail(TP_E_INVAL, "plan or dev_buf is NULL");
+    if (!p->G64) return fail(TP_E_UNSUPPORTED, "the preconditioner is built from the FP64 spectrum");
+    if ((reinterpret_cast<uintptr_t>(dev_buf) & 255) != 0) return fail(TP_E_INVAL, "dev_buf must be 256-byte aligned");
+    if (p->batch && solver_batch_active(p)) return fail(TP_E_INVAL, "a continuous batch is active on this plan");
+    size_t o64, o32, od64, od32, of;
+    const size_t need = precond_layout(p, &o64, &o32, &od64, &od32, &of);
+    if (dev_bytes < need) return fail(TP_E_NOMEM, "dev_buf smaller than toeplitz_precond_bytes()");
+    char *base = static_cast<char *>(dev_buf);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t nS = (size_t)p->Px * p->Py * p->b * p->b;
+    p->has_precond = 0;
+    p->S64 = reinterpret_cast<c128 *>(base + o64);
+    p->S32 = o32 != (size_t)-1 ? reinterpret_cast<c64 *>(base + o32) : nullptr;
+    p->D64 = od64 != (size_t)-1 ? reinterpret_cast<c128 *>(base + od64) : nullptr;
+    p->D32 = od32 != (size_t)-1 ? reinterpret_cast<c64 *>(base + od32) : nullptr;
+    int *flag = reinterpret_cast<int *>(base + of);
+    hipError_t e;
+    if ((e = hipMemsetAsync(flag, 0, sizeof(int), st)) ||
+        (e = hipMemcpyAsync(p->S64, p->G64, nS * 16, hipMemcpyDeviceToDevice, st)) ||
+        (e = precond_build(p, p->S64, flag, st)))
+        return hip_fail(e, "preconditioner build");
+    if (p->S32 && (e = cast_to_c64(p->S64, p->S32, (long)nS, st))) return hip_fail(e, "preconditioner cast");
+    if (p->D32 && (e = cast_to_c64(p->D64, p->D32, p->Nr, st))) return hip_fail(e, "preconditioner cast");
+    int hflag = 0;
+    if ((e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st)) || (e = hipStreamSynchronize(st)))
+        return hip_fail(e, "preconditioner status");
+    if (hflag) return fail(TP_E_BREAKDOWN, "a spectrum block or a diagonal entry of C is singular");
+    p->has_precond = 1;
+    return TP_OK;
+}
+
+tp_status toeplitz_precond_apply(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int nrhs,
+                                 void *hip_stream) {
+    if (!p) return fail(TP_E_INVAL, "plan is NULL");
+    if (!p->has_precond) return fail(TP_E_INVAL, "the plan has no preconditioner (toeplitz_precond_create)");
+    if (!x || !y) return fail(TP_E_INVAL, "x or y is NULL");
+    if (nrhs < 1 || nrhs > p->max_rhs) return fail(TP_E_INVAL, "nrhs must be in [1, max_rhs]");
+    if (ldx < p->Nt || ldy < p->Nt) return fail(TP_E_INVAL, "leading dimension smaller than Nt");
+    const size_t es = which == TP_FP64 ? 16 : 8;
+    const char *xa = (const char *)x, *ya = (const char *)y;
+    const size_t xb = ((size_t)ldx * (nrhs - 1) + p->Nt) * es, yb = ((size_t)ldy * (nrhs - 1) + p->Nt) * es;
+    if (xa < ya + yb && ya < xa + xb) return fail(TP_E_INVAL, "x and y overlap");
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e;
+    if (which == TP_FP64) {
+        if (!p->S64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 preconditioner");
+        e = precond_fp64(p, Cols<const c128>{(const c128 *)x, ldx, nullptr}, Cols<c128>{(c128 *)y, ldy, nullptr},
+                         Cols<const c128>{nullptr, 0, nullptr}, nrhs, st);
+    } else if (which == TP_FP32) {
+        if (!p->S32) return fail(TP_E_UNSUPPORTED, "plan holds no FP32 preconditioner");
+        e = precond_fp32(p, Cols<const c64>{(const c64 *)x, ldx, nullptr}, Cols<c64>{(c64 *)y, ldy, nullptr},
+                         Cols<const c64>{nullptr, 0, nullptr}, nrhs, st);
+    } else {
+        return fail(TP_E_INVAL, "precision must be TP_FP64 or TP_FP32");
+    }
+    if (e != hipSuccess) return hip_fail(e, "preconditioner launch");
+    return TP_OK;
+}
+
 void toeplitz_solve_opts_default(tp_solve_opts *o) {
     if (!o) return;
     o->tol = 1e-8;
@@ -383,6 +466,7 @@ void toeplitz_solve_opts_default(tp_solve_opts *o) {
     o->mode = TP_FP64;
     o->x0_given = 0;
     o->inner_tol = 1e-4;
+    o->precond = 0;
 }
 
 tp_status toeplitz_solve(tp_plan p, const void *v, long ldv, void *x, long ldx, int nrhs, const tp_solve_opts *opts,
@@ -408,6 +492,7 @@ tp_status toeplitz_solve(tp_plan p, const void *v, long ldv, void *x, long ldx, 
     } else {
         return fail(TP_E_INVAL, "solve mode must be TP_FP64 or TP_MIXED");
     }
+    if (o.precond && !p->has_precond) return fail(TP_E_INVAL, "precond requested but the plan has none");
     return solve_run(p, (const c128 *)v, ldv, (c128 *)x, ldx, nrhs, o, info, (hipStream_t)hip_stream);
 }
 
@@ -425,6 +510,7 @@ static tp_status check_batch_opts(tp_plan p, tp_solve_opts &o, const tp_solve_op
     } else {
         return fail(TP_E_INVAL, "solve mode must be TP_FP64 or TP_MIXED");
     }
+    if (o.precond && !p->has_precond) return fail(TP_E_INVAL, "precond requested but the plan has none");
     return TP_OK;
 }
 

@@ -158,6 +158,11 @@ struct tp_plan_s {
     tp::c128 *B64, *BE64, *C64;   // B [Nr][N], B_er^T [Nr][N] (non-reciprocal), C [Nr][Nr]
     tp::c64 *B32, *BE32, *C32;
     size_t spectrum_bytes, rim_bytes;
+    // block-circulant preconditioner, built on request into a second caller
+    // buffer: per-frequency S = G^-1 / (Px Py)^2 and D = 1 / diag(C)
+    tp::c128 *S64 = nullptr, *D64 = nullptr;
+    tp::c64 *S32 = nullptr, *D32 = nullptr;
+    int has_precond = 0;
     // transform tables
     tp::FFTDesc fx, fy;
     // matvec workspace
@@ -177,7 +182,7 @@ struct tp_plan_s {
     hipEvent_t ev[4] = {};
     void *host_status = nullptr;
     struct GraphEntry {
-        int mode, nslots, m, steps;
+        int mode, nslots, m, steps, precond;
         hipGraphExec_t exec;
     };
     GraphEntry graphs[8] = {};

@@ -39,7 +39,7 @@ enum : int { PH_IDLE = 0, PH_INIT = 1, PH_ARN = 2, PH_RES = 3, PH_DONE = 4 };
 // committed per-column state (two copies, by super-step parity)
 struct SlotState {
     int phase, j, xzero, iters;
-    int outer, status, first, pad;
+    int outer, status, first, pend;    // pend: a preconditioned x update waits in W (RES)
     double thr, beta, vnorm, relres;
 };
 // fixed per-solve column data
@@ -81,7 +81,11 @@ struct Eng {
     c128 **tout;
     const c128 **rin;                  // FP64 residual tables (mixed)
     c128 **rout;
+    const c128 **pin;                  // preconditioner tables: out = base + M^-1 in
+    c128 **pout;
+    const c128 **pbase;
     int nslots;
+    int prec;                          // right preconditioning on
     __device__ c128 *vec(int s, int i) const { return V + ((long)s * (m + 1) + i) * Nt; }
 };
 
@@ -114,7 +118,7 @@ static EngLayout eng_layout(long Nt, int m, int R) {
     L.cs = take((size_t)R * m * 8);
     L.PN = take((size_t)R * kMaxBlocks * 8);
     L.PR = take((size_t)R * 2 * kMaxBlocks * 8);
-    L.tabs = take((size_t)R * 4 * sizeof(void *));
+    L.tabs = take((size_t)R * 7 * sizeof(void *));
     L.total = off;
     return L;
 }
@@ -314,12 +318,14 @@ __device__ __forceinline__ Next transition(const Eng &E, int s, const SlotState 
     const SlotConst &C = E.sc[s];
     if (P.phase == PH_INIT) {
         nx.S.phase = PH_RES;
+        nx.S.pend = 0;
     } else if (P.phase == PH_ARN) {
         const SlotDec &D = E.dec[s];
         nx.S.iters = P.iters + 1;
         if (D.end) {
             nx.S.phase = PH_RES;
             nx.S.xzero = 0;
+            nx.S.pend = E.prec;
         } else {
             nx.S.j = P.j + 1;
         }
@@ -344,6 +350,7 @@ __device__ __forceinline__ Next transition(const Eng &E, int s, const SlotState 
         } else {
             nx.S.phase = PH_ARN;
             nx.S.j = 0;
+            nx.S.pend = 0;
             nx.S.beta = beta;
             const double plain_thr = 0.5 * C.tol * vn;
             nx.S.thr = E.mixed ? fmax(C.inner_tol * beta, plain_thr) : plain_thr;
@@ -362,14 +369,30 @@ __global__ void __launch_bounds__(kThreads) k_commit(Eng E, int par) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         E.st[par * E.nslots + s] = nx.S;
         const SlotConst &C = E.sc[s];
-        const c128 *in = nullptr, *rin = nullptr;
-        c128 *out = nullptr, *rout = nullptr;
+        const c128 *in = nullptr, *rin = nullptr, *pin = nullptr, *pbase = nullptr;
+        c128 *out = nullptr, *rout = nullptr, *pout = nullptr;
+        c128 *Ws = E.W + (long)s * E.Nt;
         if (nx.S.phase == PH_ARN) {
             in = E.vec(s, nx.S.j);
             out = E.vec(s, nx.S.j + 1);
+            if (E.prec) {          // w = Z (M^-1 v_j): M^-1 v_j goes through W
+                pin = in;
+                pout = Ws;
+                in = Ws;
+            }
         } else if (nx.S.phase == PH_RES && !nx.S.xzero) {
             rin = C.x;
-            rout = E.W + (long)s * E.Nt;
+            rout = Ws;
+            if (nx.S.pend) {       // x += M^-1 (V y) before the residual
+                pin = Ws;
+                pout = C.x;
+                pbase = C.x;
+            }
+        }
+        if (E.prec) {
+            E.pin[s] = pin;
+            E.pout[s] = pout;
+            E.pbase[s] = pbase;
         }
         if (E.mixed) {
             E.tin[s] = in;
@@ -521,14 +544,16 @@ __global__ void __launch_bounds__(kThreads) k_tail(Eng E, int par) {
             for (int l = threadIdx.x; l < i; l += kThreads) ys[l] = ys[l] - H[(long)i * (m + 1) + l] * yi;
             __syncthreads();
         }
-        c128 *x = C.x;
+        // x += V y, or with right preconditioning u = V y into W (the next
+        // super-step applies x += M^-1 u)
+        c128 *x = E.prec ? E.W + (long)s * E.Nt : C.x;
         const int g0 = threadIdx.x >> 8, nr = rounds(E);
 #pragma unroll
         for (int e = 0; e < kMaxEPT; ++e) {
             if (e >= nr) break;
             const long n = elem(E, e);
             const c128 sum = basis_combo(E, s, k - 1, n, E.Nt, ys, part);
-            if (g0 == 0 && n < E.Nt) x[n] = x[n] + sum;
+            if (g0 == 0 && n < E.Nt) x[n] = E.prec ? sum : x[n] + sum;
         }
     } else if (S.phase == PH_RES) {
         const c128 *v = C.v, *Wz = E.W + (long)s * E.Nt;
@@ -561,6 +586,12 @@ static hipError_t super_step(tp_plan pl, const Eng &E, int par, hipStream_t st) 
     const dim3 gv(E.nb, E.nslots), blk(kThreads);
     hipLaunchKernelGGL(k_commit, gv, blk, 0, st, E, par);
     hipError_t e;
+    if (E.prec) {
+        const Cols<const c128> pi{nullptr, 0, E.pin}, pb{nullptr, 0, E.pbase};
+        const Cols<c128> po{nullptr, 0, E.pout};
+        e = E.mixed ? precond_fp32_wide(pl, pi, po, pb, E.nslots, st) : precond_fp64(pl, pi, po, pb, E.nslots, st);
+        if (e) return e;
+    }
     if (E.mixed) {
         e = matvec_fp32_wide(pl, Cols<const c128>{nullptr, 0, E.tin}, Cols<c128>{nullptr, 0, E.tout}, E.nslots, st);
         if (e) return e;
@@ -628,7 +659,8 @@ static hipError_t solver_resources(tp_plan pl) {
 static hipError_t step_graph(tp_plan pl, const Eng &E, hipGraphExec_t *out) {
     for (int i = 0; i < pl->ngraphs; ++i) {
         const auto &g = pl->graphs[i];
-        if (g.mode == E.mixed && g.nslots == E.nslots && g.m == E.m && g.steps == kStepsPerGraph) {
+        if (g.mode == E.mixed && g.nslots == E.nslots && g.m == E.m && g.steps == kStepsPerGraph &&
+            g.precond == E.prec) {
             *out = g.exec;
             return hipSuccess;
         }
@@ -653,7 +685,7 @@ static hipError_t step_graph(tp_plan pl, const Eng &E, hipGraphExec_t *out) {
         for (int i = 1; i < 8; ++i) pl->graphs[i - 1] = pl->graphs[i];
         pl->ngraphs = 7;
     }
-    pl->graphs[pl->ngraphs++] = {E.mixed, E.nslots, E.m, kStepsPerGraph, ex};
+    pl->graphs[pl->ngraphs++] = {E.mixed, E.nslots, E.m, kStepsPerGraph, E.prec, ex};
     *out = ex;
     return hipSuccess;
 }
@@ -695,6 +727,10 @@ static Eng engine_make(tp_plan pl, int m, int mixed, int nslots) {
     E.tout = (c128 **)(tabs + pl->max_rhs);
     E.rin = (const c128 **)(tabs + 2 * pl->max_rhs);
     E.rout = (c128 **)(tabs + 3 * pl->max_rhs);
+    E.pin = (const c128 **)(tabs + 4 * pl->max_rhs);
+    E.pout = (c128 **)(tabs + 5 * pl->max_rhs);
+    E.pbase = (const c128 **)(tabs + 6 * pl->max_rhs);
+    E.prec = 0;
     return E;
 }
 
@@ -721,7 +757,8 @@ tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int 
         return fail(TP_E_UNSUPPORTED, "solves are limited to Nt <= " + std::to_string(solver_max_nt()));
     if (pl->batch && static_cast<BatchEngine *>(pl->batch)->active)
         return fail(TP_E_INVAL, "a continuous batch is active on this plan");
-    const Eng E = engine_make(pl, o.restart, o.mode == TP_MIXED, nrhs);
+    Eng E = engine_make(pl, o.restart, o.mode == TP_MIXED, nrhs);
+    E.prec = o.precond ? 1 : 0;
     hipError_t e;
     if ((e = solver_resources(pl))) return hip_fail(e, "solver resources");
     hipStream_t cs = pl->cs;
@@ -806,6 +843,7 @@ tp_status batch_begin(tp_plan pl, const tp_solve_opts &o) {
     }
     if ((e = hipStreamSynchronize(pl->cs))) return hip_fail(e, "batch begin sync");
     B->E = engine_make(pl, o.restart, o.mode == TP_MIXED, pl->max_rhs);
+    B->E.prec = o.precond ? 1 : 0;
     B->cst.assign(pl->max_rhs, SlotConst{nullptr, nullptr, o.tol, o.inner_tol, o.max_iter, o.max_outer});
     B->pending = 0;
     B->nstep = 0;
@@ -813,7 +851,7 @@ tp_status batch_begin(tp_plan pl, const tp_solve_opts &o) {
     std::memset(&idle, 0, sizeof(idle));
     idle.phase = PH_IDLE;
     std::vector<SlotState> hs(2 * (size_t)pl->max_rhs, idle);
-    std::vector<void *> ht(4 * (size_t)pl->max_rhs, nullptr);
+    std::vector<void *> ht(7 * (size_t)pl->max_rhs, nullptr);
     if ((e = hipMemcpyAsync(B->E.st, hs.data(), sizeof(SlotState) * hs.size(), hipMemcpyHostToDevice, pl->cs)) ||
         (e = hipMemcpyAsync(B->E.sc, B->cst.data(), sizeof(SlotConst) * B->cst.size(), hipMemcpyHostToDevice,
                             pl->cs)) ||
@@ -925,5 +963,7 @@ tp_status batch_end(tp_plan pl) {
 }
 
 hipStream_t solver_stream(tp_plan pl) { return pl->cs; }
+
+bool solver_batch_active(tp_plan pl) { return active_batch(pl) != nullptr; }
 
 }  // namespace tp

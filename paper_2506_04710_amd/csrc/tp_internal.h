@@ -21,6 +21,14 @@ constexpr int kMatvecStages = 7;   // rim pass, x DFT, y DFT, product, inverse y
 hipError_t matvec_fp64_timed(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st, hipEvent_t *ev);
 hipError_t matvec_fp32_timed(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStream_t st, hipEvent_t *ev);
 hipError_t spectrum_build(tp_plan pl, const c128 *gen_dev, c128 *tmp, hipStream_t st);
+// block-circulant preconditioner: y = base + M^-1 x (base columns optional)
+hipError_t precond_fp64(tp_plan pl, Cols<const c128> x, Cols<c128> y, Cols<const c128> base, int R, hipStream_t st);
+hipError_t precond_fp32(tp_plan pl, Cols<const c64> x, Cols<c64> y, Cols<const c64> base, int R, hipStream_t st);
+hipError_t precond_fp32_wide(tp_plan pl, Cols<const c128> x, Cols<c128> y, Cols<const c128> base, int R,
+                             hipStream_t st);
+// plan-time: invert every spectrum block in place (FP64, partial pivoting),
+// scale by 1 / (Px Py)^2; *flag (device int) is set nonzero on a zero pivot
+hipError_t precond_build(tp_plan pl, c128 *S, int *flag, hipStream_t st);
 hipError_t cast_to_c64(const c128 *in, c64 *out, long n, hipStream_t st);
 
 // plan-time transform tables (tp_plan.cpp side of tp_capi.hip)
@@ -44,6 +52,7 @@ tp_status batch_step(tp_plan pl, int ngraphs);
 tp_status batch_poll(tp_plan pl, int lag, int wait, int *phases, tp_solve_info *info);
 tp_status batch_end(tp_plan pl);
 hipStream_t solver_stream(tp_plan pl);
+bool solver_batch_active(tp_plan pl);
 
 // matrix-core kernels for many right-hand sides (tp_mfma.hip)
 template <typename T>

@@ -296,6 +296,25 @@ __device__ __forceinline__ void rim_finish_wave(const cpx<T> *__restrict__ part,
     if (lane == 0) ycol[N + row] = cvt<typename Out::value_type>(s);
 }
 
+// Preconditioner rim entries: y_r = base_r + D x_r (D = 1 / diag(C)); one wave
+// per (rim row block of 64, column).
+template <typename T, typename In, typename Out>
+__device__ __forceinline__ void diag_finish_wave(const cpx<T> *__restrict__ D, Cols<const In> x, Cols<Out> y,
+                                                 Cols<const Out> acc, int accumulate, long N, int Nr, int row,
+                                                 int c) {
+    const int lane = threadIdx.x & 63;
+    if (row >= Nr) return;
+    const In *xcol = x.col(c);
+    Out *ycol = y.col(c);
+    if (!xcol || !ycol) return;
+    const Out *ac = accumulate ? acc.col(c) : nullptr;
+    if (lane == 0) {
+        Out v = cvt<typename Out::value_type>(D[row] * cvt<T>(xcol[N + row]));
+        if (ac) v = v + ac[N + row];
+        ycol[N + row] = v;
+    }
+}
+
 // ------------------------------------------------ fused single-column path
 // Workgroup = (frequency column kx, 8 spectrum rows p0..p0+7).  It
 //   1. loads the x-transformed column X1[iy][kx][0..b) (iy < Ny) into LDS and
@@ -507,8 +526,9 @@ __global__ void __launch_bounds__(256) k_spec_rim(const cpx<T> *__restrict__ G, 
 // waves, in one launch: blocks [0, ninv) transform, the rest finish rim rows.
 template <typename T, typename In, typename Out>
 __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in, int R, int Nx, int b, FFTDesc fx,
-                                                   int lgCC, int nchunk, Cols<Out> y, int accumulate, int ninv,
-                                                   const cpx<T> *__restrict__ part, const cpx<T> *__restrict__ Cm,
+                                                   int lgCC, int nchunk, Cols<Out> y, int accumulate,
+                                                   Cols<const Out> acc, int ninv, const cpx<T> *__restrict__ part,
+                                                   const cpx<T> *__restrict__ Cm, const cpx<T> *__restrict__ D,
                                                    Cols<const In> x, long N, int Nr, int nslab) {
     extern __shared__ char smem_raw[];
     const int blk = blockIdx.x;
@@ -516,7 +536,10 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
         const int f = blk - ninv, w = threadIdx.x >> 6;
         const int nrowblk = (Nr + 3) >> 2;
         const int c = f / nrowblk, row = (f - c * nrowblk) * 4 + w;
-        rim_finish_wave<T, In, Out>(part, Cm, x, y, R, N, Nr, nslab, row, c);
+        if (D)
+            diag_finish_wave<T, In, Out>(D, x, y, acc, accumulate, N, Nr, row, c);
+        else
+            rim_finish_wave<T, In, Out>(part, Cm, x, y, R, N, Nr, nslab, row, c);
         return;
     }
     cpx<T> *twl = reinterpret_cast<cpx<T> *>(smem_raw);
@@ -537,10 +560,15 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
             const int r = c / b, p = c - r * b;
             Out *yc = y.col(r);
             if (!yc) continue;
-            Out *dst = yc + (long)(iy * Nx + ix) * b + p;
-            cpx<T> v = buf[i];
-            if (accumulate) v = v + cvt<T>(*dst);
-            *dst = cvt<typename Out::value_type>(v);
+            const long e = (long)(iy * Nx + ix) * b + p;
+            // the added term keeps the output's precision (an FP64 solution
+            // vector updated by an FP32 preconditioner stays FP64)
+            Out v = cvt<typename Out::value_type>(buf[i]);
+            if (accumulate) {
+                const Out *ac = acc.col(r);
+                if (ac) v = v + ac[e];
+            }
+            yc[e] = v;
         }
     }
 }
@@ -608,17 +636,20 @@ __global__ void __launch_bounds__(256) k_fft2_fwd(Cols<const In> x, int R, int N
 template <typename T, typename In, typename Out>
 __global__ void __launch_bounds__(256) k_fft2_inv_fin(const cpx<T> *__restrict__ in, int R, int Nx, int Ny, int b,
                                                       FFTDesc fx, FFTDesc fy, int lgCC, int XS, Cols<Out> y,
-                                                      int accumulate,
-                                                      int ninv, const cpx<T> *__restrict__ part,
-                                                      const cpx<T> *__restrict__ Cm, Cols<const In> x, long N,
-                                                      int Nr, int nslab) {
+                                                      int accumulate, Cols<const Out> acc, int ninv,
+                                                      const cpx<T> *__restrict__ part,
+                                                      const cpx<T> *__restrict__ Cm, const cpx<T> *__restrict__ D,
+                                                      Cols<const In> x, long N, int Nr, int nslab) {
     extern __shared__ char smem_raw[];
     const int blk = blockIdx.x;
     if (blk >= ninv) {
         const int f = blk - ninv, w = threadIdx.x >> 6;
         const int nrowblk = (Nr + 3) >> 2;
         const int c = f / nrowblk, row = (f - c * nrowblk) * 4 + w;
-        rim_finish_wave<T, In, Out>(part, Cm, x, y, R, N, Nr, nslab, row, c);
+        if (D)
+            diag_finish_wave<T, In, Out>(D, x, y, acc, accumulate, N, Nr, row, c);
+        else
+            rim_finish_wave<T, In, Out>(part, Cm, x, y, R, N, Nr, nslab, row, c);
         return;
     }
     cpx<T> *twx = reinterpret_cast<cpx<T> *>(smem_raw);
@@ -647,12 +678,14 @@ __global__ void __launch_bounds__(256) k_fft2_inv_fin(const cpx<T> *__restrict__
     Out *yc = c < C ? y.col(c / b) : nullptr;
     if (!yc) return;
     yc += c % b;
+    const Out *ac = accumulate ? acc.col(c / b) : nullptr;
+    if (ac) ac += c % b;
     const int es = kBlock >> lgCC, ne = Nx * Ny;
     for (int eb = threadIdx.x >> lgCC; eb < ne; eb += 8 * es) {
         Out old[8];
-        if (accumulate) {
+        if (ac) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) old[u] = ldg(yc + (long)min(eb + u * es, ne - 1) * b);
+            for (int u = 0; u < 8; ++u) old[u] = ldg(ac + (long)min(eb + u * es, ne - 1) * b);
 #pragma unroll
             for (int u = 0; u < 8; ++u) pin(old[u]);
         }
@@ -661,9 +694,9 @@ __global__ void __launch_bounds__(256) k_fft2_inv_fin(const cpx<T> *__restrict__
             const int e = eb + u * es;
             if (e < ne) {
                 const int iy = e / Nx, ix = e - iy * Nx;
-                cpx<T> v = buf[ix * XS + (iy << lgCC) + cl];
-                if (accumulate) v = v + cvt<T>(old[u]);
-                stg(yc + (long)e * b, cvt<typename Out::value_type>(v));
+                Out v = cvt<typename Out::value_type>(buf[ix * XS + (iy << lgCC) + cl]);
+                if (ac) v = v + old[u];
+                stg(yc + (long)e * b, v);
             }
         }
     }
@@ -717,6 +750,8 @@ struct OpPtrs<double> {
     static const c128 *B(tp_plan p) { return p->B64; }
     static const c128 *BE(tp_plan p) { return p->BE64; }
     static const c128 *C(tp_plan p) { return p->C64; }
+    static const c128 *S(tp_plan p) { return p->S64; }
+    static const c128 *D(tp_plan p) { return p->D64; }
 };
 template <>
 struct OpPtrs<float> {
@@ -724,6 +759,8 @@ struct OpPtrs<float> {
     static const c64 *B(tp_plan p) { return p->B32; }
     static const c64 *BE(tp_plan p) { return p->BE32; }
     static const c64 *C(tp_plan p) { return p->C32; }
+    static const c64 *S(tp_plan p) { return p->S32; }
+    static const c64 *D(tp_plan p) { return p->D32; }
 };
 
 static int next_pow2(int v) {
@@ -747,33 +784,34 @@ constexpr size_t kLdsLimit = 160 * 1024;
 constexpr int kMfmaMinR = TP_MFMA_MIN_R;
 
 template <typename T, typename In, typename Out, int VPL, int E, bool NBE>
-static void launch_spec_rim(tp_plan pl, Cols<const In> x, Cols<Out> y, cpx<T> *gA, cpx<T> *gB, size_t sh,
-                            hipStream_t st) {
+static void launch_spec_rim(tp_plan pl, const cpx<T> *G, Cols<const In> x, Cols<Out> y, cpx<T> *gA, cpx<T> *gB,
+                            size_t sh, hipStream_t st) {
     // rounds kept in flight per wave: fewer for wide rows and for FP64
     constexpr int U = (sizeof(T) == 8 || VPL > 8) ? 1 : 2;
     const int nchunk = (pl->b + 7) / 8, nspec = pl->Px * nchunk;
-    const int nrim = pl->Nr > 0 ? pl->rim_nslab : 0;
+    const int nrim = E > 0 ? pl->rim_nslab : 0;
     const int lgCC = ilog2(next_pow2(pl->b));
-    hipLaunchKernelGGL((k_spec_rim<T, In, Out, VPL, U, E, NBE>), dim3(nspec + nrim), dim3(256), sh, st,
-                       OpPtrs<T>::G(pl), gA, gB, pl->b, pl->Ny, pl->Px, pl->fy, lgCC, nspec, OpPtrs<T>::B(pl),
-                       OpPtrs<T>::BE(pl), x, y, pl->N, pl->Nr, reinterpret_cast<cpx<T> *>(pl->rim_part), nrim);
+    hipLaunchKernelGGL((k_spec_rim<T, In, Out, VPL, U, E, NBE>), dim3(nspec + nrim), dim3(256), sh, st, G, gA, gB,
+                       pl->b, pl->Ny, pl->Px, pl->fy, lgCC, nspec, OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl), x, y, pl->N,
+                       pl->Nr, reinterpret_cast<cpx<T> *>(pl->rim_part), nrim);
 }
 
+// rim: whether the launch carries the rim pass (the operator with Nr > 0)
 template <typename T, typename In, typename Out, int VPL>
-static void launch_spec_rim_e(tp_plan pl, Cols<const In> x, Cols<Out> y, cpx<T> *gA, cpx<T> *gB, size_t sh,
-                              hipStream_t st) {
-    if (pl->Nr == 0) {
-        launch_spec_rim<T, In, Out, VPL, 0, false>(pl, x, y, gA, gB, sh, st);
+static void launch_spec_rim_e(tp_plan pl, const cpx<T> *G, bool rim, Cols<const In> x, Cols<Out> y, cpx<T> *gA,
+                              cpx<T> *gB, size_t sh, hipStream_t st) {
+    if (!rim) {
+        launch_spec_rim<T, In, Out, VPL, 0, false>(pl, G, x, y, gA, gB, sh, st);
         return;
     }
     const bool nbe = OpPtrs<T>::BE(pl) != nullptr;
     switch ((pl->rim_te / 64) * 2 + (nbe ? 1 : 0)) {
-        case 2: launch_spec_rim<T, In, Out, VPL, 1, false>(pl, x, y, gA, gB, sh, st); break;
-        case 3: launch_spec_rim<T, In, Out, VPL, 1, true>(pl, x, y, gA, gB, sh, st); break;
-        case 4: launch_spec_rim<T, In, Out, VPL, 2, false>(pl, x, y, gA, gB, sh, st); break;
-        case 5: launch_spec_rim<T, In, Out, VPL, 2, true>(pl, x, y, gA, gB, sh, st); break;
-        case 8: launch_spec_rim<T, In, Out, VPL, 4, false>(pl, x, y, gA, gB, sh, st); break;
-        default: launch_spec_rim<T, In, Out, VPL, 4, true>(pl, x, y, gA, gB, sh, st); break;
+        case 2: launch_spec_rim<T, In, Out, VPL, 1, false>(pl, G, x, y, gA, gB, sh, st); break;
+        case 3: launch_spec_rim<T, In, Out, VPL, 1, true>(pl, G, x, y, gA, gB, sh, st); break;
+        case 4: launch_spec_rim<T, In, Out, VPL, 2, false>(pl, G, x, y, gA, gB, sh, st); break;
+        case 5: launch_spec_rim<T, In, Out, VPL, 2, true>(pl, G, x, y, gA, gB, sh, st); break;
+        case 8: launch_spec_rim<T, In, Out, VPL, 4, false>(pl, G, x, y, gA, gB, sh, st); break;
+        default: launch_spec_rim<T, In, Out, VPL, 4, true>(pl, G, x, y, gA, gB, sh, st); break;
     }
 }
 
@@ -831,9 +869,12 @@ static void launch_rim_general(tp_plan pl, Cols<const In> x, Cols<Out> y, int R,
 // ev (optional, kMatvecStages + 1 events): ev[0] before the first stage and
 // ev[i + 1] after stage i, for per-stage timing.  Stages that a path merges
 // into another are recorded as empty intervals.
-template <typename T, typename In, typename Out>
+// PRE: apply the block-circulant preconditioner instead of the operator:
+// spectrum S, no rim pass, rim entries D x_r, and y = base + M^-1 x for the
+// columns whose base pointer is set (base.tab or base.base).
+template <typename T, typename In, typename Out, bool PRE = false>
 hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipStream_t st,
-                         hipEvent_t *ev = nullptr) {
+                         hipEvent_t *ev = nullptr, Cols<const Out> base = Cols<const Out>{nullptr, 0, nullptr}) {
     const int Nx = pl->Nx, Ny = pl->Ny, b = pl->b, Nr = pl->Nr;
     const int Px = pl->Px, Py = pl->Py, C = b * R;
     cpx<T> *gA = reinterpret_cast<cpx<T> *>(pl->gridA);
@@ -844,15 +885,18 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     auto mark = [&](int i) {
         if (ev) hipEventRecord(ev[i], st);
     };
-    const size_t sh_fused = std::max(spec_lds(pl, es), Nr > 0 ? rim_lds(pl, 1, es) : (size_t)0);
+    const cpx<T> *G = PRE ? OpPtrs<T>::S(pl) : OpPtrs<T>::G(pl);
+    const bool rim = !PRE && Nr > 0;         // dense rim pass
+    const size_t sh_fused = std::max(spec_lds(pl, es), rim ? rim_lds(pl, 1, es) : (size_t)0);
     const bool fused = R == 1 && sh_fused <= kLdsLimit;
 
     // many columns: the product and the rim run on the matrix cores
     const bool mfma = !fused && R >= kMfmaMinR;
-    const bool rim_mma = mfma && Nr > 0 && pl->rim_te == 64 && rim_mfma_lds<T>(OpPtrs<T>::BE(pl) != nullptr) <= kLdsLimit;
+    const bool rim_mma =
+        mfma && rim && pl->rim_te == 64 && rim_mfma_lds<T>(OpPtrs<T>::BE(pl) != nullptr) <= kLdsLimit;
 
     mark(0);
-    if (Nr > 0 && !fused) {
+    if (rim && !fused) {
         if (rim_mma)
             rim_mfma<T, In, Out>(OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl), x, y, R, pl->N, Nr, pl->rim_nslab,
                                  reinterpret_cast<cpx<T> *>(pl->rim_part), st);
@@ -883,15 +927,15 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     mark(3);
     if (fused) {
         const int vpl = (b + 7) / 8;
-        if (vpl <= 2) launch_spec_rim_e<T, In, Out, 2>(pl, x, y, gA, gB, sh_fused, st);
-        else if (vpl <= 4) launch_spec_rim_e<T, In, Out, 4>(pl, x, y, gA, gB, sh_fused, st);
-        else if (vpl <= 6) launch_spec_rim_e<T, In, Out, 6>(pl, x, y, gA, gB, sh_fused, st);
-        else if (vpl <= 8) launch_spec_rim_e<T, In, Out, 8>(pl, x, y, gA, gB, sh_fused, st);
-        else if (vpl <= 12) launch_spec_rim_e<T, In, Out, 12>(pl, x, y, gA, gB, sh_fused, st);
-        else if (vpl <= 16) launch_spec_rim_e<T, In, Out, 16>(pl, x, y, gA, gB, sh_fused, st);
-        else launch_spec_rim_e<T, In, Out, 32>(pl, x, y, gA, gB, sh_fused, st);
+        if (vpl <= 2) launch_spec_rim_e<T, In, Out, 2>(pl, G, rim, x, y, gA, gB, sh_fused, st);
+        else if (vpl <= 4) launch_spec_rim_e<T, In, Out, 4>(pl, G, rim, x, y, gA, gB, sh_fused, st);
+        else if (vpl <= 6) launch_spec_rim_e<T, In, Out, 6>(pl, G, rim, x, y, gA, gB, sh_fused, st);
+        else if (vpl <= 8) launch_spec_rim_e<T, In, Out, 8>(pl, G, rim, x, y, gA, gB, sh_fused, st);
+        else if (vpl <= 12) launch_spec_rim_e<T, In, Out, 12>(pl, G, rim, x, y, gA, gB, sh_fused, st);
+        else if (vpl <= 16) launch_spec_rim_e<T, In, Out, 16>(pl, G, rim, x, y, gA, gB, sh_fused, st);
+        else launch_spec_rim_e<T, In, Out, 32>(pl, G, rim, x, y, gA, gB, sh_fused, st);
     } else if (mfma) {
-        prod_mfma<T>(OpPtrs<T>::G(pl), gB, b, R, (long)Px * Py, gA, act, st);
+        prod_mfma<T>(G, gB, b, R, (long)Px * Py, gA, act, st);
     } else {
         // columns per workgroup: up to 16 (the spectrum block is re-read from
         // cache by each column block of a frequency)
@@ -899,7 +943,7 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         const size_t sh = (size_t)RC * b * es;
         dim3 grid(Px * Py, (R + RC - 1) / RC);
         const int vpl = (b + 7) / 8;
-        launch_prod<T>(vpl, RC, grid, sh, st, OpPtrs<T>::G(pl), gB, b, R, gA, act);
+        launch_prod<T>(vpl, RC, grid, sh, st, G, gB, b, R, gA, act);
     }
     mark(4);
     if (!fused && lg2 < 0) {
@@ -909,12 +953,18 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         hipLaunchKernelGGL((k_inv_y<T>), grid, blk, sh, st, gA, C, Ny, Px, pl->fy, lg, gB, act, b);
     }
     mark(5);
+    // the operator adds its rim term (already in y); the preconditioner adds
+    // the caller's base columns, if any
+    const Cols<const Out> acc = PRE ? base : Cols<const Out>{y.base, y.ld, y.tab};
+    const int accumulate = PRE ? (base.base || base.tab ? 1 : 0) : (rim ? 1 : 0);
+    const cpx<T> *D = PRE ? OpPtrs<T>::D(pl) : nullptr;
+    const int nfin = Nr > 0 ? ((Nr + 3) / 4) * R : 0;
     if (lg2 >= 0) {
         const int ninv = (C + (1 << lg2) - 1) >> lg2;
-        const int nfin = Nr > 0 ? ((Nr + 3) / 4) * R : 0;
         hipLaunchKernelGGL((k_fft2_inv_fin<T, In, Out>), dim3(ninv + nfin), blk, sh2, st, gA, R, Nx, Ny, b, pl->fx,
-                           pl->fy, lg2, xs2, y, Nr > 0 ? 1 : 0, ninv, reinterpret_cast<const cpx<T> *>(pl->rim_part),
-                           OpPtrs<T>::C(pl), x, pl->N, Nr, pl->rim_nslab);
+                           pl->fy, lg2, xs2, y, accumulate, acc, ninv,
+                           reinterpret_cast<const cpx<T> *>(pl->rim_part), OpPtrs<T>::C(pl), D, x, pl->N, Nr,
+                           pl->rim_nslab);
     } else {
         // the fused path leaves Y1 in gB with channel count b (R = 1), the
         // general path in gB with b * R channels: the same layout
@@ -922,10 +972,9 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         const size_t sh = ((size_t)Px * (1 << lg) + Px) * es;
         const int nchunk = (C + (1 << lg) - 1) >> lg;
         const int ninv = nchunk * Ny;
-        const int nfin = Nr > 0 ? ((Nr + 3) / 4) * R : 0;
         hipLaunchKernelGGL((k_inv_x_fin<T, In, Out>), dim3(ninv + nfin), blk, sh, st, gB, R, Nx, b, pl->fx, lg,
-                           nchunk, y, Nr > 0 ? 1 : 0, ninv, reinterpret_cast<const cpx<T> *>(pl->rim_part),
-                           OpPtrs<T>::C(pl), x, pl->N, Nr, pl->rim_nslab);
+                           nchunk, y, accumulate, acc, ninv, reinterpret_cast<const cpx<T> *>(pl->rim_part),
+                           OpPtrs<T>::C(pl), D, x, pl->N, Nr, pl->rim_nslab);
     }
     mark(6);
     mark(7);
@@ -946,6 +995,16 @@ hipError_t matvec_fp64_timed(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R
 }
 hipError_t matvec_fp32_timed(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStream_t st, hipEvent_t *ev) {
     return matvec_launch<float, c64, c64>(pl, x, y, R, st, ev);
+}
+hipError_t precond_fp64(tp_plan pl, Cols<const c128> x, Cols<c128> y, Cols<const c128> base, int R, hipStream_t st) {
+    return matvec_launch<double, c128, c128, true>(pl, x, y, R, st, nullptr, base);
+}
+hipError_t precond_fp32(tp_plan pl, Cols<const c64> x, Cols<c64> y, Cols<const c64> base, int R, hipStream_t st) {
+    return matvec_launch<float, c64, c64, true>(pl, x, y, R, st, nullptr, base);
+}
+hipError_t precond_fp32_wide(tp_plan pl, Cols<const c128> x, Cols<c128> y, Cols<const c128> base, int R,
+                             hipStream_t st) {
+    return matvec_launch<float, c128, c128, true>(pl, x, y, R, st, nullptr, base);
 }
 
 // ------------------------------------------------------ plan-time spectrum
@@ -1040,6 +1099,110 @@ hipError_t spectrum_build(tp_plan pl, const c128 *gen_dev, c128 *tmp, hipStream_
                            1.0 / ((double)Px * (double)Py), pl->G64, pl->G32);
     }
     return hipGetLastError();
+}
+
+// ------------------------------------------------ preconditioner (plan time)
+// In-place Gauss-Jordan inversion with partial pivoting of one b x b spectrum
+// block per workgroup (row-major at S + k b^2), then scaling by scl.  Step k:
+// the largest-modulus pivot in column k (ties to the lower row) is swapped
+// into row k, row k is divided by it (its column-k entry becoming 1 / pivot),
+// and every other row i loses f_i times row k, with f_i its column-k entry
+// (which becomes -f_i / pivot).  The row interchanges are undone on the
+// columns of the result, in reverse order.
+__global__ void __launch_bounds__(256) k_block_inv(c128 *__restrict__ S, int b, double scl, int *flag) {
+    extern __shared__ char smem_raw[];
+    c128 *f = reinterpret_cast<c128 *>(smem_raw);   // [b]
+    int *perm = reinterpret_cast<int *>(f + b);      // [b]
+    __shared__ int piv;
+    c128 *A = S + (long)blockIdx.x * b * b;
+    const int tid = threadIdx.x;
+    for (int k = 0; k < b; ++k) {
+        if (tid < 64) {
+            double best = -1.0;
+            int bi = k;
+            for (int i = k + tid; i < b; i += 64) {
+                const c128 a = A[(long)i * b + k];
+                const double m = a.x * a.x + a.y * a.y;
+                if (m > best) {
+                    best = m;
+                    bi = i;
+                }
+            }
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double ob = __shfl_xor(best, o, 64);
+                const int oi = __shfl_xor(bi, o, 64);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            if (tid == 0) {
+                piv = bi;
+                perm[k] = bi;
+                if (!(best > 0.0) || !(best < INFINITY)) *flag = 1;
+            }
+        }
+        __syncthreads();
+        const int r = piv;
+        if (r != k) {
+            for (int j = tid; j < b; j += kBlock) {
+                const c128 t = A[(long)k * b + j];
+                A[(long)k * b + j] = A[(long)r * b + j];
+                A[(long)r * b + j] = t;
+            }
+            __syncthreads();
+        }
+        const c128 pv = A[(long)k * b + k];
+        const double pd = 1.0 / (pv.x * pv.x + pv.y * pv.y);
+        const c128 inv{pv.x * pd, -pv.y * pd};
+        __syncthreads();
+        for (int j = tid; j < b; j += kBlock) A[(long)k * b + j] = (j == k ? c128{1, 0} : A[(long)k * b + j]) * inv;
+        for (int i = tid; i < b; i += kBlock)
+            if (i != k) f[i] = A[(long)i * b + k];
+        __syncthreads();
+        for (long idx = tid; idx < (long)b * b; idx += kBlock) {
+            const int i = (int)(idx / b), j = (int)(idx - (long)i * b);
+            if (i == k) continue;
+            A[idx] = (j == k ? c128{0, 0} : A[idx]) - f[i] * A[(long)k * b + j];
+        }
+        __syncthreads();
+    }
+    for (int k = b - 1; k >= 0; --k) {
+        const int r = perm[k];
+        if (r != k) {
+            for (int i = tid; i < b; i += kBlock) {
+                const c128 t = A[(long)i * b + k];
+                A[(long)i * b + k] = A[(long)i * b + r];
+                A[(long)i * b + r] = t;
+            }
+        }
+        __syncthreads();
+    }
+    for (long idx = tid; idx < (long)b * b; idx += kBlock) A[idx] = scale(A[idx], scl);
+}
+
+// D[t] = 1 / C[t][t]
+__global__ void k_diag_inv(const c128 *__restrict__ Cm, int Nr, c128 *__restrict__ D, int *flag) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Nr) return;
+    const c128 c = Cm[(long)t * Nr + t];
+    const double dd = c.x * c.x + c.y * c.y;
+    if (!(dd > 0.0) || !(dd < INFINITY)) *flag = 1;
+    D[t] = c128{c.x / dd, -c.y / dd};
+}
+
+hipError_t precond_build(tp_plan pl, c128 *S, int *flag, hipStream_t st) {
+    const long P = (long)pl->Px * pl->Py;
+    const double scl = 1.0 / ((double)P * (double)P);
+    const size_t sh = (size_t)pl->b * (sizeof(c128) + sizeof(int));
+    hipLaunchKernelGGL(k_block_inv, dim3((unsigned)P), dim3(256), sh, st, S, pl->b, scl, flag);
+    hipError_t e = hipGetLastError();
+    if (e) return e;
+    if (pl->Nr > 0 && pl->D64) {
+        hipLaunchKernelGGL(k_diag_inv, dim3((pl->Nr + 255) / 256), dim3(256), 0, st, pl->C64, pl->Nr, pl->D64, flag);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t cast_to_c64(const c128 *in, c64 *out, long n, hipStream_t st) {
