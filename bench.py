@@ -3,15 +3,17 @@
 broadside plane-wave excitation, on one MI355X.
 
 One step = one complete solve of Z x = v to ||v - Z x|| / ||v|| <= 1e-8
-(FP64 residual), in the fastest form (FP32 operator inside FP64 iterative
-refinement, all Krylov arithmetic FP64), with the plan (generator spectrum
-and rim blocks) resident in HBM and the right-hand side on the device.  The
-same GPU's plain FP64 GMRES is timed beside it ("vs FP64 plain"), together
-with the operator's achieved bandwidth, per-solve latency percentiles, the
-roofline fraction of the dominant kernel and the plain FP64 CPU oracle on a
-bounded sample.
+(FP64 residual), in the fastest form (FP32 operator and block-circulant
+preconditioner inside FP64 iterative refinement, all Krylov arithmetic FP64),
+with the plan (generator spectrum, rim blocks, preconditioner) resident in HBM
+and the right-hand side on the device.  The same GPU's plain FP64 GMRES is
+timed beside it ("vs FP64 plain"), together with the operator's achieved
+bandwidth, per-solve latency percentiles, the roofline fraction of the
+dominant kernel and the plain FP64 CPU oracle on a bounded sample.  Unless
+--quick: the 81-port multi-RHS solve (matrix-core product rate, S-matrix),
+the 1e-10 precision workload and the 512-request serving stream.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--quick]
 """
 import argparse
 import hashlib
@@ -39,6 +41,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline workload only (no multi-RHS, precision or serving sections)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device-to-device copies of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -111,6 +115,117 @@ def cpu_baseline(prob, V, lu_shape=(8, 8)):
     }
 
 
+def timed_solves(plan, v, K, W, tol=1e-8, **kw):
+    """K timed solves after W warm-up ones; each returns after convergence."""
+    import numpy as np
+    import torch
+    for _ in range(W):
+        plan.solve(v, tol=tol, **kw)
+    torch.cuda.synchronize()
+    lat, last = [], None
+    t_start = time.perf_counter()
+    for _ in range(K):
+        ts = time.perf_counter()
+        last = plan.solve(v, tol=tol, **kw)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t_start, np.array(lat), last
+
+
+def multi_rhs(dev, K=3):
+    """81 port excitations of the 9 x 9, b = 96 array solved together, the
+    matrix-core product's rate, and the S-matrix post-step."""
+    import numpy as np
+    import torch
+    import paper_2506_04710_amd as tp
+    from synth import arrays as sa
+    prob, V = sa.make_config(3)
+    R = V.shape[0]
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=R, restart=40, device=dev).precond_create()
+    v = torch.from_numpy(V).to(dev)
+    total, lat, (x, inf) = timed_solves(plan, v, K, 1, mode="mixed", precond=True)
+    assert all(i["status"] == 0 and i["relres"] <= 1e-8 for i in inf), inf
+    st = plan.matvec_profile(v.to(torch.complex64), which="fp32", reps=20)
+    Pg = plan.info()["Px"] * plan.info()["Py"]
+    flops = 8.0 * Pg * prob.b ** 2 * R
+    rows = np.nonzero(V)[1]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = tp.port_smatrix(x, rows, Z0=50.0)
+    t_s = time.perf_counter() - t0
+    S = S.cpu().numpy()
+    out = {"workload": "9x9 array, b=96, 72 rim functions, 81 port excitations (one per element feed), tol 1e-8, "
+                       "mixed + preconditioner, one launch sequence for all columns",
+           "solves_per_s": round(R * K / total, 1), "ms_per_81": round(1e3 * total / K, 2),
+           "iters_max": max(i["iters"] for i in inf), "outer_max": max(i["outer_iters"] for i in inf),
+           "fp32_matvec_stages_us": {k: round(t * 1e3, 2) for k, t in st.items()},
+           "prod_mfma": {"tflops": round(flops / (st["prod"] * 1e-3) / 1e12, 1),
+                         "peak_tflops_fp32_mfma": 157.3,
+                         "frac": round(flops / (st["prod"] * 1e-3) / 1e12 / 157.3, 3),
+                         "flops_per_launch": flops},
+           "smatrix_ms": round(1e3 * t_s, 2), "smatrix_max_asymmetry": float(np.abs(S - S.T).max())}
+    plan.close()
+    return out
+
+
+def precision(dev, K=2):
+    """Eight scan-angle plane waves on the 64 x 64, b = 48 array to 1e-10:
+    mixed + preconditioner against the FP64 preconditioned solve."""
+    import numpy as np
+    import torch
+    import paper_2506_04710_amd as tp
+    from synth import arrays as sa
+    prob, V = sa.make_config(4)
+    R = V.shape[0]
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=R, restart=40, device=dev).precond_create()
+    v = torch.from_numpy(V).to(dev)
+    total, _, (x, inf) = timed_solves(plan, v, K, 1, tol=1e-10, mode="mixed", precond=True)
+    assert all(i["status"] == 0 and i["relres"] <= 1e-10 for i in inf), inf
+    total64, _, (x64, inf64) = timed_solves(plan, v, K, 1, tol=1e-10, mode="fp64", precond=True)
+    err = (torch.linalg.norm(x - x64, dim=1) / torch.linalg.norm(x64, dim=1)).max().item()
+    plan.close()
+    return {"workload": "64x64 array, b=48, no rim, 8 plane waves (theta in 0..60 deg), tol 1e-10",
+            "mixed_solves_per_s": round(R * K / total, 1), "fp64_solves_per_s": round(R * K / total64, 1),
+            "iters_max": max(i["iters"] for i in inf), "outer_max": max(i["outer_iters"] for i in inf),
+            "max_relres": max(i["relres"] for i in inf), "max_rel_diff_vs_fp64": err}
+
+
+def serving(dev, n_requests=512):
+    """Seeded Poisson stream of 512 requests over the serving mix of geometries."""
+    import numpy as np
+    import torch
+    from paper_2506_04710_amd.serve import Server, Request
+    from synth import arrays as sa
+    stream = sa.serving_stream(n_requests)
+    keys = sorted({(r["Nx"], r["Ny"], r["b"]) for r in stream})
+    G = {k: sa.serving_geometry(*k) for k in keys}
+
+    def geometry(k):
+        p = G[k]
+        return p.Nx, p.Ny, p.b, p.Nr, p.gen, p.rim_re, p.rim_rr
+
+    def reqs():
+        return [Request(id=r["id"], t=r["t"], key=(r["Nx"], r["Ny"], r["b"]),
+                        V=sa.rhs_ports(G[(r["Nx"], r["Ny"], r["b"])], r["elements"])) for r in stream]
+
+    srv = Server(geometry, slots=16, mode="mixed", tol=1e-8, restart=40, hbm_budget=160 << 30, precond=True,
+                 device=dev)
+    t0 = time.perf_counter()
+    srv.warm(keys)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    sat = srv.run(reqs(), realtime=False)
+    live = srv.run(reqs(), realtime=True)
+    srv.close()
+    keep = ("requests", "columns", "wall_s", "requests_per_s", "solves_per_s", "p50_ms", "p99_ms", "max_relres",
+            "all_ok")
+    r = lambda d: {k: (round(d[k], 4) if isinstance(d[k], float) and k != "max_relres" else d[k]) for k in keep}
+    return {"workload": f"{n_requests} requests, Poisson arrivals at 100/s, {len(keys)} geometries (Nx, Ny in "
+                        "{8..48}, b in {32, 64}), 1-16 ports each, mixed + preconditioner, tol 1e-8, 16 slots per "
+                        "plan", "plans_warm_s": round(t_warm, 2), "hbm_used_gib": round(sat["hbm_used"] / 2 ** 30, 2),
+            "saturation": r(sat), "at_stream_rate": r(live)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -133,28 +248,22 @@ def main():
     plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=1, restart=40, device=dev)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan.precond_create()
+    t_pc = time.perf_counter() - t0
     info = plan.info()
     Px, Py = info["Px"], info["Py"]
     v = torch.from_numpy(V).to(dev)
 
-    def timed_solves(mode, K, W):
-        for _ in range(W):
-            plan.solve(v, mode=mode, tol=1e-8)
-        torch.cuda.synchronize()
-        lat, last = [], None
-        t_start = time.perf_counter()
-        for _ in range(K):
-            ts = time.perf_counter()
-            x, inf = plan.solve(v, mode=mode, tol=1e-8)   # synchronous: returns after convergence
-            lat.append(time.perf_counter() - ts)
-            last = (x, inf)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t_start, np.array(lat), last
-
-    total, lat, (x, inf) = timed_solves("mixed", args.steps, args.warmup)
+    # headline: the fastest form (FP32 operator and preconditioner inside FP64
+    # refinement); then the same GPU's plain FP64 GMRES and two intermediate forms
+    total, lat, (x, inf) = timed_solves(plan, v, args.steps, args.warmup, mode="mixed", precond=True)
     assert inf[0]["status"] == 0 and inf[0]["relres"] <= 1e-8, inf
-    total64, lat64, (x64, inf64) = timed_solves("fp64", args.steps, args.warmup)
+    total64, lat64, (_, inf64) = timed_solves(plan, v, args.steps, args.warmup, mode="fp64")
     assert inf64[0]["status"] == 0 and inf64[0]["relres"] <= 1e-8, inf64
+    kb = max(3, args.steps // 3)
+    totm, _, (_, infm) = timed_solves(plan, v, kb, 1, mode="mixed")
+    totp, _, (_, infp) = timed_solves(plan, v, kb, 1, mode="fp64", precond=True)
 
     # operator bandwidth (whole matvec) and the dominant kernel's duration
     gbs = {}
@@ -172,7 +281,8 @@ def main():
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / reps
-        gbs[which] = {"us": round(ms * 1e3, 2), "GB_s": round(algorithmic_bytes(prob, Px, Py, 1, s) / (ms * 1e-3) / 1e9, 1)}
+        gbs[which] = {"us": round(ms * 1e3, 2),
+                      "GB_s": round(algorithmic_bytes(prob, Px, Py, 1, s) / (ms * 1e-3) / 1e9, 1)}
         stage[which] = plan.matvec_profile(xv, which=which, reps=50)
     # dominant kernel of the timed solve: the fused spectrum+rim launch of the
     # FP32 operator (it carries both HBM streams); its duration from HIP events
@@ -182,6 +292,8 @@ def main():
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     sha = kernel_source_sha()
     traffic = TRAFFIC["bytes"] if TRAFFIC["source_sha256"] == sha else None
+    plan.close()
+    del plan
 
     line = {
         "metric": METRIC,
@@ -194,27 +306,36 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 operator, f64 refinement/Krylov",
+        "dtype": "c64 operator and preconditioner, f64 refinement/Krylov",
         "data": "synthetic",
         "config": {"workload": "32x32 array, b=64, 256 rim functions (N=65,536, Nt=65,792), broadside plane "
                                "wave, tol 1e-8, one RHS", "Nx": 32, "Ny": 32, "b": 64, "Nr": 256,
-                   "grid": [Px, Py], "restart": 40, "solve": "mixed GMRES-IR"},
+                   "grid": [Px, Py], "restart": 40,
+                   "solve": "mixed GMRES-IR, right block-circulant preconditioner"},
         "fp64_plain_solves_per_s": round(args.steps / total64, 2),
         "speedup_vs_fp64_plain": round(total64 / total, 3),
+        "other_forms_solves_per_s": {"mixed_no_precond": round(kb / totm, 2), "fp64_precond": round(kb / totp, 2)},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3),
                        "fp64_plain_p50": round(1e3 * float(np.percentile(lat64, 50)), 3),
                        "fp64_plain_p99": round(1e3 * float(np.percentile(lat64, 99)), 3)},
-        "iters": {"mixed": inf[0]["iters"], "mixed_outer": inf[0]["outer_iters"], "fp64": inf64[0]["iters"]},
-        "relres": {"mixed": inf[0]["relres"], "fp64": inf64[0]["relres"]},
+        "iters": {"mixed_precond": inf[0]["iters"], "mixed_precond_outer": inf[0]["outer_iters"],
+                  "fp64_plain": inf64[0]["iters"], "mixed_no_precond": infm[0]["iters"],
+                  "fp64_precond": infp[0]["iters"]},
+        "relres": {"mixed_precond": inf[0]["relres"], "fp64_plain": inf64[0]["relres"]},
         "matvec": gbs,
         "matvec_stages_us": {w: {k: round(v_ * 1e3, 2) for k, v_ in st.items()} for w, st in stage.items()},
         "plan_create_s": round(t_plan, 3),
+        "precond_create_s": round(t_pc, 3),
         "roofline": {"kernel": "k_spec_rim<float> (spectrum rows + rim pass, fused)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": int(k_bytes), "launch_us": round(k_ms * 1e3, 2)},
     }
+    if not args.quick:
+        line["multi_rhs"] = multi_rhs(dev)
+        line["precision"] = precision(dev)
+        line["serving"] = serving(dev)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, V)
     print(json.dumps(line), flush=True)

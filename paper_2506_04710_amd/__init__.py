@@ -21,7 +21,7 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ToeplitzError, check  # noqa: F401
 
-__all__ = ["Plan", "plan_bytes", "port_smatrix", "far_field", "ToeplitzError", "load"]
+__all__ = ["Plan", "plan_bytes", "precond_bytes", "port_smatrix", "far_field", "ToeplitzError", "load"]
 
 
 def load():
@@ -34,6 +34,32 @@ def plan_bytes(Nx, Ny, b, Nr, prec="mixed", max_rhs=1, restart=40, reciprocal=Tr
     check(_lib.lib().toeplitz_plan_bytes(Nx, Ny, b, Nr, 1 if reciprocal else 0, PREC[prec], max_rhs, restart,
                                          ctypes.byref(n)))
     return n.value
+
+
+def precond_bytes(Nx, Ny, b, Nr, prec="mixed") -> int:
+    """Device bytes of the block-circulant preconditioner of such a plan: the
+    inverted spectrum per precision held (Px Py b^2 values), 1/diag(C), a
+    status word, each region 256-byte aligned (as toeplitz_precond_bytes)."""
+    px, py = _grid(Nx), _grid(Ny)
+    al = lambda v: (v + 255) // 256 * 256
+    per = {"fp64": (16,), "fp32": (8,), "mixed": (16, 8)}[prec]
+    total = sum(al(px * py * b * b * s) for s in per)
+    if Nr:
+        total += sum(al(Nr * s) for s in per)
+    return total + 256
+
+
+def _grid(n):
+    """Smallest 2, 3, 5, 7-smooth size >= 2n - 1 (the plan's embedding)."""
+    m = 2 * n - 1
+    while True:
+        k = m
+        for f in (2, 3, 5, 7):
+            while k % f == 0:
+                k //= f
+        if k == 1:
+            return m
+        m += 1
 
 
 def _host_c128(a, shape):

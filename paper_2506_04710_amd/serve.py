@@ -27,7 +27,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Plan, plan_bytes
+from . import Plan, plan_bytes, precond_bytes
 from . import _lib
 from ._lib import PREC, check
 
@@ -67,13 +67,15 @@ class _PlanState:
 
 class Server:
     def __init__(self, geometry, slots=16, mode="mixed", tol=1e-8, restart=40, hbm_budget=64 << 30,
-                 device="cuda:0", inner_tol=1e-4, max_iter=2000):
-        """geometry(key) -> (Nx, Ny, b, Nr, gen, rim_re, rim_rr) for a key (Nx, Ny, b)."""
+                 device="cuda:0", inner_tol=1e-4, max_iter=2000, precond=False):
+        """geometry(key) -> (Nx, Ny, b, Nr, gen, rim_re, rim_rr) for a key (Nx, Ny, b).
+        precond: give every plan the block-circulant preconditioner (its
+        memory counts against the budget)."""
         import torch
         self.torch = torch
         self.geometry = geometry
         self.slots, self.mode, self.tol, self.restart = slots, mode, tol, restart
-        self.inner_tol, self.max_iter = inner_tol, max_iter
+        self.inner_tol, self.max_iter, self.precond = inner_tol, max_iter, precond
         self.budget = hbm_budget
         self.device = torch.device(device)
         self.plans: "collections.OrderedDict[tuple, _PlanState]" = collections.OrderedDict()
@@ -83,7 +85,10 @@ class Server:
     # ----------------------------------------------------------- plans
     def _need(self, key):
         Nx, Ny, b, Nr = self.geometry(key)[:4]
-        return plan_bytes(Nx, Ny, b, Nr, "mixed", self.slots, self.restart)
+        need = plan_bytes(Nx, Ny, b, Nr, "mixed", self.slots, self.restart)
+        if self.precond:
+            need += precond_bytes(Nx, Ny, b, Nr, "mixed")
+        return need
 
     def _get_plan(self, key, now):
         ps = self.plans.get(key)
@@ -101,10 +106,13 @@ class Server:
         t0 = time.perf_counter()
         plan = Plan.create(Nx, Ny, b, Nr, gen, rim_re, rim_rr, prec="mixed", max_rhs=self.slots,
                            restart=self.restart, device=self.device)
+        if self.precond:
+            plan.precond_create()
         o = _lib.SolveOpts()
         _lib.lib().toeplitz_solve_opts_default(ctypes.byref(o))
         o.tol, o.restart, o.mode, o.inner_tol, o.max_iter = self.tol, self.restart, PREC[self.mode], \
             self.inner_tol, self.max_iter
+        o.precond = 1 if self.precond else 0
         check(_lib.lib().toeplitz_batch_begin(plan._h, ctypes.byref(o)))
         self.stats["plan_create_s"] += time.perf_counter() - t0
         self.stats["plans_created"] += 1

@@ -45,6 +45,19 @@ def test_precond_apply_parity(tp, case, which):
     plan.close()
 
 
+def test_precond_bytes_host_formula(tp):
+    """The host-side size used for HBM admission equals the library's."""
+    import ctypes
+    from paper_2506_04710_amd import _lib
+    for shape in [(3, 2, 4, 5), (8, 8, 32, 0), (9, 9, 96, 72), (17, 5, 7, 3)]:
+        prob = sa.make_problem(*shape, 90)
+        plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=1, restart=4)
+        n = ctypes.c_size_t(0)
+        _lib.check(_lib.lib().toeplitz_precond_bytes(plan._h, ctypes.byref(n)))
+        assert n.value == tp.precond_bytes(*shape, "mixed"), shape
+        plan.close()
+
+
 def test_precond_errors(tp):
     banner("precond errors")
     import torch
