@@ -93,6 +93,18 @@ __device__ __forceinline__ void stg(cpx<T> *p, cpx<T> v) {
     g->y = v.y;
 }
 
+// v if c, else 0, by masking the bits: the load of v always issues (the
+// caller clamps its address), so no branch forms around it.
+__device__ __forceinline__ c64 keep(c64 v, bool c) {
+    const unsigned m = c ? ~0u : 0u;
+    return c64{__uint_as_float(__float_as_uint(v.x) & m), __uint_as_float(__float_as_uint(v.y) & m)};
+}
+__device__ __forceinline__ c128 keep(c128 v, bool c) {
+    const unsigned long long m = c ? ~0ull : 0ull;
+    return c128{__longlong_as_double((long long)((unsigned long long)__double_as_longlong(v.x) & m)),
+                __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v.y) & m))};
+}
+
 // Keep a value in registers at this point: an empty asm statement that reads
 // it, so a load producing it completes here and is not moved into the code
 // that consumes it.

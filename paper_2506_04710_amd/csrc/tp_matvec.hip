@@ -352,52 +352,66 @@ __device__ __forceinline__ void spec_block(const cpx<T> *__restrict__ G, const c
     const int pl = lane >> 3, qs = (lane & 7) * VPL, p = p0 + pl;
     const bool prow = p < b;
     const long kstride = (long)b * b;
-    const cpx<T> *Grow = G + (long)kx * P * kstride + (long)(prow ? p : 0) * b;
+    const cpx<T> *Grow = G + (long)kx * P * kstride + (long)min(p, b - 1) * b;
+    int *perm = reinterpret_cast<int *>(ys + P * TP);   // [Py] digit reversal, in LDS
+    // Spectrum loads use clamped addresses and are masked only where used, so
+    // no branch forms around them and the waits stay exact: the next U panels
+    // stay in flight while the current ones are reduced.
     cpx<T> gc[U][VPL], gn[U][VPL];
     auto load = [&](cpx<T>(&g)[U][VPL], int ky0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int ky = ky0 + u * nw;
+            const long ky = min(ky0 + u * nw, P - 1);
 #pragma unroll
-            for (int v = 0; v < VPL; ++v) {
-                const int q = qs + v;
-                g[u][v] = (ky < P && prow && q < b) ? Grow[ky * kstride + q] : mk<T>(0, 0);
-            }
+            for (int v = 0; v < VPL; ++v) g[u][v] = Grow[ky * kstride + min(qs + v, b - 1)];
         }
     };
     load(gc, w);
     load_twiddles<T>(twl, fy);
+    for (int i = threadIdx.x; i < P; i += kBlock) perm[i] = fy.perm[i];
     zero_lds<T>(xs, P * CC);
     __syncthreads();
-    for (int i = threadIdx.x; i < Ny * CC; i += kBlock) {
-        const int iy = i >> lgCC, c = i & (CC - 1);
-        if (c < b) xs[(fy.perm[iy] << lgCC) + c] = X1[((long)iy * Px + kx) * b + c];
-    }
+    batched<8, cpx<T>>(
+        Ny * CC, [&](int i) { return X1[((long)(i >> lgCC) * Px + kx) * b + min(i & (CC - 1), b - 1)]; },
+        [&](int i, cpx<T> v) {
+            const int iy = i >> lgCC, c = i & (CC - 1);
+            if (c < b) xs[(perm[iy] << lgCC) + c] = v;
+        });
     __syncthreads();
     lds_fft<T, false>(xs, lgCC, fy, twl);
-    for (int ky0 = w; ky0 < P; ky0 += nw * U) {
-        const int nxt = ky0 + nw * U;
-        if (nxt < P) load(gn, nxt);
+    // values past the row (q >= b) are masked to zero; their LDS index is
+    // clamped into the row so that no other row's (or uninitialised) value
+    // enters the sum
+    bool qok[VPL];
+    int qi[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        qok[v] = prow && qs + v < b;
+        qi[v] = min(qs + v, CC - 1);
+    }
+    auto reduce = [&](const cpx<T>(&g)[U][VPL], int ky0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int ky = ky0 + u * nw;
+            const cpx<T> *xk = xs + (min(ky, P - 1) << lgCC);
             cpx<T> acc = mk<T>(0, 0);
-            if (ky < P) {
-                const cpx<T> *xk = xs + (ky << lgCC) + qs;
 #pragma unroll
-                for (int v = 0; v < VPL; ++v)
-                    if (qs + v < b) acc = cmac(acc, gc[u][v], xk[v]);
-            }
+            for (int v = 0; v < VPL; ++v) acc = cmac(acc, keep(g[u][v], qok[v]), xk[qi[v]]);
             acc = sum8(acc);
             // the inverse transform takes its input in digit-reversed slots
-            if ((lane & 7) == 0 && ky < P) ys[(fy.perm[ky] << 3) + pl] = acc;
+            if ((lane & 7) == 0 && ky < P) ys[(perm[ky] << 3) + pl] = acc;
         }
-        if (nxt < P) {
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int v = 0; v < VPL; ++v) gc[u][v] = gn[u][v];
-        }
+    };
+    // two register buffers in turn (no copies between them, so the compiler
+    // never has to wait for a buffer's loads before the other one is used)
+    // The loads are unconditional (clamped past the end): a load under a
+    // branch would make the wait before the other buffer's use cover it too.
+    const int step = nw * U;
+    for (int ky0 = w; ky0 < P; ky0 += 2 * step) {
+        load(gn, ky0 + step);
+        reduce(gc, ky0);
+        load(gc, ky0 + 2 * step);
+        if (ky0 + step < P) reduce(gn, ky0 + step);
     }
     __syncthreads();
     lds_fft<T, true>(ys, 3, fy, twl);
@@ -437,40 +451,46 @@ __device__ __forceinline__ void rim_block1(const cpx<T> *__restrict__ B, const c
         acc[v] = mk<T>(0, 0);
     }
     __syncthreads();
+    // rim loads: clamped addresses, masked where used (no branches, exact waits)
+    bool eok[VE];
+    long ei[VE];
+#pragma unroll
+    for (int v = 0; v < VE; ++v) {
+        eok[v] = e0 + cs + v < N;
+        ei[v] = min(e0 + cs + v, N - 1);
+    }
     cpx<T> gc[VE], gn[VE], ec[NBE ? VE : 1], en[NBE ? VE : 1];
     auto load = [&](cpx<T>(&g)[VE], cpx<T>(&ge)[NBE ? VE : 1], int row) {
+        const long rr = (long)min(row, Nr - 1) * N;
 #pragma unroll
         for (int v = 0; v < VE; ++v) {
-            const long e = e0 + cs + v;
-            const bool ok = row < Nr && e < N;
-            g[v] = ok ? B[(long)row * N + e] : mk<T>(0, 0);
-            if constexpr (NBE) ge[v] = ok ? BE[(long)row * N + e] : mk<T>(0, 0);
+            g[v] = B[rr + ei[v]];
+            if constexpr (NBE) ge[v] = BE[rr + ei[v]];
         }
     };
-    int row = w * 4 + ro;
-    load(gc, ec, row);
-    for (int g0 = w * 4; g0 < Nr; g0 += nw * 4) {
-        const int nrow = row + nw * 4;
-        const bool more = g0 + nw * 4 < Nr;
-        if (more) load(gn, en, nrow);
+    auto rows = [&](const cpx<T>(&g)[VE], const cpx<T>(&ge)[NBE ? VE : 1], int row) {
         cpx<T> sr = mk<T>(0, 0);
-        const cpx<T> xrow = row < Nr ? xr[row] : mk<T>(0, 0);
+        const bool rok = row < Nr;
+        const cpx<T> xrow = xr[min(row, Nr - 1)];
 #pragma unroll
         for (int v = 0; v < VE; ++v) {
-            sr = cmac(sr, gc[v], xa[v]);
-            acc[v] = cmac(acc[v], NBE ? ec[NBE ? v : 0] : gc[v], xrow);
+            const cpx<T> gv = keep(g[v], rok && eok[v]);
+            sr = cmac(sr, gv, xa[v]);
+            acc[v] = cmac(acc[v], NBE ? keep(ge[NBE ? v : 0], rok && eok[v]) : gv, xrow);
         }
         sr = sr + shfl_xor_c(sr, 8);
         sr = sum8(sr);
-        if ((lane & 15) == 0 && row < Nr) part[(long)slab * Nr + row] = sr;
-        if (more) {
-#pragma unroll
-            for (int v = 0; v < VE; ++v) {
-                gc[v] = gn[v];
-                if constexpr (NBE) ec[v] = en[v];
-            }
-        }
-        row = nrow;
+        if ((lane & 15) == 0 && rok) part[(long)slab * Nr + row] = sr;
+    };
+    // groups of 4 rows; two register buffers in turn
+    const int r0 = w * 4 + ro, step = nw * 4;
+    load(gc, ec, r0);
+    for (int g0 = w * 4; g0 < Nr; g0 += 2 * step) {
+        const int row = r0 + (g0 - w * 4);
+        load(gn, en, row + step);          // unconditional: see the spectrum stream
+        rows(gc, ec, row);
+        load(gc, ec, row + 2 * step);
+        if (g0 + step < Nr) rows(gn, en, row + step);
     }
     // sum the four row lanes of each column, then the waves
 #pragma unroll
@@ -772,7 +792,7 @@ static int next_pow2(int v) {
 // Fused single-column path: LDS bytes.
 static size_t spec_lds(tp_plan pl, size_t es) {
     const int P = pl->Py, CC = next_pow2(pl->b);
-    return ((size_t)P + (size_t)P * CC + (size_t)P * 8) * es;
+    return ((size_t)P + (size_t)P * CC + (size_t)P * 8) * es + (size_t)P * sizeof(int);
 }
 static size_t rim_lds(tp_plan pl, int RB, size_t es) { return ((size_t)RB * pl->Nr + 4 * (size_t)pl->rim_te * RB) * es; }
 constexpr size_t kLdsLimit = 160 * 1024;
@@ -787,7 +807,16 @@ template <typename T, typename In, typename Out, int VPL, int E, bool NBE>
 static void launch_spec_rim(tp_plan pl, const cpx<T> *G, Cols<const In> x, Cols<Out> y, cpx<T> *gA, cpx<T> *gB,
                             size_t sh, hipStream_t st) {
     // rounds kept in flight per wave: fewer for wide rows and for FP64
-    constexpr int U = (sizeof(T) == 8 || VPL > 8) ? 1 : 2;
+#ifndef TP_SPEC_U32
+#define TP_SPEC_U32 2
+#endif
+#ifndef TP_SPEC_U32_NORIM
+#define TP_SPEC_U32_NORIM TP_SPEC_U32
+#endif
+#ifndef TP_SPEC_U64
+#define TP_SPEC_U64 2
+#endif
+    constexpr int U = sizeof(T) == 8 ? TP_SPEC_U64 : VPL > 8 ? 1 : (E == 0 ? TP_SPEC_U32_NORIM : TP_SPEC_U32);
     const int nchunk = (pl->b + 7) / 8, nspec = pl->Px * nchunk;
     const int nrim = E > 0 ? pl->rim_nslab : 0;
     const int lgCC = ilog2(next_pow2(pl->b));

@@ -33,18 +33,6 @@ struct Mfma<double> {
     static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
 };
 
-// v if c, else 0, by masking the bits: the load of v always issues (the
-// caller clamps its address), so no branch forms around it.
-__device__ __forceinline__ c64 keep(c64 v, bool c) {
-    const unsigned m = c ? ~0u : 0u;
-    return c64{__uint_as_float(__float_as_uint(v.x) & m), __uint_as_float(__float_as_uint(v.y) & m)};
-}
-__device__ __forceinline__ c128 keep(c128 v, bool c) {
-    const unsigned long long m = c ? ~0ull : 0ull;
-    return c128{__longlong_as_double((long long)((unsigned long long)__double_as_longlong(v.x) & m)),
-                __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v.y) & m))};
-}
-
 // Stage n values into LDS with U loads in flight per thread: every load of a
 // round issues (addresses clamped by `ld`) before any value is stored, so the
 // round costs one memory latency rather than U.  Indices past the end are
@@ -164,10 +152,12 @@ __global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G
     cpair<T> a0[KC], a1[KC];
     load(a0, 0);
     __syncthreads();
+    // loads unconditional (clamped addresses): a load under a branch would
+    // make the wait before the other buffer's use cover it too
     for (int t0 = 0; t0 < KP; t0 += 2 * KC) {
-        if (t0 + KC < KP) load(a1, t0 + KC);
+        load(a1, t0 + KC);
         compute(a0, t0);
-        if (t0 + 2 * KC < KP) load(a0, t0 + 2 * KC);
+        load(a0, t0 + 2 * KC);
         if (t0 + KC < KP) compute(a1, t0 + KC);
     }
 #pragma unroll
