@@ -63,7 +63,7 @@ def copy_calibration(mib):
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("tp_matvec.hip", "tp_fft.h", "tp_common.h"):
+    for f in ("tp_matvec.h", "tp_apply_f32.hip", "tp_fft.h", "tp_common.h"):
         with open(os.path.join(ROOT, "paper_2506_04710_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -60,31 +60,57 @@ typedef struct {
     long N, Nt;
     int max_rhs, restart;
     tp_prec prec;
-    size_t spectrum_bytes;   /* per copy: Px*Py*b*b complex values */
+    size_t spectrum_bytes;   /* per copy: Px*Py*b*b complex values, or (Px/2+1)*Py*b*b with half_spectrum */
     size_t rim_bytes;        /* per copy: B (Nr x N), optional B_er^T (Nr x N), C (Nr x Nr) */
     size_t workspace_bytes;  /* FFT grids, partial sums and the Krylov workspace */
     size_t total_bytes;      /* == toeplitz_plan_bytes() */
     int reciprocal;          /* 1 if the element-rim block is rim_re transposed */
+    int half_spectrum;       /* 1 if the generators are symmetric and half the spectrum is stored */
 } tp_plan_desc;
+
+/*
+ * Symmetry of the operator (the impedance matrix is symmetric, Sec. II-B), as
+ * bits of the sym argument of toeplitz_plan_bytes:
+ *   TP_SYM_RIM  the element-rim block is rim_re transposed (rim_er NULL): one
+ *               dense rim block per precision instead of two;
+ *   TP_SYM_GEN  the generators satisfy Z_{-m,-n} = Z_{m,n}^T: then the
+ *               spectrum satisfies Ghat(-k) = Ghat(k)^T and the plan stores
+ *               only the columns kx <= Px/2 (about half the spectrum bytes,
+ *               and half the spectrum stream of every matvec).
+ */
+#define TP_SYM_RIM 1
+#define TP_SYM_GEN 2
 
 /*
  * Device bytes a plan needs: the operator copies selected by prec (spectrum of
  * the generators, Sec. I / eq. submatrixAA, plus the dense rim of eqs.
  * submatrixBB..submatrixC456), FFT grids for up to max_rhs columns and the
  * Krylov workspace of GMRES(restart) for max_rhs columns.  Use it for admission
- * before creating a plan.  reciprocal = 1 when rim_er will be NULL (one dense
- * rim block instead of two).  bytes receives the size; returns TP_E_INVAL for
- * Nx, Ny, b < 1, Nr < 0, max_rhs < 1, restart < 1, Nx or Ny > 256, b > 256,
- * Nr > 2048, restart > 512 or sizes that overflow.
+ * before creating a plan.  sym: TP_SYM_RIM when rim_er will be NULL, plus
+ * TP_SYM_GEN when toeplitz_gen_symmetric reports the generators symmetric
+ * (toeplitz_plan_create decides the same way).  bytes receives the size;
+ * returns TP_E_INVAL for Nx, Ny, b < 1, Nr < 0, max_rhs < 1, restart < 1, Nx or
+ * Ny > 256, b > 256, Nr > 2048, restart > 512, unknown sym bits or sizes that
+ * overflow.
  */
-tp_status toeplitz_plan_bytes(int Nx, int Ny, int b, int Nr, int reciprocal, tp_prec prec,
+tp_status toeplitz_plan_bytes(int Nx, int Ny, int b, int Nr, int sym, tp_prec prec,
                               int max_rhs, int restart, size_t *bytes);
+
+/*
+ * Host check of the generator symmetry Z_{-m,-n} = Z_{m,n}^T (Sec. II-B):
+ * *symmetric = 1 if gen[2Ny-2-n][2Nx-2-m][q][p] equals gen[n][m][p][q] bit for
+ * bit for every entry, else 0.  gen: host complex128 in the layout of
+ * toeplitz_plan_create.  Errors: TP_E_INVAL (NULL pointers, Nx, Ny, b outside
+ * [1, 256]).
+ */
+tp_status toeplitz_gen_symmetric(int Nx, int Ny, int b, const double *gen, int *symmetric);
 
 /*
  * Build a plan in the caller's device buffer (Sec. II-C structure; Sec. I FFT
  * route): the generators are circulant-embedded in a Px x Py grid, transformed
  * by a 2-D DFT (forward sign exp(-2 pi i k n / P)) and scaled by 1/(Px Py); the
- * rim blocks are copied.  Every host input is copied; the caller may free them
+ * rim blocks are copied.  Symmetric generators (toeplitz_gen_symmetric) keep
+ * only the spectrum columns kx <= Px/2; the others are applied as transposes.  Every host input is copied; the caller may free them
  * on return.  The call synchronises hip_stream before returning.
  *
  *   gen     host complex128 [2Ny-1][2Nx-1][b][b] with
@@ -99,7 +125,8 @@ tp_status toeplitz_plan_bytes(int Nx, int Ny, int b, int Nr, int reciprocal, tp_
  *           toeplitz_plan_destroy and free it afterwards.
  *   out     receives the plan handle.
  * Errors: TP_E_INVAL (shapes, NULL pointers, misaligned buffer), TP_E_NOMEM
- * (dev_bytes too small), TP_E_HIP.
+ * (dev_bytes below toeplitz_plan_bytes with the sym bits this call implies),
+ * TP_E_HIP.
  */
 tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
                                const double *rim_re, const double *rim_er, const double *rim_rr,

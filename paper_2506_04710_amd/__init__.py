@@ -21,7 +21,8 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ToeplitzError, check  # noqa: F401
 
-__all__ = ["Plan", "plan_bytes", "precond_bytes", "port_smatrix", "far_field", "ToeplitzError", "load"]
+__all__ = ["Plan", "plan_bytes", "precond_bytes", "gen_symmetric", "port_smatrix", "far_field", "ToeplitzError",
+           "load"]
 
 
 def load():
@@ -29,21 +30,36 @@ def load():
     return _lib.lib()
 
 
-def plan_bytes(Nx, Ny, b, Nr, prec="mixed", max_rhs=1, restart=40, reciprocal=True) -> int:
+def plan_bytes(Nx, Ny, b, Nr, prec="mixed", max_rhs=1, restart=40, reciprocal=True, symmetric=False) -> int:
+    """Device bytes of a plan.  reciprocal: rim_er will be omitted (B_er = B^T);
+    symmetric: the generators are symmetric (gen_symmetric), so the plan keeps
+    half the spectrum."""
     n = ctypes.c_size_t(0)
-    check(_lib.lib().toeplitz_plan_bytes(Nx, Ny, b, Nr, 1 if reciprocal else 0, PREC[prec], max_rhs, restart,
-                                         ctypes.byref(n)))
+    sym = (_lib.TP_SYM_RIM if reciprocal else 0) | (_lib.TP_SYM_GEN if symmetric else 0)
+    check(_lib.lib().toeplitz_plan_bytes(Nx, Ny, b, Nr, sym, PREC[prec], max_rhs, restart, ctypes.byref(n)))
     return n.value
 
 
-def precond_bytes(Nx, Ny, b, Nr, prec="mixed") -> int:
+def gen_symmetric(Nx, Ny, b, gen) -> bool:
+    """Whether the generators satisfy Z_{-m,-n} = Z_{m,n}^T bit for bit (the
+    library's own host check; a plan of such generators stores half the
+    spectrum)."""
+    g = _host_c128(gen, (2 * Ny - 1, 2 * Nx - 1, b, b))
+    out = ctypes.c_int(0)
+    check(_lib.lib().toeplitz_gen_symmetric(Nx, Ny, b, g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)))
+    return bool(out.value)
+
+
+def precond_bytes(Nx, Ny, b, Nr, prec="mixed", symmetric=False) -> int:
     """Device bytes of the block-circulant preconditioner of such a plan: the
-    inverted spectrum per precision held (Px Py b^2 values), 1/diag(C), a
+    inverted spectrum per precision held (the plan's stored blocks: Px Py, or
+    (Px / 2 + 1) Py for symmetric generators, of b^2 values), 1/diag(C), a
     status word, each region 256-byte aligned (as toeplitz_precond_bytes)."""
     px, py = _grid(Nx), _grid(Ny)
+    nblk = (px // 2 + 1) * py if symmetric else px * py
     al = lambda v: (v + 255) // 256 * 256
     per = {"fp64": (16,), "fp32": (8,), "mixed": (16, 8)}[prec]
-    total = sum(al(px * py * b * b * s) for s in per)
+    total = sum(al(nblk * b * b * s) for s in per)
     if Nr:
         total += sum(al(Nr * s) for s in per)
     return total + 256
@@ -93,7 +109,8 @@ class Plan:
         rim_re = _host_c128(rim_re, (Nr, N)) if Nr else None
         rim_rr = _host_c128(rim_rr, (Nr, Nr)) if Nr else None
         rim_er = _host_c128(rim_er, (N, Nr)) if (Nr and rim_er is not None) else None
-        nbytes = plan_bytes(Nx, Ny, b, Nr, prec, max_rhs, restart, reciprocal=rim_er is None)
+        nbytes = plan_bytes(Nx, Ny, b, Nr, prec, max_rhs, restart, reciprocal=rim_er is None,
+                            symmetric=gen_symmetric(Nx, Ny, b, gen))
         self = cls()
         self.device = torch.device(device)
         self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)

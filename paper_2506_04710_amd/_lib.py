@@ -26,7 +26,9 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_solve_opts_default", "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_plan_destroy",
            "toeplitz_last_error", "toeplitz_batch_begin", "toeplitz_batch_admit", "toeplitz_batch_release",
            "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end", "toeplitz_port_smatrix",
-           "toeplitz_far_field", "toeplitz_precond_bytes", "toeplitz_precond_create", "toeplitz_precond_apply")
+           "toeplitz_far_field", "toeplitz_precond_bytes", "toeplitz_precond_create", "toeplitz_precond_apply",
+           "toeplitz_gen_symmetric")
+TP_SYM_RIM, TP_SYM_GEN = 1, 2
 
 
 class PlanDesc(ctypes.Structure):
@@ -35,7 +37,7 @@ class PlanDesc(ctypes.Structure):
                 ("max_rhs", ctypes.c_int), ("restart", ctypes.c_int), ("prec", ctypes.c_int),
                 ("spectrum_bytes", ctypes.c_size_t), ("rim_bytes", ctypes.c_size_t),
                 ("workspace_bytes", ctypes.c_size_t), ("total_bytes", ctypes.c_size_t),
-                ("reciprocal", ctypes.c_int)]
+                ("reciprocal", ctypes.c_int), ("half_spectrum", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -67,6 +69,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, ci, cl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_size_t
         L.toeplitz_plan_bytes.argtypes = [ci, ci, ci, ci, ci, ci, ci, ci, ctypes.POINTER(sz)]
+        L.toeplitz_gen_symmetric.argtypes = [ci, ci, ci, vp, ctypes.POINTER(ci)]
         L.toeplitz_plan_create.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, ci, ci, ci, vp, sz, vp,
                                            ctypes.POINTER(vp)]
         L.toeplitz_plan_info.argtypes = [vp, ctypes.POINTER(PlanDesc)]
@@ -97,7 +100,7 @@ def lib():
                      "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_batch_begin", "toeplitz_batch_admit",
                      "toeplitz_batch_release", "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end",
                      "toeplitz_port_smatrix", "toeplitz_far_field", "toeplitz_precond_bytes",
-                     "toeplitz_precond_create", "toeplitz_precond_apply"):
+                     "toeplitz_precond_create", "toeplitz_precond_apply", "toeplitz_gen_symmetric"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib

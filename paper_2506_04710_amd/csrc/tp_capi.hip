@@ -39,8 +39,8 @@ int choose_grid(int n) {
 int fft_factor(int P, int *radix, int *L) {
     int n = P, ns = 0;
     std::vector<int> f;
-    while (n % 4 == 0) { f.push_back(4); n /= 4; }
-    for (int r : {2, 3, 5, 7})
+    // fewest stages: radix 8 and 9 where they divide, then 4, 2, 3, 5, 7
+    for (int r : {8, 4, 2, 9, 3, 5, 7})
         while (n % r == 0) { f.push_back(r); n /= r; }
     int len = 1;
     for (int r : f) {
@@ -82,8 +82,9 @@ struct Layout {
     size_t G64, G32, B64, BE64, C64, B32, BE32, C32;   // offsets (SIZE_MAX = absent)
     size_t tab, ws, total;
     size_t spec1, rim1;      // bytes per copy (complex128)
-    size_t grid_bytes, rimpart_bytes, solver_bytes, scratch_bytes, ws_bytes;
+    size_t grid_bytes, rimpart_bytes, ypart_bytes, solver_bytes, scratch_bytes, ws_bytes;
     int rim_te, rim_nslab;
+    int kxh;                 // stored spectrum columns
 };
 
 static bool overflow_mul(size_t a, size_t b, size_t *out) {
@@ -92,8 +93,10 @@ static bool overflow_mul(size_t a, size_t b, size_t *out) {
     return false;
 }
 
-static tp_status make_layout(int Nx, int Ny, int b, int Nr, int reciprocal, tp_prec prec, int max_rhs,
-                             int restart, Layout *L) {
+// sym: TP_SYM_RIM (one dense rim block) | TP_SYM_GEN (half the spectrum)
+static tp_status make_layout(int Nx, int Ny, int b, int Nr, int sym, tp_prec prec, int max_rhs, int restart,
+                             Layout *L) {
+    const bool reciprocal = (sym & TP_SYM_RIM) != 0, half = (sym & TP_SYM_GEN) != 0;
     if (Nx < 1 || Ny < 1 || b < 1 || Nr < 0 || max_rhs < 1 || restart < 1)
         return fail(TP_E_INVAL, "Nx, Ny, b, max_rhs, restart must be >= 1 and Nr >= 0");
     if (prec != TP_FP64 && prec != TP_FP32 && prec != TP_MIXED) return fail(TP_E_INVAL, "unknown precision");
@@ -106,8 +109,11 @@ static tp_status make_layout(int Nx, int Ny, int b, int Nr, int reciprocal, tp_p
     if (L->Px > kMaxP || L->Py > kMaxP) return fail(TP_E_INVAL, "transform length exceeds 512");
     const size_t N = (size_t)Nx * Ny * b, Nt = N + Nr, P = (size_t)L->Px * L->Py;
     const size_t bb = (size_t)b * b;
+    // half spectrum: columns kx <= Px / 2 (Ghat(-k) = Ghat(k)^T)
+    L->kxh = half ? L->Px / 2 + 1 : L->Px;
+    const size_t nblk = (size_t)L->kxh * L->Py;
     size_t t;
-    if (overflow_mul(P, bb, &t) || overflow_mul(t, 16, &L->spec1)) return fail(TP_E_INVAL, "size overflow");
+    if (overflow_mul(nblk, bb, &t) || overflow_mul(t, 16, &L->spec1)) return fail(TP_E_INVAL, "size overflow");
     const size_t nrim = reciprocal ? 1 : 2;
     L->rim1 = (nrim * (size_t)Nr * N + (size_t)Nr * Nr) * 16;
     const bool f64 = prec != TP_FP32, f32 = prec != TP_FP64;
@@ -135,11 +141,14 @@ static tp_status make_layout(int Nx, int Ny, int b, int Nr, int reciprocal, tp_p
     L->rim_te = rim_slab_width((long)N);
     L->rim_nslab = (int)((N + L->rim_te - 1) / L->rim_te);
     L->rimpart_bytes = al((size_t)L->rim_nslab * (Nr ? Nr : 1) * max_rhs * 16);
+    // single-column half-spectrum path: mirror parts per row chunk of 8
+    L->ypart_bytes = half ? al((size_t)((b + 7) / 8) * Ny * (L->Px - L->kxh) * b * 16) : 0;
     L->solver_bytes = al(solver_ws_bytes((long)Nt, restart, max_rhs));
     // plan-time scratch: device copy of the generators + the x-transformed rows
     L->scratch_bytes = al((size_t)(2 * Ny - 1) * (2 * Nx - 1) * bb * 16) + al((size_t)(2 * Ny - 1) * L->Px * bb * 16) +
                        al((size_t)Nr * std::max(N, (size_t)Nr) * 16);
-    L->ws_bytes = std::max(2 * L->grid_bytes + L->rimpart_bytes + L->solver_bytes, L->scratch_bytes);
+    L->ws_bytes =
+        std::max(2 * L->grid_bytes + L->rimpart_bytes + L->ypart_bytes + L->solver_bytes, L->scratch_bytes);
     L->ws = take(true, L->ws_bytes);
     L->total = off;
     return TP_OK;
@@ -153,11 +162,34 @@ extern "C" {
 
 const char *toeplitz_last_error(void) { return g_err.c_str(); }
 
-tp_status toeplitz_plan_bytes(int Nx, int Ny, int b, int Nr, int reciprocal, tp_prec prec, int max_rhs,
-                              int restart, size_t *bytes) {
+tp_status toeplitz_gen_symmetric(int Nx, int Ny, int b, const double *gen, int *symmetric) {
+    if (!symmetric) return fail(TP_E_INVAL, "symmetric is NULL");
+    *symmetric = 0;
+    if (!gen) return fail(TP_E_INVAL, "gen is NULL");
+    if (Nx < 1 || Ny < 1 || b < 1 || Nx > 256 || Ny > 256 || b > 256)
+        return fail(TP_E_INVAL, "Nx, Ny, b must be in [1, 256]");
+    // gen[n][m][p][q] against gen[2Ny-2-n][2Nx-2-m][q][p], bit for bit
+    const long W = 2 * Nx - 1, H = 2 * Ny - 1, bb = (long)b * b;
+    for (long n = 0; n < H; ++n)
+        for (long m = 0; m < W; ++m) {
+            const double *a = gen + 2 * ((n * W + m) * bb);
+            const double *c = gen + 2 * (((H - 1 - n) * W + (W - 1 - m)) * bb);
+            for (int pp = 0; pp < b; ++pp)
+                for (int q = 0; q < b; ++q) {
+                    const double *u = a + 2 * ((long)pp * b + q), *v = c + 2 * ((long)q * b + pp);
+                    if (memcmp(u, v, 2 * sizeof(double)) != 0) return TP_OK;
+                }
+        }
+    *symmetric = 1;
+    return TP_OK;
+}
+
+tp_status toeplitz_plan_bytes(int Nx, int Ny, int b, int Nr, int sym, tp_prec prec, int max_rhs, int restart,
+                              size_t *bytes) {
     if (!bytes) return fail(TP_E_INVAL, "bytes is NULL");
+    if (sym & ~(TP_SYM_RIM | TP_SYM_GEN)) return fail(TP_E_INVAL, "sym holds unknown bits");
     Layout L;
-    tp_status s = make_layout(Nx, Ny, b, Nr, reciprocal ? 1 : 0, prec, max_rhs, restart, &L);
+    tp_status s = make_layout(Nx, Ny, b, Nr, sym, prec, max_rhs, restart, &L);
     if (s != TP_OK) return s;
     *bytes = L.total;
     return TP_OK;
@@ -173,8 +205,11 @@ tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
     if (!dev_buf) return fail(TP_E_INVAL, "dev_buf is NULL");
     if (((uintptr_t)dev_buf) & 255) return fail(TP_E_INVAL, "dev_buf must be 256-byte aligned");
     const int reciprocal = (rim_er == nullptr) ? 1 : 0;
+    int gsym = 0;
+    toeplitz_gen_symmetric(Nx, Ny, b, gen, &gsym);
     Layout L;
-    tp_status s = make_layout(Nx, Ny, b, Nr, reciprocal, prec, max_rhs, restart, &L);
+    tp_status s = make_layout(Nx, Ny, b, Nr, (reciprocal ? TP_SYM_RIM : 0) | (gsym ? TP_SYM_GEN : 0), prec, max_rhs,
+                              restart, &L);
     if (s != TP_OK) return s;
     if (dev_bytes < L.total)
         return fail(TP_E_NOMEM, "device buffer holds " + std::to_string(dev_bytes) + " bytes, plan needs " +
@@ -188,6 +223,7 @@ tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
     pl->Px = L.Px; pl->Py = L.Py;
     pl->N = (long)Nx * Ny * b; pl->Nt = pl->N + Nr;
     pl->max_rhs = max_rhs; pl->restart = restart; pl->prec = prec; pl->reciprocal = reciprocal;
+    pl->half = gsym; pl->kxh = L.kxh;
     pl->base = base; pl->total = L.total;
     pl->G64 = (c128 *)at(L.G64); pl->G32 = (c64 *)at(L.G32);
     pl->B64 = (c128 *)at(L.B64); pl->BE64 = (c128 *)at(L.BE64); pl->C64 = (c128 *)at(L.C64);
@@ -197,6 +233,8 @@ tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
     pl->gridA = pl->ws;
     pl->gridB = pl->ws + L.grid_bytes;
     pl->rim_part = pl->ws + 2 * L.grid_bytes;
+    pl->ypart = L.ypart_bytes ? pl->ws + 2 * L.grid_bytes + L.rimpart_bytes : nullptr;
+    pl->solver_ws = pl->ws + 2 * L.grid_bytes + L.rimpart_bytes + L.ypart_bytes;
     pl->rim_te = L.rim_te; pl->rim_nslab = L.rim_nslab;
 
     // transform tables
@@ -293,6 +331,7 @@ tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *d) {
     d->spectrum_bytes = p->spectrum_bytes; d->rim_bytes = p->rim_bytes;
     d->workspace_bytes = p->workspace_bytes; d->total_bytes = p->total;
     d->reciprocal = p->reciprocal;
+    d->half_spectrum = p->half;
     return TP_OK;
 }
 
@@ -360,22 +399,39 @@ tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void 
     if (!p || !host_out) return fail(TP_E_INVAL, "NULL argument");
     if (kx < 0 || kx >= p->Px || ky < 0 || ky >= p->Py) return fail(TP_E_INVAL, "frequency out of range");
     const size_t bb = (size_t)p->b * p->b;
-    const size_t k = (size_t)kx * p->Py + ky;
+    // a column the plan does not store is the transpose of the block at (-kx, -ky)
+    const bool tr = kx >= p->kxh;
+    const size_t k = tr ? (size_t)(p->Px - kx) * p->Py + (ky ? p->Py - ky : 0) : (size_t)kx * p->Py + ky;
     hipError_t e;
+    size_t es;
     if (which == TP_FP64) {
         if (!p->G64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 operator");
-        e = hipMemcpy(host_out, p->G64 + k * bb, bb * 16, hipMemcpyDeviceToHost);
+        es = 16;
+        e = hipMemcpy(host_out, p->G64 + k * bb, bb * es, hipMemcpyDeviceToHost);
     } else if (which == TP_FP32) {
         if (!p->G32) return fail(TP_E_UNSUPPORTED, "plan holds no FP32 operator");
-        e = hipMemcpy(host_out, p->G32 + k * bb, bb * 8, hipMemcpyDeviceToHost);
+        es = 8;
+        e = hipMemcpy(host_out, p->G32 + k * bb, bb * es, hipMemcpyDeviceToHost);
     } else {
         return fail(TP_E_INVAL, "precision must be TP_FP64 or TP_FP32");
     }
-    return e == hipSuccess ? TP_OK : hip_fail(e, "spectrum copy");
+    if (e != hipSuccess) return hip_fail(e, "spectrum copy");
+    if (tr) {
+        char *o = static_cast<char *>(host_out), tmp[16];
+        const int b = p->b;
+        for (int i = 0; i < b; ++i)
+            for (int j = i + 1; j < b; ++j) {
+                char *a = o + ((size_t)i * b + j) * es, *c = o + ((size_t)j * b + i) * es;
+                memcpy(tmp, a, es);
+                memcpy(a, c, es);
+                memcpy(c, tmp, es);
+            }
+    }
+    return TP_OK;
 }
 
 static size_t precond_layout(tp_plan p, size_t *s64, size_t *s32, size_t *d64, size_t *d32, size_t *flag) {
-    const size_t P = (size_t)p->Px * p->Py, bb = (size_t)p->b * p->b;
+    const size_t P = (size_t)p->kxh * p->Py, bb = (size_t)p->b * p->b;   // stored blocks
     size_t off = 0;
     auto take = [&](bool on, size_t bytes) {
         const size_t o = off;
@@ -407,7 +463,7 @@ tp_status toeplitz_precond_create(tp_plan p, void *dev_buf, size_t dev_bytes, vo
     if (dev_bytes < need) return fail(TP_E_NOMEM, "dev_buf smaller than toeplitz_precond_bytes()");
     char *base = static_cast<char *>(dev_buf);
     hipStream_t st = (hipStream_t)hip_stream;
-    const size_t nS = (size_t)p->Px * p->Py * p->b * p->b;
+    const size_t nS = (size_t)p->kxh * p->Py * p->b * p->b;
     p->has_precond = 0;
     p->S64 = reinterpret_cast<c128 *>(base + o64);
     p->S32 = o32 != (size_t)-1 ? reinterpret_cast<c64 *>(base + o32) : nullptr;

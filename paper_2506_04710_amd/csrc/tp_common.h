@@ -113,6 +113,92 @@ __device__ __forceinline__ void pin(const cpx<T> &v) {
     asm volatile("" : : "v"(v.x), "v"(v.y));
 }
 
+// ------------------------------------------------------------- lane sums
+// Sums with a partner lane inside a wave without the LDS crossbar
+// (__shfl_xor compiles to ds_bpermute): DPP quad permutations for lane l ^ 1
+// and l ^ 2, the row rotation by 8 for l ^ 8, the half-row mirror l ^ 7 (used
+// once the quads agree), and the gfx950 permlane swaps for l ^ 16 and l ^ 32:
+// permlane32_swap(a, b) leaves (a_lo, b_lo) in its first result and
+// (a_hi, b_hi) in its second (halves of 32 lanes); permlane16_swap does the
+// same with the even and odd rows of 16 lanes.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppRor8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) { return __uint_as_float(dpp_u32<CTRL>(__float_as_uint(v))); }
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long lo = dpp_u32<CTRL>((unsigned)u), hi = dpp_u32<CTRL>((unsigned)(u >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ cpx<T> dpp(cpx<T> v) { return cpx<T>{dpp<CTRL>(v.x), dpp<CTRL>(v.y)}; }
+
+template <int B>
+__device__ __forceinline__ void lane_swap(unsigned a, unsigned b, unsigned &d, unsigned &s) {
+    static_assert(B == 16 || B == 32, "permlane swaps exchange rows (16) or halves (32)");
+    if constexpr (B == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        d = r[0];
+        s = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        d = r[0];
+        s = r[1];
+    }
+}
+// Halving step on lane bit B (16 or 32): lanes with the bit clear return
+// lo + the partner's lo, the others hi + the partner's hi.
+template <int B>
+__device__ __forceinline__ float half_sum(float lo, float hi) {
+    unsigned d, s;
+    lane_swap<B>(__float_as_uint(lo), __float_as_uint(hi), d, s);
+    return __uint_as_float(d) + __uint_as_float(s);
+}
+template <int B>
+__device__ __forceinline__ double half_sum(double lo, double hi) {
+    const unsigned long long a = (unsigned long long)__double_as_longlong(lo),
+                             b = (unsigned long long)__double_as_longlong(hi);
+    unsigned d0, s0, d1, s1;
+    lane_swap<B>((unsigned)a, (unsigned)b, d0, s0);
+    lane_swap<B>((unsigned)(a >> 32), (unsigned)(b >> 32), d1, s1);
+    const double d = __longlong_as_double((long long)(((unsigned long long)d1 << 32) | d0));
+    const double s = __longlong_as_double((long long)(((unsigned long long)s1 << 32) | s0));
+    return d + s;
+}
+template <int B, typename T>
+__device__ __forceinline__ cpx<T> half_sum(cpx<T> lo, cpx<T> hi) {
+    return cpx<T>{half_sum<B>(lo.x, hi.x), half_sum<B>(lo.y, hi.y)};
+}
+// v + v of lane l ^ M (M = 1, 2, 8, 16, 32)
+template <int M, typename V>
+__device__ __forceinline__ V xor_sum(V v) {
+    static_assert(M == 1 || M == 2 || M == 8 || M == 16 || M == 32, "no single-instruction partner for M");
+    if constexpr (M == 1) return v + dpp<kDppXor1>(v);
+    else if constexpr (M == 2) return v + dpp<kDppXor2>(v);
+    else if constexpr (M == 8) return v + dpp<kDppRor8>(v);
+    else return half_sum<M>(v, v);
+}
+// Sum over the 8 lanes that share lane >> 3 (every one of them gets it).
+template <typename V>
+__device__ __forceinline__ V sum8(V v) {
+    v = xor_sum<1>(v);
+    v = xor_sum<2>(v);
+    return v + dpp<kDppHalfMirror>(v);
+}
+// Sum over the whole wave (every lane gets it).
+template <typename V>
+__device__ __forceinline__ V wave_allsum(V v) {
+    v = xor_sum<32>(v);
+    v = xor_sum<16>(v);
+    v = xor_sum<8>(v);
+    return sum8(v);
+}
+
 // Threads per workgroup of the transform, product and rim kernels.  Loops use
 // this constant rather than blockDim.x: the latter is read from the dispatch
 // packet in memory, and a barrier between two uses forces a fresh read.
@@ -152,6 +238,15 @@ struct FFTDesc {
 
 constexpr int kMaxP = 512;
 
+// Stored spectrum block of frequency k = kx Py + ky.  With half the spectrum
+// stored (columns kx < kxh), a column kx >= kxh is read as the transpose of
+// the block at (Px - kx, -ky mod Py).
+__device__ __forceinline__ long spec_src(long k, int Px, int Py, int kxh, bool &tr) {
+    const int kx = (int)(k / Py), ky = (int)(k - (long)kx * Py);
+    tr = kx >= kxh;
+    return tr ? (long)(Px - kx) * Py + (ky == 0 ? 0 : Py - ky) : k;
+}
+
 }  // namespace tp
 
 // Plan record (host memory; every pointer is into the caller's device buffer).
@@ -162,6 +257,10 @@ struct tp_plan_s {
     int max_rhs, restart;
     tp_prec prec;
     int reciprocal;
+    // symmetric generators (Z_{-m,-n} = Z_{m,n}^T): the spectrum holds only
+    // the columns kx < kxh = Px / 2 + 1, since Ghat(-k) = Ghat(k)^T; else
+    // kxh = Px and every column is stored
+    int half, kxh;
     char *base;
     size_t total;
     // operator copies
@@ -180,6 +279,8 @@ struct tp_plan_s {
     // matvec workspace
     void *gridA, *gridB;          // [max(Ny*Px, Px*Py)][b*max_rhs] complex128-sized each
     void *rim_part;               // [nslab][Nr][max_rhs] complex128-sized
+    void *ypart;                  // half spectrum, one column: mirror parts [nchunk][Ny][Px - kxh][b]
+    char *solver_ws;              // Krylov workspace
     int rim_te;                   // rim columns per slab
     int rim_nslab;
     // solver workspace

@@ -58,7 +58,28 @@ struct Roots<7> {
                                     -0.7818314824680298087084445266740577502323};
 };
 
+// exp(-2 pi i m / 9), m = 1, 2, 4, and cos(pi / 4), to 40 digits
+struct Roots9 {
+    static constexpr double c1 = 0.7660444431189780352023926505554166739358, s1 = 0.6427876096865393263226434099072634329076;
+    static constexpr double c2 = 0.1736481776669303488517166267693147960004, s2 = 0.9848077530122080593667430245895230136706;
+    static constexpr double c4 = -0.9396926207859083840541092773247314699362, s4 = 0.3420201433256687330440996146822595807631;
+};
+constexpr double kSqrtHalf = 0.7071067811865475244008443621048490392848;
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void small_dft(cpx<T> (&a)[R]);
+
+// a * exp(-+ i t) for the root (c, s) = (cos t, sin t)
+template <typename T, bool INV>
+__device__ __forceinline__ cpx<T> rot(cpx<T> a, T c, T s) {
+    const T sg = INV ? s : -s;   // forward multiplies by c - i s
+    return mk<T>(a.x * c - a.y * sg, a.x * sg + a.y * c);
+}
+
 // Radix-R DFT of a[0..R) in registers (forward: w = exp(-2 pi i / R)).
+// R = 8 is two radix-4 DFTs of the even and odd inputs joined by w^k; R = 9
+// is 3 x 3: radix-3 DFTs over n1 (n = 3 n1 + n2), the twiddles
+// w9^(n2 k1), radix-3 DFTs over n2, giving y[k1 + 3 k2].
 // Odd R pairs inputs q and R - q: with s_q = a_q + a_{R-q}, d_q = a_q - a_{R-q}
 // and t = 2 pi q k / R,
 //   y_k     = a_0 + sum_q (cos t) s_q - i (sin t) d_q
@@ -66,7 +87,44 @@ struct Roots<7> {
 // (signs of the sine terms swap for the inverse).
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void small_dft(cpx<T> (&a)[R]) {
-    if constexpr (R == 2) {
+    if constexpr (R == 8) {
+        cpx<T> e[4] = {a[0], a[2], a[4], a[6]}, o[4] = {a[1], a[3], a[5], a[7]};
+        small_dft<T, 4, INV>(e);
+        small_dft<T, 4, INV>(o);
+        const T h = (T)kSqrtHalf;
+        const cpx<T> o1 = rot<T, INV>(o[1], h, h), o3 = rot<T, INV>(o[3], -h, h);
+        // w^2 = -i (forward) or +i (inverse)
+        const cpx<T> o2 = INV ? mk<T>(-o[2].y, o[2].x) : mk<T>(o[2].y, -o[2].x);
+        a[0] = e[0] + o[0];
+        a[4] = e[0] - o[0];
+        a[1] = e[1] + o1;
+        a[5] = e[1] - o1;
+        a[2] = e[2] + o2;
+        a[6] = e[2] - o2;
+        a[3] = e[3] + o3;
+        a[7] = e[3] - o3;
+    } else if constexpr (R == 9) {
+        cpx<T> t[3][3];
+#pragma unroll
+        for (int n2 = 0; n2 < 3; ++n2) {
+            cpx<T> u[3] = {a[n2], a[n2 + 3], a[n2 + 6]};
+            small_dft<T, 3, INV>(u);
+#pragma unroll
+            for (int k1 = 0; k1 < 3; ++k1) t[n2][k1] = u[k1];
+        }
+        t[1][1] = rot<T, INV>(t[1][1], (T)Roots9::c1, (T)Roots9::s1);
+        t[1][2] = rot<T, INV>(t[1][2], (T)Roots9::c2, (T)Roots9::s2);
+        t[2][1] = rot<T, INV>(t[2][1], (T)Roots9::c2, (T)Roots9::s2);
+        t[2][2] = rot<T, INV>(t[2][2], (T)Roots9::c4, (T)Roots9::s4);
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) {
+            cpx<T> u[3] = {t[0][k1], t[1][k1], t[2][k1]};
+            small_dft<T, 3, INV>(u);
+            a[k1] = u[0];
+            a[k1 + 3] = u[1];
+            a[k1 + 6] = u[2];
+        }
+    } else if constexpr (R == 2) {
         cpx<T> t = a[0] - a[1];
         a[0] = a[0] + a[1];
         a[1] = t;
@@ -172,7 +230,87 @@ __device__ __forceinline__ void fft_stage(cpx<T> *buf, int lgCC, int P, int L, c
     fft_stage_axis<T, R, INV>(buf, lgCC, P, L, 1 << lgCC, 1, 0, twl);
 }
 
-// Transform all CC = 2^lgCC channels of buf (loaded in perm order, barrier done).
+// Decimation in frequency.  A stage above maps the R slots base + q L of one
+// butterfly by M[k2][q] = F_R[k2][q] w^(q j stride); the DFT matrix is
+// symmetric, so the transposed stages, applied in reverse order to input in
+// natural order, give the same transform with the output in digit-reversed
+// order (slot perm[k] holds X[k]).  The transposed stage takes the radix-R
+// DFT first and then multiplies output q by w^(q j stride).
+//
+// fft_stage2 runs one stage (DIT or DIF) over two tiles at once, b1 with
+// 2^lg1 channels and b2 (may be null) with 2^lg2, so that the two transforms
+// share the stage's barrier.
+template <typename T, int R, bool INV, bool DIF, int NT = kBlock>
+__device__ __forceinline__ void fft_stage2(cpx<T> *b1, int lg1, cpx<T> *b2, int lg2, int P, int L,
+                                           const cpx<T> *twl) {
+    // NI butterflies per thread and round: their LDS reads issue together
+    // (indices past the end are clamped; such a duplicate is not stored)
+    constexpr int NI = sizeof(T) == 4 ? 2 : 1;
+    const int nb = P / R;
+    const int stride = P / (L * R);
+    const int n1 = nb << lg1, total = n1 + (b2 ? (nb << lg2) : 0);
+    const float rL = 1.0f / (float)L;
+    for (int it0 = threadIdx.x; it0 < total; it0 += NI * NT) {
+        cpx<T> a[NI][R], w[NI][R];
+        cpx<T> *b0[NI];
+        int base[NI], lgv[NI];
+#pragma unroll
+        for (int ii = 0; ii < NI; ++ii) {
+            const int it = min(it0 + ii * NT, total - 1);
+            const bool sec = it >= n1;
+            const int lg = sec ? lg2 : lg1, i2 = sec ? it - n1 : it;
+            const int ch = i2 & ((1 << lg) - 1), bf = i2 >> lg;
+            int j;
+            const int grp = small_divmod(bf, L, rL, j);
+            base[ii] = grp * L * R + j;
+            lgv[ii] = lg;
+            b0[ii] = (sec ? b2 : b1) + ch;
+#pragma unroll
+            for (int q = 0; q < R; ++q) a[ii][q] = b0[ii][(base[ii] + q * L) << lg];
+#pragma unroll
+            for (int q = 1; q < R; ++q) w[ii][q] = twid<T, INV>(twl, q * j * stride);
+        }
+#pragma unroll
+        for (int ii = 0; ii < NI; ++ii) {
+            if constexpr (DIF) {
+                small_dft<T, R, INV>(a[ii]);
+#pragma unroll
+                for (int q = 1; q < R; ++q) a[ii][q] = a[ii][q] * w[ii][q];
+            } else {
+#pragma unroll
+                for (int q = 1; q < R; ++q) a[ii][q] = a[ii][q] * w[ii][q];
+                small_dft<T, R, INV>(a[ii]);
+            }
+        }
+#pragma unroll
+        for (int ii = 0; ii < NI; ++ii)
+            if (it0 + ii * NT < total)
+#pragma unroll
+                for (int q = 0; q < R; ++q) b0[ii][(base[ii] + q * L) << lgv[ii]] = a[ii][q];
+    }
+    __syncthreads();
+}
+
+// Two tiles transformed together (b2 may be null; barrier done before) by NT
+// threads.  DIT: input in digit-reversed order, output natural.  DIF: input
+// natural, output digit-reversed.
+template <typename T, bool INV, bool DIF, int NT = kBlock>
+__device__ void lds_fft2(cpx<T> *b1, int lg1, cpx<T> *b2, int lg2, const FFTDesc &d, const cpx<T> *twl) {
+    for (int t = 0; t < d.nst; ++t) {
+        const int s = DIF ? d.nst - 1 - t : t;
+        switch (d.radix[s]) {
+            case 2: fft_stage2<T, 2, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
+            case 3: fft_stage2<T, 3, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
+            case 4: fft_stage2<T, 4, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
+            case 5: fft_stage2<T, 5, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
+            case 7: fft_stage2<T, 7, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
+            case 8: fft_stage2<T, 8, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
+            case 9: fft_stage2<T, 9, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
+            default: break;
+        }
+    }
+}
+
 template <typename T, bool INV>
 __device__ void lds_fft(cpx<T> *buf, int lgCC, const FFTDesc &d, const cpx<T> *twl) {
     for (int s = 0; s < d.nst; ++s) {
@@ -182,7 +320,9 @@ __device__ void lds_fft(cpx<T> *buf, int lgCC, const FFTDesc &d, const cpx<T> *t
             case 4: fft_stage<T, 4, INV>(buf, lgCC, d.P, d.L[s], twl); break;
             case 5: fft_stage<T, 5, INV>(buf, lgCC, d.P, d.L[s], twl); break;
             case 7: fft_stage<T, 7, INV>(buf, lgCC, d.P, d.L[s], twl); break;
-            default: break;   // the host only builds radices 2, 3, 4, 5, 7
+            case 8: fft_stage<T, 8, INV>(buf, lgCC, d.P, d.L[s], twl); break;
+            case 9: fft_stage<T, 9, INV>(buf, lgCC, d.P, d.L[s], twl); break;
+            default: break;   // the host only builds radices 2, 3, 4, 5, 7, 8, 9
         }
     }
 }
@@ -201,6 +341,8 @@ __device__ void lds_fft_axis(cpx<T> *buf, int lgCC, const FFTDesc &d, int sp, in
             case 4: fft_stage_axis<T, 4, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
             case 5: fft_stage_axis<T, 5, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
             case 7: fft_stage_axis<T, 7, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
+            case 8: fft_stage_axis<T, 8, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
+            case 9: fft_stage_axis<T, 9, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
             default: break;
         }
     }

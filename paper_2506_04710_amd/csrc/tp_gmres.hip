@@ -139,9 +139,13 @@ __device__ __forceinline__ void tsum_step(c128 (&v)[16], int lane) {
     const bool hi = (lane & MSK) != 0;
 #pragma unroll
     for (int q = 0; q < HALF; ++q) {
-        const c128 mine = hi ? v[HALF + q] : v[q];
-        const c128 oth = hi ? v[q] : v[HALF + q];
-        v[q] = mine + shfl_xor_c(oth, MSK);
+        if constexpr (MSK >= 16) {
+            v[q] = half_sum<MSK>(v[q], v[HALF + q]);   // permlane swap of the two halves
+        } else {
+            const c128 mine = hi ? v[HALF + q] : v[q];
+            const c128 oth = hi ? v[q] : v[HALF + q];
+            v[q] = mine + (MSK == 8 ? dpp<kDppRor8>(oth) : shfl_xor_c(oth, MSK));
+        }
     }
 }
 __device__ __forceinline__ c128 wave_tsum16(c128 (&v)[16]) {
@@ -150,14 +154,11 @@ __device__ __forceinline__ c128 wave_tsum16(c128 (&v)[16]) {
     tsum_step<4, 16>(v, lane);
     tsum_step<2, 8>(v, lane);
     tsum_step<1, 4>(v, lane);
-    c128 t = v[0];
-    t = t + shfl_xor_c(t, 2);
-    return t + shfl_xor_c(t, 1);
+    return xor_sum<1>(xor_sum<2>(v[0]));
 }
 
 __device__ __forceinline__ double block_sum_d(double v, double *red /* [kWaves] LDS */) {
-#pragma unroll
-    for (int msk = 32; msk >= 1; msk >>= 1) v += __shfl_xor(v, msk, 64);
+    v = wave_allsum(v);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[w] = v;
@@ -187,8 +188,7 @@ __device__ __forceinline__ void reduce_partials(const c128 *P, int j, int nb, c1
         c128 t = v[0];
 #pragma unroll
         for (int u = 1; u < MAXL; ++u) t = t + v[u];
-#pragma unroll
-        for (int msk = TPI / 2; msk >= 1; msk >>= 1) t = t + shfl_xor_c(t, msk);
+        t = sum8(xor_sum<8>(xor_sum<16>(t)));   // the 32 lanes of this i (TPI = 32)
         if (k == 0 && i <= j) h[i] = t;
     }
     __syncthreads();
@@ -696,7 +696,7 @@ long solver_max_nt() { return (long)kLanes * kMaxEPT * kMaxBlocks; }
 static Eng engine_make(tp_plan pl, int m, int mixed, int nslots) {
     const long Nt = pl->Nt;
     EngLayout L = eng_layout(Nt, pl->restart, pl->max_rhs);
-    char *wsb = (char *)pl->rim_part + a256((size_t)pl->rim_nslab * (pl->Nr ? pl->Nr : 1) * pl->max_rhs * 16);
+    char *wsb = pl->solver_ws;
     Eng E;
     E.Nt = Nt;
     E.m = m;        // a shorter restart than the plan's uses a prefix of each region

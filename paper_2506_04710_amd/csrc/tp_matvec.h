@@ -1,3 +1,4 @@
+#pragma once
 // Operator application y = Z x for the array impedance matrix
 // Z = [[A, B_er], [B, C]] (eq. matrixForm; B_er = B^T when reciprocal).
 //
@@ -21,6 +22,11 @@
 //                extra workgroups of the same launch
 // A single column runs k_fwd_x -> k_spec_rim -> k_inv_x_fin; several columns
 // run k_rim_main, k_fwd_x, k_fwd_y, k_prod, k_inv_y, k_inv_x_fin.
+//
+// Symmetric generators (Z_{-m,-n} = Z_{m,n}^T) give Ghat(-k) = Ghat(k)^T, and
+// the plan then stores the spectrum columns kx <= Px/2 only: the products read
+// a mirrored frequency's block transposed, and the fused single-column path
+// applies each stored block to both of its frequencies (spec_block_half).
 #include "tp_fft.h"
 #include "tp_internal.h"
 
@@ -28,19 +34,13 @@ namespace tp {
 
 // ------------------------------------------------------------------ helpers
 template <typename T>
-__device__ __forceinline__ cpx<T> shfl_xor_c(cpx<T> v, int m) {
-    return mk<T>(__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64));
-}
-template <typename T>
 __device__ __forceinline__ cpx<T> wave_sum(cpx<T> v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = v + shfl_xor_c(v, m);
-    return v;
+    return wave_allsum(v);
 }
 
 template <typename T>
-__device__ __forceinline__ void zero_lds(cpx<T> *buf, int n) {
-    for (int i = threadIdx.x; i < n; i += kBlock) buf[i] = mk<T>(0, 0);
+__device__ __forceinline__ void zero_lds(cpx<T> *buf, int n, int nt = kBlock) {
+    for (int i = threadIdx.x; i < n; i += nt) buf[i] = mk<T>(0, 0);
 }
 
 // ------------------------------------------------------------ FFT passes
@@ -129,7 +129,8 @@ __global__ void __launch_bounds__(256) k_inv_y(const cpx<T> *__restrict__ in, in
 // takes panels w, w + 4, ... with the next panel's loads issued first.
 template <typename T, int VPL, int RC>
 __global__ void __launch_bounds__(256) k_prod(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ in,
-                                              int b, int R, cpx<T> *__restrict__ out, const void *const *act) {
+                                              int b, int R, cpx<T> *__restrict__ out, const void *const *act,
+                                              int Px, int Py, int kxh) {
     extern __shared__ char smem_raw[];
     cpx<T> *xs = reinterpret_cast<cpx<T> *>(smem_raw);   // [RC][b]
     const int C = b * R, r0 = blockIdx.y * RC;
@@ -138,7 +139,10 @@ __global__ void __launch_bounds__(256) k_prod(const cpx<T> *__restrict__ G, cons
     const int rn = min(RC, R - r0);
     if (!cols_live(act, r0, r0 + rn - 1)) return;
     const int pl = lane >> 3, qs = (lane & 7) * VPL;
-    const cpx<T> *Gk = G + k * (long)b * b;
+    // a mirrored frequency reads its stored block transposed
+    bool tr;
+    const cpx<T> *Gk = G + spec_src(k, Px, Py, kxh, tr) * (long)b * b;
+    const long sp = tr ? 1 : b, sq = tr ? b : 1;
     const int npanel = (b + 7) >> 3;
     cpx<T> gc[VPL], gn[VPL];
     auto load = [&](cpx<T>(&g)[VPL], int panel) {
@@ -146,7 +150,7 @@ __global__ void __launch_bounds__(256) k_prod(const cpx<T> *__restrict__ G, cons
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
             const int q = qs + v;
-            g[v] = (panel < npanel && p < b && q < b) ? Gk[(long)p * b + q] : mk<T>(0, 0);
+            g[v] = (panel < npanel && p < b && q < b) ? Gk[p * sp + q * sq] : mk<T>(0, 0);
         }
     };
     load(gc, w);
@@ -171,9 +175,7 @@ __global__ void __launch_bounds__(256) k_prod(const cpx<T> *__restrict__ G, cons
         }
 #pragma unroll
         for (int c = 0; c < RC; ++c) {
-            acc[c] = acc[c] + shfl_xor_c(acc[c], 1);
-            acc[c] = acc[c] + shfl_xor_c(acc[c], 2);
-            acc[c] = acc[c] + shfl_xor_c(acc[c], 4);
+            acc[c] = sum8(acc[c]);
         }
         if ((lane & 7) == 0 && p < b) {
 #pragma unroll
@@ -330,12 +332,7 @@ __device__ __forceinline__ void diag_finish_wave(const cpx<T> *__restrict__ D, C
 //      rows iy < Ny of Y1.
 // The y transform of the input column is repeated by the b / 8 workgroups of
 // a column; it is small next to the spectrum stream.
-template <typename T>
-__device__ __forceinline__ cpx<T> sum8(cpx<T> v) {
-    v = v + shfl_xor_c(v, 1);
-    v = v + shfl_xor_c(v, 2);
-    return v + shfl_xor_c(v, 4);
-}
+
 
 template <typename T, int VPL, int U>
 __device__ __forceinline__ void spec_block(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ X1,
@@ -366,19 +363,42 @@ __device__ __forceinline__ void spec_block(const cpx<T> *__restrict__ G, const c
             for (int v = 0; v < VPL; ++v) g[u][v] = Grow[ky * kstride + min(qs + v, b - 1)];
         }
     };
-    load(gc, w);
-    load_twiddles<T>(twl, fy);
-    for (int i = threadIdx.x; i < P; i += kBlock) perm[i] = fy.perm[i];
+    // The prologue's own loads (tables, the first 8 input values per thread)
+    // all issue together; the first panels follow the transform (issued
+    // earlier, they hold the waves at the load queue until the memory system
+    // has served the panels of every workgroup).
+    const int t = threadIdx.x, nx = Ny * CC;
+    const cpx<T> *tw = tw_of<T>(fy);
+    const cpx<T> tw0 = tw[min(t, P - 1)], tw1 = tw[min(t + kBlock, P - 1)];
+    const int pm0 = fy.perm[min(t, P - 1)], pm1 = fy.perm[min(t + kBlock, P - 1)];
+    auto xload = [&](int i) { return X1[((long)(i >> lgCC) * Px + kx) * b + min(i & (CC - 1), b - 1)]; };
+    cpx<T> xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = xload(min(t + u * kBlock, nx - 1));
     zero_lds<T>(xs, P * CC);
+    if (t < P) {
+        twl[t] = tw0;
+        perm[t] = pm0;
+    }
+    if (t + kBlock < P) {
+        twl[t + kBlock] = tw1;
+        perm[t + kBlock] = pm1;
+    }
     __syncthreads();
-    batched<8, cpx<T>>(
-        Ny * CC, [&](int i) { return X1[((long)(i >> lgCC) * Px + kx) * b + min(i & (CC - 1), b - 1)]; },
-        [&](int i, cpx<T> v) {
-            const int iy = i >> lgCC, c = i & (CC - 1);
-            if (c < b) xs[(perm[iy] << lgCC) + c] = v;
-        });
+    auto xstore = [&](int i, cpx<T> v) {
+        const int iy = i >> lgCC, c = i & (CC - 1);
+        if (c < b) xs[(perm[iy] << lgCC) + c] = v;
+    };
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (t + u * kBlock < nx) xstore(t + u * kBlock, xv[u]);
+    if (nx > 8 * kBlock)
+        batched<8, cpx<T>>(
+            nx - 8 * kBlock, [&](int i) { return xload(i + 8 * kBlock); },
+            [&](int i, cpx<T> v) { xstore(i + 8 * kBlock, v); });
     __syncthreads();
     lds_fft<T, false>(xs, lgCC, fy, twl);
+    load(gc, w);
     // values past the row (q >= b) are masked to zero; their LDS index is
     // clamped into the row so that no other row's (or uninitialised) value
     // enters the sum
@@ -421,15 +441,235 @@ __device__ __forceinline__ void spec_block(const cpx<T> *__restrict__ G, const c
     }
 }
 
+// Sum v[0..V) (V a power of two) over the 8 lanes that share lane & 7 (lane
+// bits 3..5), leaving each lane a share of the totals.  While more than one
+// value is left, a step on lane bit 5, 4, 3 keeps the half of the values that
+// the lane's bit selects and adds the partner's copy of that half; remaining
+// bits take plain sums.  With S = min(3, log2 V) halving steps and
+// g = (lane >> 3) >> (3 - S), v[i] (i < max(V / 8, 1)) ends up holding the
+// total of value i + (V >> S) g; for V < 8 the lanes with (lane >> 3) not a
+// multiple of 2^(3 - S) hold copies.
+template <int V>
+struct RS8 {
+    static constexpr int S = V >= 8 ? 3 : V >= 4 ? 2 : V >= 2 ? 1 : 0;
+    static constexpr int NV = V >= 8 ? V / 8 : 1;
+};
+template <typename T, int V, int STEP = 0>
+__device__ __forceinline__ void rs8(cpx<T> (&v)[V], int lane) {
+    constexpr int bit = 32 >> STEP;
+    if constexpr (STEP < RS8<V>::S) {
+        constexpr int h = V >> (STEP + 1);
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            if constexpr (bit == 8) {
+                const bool hi = (lane & bit) != 0;
+                const cpx<T> send = hi ? v[i] : v[i + h];
+                const cpx<T> kept = hi ? v[i + h] : v[i];
+                v[i] = kept + dpp<kDppRor8>(send);
+            } else {
+                v[i] = half_sum<bit>(v[i], v[i + h]);   // permlane swap of the two halves
+            }
+        }
+    } else {
+        v[0] = xor_sum<bit>(v[0]);
+    }
+    if constexpr (STEP < 2) rs8<T, V, STEP + 1>(v, lane);
+}
+
+constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 1) / 2); }
+
+// Fused single-column path over half the spectrum.  A symmetric operator
+// (Z_{-m,-n} = Z_{m,n}^T, Sec. II-B) has Ghat(-k) = Ghat(k)^T, and the plan
+// stores the columns kx < kxh = Px / 2 + 1 only.  Workgroup = stored column kx
+// and 8 rows p0..p0+7:
+//   * rows p0..p0+7 of yhat(kx, .) as in spec_block;
+//   * for the mirror column kxm = Px - kx (when it differs from kx), the part
+//     of yhat(kxm, -ky) = Ghat(kx, ky)^T xhat(kxm, -ky) that the 8 rows give,
+//     for every channel q: lanes form G[p][q] xhat(kxm, -ky)[p] and the 8
+//     lanes of a channel sum them (rs8).  The part is inverse-transformed
+//     along y here; the inverse x pass adds the nchunk parts.
+// The forward y transforms run in decimation-in-frequency order, so xhat(ky)
+// sits in LDS row perm[ky], the slot the inverse transform reads ky from.
+// Wave w takes the frequency pairs {j, -j}, j = w, w + 4, ... (j <= Py / 2), so
+// the mirror outputs of a pair go to the pair's own two rows, which no other
+// wave touches: they overwrite xhat(kx, .) there once both forward products
+// have read it.
+template <typename T, int VPL, int UP, int NT>
+__device__ __forceinline__ void spec_block_half(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ X1,
+                                                cpx<T> *__restrict__ Y1, cpx<T> *__restrict__ Yp, int b, int Ny,
+                                                int Px, int kxh, const FFTDesc &fy, int lgCC, int blk, char *smem) {
+    constexpr int TP = 8, VP = pow2_at_least(VPL), S = RS8<VP>::S, NV = RS8<VP>::NV;
+    const int P = fy.P, CC = 1 << lgCC;
+    const int nchunk = (b + TP - 1) / TP;
+    const int kx = blk / nchunk, ch = blk - kx * nchunk, p0 = ch * TP;
+    const int kxm = kx == 0 ? 0 : Px - kx;
+    const bool mir = kxm != kx;
+    cpx<T> *twl = reinterpret_cast<cpx<T> *>(smem);
+    cpx<T> *xs = twl + P;          // [Py][CC] xhat(kx, .), then the mirror part
+    cpx<T> *ys = xs + P * CC;      // [Py][TP] rows p0.. of yhat(kx, .)
+    cpx<T> *xm = ys + P * TP;      // [Py][TP] channels p0.. of xhat(kxm, .)
+    int *perm = reinterpret_cast<int *>(xm + P * TP);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = NT >> 6;
+    const int pl = lane >> 3, qs = (lane & 7) * VPL, p = p0 + pl;
+    const bool prow = p < b;
+    const long kstride = (long)b * b;
+    const cpx<T> *Grow = G + (long)kx * P * kstride + (long)min(p, b - 1) * b;
+    const int npair = P / 2 + 1;
+    // a register buffer holds the two panels of each of UP pairs (the wave's
+    // pairs j, j + 4, ...); clamped addresses (no branches around the loads)
+    cpx<T> gc[2 * UP][VPL], gn[2 * UP][VPL];
+    auto load = [&](cpx<T>(&g)[2 * UP][VPL], int j0) {
+#pragma unroll
+        for (int up = 0; up < UP; ++up) {
+            const int ja = min(j0 + up * nw, npair - 1), jb = ja == 0 ? 0 : P - ja;
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+                g[2 * up][v] = Grow[ja * kstride + min(qs + v, b - 1)];
+                g[2 * up + 1][v] = Grow[jb * kstride + min(qs + v, b - 1)];
+            }
+        }
+    };
+    // The prologue's own loads (tables, the first input values of both
+    // columns) all issue together; the first panels follow the transforms
+    // (issued earlier, they hold the waves at the load queue until the
+    // memory system has served the panels of every workgroup).  Inputs go in
+    // natural order: rows iy < Ny of column kx (all channels) and of column
+    // kxm (channels p0..p0+7).
+    const int t = threadIdx.x, nx = Ny * CC, nxm = mir ? Ny * TP : 0;
+    const cpx<T> *tw = tw_of<T>(fy);
+    const cpx<T> tw0 = tw[min(t, P - 1)], tw1 = tw[min(t + NT, P - 1)];
+    const int pm0 = fy.perm[min(t, P - 1)], pm1 = fy.perm[min(t + NT, P - 1)];
+    auto xload = [&](int i) { return X1[((long)(i >> lgCC) * Px + kx) * b + min(i & (CC - 1), b - 1)]; };
+    auto mload = [&](int i) { return X1[((long)(i >> 3) * Px + kxm) * b + min(p0 + (i & (TP - 1)), b - 1)]; };
+    constexpr int XU = NT >= 2048 ? 1 : 2048 / NT;   // first-round input values per thread
+    cpx<T> xv[XU];
+#pragma unroll
+    for (int u = 0; u < XU; ++u) xv[u] = xload(min(t + u * NT, nx - 1));
+    const cpx<T> mv = mload(min(t, Ny * TP - 1));
+    zero_lds<T>(xs, P * CC, NT);
+    if (mir) zero_lds<T>(xm, P * TP, NT);
+    if (t < P) {
+        twl[t] = tw0;
+        perm[t] = pm0;
+    }
+    if (t + NT < P) {
+        twl[t + NT] = tw1;
+        perm[t + NT] = pm1;
+    }
+    __syncthreads();
+    auto xstore = [&](int i, cpx<T> v) {
+        if ((i & (CC - 1)) < b) xs[i] = v;
+    };
+    auto mstore = [&](int i, cpx<T> v) {
+        if (p0 + (i & (TP - 1)) < b) xm[i] = v;
+    };
+#pragma unroll
+    for (int u = 0; u < XU; ++u)
+        if (t + u * NT < nx) xstore(t + u * NT, xv[u]);
+    if (t < nxm) mstore(t, mv);
+    if (nx > XU * NT)
+        batched<8, cpx<T>>(
+            nx - XU * NT, [&](int i) { return xload(i + XU * NT); },
+            [&](int i, cpx<T> v) { xstore(i + XU * NT, v); }, NT);
+    if (nxm > NT)
+        batched<8, cpx<T>>(
+            nxm - NT, [&](int i) { return mload(i + NT); }, [&](int i, cpx<T> v) { mstore(i + NT, v); }, NT);
+    __syncthreads();
+    lds_fft2<T, false, true, NT>(xs, lgCC, mir ? xm : nullptr, 3, fy, twl);
+    load(gc, w);
+    bool qok[VPL];
+    int qi[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        qok[v] = prow && qs + v < b;
+        qi[v] = min(qs + v, CC - 1);
+    }
+    const int grp = pl >> (3 - S);
+    const bool writer = (pl & ((1 << (3 - S)) - 1)) == 0;
+    auto reduce_pair = [&](const cpx<T>(&g)[2 * UP][VPL], int up, int j) {
+        const bool aok = j < npair;
+        const int ja = min(j, npair - 1), jb = ja == 0 ? 0 : P - ja;
+        const bool bok = aok && jb != ja;
+        const int ra = perm[ja], rb = perm[jb];
+        cpx<T> acc[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const cpx<T> *xk = xs + ((u ? rb : ra) << lgCC);
+            cpx<T> a = mk<T>(0, 0);
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) a = cmac(a, keep(g[2 * up + u][v], qok[v]), xk[qi[v]]);
+            acc[u] = sum8(a);
+        }
+        cpx<T> mo[2][NV];
+        if (mir) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                // panel u's mirror frequency is the other member of the pair
+                const cpx<T> xv = xm[((u ? ra : rb) << 3) + pl];
+                cpx<T> m[VP];
+#pragma unroll
+                for (int v = 0; v < VP; ++v) m[v] = v < VPL ? keep(g[2 * up + u][v], qok[v]) * xv : mk<T>(0, 0);
+                rs8<T, VP>(m, lane);
+#pragma unroll
+                for (int i = 0; i < NV; ++i) mo[u][i] = m[i];
+            }
+        }
+        // rows ra and rb have been read above; from here on they are written
+        if ((lane & 7) == 0) {
+            if (aok) ys[(ra << 3) + pl] = acc[0];
+            if (bok) ys[(rb << 3) + pl] = acc[1];
+        }
+        if (mir) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const bool ok = (u ? bok : aok) && writer;
+                cpx<T> *row = xs + ((u ? ra : rb) << lgCC);
+#pragma unroll
+                for (int i = 0; i < NV; ++i) {
+                    const int v = i + (VP >> S) * grp;
+                    if (ok && v < VPL && qs + v < b) row[qs + v] = mo[u][i];
+                }
+            }
+        }
+    };
+    auto reduce = [&](const cpx<T>(&g)[2 * UP][VPL], int j0) {
+#pragma unroll
+        for (int up = 0; up < UP; ++up) reduce_pair(g, up, j0 + up * nw);
+    };
+    // two register buffers in turn, loads unconditional (see spec_block)
+    const int bstep = UP * nw;
+    for (int j0 = w; j0 < npair; j0 += 2 * bstep) {
+        load(gn, j0 + bstep);
+        reduce(gc, j0);
+        load(gc, j0 + 2 * bstep);
+        if (j0 + bstep < npair) reduce(gn, j0 + bstep);
+    }
+    __syncthreads();
+    lds_fft2<T, true, false, NT>(ys, 3, mir ? xs : nullptr, lgCC, fy, twl);
+    for (int i = threadIdx.x; i < Ny * TP; i += NT) {
+        const int iy = i >> 3, pr = i & 7, pp = p0 + pr;
+        if (pp < b) Y1[((long)iy * Px + kx) * b + pp] = ys[i];
+    }
+    if (mir) {
+        const int nmir = Px - kxh;
+        cpx<T> *yp = Yp + ((long)ch * Ny * nmir + (kxm - kxh)) * b;
+        for (int i = threadIdx.x; i < Ny * CC; i += NT) {
+            const int iy = i >> lgCC, q = i & (CC - 1);
+            if (q < b) yp[(long)iy * nmir * b + q] = xs[i];
+        }
+    }
+}
+
 // Rim pass for a single column.  Slab = TE = 64 E element columns x all Nr
 // rows; 16 lanes per row: lane l takes row offset l >> 4 of each group of 4
 // rows and the VE = 4 E columns [(l & 15) VE, (l & 15) VE + VE) of the slab,
 // so a group of 4 rows is 4 contiguous TE-column runs.  Per row the 16 lanes
 // add up sum_e B[row][e] x_A[e] (-> slab partial of y_r); every lane keeps
 // sum_row BE[row][e] x_r[row] for its columns, and those are summed over the
-// row lanes and the waves at the end (-> y_A).  The next group's loads are
-// issued before the current group is used.
-template <typename T, typename In, typename Out, int E, bool NBE>
+// row lanes and the waves at the end (-> y_A).  A register buffer holds UR
+// groups (the wave's next UR groups); the next buffer's loads are issued
+// before the current one is used.
+template <typename T, typename In, typename Out, int E, bool NBE, int UR>
 __device__ __forceinline__ void rim_block1(const cpx<T> *__restrict__ B, const cpx<T> *__restrict__ BE,
                                            Cols<const In> x, Cols<Out> y, long N, int Nr,
                                            cpx<T> *__restrict__ part, int slab, char *smem) {
@@ -459,44 +699,53 @@ __device__ __forceinline__ void rim_block1(const cpx<T> *__restrict__ B, const c
         eok[v] = e0 + cs + v < N;
         ei[v] = min(e0 + cs + v, N - 1);
     }
-    cpx<T> gc[VE], gn[VE], ec[NBE ? VE : 1], en[NBE ? VE : 1];
-    auto load = [&](cpx<T>(&g)[VE], cpx<T>(&ge)[NBE ? VE : 1], int row) {
-        const long rr = (long)min(row, Nr - 1) * N;
+    constexpr int NE = NBE ? VE : 1;
+    const int step = nw * 4, bstep = UR * step;   // rows between a wave's groups, between buffers
+    cpx<T> gc[UR][VE], gn[UR][VE], ec[UR][NE], en[UR][NE];
+    auto load = [&](cpx<T>(&g)[UR][VE], cpx<T>(&ge)[UR][NE], int row) {
 #pragma unroll
-        for (int v = 0; v < VE; ++v) {
-            g[v] = B[rr + ei[v]];
-            if constexpr (NBE) ge[v] = BE[rr + ei[v]];
+        for (int u = 0; u < UR; ++u) {
+            const long rr = (long)min(row + u * step, Nr - 1) * N;
+#pragma unroll
+            for (int v = 0; v < VE; ++v) {
+                g[u][v] = B[rr + ei[v]];
+                if constexpr (NBE) ge[u][v] = BE[rr + ei[v]];
+            }
         }
     };
-    auto rows = [&](const cpx<T>(&g)[VE], const cpx<T>(&ge)[NBE ? VE : 1], int row) {
-        cpx<T> sr = mk<T>(0, 0);
-        const bool rok = row < Nr;
-        const cpx<T> xrow = xr[min(row, Nr - 1)];
+    auto rows = [&](const cpx<T>(&g)[UR][VE], const cpx<T>(&ge)[UR][NE], int row0) {
 #pragma unroll
-        for (int v = 0; v < VE; ++v) {
-            const cpx<T> gv = keep(g[v], rok && eok[v]);
-            sr = cmac(sr, gv, xa[v]);
-            acc[v] = cmac(acc[v], NBE ? keep(ge[NBE ? v : 0], rok && eok[v]) : gv, xrow);
+        for (int u = 0; u < UR; ++u) {
+            const int row = row0 + u * step;
+            cpx<T> sr = mk<T>(0, 0);
+            const bool rok = row < Nr;
+            const cpx<T> xrow = xr[min(row, Nr - 1)];
+#pragma unroll
+            for (int v = 0; v < VE; ++v) {
+                const cpx<T> gv = keep(g[u][v], rok && eok[v]);
+                sr = cmac(sr, gv, xa[v]);
+                acc[v] = cmac(acc[v], NBE ? keep(ge[u][NBE ? v : 0], rok && eok[v]) : gv, xrow);
+            }
+            sr = xor_sum<8>(sr);
+            sr = sum8(sr);
+            if ((lane & 15) == 0 && rok) part[(long)slab * Nr + row] = sr;
         }
-        sr = sr + shfl_xor_c(sr, 8);
-        sr = sum8(sr);
-        if ((lane & 15) == 0 && rok) part[(long)slab * Nr + row] = sr;
     };
     // groups of 4 rows; two register buffers in turn
-    const int r0 = w * 4 + ro, step = nw * 4;
+    const int r0 = w * 4 + ro;
     load(gc, ec, r0);
-    for (int g0 = w * 4; g0 < Nr; g0 += 2 * step) {
+    for (int g0 = w * 4; g0 < Nr; g0 += 2 * bstep) {
         const int row = r0 + (g0 - w * 4);
-        load(gn, en, row + step);          // unconditional: see the spectrum stream
+        load(gn, en, row + bstep);          // unconditional: see the spectrum stream
         rows(gc, ec, row);
-        load(gc, ec, row + 2 * step);
-        if (g0 + step < Nr) rows(gn, en, row + step);
+        load(gc, ec, row + 2 * bstep);
+        if (g0 + bstep < Nr) rows(gn, en, row + bstep);
     }
     // sum the four row lanes of each column, then the waves
 #pragma unroll
     for (int v = 0; v < VE; ++v) {
-        acc[v] = acc[v] + shfl_xor_c(acc[v], 16);
-        acc[v] = acc[v] + shfl_xor_c(acc[v], 32);
+        acc[v] = xor_sum<16>(acc[v]);
+        acc[v] = xor_sum<32>(acc[v]);
     }
     if (ro == 0)
 #pragma unroll
@@ -515,12 +764,13 @@ __device__ __forceinline__ void rim_block1(const cpx<T> *__restrict__ B, const c
 // Spectrum workgroups and rim workgroups share one launch so that both HBM
 // streams (the spectrum and the dense rim) run together; the two kinds are
 // interleaved in block order.
-template <typename T, typename In, typename Out, int VPL, int U, int E, bool NBE>
-__global__ void __launch_bounds__(256) k_spec_rim(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ X1,
+template <typename T, typename In, typename Out, int VPL, int U, int E, bool NBE, bool HALF, int NT = kBlock>
+__global__ void __launch_bounds__(NT) k_spec_rim(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ X1,
                                                   cpx<T> *__restrict__ Y1, int b, int Ny, int Px, FFTDesc fy,
                                                   int lgCC, int nspec, const cpx<T> *__restrict__ B,
                                                   const cpx<T> *__restrict__ BE, Cols<const In> x, Cols<Out> y,
-                                                  long N, int Nr, cpx<T> *__restrict__ part, int nrim) {
+                                                  long N, int Nr, cpx<T> *__restrict__ part, int nrim,
+                                                  cpx<T> *__restrict__ Yp, int kxh) {
     extern __shared__ char smem_raw[];
     const int i = blockIdx.x, both = 2 * min(nspec, nrim);
     int spec_id, rim_id;
@@ -536,20 +786,39 @@ __global__ void __launch_bounds__(256) k_spec_rim(const cpx<T> *__restrict__ G, 
     }
     if (spec_id >= 0) {
         if (!cols_live((const void *const *)x.tab, 0, 0)) return;
-        spec_block<T, VPL, U>(G, X1, Y1, b, Ny, Px, fy, lgCC, spec_id, smem_raw);
+        // without the rim pass the spectrum stream alone must keep HBM busy:
+        // two pairs per register buffer (FP32)
+        if constexpr (HALF)
+            spec_block_half<T, VPL, (E == 0 && sizeof(T) == 4) ? 2 : 1, NT>(G, X1, Y1, Yp, b, Ny, Px, kxh, fy,
+                                                                         lgCC, spec_id, smem_raw);
+        else
+            spec_block<T, VPL, U>(G, X1, Y1, b, Ny, Px, fy, lgCC, spec_id, smem_raw);
     } else if constexpr (E > 0) {
-        rim_block1<T, In, Out, E, NBE>(B, BE, x, y, N, Nr, part, rim_id, smem_raw);
+        // two groups per buffer for FP32 slabs of up to 128 columns (the
+        // register budget of wider slabs and of FP64 holds one)
+        rim_block1<T, In, Out, E, NBE, (sizeof(T) == 4 && E <= 2) ? 2 : 1>(B, BE, x, y, N, Nr, part, rim_id,
+                                                                          smem_raw);
     }
 }
 
 // Inverse x transform + crop (+ rim term already in y), and the rim finish
 // waves, in one launch: blocks [0, ninv) transform, the rest finish rim rows.
+// Mirror parts of the half-spectrum single-column path: columns kx >= kxh of
+// the y-transformed grid are the sum over nch parts, part h of (iy, kx, c) at
+// yp[h * hstride + (iy * nmir + kx - kxh) * b + c].
+template <typename T>
+struct MirrorParts {
+    const cpx<T> *yp;
+    int kxh, nmir, nch;
+    long hstride;
+};
+
 template <typename T, typename In, typename Out>
 __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in, int R, int Nx, int b, FFTDesc fx,
                                                    int lgCC, int nchunk, Cols<Out> y, int accumulate,
                                                    Cols<const Out> acc, int ninv, const cpx<T> *__restrict__ part,
                                                    const cpx<T> *__restrict__ Cm, const cpx<T> *__restrict__ D,
-                                                   Cols<const In> x, long N, int Nr, int nslab) {
+                                                   Cols<const In> x, long N, int Nr, int nslab, MirrorParts<T> mp) {
     extern __shared__ char smem_raw[];
     const int blk = blockIdx.x;
     if (blk >= ninv) {
@@ -570,7 +839,16 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
     load_twiddles<T>(twl, fx);
     for (int i = threadIdx.x; i < P * CC; i += kBlock) {
         const int kx = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
-        buf[(fx.perm[kx] << lgCC) + cl] = (c < C) ? in[((long)iy * P + kx) * C + c] : mk<T>(0, 0);
+        cpx<T> v = mk<T>(0, 0);
+        if (c < C) {
+            if (mp.yp && kx >= mp.kxh) {
+                const cpx<T> *src = mp.yp + ((long)iy * mp.nmir + (kx - mp.kxh)) * b + c;
+                for (int h = 0; h < mp.nch; ++h) v = v + src[h * mp.hstride];
+            } else {
+                v = in[((long)iy * P + kx) * C + c];
+            }
+        }
+        buf[(fx.perm[kx] << lgCC) + cl] = v;
     }
     __syncthreads();
     lds_fft<T, true>(buf, lgCC, fx, twl);
@@ -792,7 +1070,8 @@ static int next_pow2(int v) {
 // Fused single-column path: LDS bytes.
 static size_t spec_lds(tp_plan pl, size_t es) {
     const int P = pl->Py, CC = next_pow2(pl->b);
-    return ((size_t)P + (size_t)P * CC + (size_t)P * 8) * es + (size_t)P * sizeof(int);
+    const size_t xm = pl->half ? (size_t)P * 8 : 0;   // mirror column channels
+    return ((size_t)P + (size_t)P * CC + (size_t)P * 8 + xm) * es + (size_t)P * sizeof(int);
 }
 static size_t rim_lds(tp_plan pl, int RB, size_t es) { return ((size_t)RB * pl->Nr + 4 * (size_t)pl->rim_te * RB) * es; }
 constexpr size_t kLdsLimit = 160 * 1024;
@@ -817,12 +1096,28 @@ static void launch_spec_rim(tp_plan pl, const cpx<T> *G, Cols<const In> x, Cols<
 #define TP_SPEC_U64 2
 #endif
     constexpr int U = sizeof(T) == 8 ? TP_SPEC_U64 : VPL > 8 ? 1 : (E == 0 ? TP_SPEC_U32_NORIM : TP_SPEC_U32);
-    const int nchunk = (pl->b + 7) / 8, nspec = pl->Px * nchunk;
+    // half spectrum: one workgroup per stored column and row chunk
+    const int nchunk = (pl->b + 7) / 8, nspec = pl->kxh * nchunk;
     const int nrim = E > 0 ? pl->rim_nslab : 0;
     const int lgCC = ilog2(next_pow2(pl->b));
-    hipLaunchKernelGGL((k_spec_rim<T, In, Out, VPL, U, E, NBE>), dim3(nspec + nrim), dim3(256), sh, st, G, gA, gB,
-                       pl->b, pl->Ny, pl->Px, pl->fy, lgCC, nspec, OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl), x, y, pl->N,
-                       pl->Nr, reinterpret_cast<cpx<T> *>(pl->rim_part), nrim);
+    cpx<T> *yp = reinterpret_cast<cpx<T> *>(pl->ypart);
+    // (the half-spectrum form holds two panels per register buffer: rows of at
+    // most 64 values, VPL <= 8)
+    // Without the rim pass (E = 0) the spectrum workgroups have the GPU to
+    // themselves: 8 waves each (FP32), so a column's stream and transforms
+    // use a whole compute unit.
+    if constexpr (VPL <= 8)
+        if (pl->half) {
+            constexpr int NT = (E == 0 && sizeof(T) == 4) ? 512 : kBlock;
+            hipLaunchKernelGGL((k_spec_rim<T, In, Out, VPL, U, E, NBE, true, NT>), dim3(nspec + nrim), dim3(NT), sh,
+                               st, G, gA, gB, pl->b, pl->Ny, pl->Px, pl->fy, lgCC, nspec, OpPtrs<T>::B(pl),
+                               OpPtrs<T>::BE(pl), x, y, pl->N, pl->Nr, reinterpret_cast<cpx<T> *>(pl->rim_part), nrim,
+                               yp, pl->kxh);
+            return;
+        }
+        hipLaunchKernelGGL((k_spec_rim<T, In, Out, VPL, U, E, NBE, false>), dim3(nspec + nrim), dim3(256), sh, st, G,
+                           gA, gB, pl->b, pl->Ny, pl->Px, pl->fy, lgCC, nspec, OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl),
+                           x, y, pl->N, pl->Nr, reinterpret_cast<cpx<T> *>(pl->rim_part), nrim, yp, pl->kxh);
 }
 
 // rim: whether the launch carries the rim pass (the operator with Nr > 0)
@@ -845,25 +1140,31 @@ static void launch_spec_rim_e(tp_plan pl, const cpx<T> *G, bool rim, Cols<const 
 }
 
 template <typename T, int VPL>
-static void launch_prod_v(int RC, dim3 grid, size_t sh, hipStream_t st, const cpx<T> *G, const cpx<T> *in, int b,
-                          int R, cpx<T> *out, const void *const *act) {
+static void launch_prod_v(tp_plan pl, int RC, dim3 grid, size_t sh, hipStream_t st, const cpx<T> *G,
+                          const cpx<T> *in, int b, int R, cpx<T> *out, const void *const *act) {
+    const int Px = pl->Px, Py = pl->Py, kxh = pl->kxh;
     switch (RC) {
-        case 2: hipLaunchKernelGGL((k_prod<T, VPL, 2>), grid, dim3(256), sh, st, G, in, b, R, out, act); break;
-        case 4: hipLaunchKernelGGL((k_prod<T, VPL, 4>), grid, dim3(256), sh, st, G, in, b, R, out, act); break;
-        case 8: hipLaunchKernelGGL((k_prod<T, VPL, 8>), grid, dim3(256), sh, st, G, in, b, R, out, act); break;
-        default: hipLaunchKernelGGL((k_prod<T, VPL, 16>), grid, dim3(256), sh, st, G, in, b, R, out, act); break;
+        case 2: hipLaunchKernelGGL((k_prod<T, VPL, 2>), grid, dim3(256), sh, st, G, in, b, R, out, act, Px, Py, kxh);
+                break;
+        case 4: hipLaunchKernelGGL((k_prod<T, VPL, 4>), grid, dim3(256), sh, st, G, in, b, R, out, act, Px, Py, kxh);
+                break;
+        case 8: hipLaunchKernelGGL((k_prod<T, VPL, 8>), grid, dim3(256), sh, st, G, in, b, R, out, act, Px, Py, kxh);
+                break;
+        default: hipLaunchKernelGGL((k_prod<T, VPL, 16>), grid, dim3(256), sh, st, G, in, b, R, out, act, Px, Py,
+                                    kxh);
+                 break;
     }
 }
 template <typename T>
-static void launch_prod(int vpl, int RC, dim3 grid, size_t sh, hipStream_t st, const cpx<T> *G, const cpx<T> *in,
-                        int b, int R, cpx<T> *out, const void *const *act) {
-    if (vpl <= 2) launch_prod_v<T, 2>(RC, grid, sh, st, G, in, b, R, out, act);
-    else if (vpl <= 4) launch_prod_v<T, 4>(RC, grid, sh, st, G, in, b, R, out, act);
-    else if (vpl <= 6) launch_prod_v<T, 6>(RC, grid, sh, st, G, in, b, R, out, act);
-    else if (vpl <= 8) launch_prod_v<T, 8>(RC, grid, sh, st, G, in, b, R, out, act);
-    else if (vpl <= 12) launch_prod_v<T, 12>(RC, grid, sh, st, G, in, b, R, out, act);
-    else if (vpl <= 16) launch_prod_v<T, 16>(RC, grid, sh, st, G, in, b, R, out, act);
-    else launch_prod_v<T, 32>(RC, grid, sh, st, G, in, b, R, out, act);
+static void launch_prod(tp_plan pl, int vpl, int RC, dim3 grid, size_t sh, hipStream_t st, const cpx<T> *G,
+                        const cpx<T> *in, int b, int R, cpx<T> *out, const void *const *act) {
+    if (vpl <= 2) launch_prod_v<T, 2>(pl, RC, grid, sh, st, G, in, b, R, out, act);
+    else if (vpl <= 4) launch_prod_v<T, 4>(pl, RC, grid, sh, st, G, in, b, R, out, act);
+    else if (vpl <= 6) launch_prod_v<T, 6>(pl, RC, grid, sh, st, G, in, b, R, out, act);
+    else if (vpl <= 8) launch_prod_v<T, 8>(pl, RC, grid, sh, st, G, in, b, R, out, act);
+    else if (vpl <= 12) launch_prod_v<T, 12>(pl, RC, grid, sh, st, G, in, b, R, out, act);
+    else if (vpl <= 16) launch_prod_v<T, 16>(pl, RC, grid, sh, st, G, in, b, R, out, act);
+    else launch_prod_v<T, 32>(pl, RC, grid, sh, st, G, in, b, R, out, act);
 }
 
 // Rows per group (UR) depend only on the slab width, in the fused and the
@@ -917,7 +1218,8 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     const cpx<T> *G = PRE ? OpPtrs<T>::S(pl) : OpPtrs<T>::G(pl);
     const bool rim = !PRE && Nr > 0;         // dense rim pass
     const size_t sh_fused = std::max(spec_lds(pl, es), rim ? rim_lds(pl, 1, es) : (size_t)0);
-    const bool fused = R == 1 && sh_fused <= kLdsLimit;
+    // one column: the fused path (for a half spectrum, rows of at most 64)
+    const bool fused = R == 1 && sh_fused <= kLdsLimit && !(pl->half && b > 64);
 
     // many columns: the product and the rim run on the matrix cores
     const bool mfma = !fused && R >= kMfmaMinR;
@@ -964,7 +1266,7 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         else if (vpl <= 16) launch_spec_rim_e<T, In, Out, 16>(pl, G, rim, x, y, gA, gB, sh_fused, st);
         else launch_spec_rim_e<T, In, Out, 32>(pl, G, rim, x, y, gA, gB, sh_fused, st);
     } else if (mfma) {
-        prod_mfma<T>(G, gB, b, R, (long)Px * Py, gA, act, st);
+        prod_mfma<T>(G, gB, b, R, Px, Py, pl->kxh, gA, act, st);
     } else {
         // columns per workgroup: up to 16 (the spectrum block is re-read from
         // cache by each column block of a frequency)
@@ -972,7 +1274,7 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         const size_t sh = (size_t)RC * b * es;
         dim3 grid(Px * Py, (R + RC - 1) / RC);
         const int vpl = (b + 7) / 8;
-        launch_prod<T>(vpl, RC, grid, sh, st, G, gB, b, R, gA, act);
+        launch_prod<T>(pl, vpl, RC, grid, sh, st, G, gB, b, R, gA, act);
     }
     mark(4);
     if (!fused && lg2 < 0) {
@@ -1001,244 +1303,21 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         const size_t sh = ((size_t)Px * (1 << lg) + Px) * es;
         const int nchunk = (C + (1 << lg) - 1) >> lg;
         const int ninv = nchunk * Ny;
+        // the half-spectrum fused path leaves the mirror columns as parts
+        MirrorParts<T> mp{nullptr, Px, 0, 0, 0};
+        if (fused && pl->half) {
+            mp.yp = reinterpret_cast<const cpx<T> *>(pl->ypart);
+            mp.kxh = pl->kxh;
+            mp.nmir = Px - pl->kxh;
+            mp.nch = (b + 7) / 8;
+            mp.hstride = (long)Ny * mp.nmir * b;
+        }
         hipLaunchKernelGGL((k_inv_x_fin<T, In, Out>), dim3(ninv + nfin), blk, sh, st, gB, R, Nx, b, pl->fx, lg,
                            nchunk, y, accumulate, acc, ninv, reinterpret_cast<const cpx<T> *>(pl->rim_part),
-                           OpPtrs<T>::C(pl), D, x, pl->N, Nr, pl->rim_nslab);
+                           OpPtrs<T>::C(pl), D, x, pl->N, Nr, pl->rim_nslab, mp);
     }
     mark(6);
     mark(7);
-    return hipGetLastError();
-}
-
-hipError_t matvec_fp64(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st) {
-    return matvec_launch<double, c128, c128>(pl, x, y, R, st);
-}
-hipError_t matvec_fp32(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStream_t st) {
-    return matvec_launch<float, c64, c64>(pl, x, y, R, st);
-}
-hipError_t matvec_fp32_wide(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st) {
-    return matvec_launch<float, c128, c128>(pl, x, y, R, st);
-}
-hipError_t matvec_fp64_timed(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st, hipEvent_t *ev) {
-    return matvec_launch<double, c128, c128>(pl, x, y, R, st, ev);
-}
-hipError_t matvec_fp32_timed(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStream_t st, hipEvent_t *ev) {
-    return matvec_launch<float, c64, c64>(pl, x, y, R, st, ev);
-}
-hipError_t precond_fp64(tp_plan pl, Cols<const c128> x, Cols<c128> y, Cols<const c128> base, int R, hipStream_t st) {
-    return matvec_launch<double, c128, c128, true>(pl, x, y, R, st, nullptr, base);
-}
-hipError_t precond_fp32(tp_plan pl, Cols<const c64> x, Cols<c64> y, Cols<const c64> base, int R, hipStream_t st) {
-    return matvec_launch<float, c64, c64, true>(pl, x, y, R, st, nullptr, base);
-}
-hipError_t precond_fp32_wide(tp_plan pl, Cols<const c128> x, Cols<c128> y, Cols<const c128> base, int R,
-                             hipStream_t st) {
-    return matvec_launch<float, c128, c128, true>(pl, x, y, R, st, nullptr, base);
-}
-
-// ------------------------------------------------------ plan-time spectrum
-// x pass over the generator rows: Z_{m,n} for m in (-Nx, Nx) sits at grid
-// column m mod Px; the other columns are zero.
-__global__ void __launch_bounds__(256) k_gen_fwd_x(const c128 *__restrict__ gen, int Nx, long bb, FFTDesc fx,
-                                                   int lgCC, c128 *__restrict__ out) {
-    extern __shared__ char smem_raw[];
-    c128 *twl = reinterpret_cast<c128 *>(smem_raw);
-    c128 *buf = twl + fx.P;
-    const int CC = 1 << lgCC, P = fx.P, W = 2 * Nx - 1;
-    const long c0 = (long)blockIdx.x * CC;
-    const int ni = blockIdx.y;
-    load_twiddles<double>(twl, fx);
-    zero_lds<double>(buf, P * CC);
-    __syncthreads();
-    for (int i = threadIdx.x; i < W * CC; i += kBlock) {
-        const int mi = i >> lgCC, cl = i & (CC - 1);
-        const long c = c0 + cl;
-        if (c < bb) {
-            int g = mi - (Nx - 1);
-            if (g < 0) g += P;
-            buf[(fx.perm[g] << lgCC) + cl] = gen[((long)ni * W + mi) * bb + c];
-        }
-    }
-    __syncthreads();
-    lds_fft<double, false>(buf, lgCC, fx, twl);
-    for (int i = threadIdx.x; i < P * CC; i += kBlock) {
-        const int k = i >> lgCC, cl = i & (CC - 1);
-        const long c = c0 + cl;
-        if (c < bb) out[((long)ni * P + k) * bb + c] = buf[i];
-    }
-}
-
-// y pass: rows n in (-Ny, Ny) at grid row n mod Py; result scaled by 1/(Px Py)
-// and stored frequency-major, k = kx * Py + ky, as complex128 and/or complex64.
-__global__ void __launch_bounds__(256) k_gen_fwd_y(const c128 *__restrict__ in, int Ny, int Px, long bb,
-                                                   FFTDesc fy, int lgCC, double scl, c128 *__restrict__ G64,
-                                                   c64 *__restrict__ G32) {
-    extern __shared__ char smem_raw[];
-    c128 *twl = reinterpret_cast<c128 *>(smem_raw);
-    c128 *buf = twl + fy.P;
-    const int CC = 1 << lgCC, P = fy.P, H = 2 * Ny - 1;
-    const long c0 = (long)blockIdx.x * CC;
-    const int kx = blockIdx.y;
-    load_twiddles<double>(twl, fy);
-    zero_lds<double>(buf, P * CC);
-    __syncthreads();
-    for (int i = threadIdx.x; i < H * CC; i += kBlock) {
-        const int ni = i >> lgCC, cl = i & (CC - 1);
-        const long c = c0 + cl;
-        if (c < bb) {
-            int g = ni - (Ny - 1);
-            if (g < 0) g += P;
-            buf[(fy.perm[g] << lgCC) + cl] = in[((long)ni * Px + kx) * bb + c];
-        }
-    }
-    __syncthreads();
-    lds_fft<double, false>(buf, lgCC, fy, twl);
-    for (int i = threadIdx.x; i < P * CC; i += kBlock) {
-        const int ky = i >> lgCC, cl = i & (CC - 1);
-        const long c = c0 + cl;
-        if (c < bb) {
-            const c128 v = scale(buf[i], scl);
-            const long o = ((long)kx * P + ky) * bb + c;
-            if (G64) G64[o] = v;
-            if (G32) G32[o] = cvt<float>(v);
-        }
-    }
-}
-
-__global__ void k_cast_c64(const c128 *__restrict__ in, c64 *__restrict__ out, long n) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        out[i] = cvt<float>(in[i]);
-}
-
-hipError_t spectrum_build(tp_plan pl, const c128 *gen_dev, c128 *tmp, hipStream_t st) {
-    const int Nx = pl->Nx, Ny = pl->Ny, Px = pl->Px, Py = pl->Py;
-    const long bb = (long)pl->b * pl->b;
-    const size_t es = sizeof(c128);
-    {
-        const int lg = fft_lgcc(Px, (int)std::min<long>(bb, 64), es);
-        const size_t sh = ((size_t)Px * (1 << lg) + Px) * es;
-        dim3 grid((unsigned)((bb + (1 << lg) - 1) >> lg), 2 * Ny - 1);
-        hipLaunchKernelGGL(k_gen_fwd_x, grid, dim3(256), sh, st, gen_dev, Nx, bb, pl->fx, lg, tmp);
-    }
-    {
-        const int lg = fft_lgcc(Py, (int)std::min<long>(bb, 64), es);
-        const size_t sh = ((size_t)Py * (1 << lg) + Py) * es;
-        dim3 grid((unsigned)((bb + (1 << lg) - 1) >> lg), Px);
-        hipLaunchKernelGGL(k_gen_fwd_y, grid, dim3(256), sh, st, tmp, Ny, Px, bb, pl->fy, lg,
-                           1.0 / ((double)Px * (double)Py), pl->G64, pl->G32);
-    }
-    return hipGetLastError();
-}
-
-// ------------------------------------------------ preconditioner (plan time)
-// In-place Gauss-Jordan inversion with partial pivoting of one b x b spectrum
-// block per workgroup (row-major at S + k b^2), then scaling by scl.  Step k:
-// the largest-modulus pivot in column k (ties to the lower row) is swapped
-// into row k, row k is divided by it (its column-k entry becoming 1 / pivot),
-// and every other row i loses f_i times row k, with f_i its column-k entry
-// (which becomes -f_i / pivot).  The row interchanges are undone on the
-// columns of the result, in reverse order.
-__global__ void __launch_bounds__(256) k_block_inv(c128 *__restrict__ S, int b, double scl, int *flag) {
-    extern __shared__ char smem_raw[];
-    c128 *f = reinterpret_cast<c128 *>(smem_raw);   // [b]
-    int *perm = reinterpret_cast<int *>(f + b);      // [b]
-    __shared__ int piv;
-    c128 *A = S + (long)blockIdx.x * b * b;
-    const int tid = threadIdx.x;
-    for (int k = 0; k < b; ++k) {
-        if (tid < 64) {
-            double best = -1.0;
-            int bi = k;
-            for (int i = k + tid; i < b; i += 64) {
-                const c128 a = A[(long)i * b + k];
-                const double m = a.x * a.x + a.y * a.y;
-                if (m > best) {
-                    best = m;
-                    bi = i;
-                }
-            }
-            for (int o = 32; o >= 1; o >>= 1) {
-                const double ob = __shfl_xor(best, o, 64);
-                const int oi = __shfl_xor(bi, o, 64);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
-            }
-            if (tid == 0) {
-                piv = bi;
-                perm[k] = bi;
-                if (!(best > 0.0) || !(best < INFINITY)) *flag = 1;
-            }
-        }
-        __syncthreads();
-        const int r = piv;
-        if (r != k) {
-            for (int j = tid; j < b; j += kBlock) {
-                const c128 t = A[(long)k * b + j];
-                A[(long)k * b + j] = A[(long)r * b + j];
-                A[(long)r * b + j] = t;
-            }
-            __syncthreads();
-        }
-        const c128 pv = A[(long)k * b + k];
-        const double pd = 1.0 / (pv.x * pv.x + pv.y * pv.y);
-        const c128 inv{pv.x * pd, -pv.y * pd};
-        __syncthreads();
-        for (int j = tid; j < b; j += kBlock) A[(long)k * b + j] = (j == k ? c128{1, 0} : A[(long)k * b + j]) * inv;
-        for (int i = tid; i < b; i += kBlock)
-            if (i != k) f[i] = A[(long)i * b + k];
-        __syncthreads();
-        for (long idx = tid; idx < (long)b * b; idx += kBlock) {
-            const int i = (int)(idx / b), j = (int)(idx - (long)i * b);
-            if (i == k) continue;
-            A[idx] = (j == k ? c128{0, 0} : A[idx]) - f[i] * A[(long)k * b + j];
-        }
-        __syncthreads();
-    }
-    for (int k = b - 1; k >= 0; --k) {
-        const int r = perm[k];
-        if (r != k) {
-            for (int i = tid; i < b; i += kBlock) {
-                const c128 t = A[(long)i * b + k];
-                A[(long)i * b + k] = A[(long)i * b + r];
-                A[(long)i * b + r] = t;
-            }
-        }
-        __syncthreads();
-    }
-    for (long idx = tid; idx < (long)b * b; idx += kBlock) A[idx] = scale(A[idx], scl);
-}
-
-// D[t] = 1 / C[t][t]
-__global__ void k_diag_inv(const c128 *__restrict__ Cm, int Nr, c128 *__restrict__ D, int *flag) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= Nr) return;
-    const c128 c = Cm[(long)t * Nr + t];
-    const double dd = c.x * c.x + c.y * c.y;
-    if (!(dd > 0.0) || !(dd < INFINITY)) *flag = 1;
-    D[t] = c128{c.x / dd, -c.y / dd};
-}
-
-hipError_t precond_build(tp_plan pl, c128 *S, int *flag, hipStream_t st) {
-    const long P = (long)pl->Px * pl->Py;
-    const double scl = 1.0 / ((double)P * (double)P);
-    const size_t sh = (size_t)pl->b * (sizeof(c128) + sizeof(int));
-    hipLaunchKernelGGL(k_block_inv, dim3((unsigned)P), dim3(256), sh, st, S, pl->b, scl, flag);
-    hipError_t e = hipGetLastError();
-    if (e) return e;
-    if (pl->Nr > 0 && pl->D64) {
-        hipLaunchKernelGGL(k_diag_inv, dim3((pl->Nr + 255) / 256), dim3(256), 0, st, pl->C64, pl->Nr, pl->D64, flag);
-        e = hipGetLastError();
-    }
-    return e;
-}
-
-hipError_t cast_to_c64(const c128 *in, c64 *out, long n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    long nb = (n + 255) / 256;
-    if (nb > 65536) nb = 65536;
-    hipLaunchKernelGGL(k_cast_c64, dim3((unsigned)nb), dim3(256), 0, st, in, out, n);
     return hipGetLastError();
 }
 

@@ -82,8 +82,8 @@ struct alignas(4 * sizeof(T)) cpair {
 
 template <typename T, int NT, int KC, bool EVEN>
 __global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ in,
-                                                    int b, int R, long P, cpx<T> *__restrict__ out,
-                                                    const void *const *act) {
+                                                    int b, int R, int Px, int Py, int kxh,
+                                                    cpx<T> *__restrict__ out, const void *const *act) {
     extern __shared__ char smem_raw[];
     cpx<T> *xs = reinterpret_cast<cpx<T> *>(smem_raw);
     const int KP = (b + 7) >> 3, W = 8 * KP, bs = W + 2;
@@ -93,6 +93,7 @@ __global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G
     // (frequency, column block) items, and the column blocks of a frequency
     // run back to back on the XCD whose L2 holds that frequency's G block
     const int ncb = (R + 16 * NT - 1) / (16 * NT);
+    const long P = (long)Px * Py;
     const long nitem = P * ncb, per = (long)gridDim.x >> 3;
     const long item = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (item >= nitem) return;
@@ -114,9 +115,13 @@ __global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G
         nthr);
     const int p = 16 * w + i;
     const bool prow = p < b;
+    // a mirrored frequency (half spectrum) reads its stored block transposed
+    bool tr;
+    const cpx<T> *Gk = G + spec_src(k, Px, Py, kxh, tr) * (long)b * b;
     // loads use clamped addresses, so they issue without branches; values
     // outside the row are masked to zero only when they are used
-    const cpx<T> *arow = G + k * (long)b * b + (long)min(p, b - 1) * b;
+    const cpx<T> *arow = Gk + (long)min(p, b - 1) * b;
+    const cpx<T> *acol = Gk + min(p, b - 1);
     auto load = [&](cpair<T>(&a)[KC], int t0) {
 #pragma unroll
         for (int u = 0; u < KC; ++u) {
@@ -127,6 +132,16 @@ __global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G
                 a[u].a = arow[min(q, b - 1)];
                 a[u].b = arow[min(q + 1, b - 1)];
             }
+        }
+    };
+    // transposed: A[p][q] = stored[q][p], a column walk (16 lanes of a group
+    // read 16 consecutive values of one stored row)
+    auto load_tr = [&](cpair<T>(&a)[KC], int t0) {
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            const int q = 8 * (t0 + u) + 2 * g;
+            a[u].a = acol[(long)min(q, b - 1) * b];
+            a[u].b = acol[(long)min(q + 1, b - 1) * b];
         }
     };
     CAcc<T> acc[NT];
@@ -149,17 +164,24 @@ __global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G
             }
         }
     };
-    cpair<T> a0[KC], a1[KC];
-    load(a0, 0);
-    __syncthreads();
     // loads unconditional (clamped addresses): a load under a branch would
-    // make the wait before the other buffer's use cover it too
-    for (int t0 = 0; t0 < KP; t0 += 2 * KC) {
-        load(a1, t0 + KC);
-        compute(a0, t0);
-        load(a0, t0 + 2 * KC);
-        if (t0 + KC < KP) compute(a1, t0 + KC);
-    }
+    // make the wait before the other buffer's use cover it too.  The two
+    // orientations are two copies of the loop (tr is uniform).
+    auto run = [&](auto ld) {
+        cpair<T> a0[KC], a1[KC];
+        ld(a0, 0);
+        __syncthreads();
+        for (int t0 = 0; t0 < KP; t0 += 2 * KC) {
+            ld(a1, t0 + KC);
+            compute(a0, t0);
+            ld(a0, t0 + 2 * KC);
+            if (t0 + KC < KP) compute(a1, t0 + KC);
+        }
+    };
+    if (tr)
+        run(load_tr);
+    else
+        run(load);
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
         const int j = n * 16 + i;
@@ -178,24 +200,26 @@ template <typename T>
 static constexpr int prod_nt() { return sizeof(T) == 4 ? 2 : 1; }
 
 template <typename T>
-hipError_t prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, long P, cpx<T> *out, const void *const *act,
-                     hipStream_t st) {
+hipError_t prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, int Px, int Py, int kxh, cpx<T> *out,
+                     const void *const *act, hipStream_t st) {
     constexpr int NT = prod_nt<T>();
     const int KP = (b + 7) >> 3;
     const size_t sh = (size_t)16 * NT * (8 * KP + 2) * sizeof(cpx<T>);
     const int waves = (b + 15) / 16;
-    const long nitem = P * ((R + 16 * NT - 1) / (16 * NT));
+    const long nitem = (long)Px * Py * ((R + 16 * NT - 1) / (16 * NT));
     dim3 grid((unsigned)(((nitem + 7) / 8) * 8));
     if (b % 2 == 0)
-        hipLaunchKernelGGL((k_prod_mfma<T, NT, 4, true>), grid, dim3(64 * waves), sh, st, G, in, b, R, P, out, act);
+        hipLaunchKernelGGL((k_prod_mfma<T, NT, 4, true>), grid, dim3(64 * waves), sh, st, G, in, b, R, Px, Py, kxh,
+                           out, act);
     else
-        hipLaunchKernelGGL((k_prod_mfma<T, NT, 4, false>), grid, dim3(64 * waves), sh, st, G, in, b, R, P, out, act);
+        hipLaunchKernelGGL((k_prod_mfma<T, NT, 4, false>), grid, dim3(64 * waves), sh, st, G, in, b, R, Px, Py, kxh,
+                           out, act);
     return hipGetLastError();
 }
-template hipError_t prod_mfma<float>(const c64 *, const c64 *, int, int, long, c64 *, const void *const *,
+template hipError_t prod_mfma<float>(const c64 *, const c64 *, int, int, int, int, int, c64 *, const void *const *,
                                      hipStream_t);
-template hipError_t prod_mfma<double>(const c128 *, const c128 *, int, int, long, c128 *, const void *const *,
-                                      hipStream_t);
+template hipError_t prod_mfma<double>(const c128 *, const c128 *, int, int, int, int, int, c128 *,
+                                      const void *const *, hipStream_t);
 
 // ---------------------------------------------------------------- rim
 // One slab of 64 element columns e0 .. e0 + 63 and a block of 16 NT

@@ -27,7 +27,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Plan, plan_bytes, precond_bytes
+from . import Plan, gen_symmetric, plan_bytes, precond_bytes
 from . import _lib
 from ._lib import PREC, check
 
@@ -84,10 +84,11 @@ class Server:
 
     # ----------------------------------------------------------- plans
     def _need(self, key):
-        Nx, Ny, b, Nr = self.geometry(key)[:4]
-        need = plan_bytes(Nx, Ny, b, Nr, "mixed", self.slots, self.restart)
+        Nx, Ny, b, Nr, gen = self.geometry(key)[:5]
+        sym = gen_symmetric(Nx, Ny, b, gen)
+        need = plan_bytes(Nx, Ny, b, Nr, "mixed", self.slots, self.restart, symmetric=sym)
         if self.precond:
-            need += precond_bytes(Nx, Ny, b, Nr, "mixed")
+            need += precond_bytes(Nx, Ny, b, Nr, "mixed", symmetric=sym)
         return need
 
     def _get_plan(self, key, now):

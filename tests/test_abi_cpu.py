@@ -1,6 +1,8 @@
 """Host-only checks of the C ABI: the library loads, exports every declared
 symbol, and rejects bad arguments before touching a device."""
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -50,6 +52,40 @@ def test_plan_bytes_matches_layout_accounting(L):
     small = plan_bytes(8, 8, 16, 0, "mixed", 4, 40)
     assert plan_bytes(8, 8, 16, 0, "mixed", 64, 40) > small
     assert plan_bytes(8, 8, 16, 0, "mixed", 4, 200) > small
+
+
+def test_plan_bytes_half_spectrum(L):
+    """Symmetric generators keep the spectrum columns kx <= Px/2: at Px = Py = 63
+    that is 32 of 63 columns, 31 * 63 blocks fewer per precision (the
+    single-column path's mirror parts, 8 * 32 * 31 * 64 values, come back as
+    workspace)."""
+    from paper_2506_04710_amd import plan_bytes
+    for prec, s in (("fp64", 16), ("mixed", 24)):
+        full = plan_bytes(32, 32, 64, 256, prec, 1, 40)
+        half = plan_bytes(32, 32, 64, 256, prec, 1, 40, symmetric=True)
+        saved = 31 * 63 * 64 * 64 * s
+        assert saved - 8 * 32 * 31 * 64 * 16 - 4096 <= full - half <= saved, prec
+    n = ctypes.c_size_t(0)
+    assert L.toeplitz_plan_bytes(4, 4, 16, 0, 4, 0, 1, 40, ctypes.byref(n)) == 1   # unknown sym bit
+
+
+def test_gen_symmetric_host_check(L):
+    """The library's generator symmetry test: Z_{-m,-n} = Z_{m,n}^T bit for bit."""
+    from paper_2506_04710_amd import gen_symmetric
+    from synth import arrays as sa
+    prob = sa.make_problem(3, 2, 4, 0, 7)
+    assert gen_symmetric(3, 2, 4, prob.gen)
+    g = prob.gen.copy()
+    g[0, 1, 1, 2] += 1.0                 # one entry of Z_{-2,-1} changed
+    assert not gen_symmetric(3, 2, 4, g)
+    # mirrored blocks equal but not transposed: not the symmetry
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((3, 5, 4, 4)) + 1j * rng.standard_normal((3, 5, 4, 4))
+    assert not gen_symmetric(3, 2, 4, a + a[::-1, ::-1])
+    assert gen_symmetric(3, 2, 4, a + a[::-1, ::-1].transpose(0, 1, 3, 2))
+    out = ctypes.c_int(5)
+    assert L.toeplitz_gen_symmetric(3, 2, 4, None, ctypes.byref(out)) == 1 and out.value == 0
+    assert L.toeplitz_gen_symmetric(0, 2, 4, prob.gen.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)) == 1
 
 
 @pytest.mark.parametrize("args", [

@@ -60,6 +60,53 @@ def test_matvec_parity(torch_cuda, case, which):
     assert err <= (TOL64 if which == "fp64" else TOL32), err
 
 
+def _general_problem(Nx, Ny, b, Nr, seed):
+    """A synthetic array with its generator blocks perturbed so that
+    Z_{-m,-n} != Z_{m,n}^T: the plan keeps every spectrum column."""
+    prob = sa.make_problem(Nx, Ny, b, Nr, seed)
+    rng = np.random.default_rng(seed + 1)
+    prob.gen = prob.gen + 0.05 * (rng.standard_normal(prob.gen.shape) + 1j * rng.standard_normal(prob.gen.shape))
+    return prob
+
+
+GENERAL_CASES = [(4, 4, 16, 24, 1), (7, 2, 3, 0, 1), (9, 8, 8, 0, 1), (5, 3, 33, 10, 3), (3, 4, 70, 5, 17),
+                 (6, 4, 7, 0, 18)]
+
+
+@pytest.mark.parametrize("case", GENERAL_CASES, ids=[f"{c[0]}x{c[1]}b{c[2]}r{c[3]}R{c[4]}" for c in GENERAL_CASES])
+@pytest.mark.parametrize("which", ["fp64", "fp32"])
+def test_matvec_parity_general_generators(torch_cuda, case, which):
+    """Generators without the symmetry: whole spectrum, every kernel path."""
+    Nx, Ny, b, Nr, R = case
+    banner(f"matvec general generators {which} {case}")
+    prob = _general_problem(Nx, Ny, b, Nr, 5000 + Nx * 100 + Ny * 10 + b)
+    X = sa.rhs_random(prob, R)
+    if which == "fp32":
+        X = X.astype(np.complex64).astype(np.complex128)
+    Y, plan = _matvec_case(torch_cuda, prob, X, which=which)
+    assert plan.info()["half_spectrum"] == 0
+    assert rel_err(Y, oracle.matvec(prob, X)) <= (TOL64 if which == "fp64" else TOL32)
+
+
+def test_half_spectrum_storage(torch_cuda):
+    """Symmetric generators: the plan stores the columns kx <= Px/2 only."""
+    banner("half spectrum storage")
+    import paper_2506_04710_amd as tp
+    for shape in [(5, 4, 24, 12), (7, 2, 3, 0), (9, 9, 8, 0)]:
+        prob = sa.make_problem(*shape, 46)
+        plan = tp.Plan.from_problem(prob, prec="fp64", max_rhs=1, restart=4)
+        info = plan.info()
+        assert info["half_spectrum"] == 1
+        assert info["spectrum_bytes"] == (info["Px"] // 2 + 1) * info["Py"] * prob.b ** 2 * 16
+        gprob = _general_problem(*shape, 46)
+        gplan = tp.Plan.from_problem(gprob, prec="fp64", max_rhs=1, restart=4)
+        ginfo = gplan.info()
+        assert ginfo["half_spectrum"] == 0
+        assert ginfo["spectrum_bytes"] == ginfo["Px"] * ginfo["Py"] * prob.b ** 2 * 16
+        plan.close()
+        gplan.close()
+
+
 @pytest.mark.parametrize("which", ["fp64", "fp32"])
 def test_matvec_nonreciprocal_rim(torch_cuda, which):
     banner(f"matvec non-reciprocal {which}")

@@ -78,7 +78,7 @@ def test_serving_hbm_budget_evicts_idle_plans(server_cls):
     banner("serving HBM-bounded admission")
     from paper_2506_04710_amd import plan_bytes
     keys = [(4, 4, 8), (5, 4, 8)]
-    need = max(plan_bytes(k[0], k[1], k[2], 0, "mixed", 4, 20) for k in keys)
+    need = max(plan_bytes(k[0], k[1], k[2], 0, "mixed", 4, 20, symmetric=True) for k in keys)
     reqs = make_requests(6, 7, keys)
     srv = server_cls(geometry, slots=4, mode="mixed", tol=1e-8, restart=20, hbm_budget=int(need * 1.5))
     stats = srv.run(reqs, realtime=False)
