@@ -67,10 +67,14 @@ void fft_perm(int P, int nst, const int *radix, int *perm) {
     }
 }
 
+#ifndef TP_RIM_SLAB_MAX
+#define TP_RIM_SLAB_MAX 256
+#endif
 int rim_slab_width(long N) {
-    // widest slab (64, 128 or 256 columns) that still gives >= 512 workgroups
-    if (N >= 512L * 256) return 256;
-    if (N >= 512L * 128) return 128;
+    // widest slab (64, 128 or 256 columns, at most TP_RIM_SLAB_MAX) that
+    // still gives >= 512 workgroups
+    if (N >= 512L * 256 && TP_RIM_SLAB_MAX >= 256) return 256;
+    if (N >= 512L * 128 && TP_RIM_SLAB_MAX >= 128) return 128;
     return 64;
 }
 

@@ -637,12 +637,25 @@ __device__ __forceinline__ void spec_block_half(const cpx<T> *__restrict__ G, co
         for (int up = 0; up < UP; ++up) reduce_pair(g, up, j0 + up * nw);
     };
     // two register buffers in turn, loads unconditional (see spec_block)
+    // Buffer tb of this wave holds its pairs j = w + tb UP nw + up nw.  The
+    // steady loop issues no load past the wave's last buffer; the one or two
+    // buffers left are reduced after it (a uniform branch with nothing
+    // pending behind it).
     const int bstep = UP * nw;
-    for (int j0 = w; j0 < npair; j0 += 2 * bstep) {
-        load(gn, j0 + bstep);
-        reduce(gc, j0);
-        load(gc, j0 + 2 * bstep);
-        if (j0 + bstep < npair) reduce(gn, j0 + bstep);
+    const int nbuf = npair > w ? (npair - w + bstep - 1) / bstep : 0;
+    int tb = 0;
+    for (; tb + 2 < nbuf; tb += 2) {
+        load(gn, w + (tb + 1) * bstep);
+        reduce(gc, w + tb * bstep);
+        load(gc, w + (tb + 2) * bstep);
+        reduce(gn, w + (tb + 1) * bstep);
+    }
+    if (nbuf - tb == 2) {
+        load(gn, w + (tb + 1) * bstep);
+        reduce(gc, w + tb * bstep);
+        reduce(gn, w + (tb + 1) * bstep);
+    } else if (nbuf - tb == 1) {
+        reduce(gc, w + tb * bstep);
     }
     __syncthreads();
     lds_fft2<T, true, false, NT>(ys, 3, mir ? xs : nullptr, lgCC, fy, twl);
@@ -731,12 +744,13 @@ __device__ __forceinline__ void rim_block1(const cpx<T> *__restrict__ B, const c
             if ((lane & 15) == 0 && rok) part[(long)slab * Nr + row] = sr;
         }
     };
-    // groups of 4 rows; two register buffers in turn
+    // groups of 4 rows; two register buffers in turn, loads unconditional
+    // (see the spectrum stream)
     const int r0 = w * 4 + ro;
     load(gc, ec, r0);
     for (int g0 = w * 4; g0 < Nr; g0 += 2 * bstep) {
         const int row = r0 + (g0 - w * 4);
-        load(gn, en, row + bstep);          // unconditional: see the spectrum stream
+        load(gn, en, row + bstep);
         rows(gc, ec, row);
         load(gc, ec, row + 2 * bstep);
         if (g0 + bstep < Nr) rows(gn, en, row + bstep);
