@@ -775,6 +775,32 @@ __device__ __forceinline__ void rim_block1(const cpx<T> *__restrict__ B, const c
     }
 }
 
+// Which task a workgroup of the fused launch takes.  Workgroups are dealt to
+// the 8 XCDs in turn (XCD x runs blocks x, x + 8, ...), and each XCD has its
+// own share of the memory bandwidth, so every XCD gets the same mix: XCD x
+// takes s_x of the nspec spectrum tasks, spread evenly over its sequence of
+// blocks, and rim tasks in between.  Then the rim streams of an XCD keep its
+// bandwidth busy while its spectrum workgroups transform.  The spectrum tasks
+// of an XCD are consecutive (the row chunks of one column share its input).
+__device__ __forceinline__ void block_task(int i, int nspec, int nrim, int &spec_id, int &rim_id) {
+    const int ntot = nspec + nrim, x = i & 7, q = i >> 3;
+    const int nq = (ntot - x + 7) >> 3;                       // blocks on XCD x
+    int c0 = 0;                                               // blocks on the XCDs before x
+    for (int xx = 0; xx < x; ++xx) c0 += (ntot - xx + 7) >> 3;
+    // spectrum tasks in proportion to the blocks: s0 before XCD x, sx on it
+    auto share = [&](int c) { return (int)((long)nspec * c / ntot); };
+    const int s0 = share(c0), sx = share(c0 + nq) - s0;
+    auto specs = [&](int qq) { return (int)((long)qq * sx / nq); };   // among its first qq blocks
+    const int before = specs(q), upto = specs(q + 1);
+    if (upto > before) {
+        spec_id = s0 + before;
+        rim_id = -1;
+    } else {
+        spec_id = -1;
+        rim_id = (c0 - s0) + (q - before);
+    }
+}
+
 // Spectrum workgroups and rim workgroups share one launch so that both HBM
 // streams (the spectrum and the dense rim) run together; the two kinds are
 // interleaved in block order.
@@ -786,17 +812,23 @@ __global__ void __launch_bounds__(NT) k_spec_rim(const cpx<T> *__restrict__ G, c
                                                   long N, int Nr, cpx<T> *__restrict__ part, int nrim,
                                                   cpx<T> *__restrict__ Yp, int kxh) {
     extern __shared__ char smem_raw[];
-    const int i = blockIdx.x, both = 2 * min(nspec, nrim);
     int spec_id, rim_id;
-    if (i < both) {
-        spec_id = (i & 1) ? -1 : (i >> 1);
-        rim_id = (i & 1) ? (i >> 1) : -1;
-    } else if (nspec > nrim) {
-        spec_id = i - both + nrim;
-        rim_id = -1;
+    if constexpr (sizeof(T) == 4) {
+        block_task(blockIdx.x, nspec, nrim, spec_id, rim_id);
     } else {
-        spec_id = -1;
-        rim_id = i - both + nspec;
+        // FP64 (two waves per SIMD, not every workgroup resident at once):
+        // spectrum and rim tasks alternate in block order
+        const int i = blockIdx.x, both = 2 * min(nspec, nrim);
+        if (i < both) {
+            spec_id = (i & 1) ? -1 : (i >> 1);
+            rim_id = (i & 1) ? (i >> 1) : -1;
+        } else if (nspec > nrim) {
+            spec_id = i - both + nrim;
+            rim_id = -1;
+        } else {
+            spec_id = -1;
+            rim_id = i - both + nspec;
+        }
     }
     if (spec_id >= 0) {
         if (!cols_live((const void *const *)x.tab, 0, 0)) return;
