@@ -31,8 +31,8 @@ METRIC = "solves/s at rel-residual 1e-8 (32x32,b=64) vs FP64 plain; matvec GB/s;
 # HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the same counters on a plain copy of known size),
 # valid only for the kernel source it was measured on.
-TRAFFIC = {"source_sha256": "9297ba73d7ddda8a32698ee378ed5708469e3869ad01d15e1efc5a60e4c7ae57",
-           "bytes": 274114757, "fetch_factor": 0.50001, "write_factor": 1.0}
+TRAFFIC = {"source_sha256": "6f51b54bc9255752cc4d03df4008653375b84381ab141b4fbfebc5395a2f71fb",
+           "bytes": 211084144, "fetch_factor": 0.500009, "write_factor": 1.0}
 
 
 def parse():
