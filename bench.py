@@ -32,7 +32,7 @@ METRIC = "solves/s at rel-residual 1e-8 (32x32,b=64) vs FP64 plain; matvec GB/s;
 # WRITE_SIZE (scaled by the same counters on a plain copy of known size),
 # valid only for the kernel source it was measured on.
 TRAFFIC = {"source_sha256": "6f51b54bc9255752cc4d03df4008653375b84381ab141b4fbfebc5395a2f71fb",
-           "bytes": 211084144, "fetch_factor": 0.500009, "write_factor": 1.0}
+           "bytes": 211255110, "fetch_factor": 0.500009, "write_factor": 1.0}
 
 
 def parse():
@@ -270,29 +270,52 @@ def main():
     totm, _, (_, infm) = timed_solves(plan, v, kb, 1, mode="mixed")
     totp, _, (_, infp) = timed_solves(plan, v, kb, 1, mode="fp64", precond=True)
 
-    # operator bandwidth (whole matvec) and the dominant kernel's duration
+    # operator bandwidth (whole matvec) and the dominant kernel's duration.
+    # The half-spectrum operator (203 MB in FP32) fits the 256 MB MALL, so
+    # back-to-back repeats could be served partly from it: every timed
+    # application follows a 512 MB read that evicts the operator with clean
+    # lines (a write would leave dirty lines whose write-back lands in the
+    # timed region); the back-to-back figure is reported beside it as "warm".
+    flush = torch.ones(128 << 20, dtype=torch.float32, device=dev)
     gbs = {}
     stage = {}
+    stage_warm = {}
     for which, dt, s in (("fp32", torch.complex64, 8), ("fp64", torch.complex128, 16)):
         xv = v.to(dt)
         for _ in range(3):
             plan.matvec(xv)
         torch.cuda.synchronize()
-        reps = 50
+        reps = 30
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in ev:
+            flush.sum()
+            e0.record()
+            plan.matvec(xv)
+            e1.record()
+        torch.cuda.synchronize()
+        ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
         for _ in range(reps):
             plan.matvec(xv)
         ev1.record()
         torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / reps
-        gbs[which] = {"us": round(ms * 1e3, 2),
-                      "GB_s": round(algorithmic_bytes(prob, 1, s, half) / (ms * 1e-3) / 1e9, 1)}
-        stage[which] = plan.matvec_profile(xv, which=which, reps=50)
+        ms_warm = ev0.elapsed_time(ev1) / reps
+        nb = algorithmic_bytes(prob, 1, s, half)
+        gbs[which] = {"us": round(ms * 1e3, 2), "GB_s": round(nb / (ms * 1e-3) / 1e9, 1),
+                      "us_warm": round(ms_warm * 1e3, 2), "GB_s_warm": round(nb / (ms_warm * 1e-3) / 1e9, 1)}
+        cold = []
+        for _ in range(reps):
+            flush.sum()
+            cold.append(plan.matvec_profile(xv, which=which, reps=1))
+        stage[which] = {k: sum(c[k] for c in cold) / reps for k in cold[0]}
+        stage_warm[which] = plan.matvec_profile(xv, which=which, reps=50)
+    del flush
     # dominant kernel of the timed solve: the fused spectrum+rim launch of the
     # FP32 operator (it carries both HBM streams); its duration from HIP events
-    # recorded on the stream it is launched on
+    # recorded on the stream it is launched on, after the MALL flush
     k_ms = stage["fp32"]["prod"]
+    k_ms_warm = stage_warm["fp32"]["prod"]
     k_bytes = spec_rim_bytes(prob, Px, 8, half)
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     sha = kernel_source_sha()
@@ -330,12 +353,16 @@ def main():
         "relres": {"mixed_precond": inf[0]["relres"], "fp64_plain": inf64[0]["relres"]},
         "matvec": gbs,
         "matvec_stages_us": {w: {k: round(v_ * 1e3, 2) for k, v_ in st.items()} for w, st in stage.items()},
+        "matvec_stages_us_warm": {w: {k: round(v_ * 1e3, 2) for k, v_ in st.items()} for w, st in stage_warm.items()},
         "plan_create_s": round(t_plan, 3),
         "precond_create_s": round(t_pc, 3),
-        "roofline": {"kernel": "k_spec_rim<float> (spectrum rows + rim pass, fused)", "bound": "hbm",
+        "roofline": {"kernel": "k_spec_rim<float> (stored spectrum half, mirror parts + rim pass, fused)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "bytes_per_launch": int(k_bytes), "launch_us": round(k_ms * 1e3, 2)},
+                     "bytes_per_launch": int(k_bytes), "launch_us": round(k_ms * 1e3, 2),
+                     "launch_us_warm": round(k_ms_warm * 1e3, 2),
+                     "note": "launch_us after a 512 MB read that evicts the operator from the 256 MB MALL; "
+                             "launch_us_warm back to back"},
     }
     if not args.quick:
         line["multi_rhs"] = multi_rhs(dev)
