@@ -12,7 +12,7 @@ void set_error(const std::string &msg);
 tp_status fail(tp_status s, const std::string &msg);
 tp_status hip_fail(hipError_t e, const char *what);
 
-// operator application (tp_matvec.hip)
+// operator application (tp_matvec.h; instances in tp_apply_f64/f32/wide.hip)
 hipError_t matvec_fp64(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st);
 hipError_t matvec_fp32(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStream_t st);
 // FP32 operator on complex128 vectors (inner solves of the mixed scheme)
