@@ -242,6 +242,36 @@ tp_status toeplitz_batch_poll(tp_plan p, int lag, int wait, int *phases, tp_solv
 tp_status toeplitz_batch_end(tp_plan p);
 
 /*
+ * Schur-complement elimination of the rim (the solve structure of Sec. II-D on
+ * eq. matrixForm): with Z = [[A, B_er], [B, C]],
+ *   setup  F = A^-1 B_er (Nr solves with the element operator A alone),
+ *          S = C - B F and its inverse;
+ *   solve  w = A^-1 v_A,  x_r = S^-1 (v_r - B w),  x_A = w - F x_r,
+ * so the iterated operator is the two-level block-Toeplitz A.  `a` is a plan of
+ * the same array (same Nx, Ny, b and generators) with Nr = 0: it supplies A and
+ * runs the Toeplitz solves (its preconditioner, if opts->precond).  The plan p
+ * must hold the FP64 operator.  The caller owns the buffer (dev_bytes >=
+ * toeplitz_schur_bytes, 256-byte aligned) and keeps it until p is destroyed.
+ * toeplitz_schur_create synchronises hip_stream; the element solves use opts
+ * (mode, tol, precond, ...) and may return TP_E_NOCONV.  Errors: TP_E_INVAL,
+ * TP_E_NOMEM, TP_E_UNSUPPORTED, TP_E_BREAKDOWN (S singular), TP_E_HIP.
+ */
+tp_status toeplitz_schur_bytes(tp_plan p, size_t *bytes);
+tp_status toeplitz_schur_create(tp_plan p, tp_plan a, void *dev_buf, size_t dev_bytes,
+                                const tp_solve_opts *opts, void *hip_stream);
+
+/*
+ * Solve Z x = v through the elimination built by toeplitz_schur_create.  v, x:
+ * device complex128, column-major Nt x nrhs (ld >= Nt), 1 <= nrhs <= max_rhs of
+ * both plans.  The element solves run to opts->tol / 2; info[r].relres is the
+ * true ||v - Z x|| / ||v|| of the full system from an FP64 application, and
+ * status TP_OK when it is <= opts->tol (else TP_E_NOCONV, x holds the result);
+ * iters and outer_iters are those of the element solve.  Synchronises hip_stream.
+ */
+tp_status toeplitz_schur_solve(tp_plan p, tp_plan a, const void *v, long ldv, void *x, long ldx, int nrhs,
+                               const tp_solve_opts *opts, tp_solve_info *info, void *hip_stream);
+
+/*
  * Copy one block of the stored spectrum to the host (the b x b matrix at
  * frequency (kx, ky), row-major; complex128 for TP_FP64, complex64 for TP_FP32).
  * It equals (1/(Px Py)) sum_{m,n} Z_{m,n} exp(-2 pi i (kx m / Px + ky n / Py)).

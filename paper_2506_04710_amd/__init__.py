@@ -229,6 +229,54 @@ class Plan:
         infos = [dict(iters=i.iters, outer_iters=i.outer_iters, status=i.status, relres=i.relres) for i in info]
         return x.reshape(v.shape), infos
 
+    @staticmethod
+    def _opts(mode, tol, restart, max_iter, max_outer, inner_tol, precond):
+        o = _lib.SolveOpts()
+        _lib.lib().toeplitz_solve_opts_default(ctypes.byref(o))
+        o.tol, o.restart, o.max_iter, o.max_outer = tol, restart, max_iter, max_outer
+        o.mode, o.x0_given, o.inner_tol = PREC[mode], 0, inner_tol
+        o.precond = 1 if precond else 0
+        return o
+
+    def schur_create(self, element_plan, mode="mixed", tol=1e-10, restart=0, max_iter=2000, max_outer=50,
+                     inner_tol=1e-4, precond=False, stream=None):
+        """Eliminate the rim through its Schur complement: F = A^-1 B_er and
+        (C - B F)^-1 into a device buffer owned by this plan object.
+        element_plan: a Plan of the same array (Nx, Ny, b, generators) with
+        Nr = 0; it runs the solves with the element operator A (options as
+        for solve, applied to those solves)."""
+        import torch
+        L = _lib.lib()
+        n = ctypes.c_size_t(0)
+        check(L.toeplitz_schur_bytes(self._h, ctypes.byref(n)))
+        self.sbuf = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.sbuf.data_ptr()
+        off = (-base) % 256
+        o = self._opts(mode, tol, restart, max_iter, max_outer, inner_tol, precond)
+        with torch.cuda.device(self.device):
+            check(L.toeplitz_schur_create(self._h, element_plan._h, ctypes.c_void_p(base + off), n.value,
+                                          ctypes.byref(o), _stream_handle(stream)))
+        self.element = element_plan
+        return self
+
+    def schur_solve(self, v, mode="mixed", tol=1e-8, restart=0, max_iter=2000, max_outer=50, inner_tol=1e-4,
+                    precond=False, stream=None, raise_on_noconv=False):
+        """Solve Z x = v through the rim elimination (schur_create first)."""
+        import torch
+        v2, R, ldv = self._cols(v, torch.complex128)
+        x = torch.empty((R, self.Nt), dtype=torch.complex128, device=v.device)
+        x2, _, ldx = self._cols(x, torch.complex128)
+        o = self._opts(mode, tol, restart, max_iter, max_outer, inner_tol, precond)
+        info = (_lib.SolveInfo * R)()
+        el = getattr(self, "element", None)
+        st = _lib.lib().toeplitz_schur_solve(self._h, el._h if el is not None else None,
+                                             ctypes.c_void_p(v2.data_ptr()), ldv, ctypes.c_void_p(x2.data_ptr()),
+                                             ldx, R, ctypes.byref(o), info, _stream_handle(stream))
+        if st not in (_lib.TP_OK, _lib.TP_E_NOCONV) or (raise_on_noconv and st != _lib.TP_OK):
+            check(st)
+        infos = [dict(iters=i.iters, outer_iters=i.outer_iters, status=i.status, relres=i.relres) for i in info]
+        return x.reshape(v.shape), infos
+
     def spectrum(self, kx, ky, which="fp64") -> np.ndarray:
         dt = np.complex128 if which == "fp64" else np.complex64
         out = np.empty((self.b, self.b), dtype=dt)

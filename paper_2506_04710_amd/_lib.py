@@ -27,7 +27,7 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_last_error", "toeplitz_batch_begin", "toeplitz_batch_admit", "toeplitz_batch_release",
            "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end", "toeplitz_port_smatrix",
            "toeplitz_far_field", "toeplitz_precond_bytes", "toeplitz_precond_create", "toeplitz_precond_apply",
-           "toeplitz_gen_symmetric")
+           "toeplitz_gen_symmetric", "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve")
 TP_SYM_RIM, TP_SYM_GEN = 1, 2
 
 
@@ -70,6 +70,10 @@ def lib():
         vp, ci, cl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_size_t
         L.toeplitz_plan_bytes.argtypes = [ci, ci, ci, ci, ci, ci, ci, ci, ctypes.POINTER(sz)]
         L.toeplitz_gen_symmetric.argtypes = [ci, ci, ci, vp, ctypes.POINTER(ci)]
+        L.toeplitz_schur_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.toeplitz_schur_create.argtypes = [vp, vp, vp, sz, ctypes.POINTER(SolveOpts), vp]
+        L.toeplitz_schur_solve.argtypes = [vp, vp, vp, cl, vp, cl, ci, ctypes.POINTER(SolveOpts),
+                                           ctypes.POINTER(SolveInfo), vp]
         L.toeplitz_plan_create.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, ci, ci, ci, vp, sz, vp,
                                            ctypes.POINTER(vp)]
         L.toeplitz_plan_info.argtypes = [vp, ctypes.POINTER(PlanDesc)]
@@ -100,7 +104,8 @@ def lib():
                      "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_batch_begin", "toeplitz_batch_admit",
                      "toeplitz_batch_release", "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end",
                      "toeplitz_port_smatrix", "toeplitz_far_field", "toeplitz_precond_bytes",
-                     "toeplitz_precond_create", "toeplitz_precond_apply", "toeplitz_gen_symmetric"):
+                     "toeplitz_precond_create", "toeplitz_precond_apply", "toeplitz_gen_symmetric",
+                     "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib

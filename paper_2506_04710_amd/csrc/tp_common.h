@@ -274,6 +274,13 @@ struct tp_plan_s {
     tp::c128 *S64 = nullptr, *D64 = nullptr;
     tp::c64 *S32 = nullptr, *D32 = nullptr;
     int has_precond = 0;
+    // Schur-complement elimination of the rim, built on request into a third
+    // caller buffer: F = A^-1 B_er [Nr][N], S^-1 = (C - B F)^-1 [Nr][Nr], and
+    // scratch columns for the solves
+    tp::c128 *schurF = nullptr, *schurSinv = nullptr, *schurT = nullptr, *schurY = nullptr;
+    double *schurRed = nullptr;
+    int *schurFlag = nullptr;
+    int has_schur = 0;
     // transform tables
     tp::FFTDesc fx, fy;
     // matvec workspace

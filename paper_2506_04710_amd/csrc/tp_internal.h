@@ -29,6 +29,7 @@ hipError_t precond_fp32_wide(tp_plan pl, Cols<const c128> x, Cols<c128> y, Cols<
 // plan-time: invert every spectrum block in place (FP64, partial pivoting),
 // scale by 1 / (Px Py)^2; *flag (device int) is set nonzero on a zero pivot
 hipError_t precond_build(tp_plan pl, c128 *S, int *flag, hipStream_t st);
+hipError_t dense_inverse(c128 *A, int n, int *flag, hipStream_t st);
 hipError_t cast_to_c64(const c128 *in, c64 *out, long n, hipStream_t st);
 
 // plan-time transform tables (tp_plan.cpp side of tp_capi.hip)

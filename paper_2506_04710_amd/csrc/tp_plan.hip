@@ -188,6 +188,14 @@ __global__ void k_diag_inv(const c128 *__restrict__ Cm, int Nr, c128 *__restrict
     D[t] = c128{c.x / dd, -c.y / dd};
 }
 
+// In-place inverse of one dense n x n complex128 matrix (row-major), one
+// workgroup; flag set when a pivot vanishes.
+hipError_t dense_inverse(c128 *A, int n, int *flag, hipStream_t st) {
+    const size_t sh = (size_t)n * (sizeof(c128) + sizeof(int));
+    hipLaunchKernelGGL(k_block_inv, dim3(1), dim3(256), sh, st, A, n, 1.0, flag);
+    return hipGetLastError();
+}
+
 hipError_t precond_build(tp_plan pl, c128 *S, int *flag, hipStream_t st) {
     const long P = (long)pl->Px * pl->Py;
     const double scl = 1.0 / ((double)P * (double)P);

@@ -129,6 +129,10 @@ def test_null_plan_calls_fail_cleanly(L):
     assert L.toeplitz_matvec(None, 0, None, 1, None, 1, 1, None) == _lib.TP_E_INVAL
     assert L.toeplitz_solve(None, None, 1, None, 1, 1, None, None, None) == _lib.TP_E_INVAL
     assert L.toeplitz_plan_info(None, None) == _lib.TP_E_INVAL
+    n = ctypes.c_size_t(0)
+    assert L.toeplitz_schur_bytes(None, ctypes.byref(n)) == _lib.TP_E_INVAL
+    assert L.toeplitz_schur_create(None, None, None, 0, None, None) == _lib.TP_E_INVAL
+    assert L.toeplitz_schur_solve(None, None, None, 1, None, 1, 1, None, None, None) == _lib.TP_E_INVAL
     L.toeplitz_plan_destroy(None)
 
 

@@ -1,0 +1,73 @@
+"""GPU parity of the Schur-complement elimination of the rim (solves with the
+element operator A, dense C - B A^-1 B_er) against the oracle's dense LU."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import arrays as sa
+from helpers import banner, random_rim_er, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2506_04710_amd as tp
+    tp.load()
+    return tp
+
+
+def _pair(tp, prob, rim_er=None, max_rhs=4, precond=True):
+    plan = tp.Plan.create(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, rim_er=rim_er,
+                          prec="mixed", max_rhs=max_rhs, restart=40)
+    elem = tp.Plan.create(prob.Nx, prob.Ny, prob.b, 0, prob.gen, prec="mixed", max_rhs=8, restart=40)
+    if precond:
+        elem.precond_create()
+    return plan, elem
+
+
+@pytest.mark.parametrize("mode,precond", [("mixed", True), ("fp64", False)])
+def test_schur_solve_matches_lu(tp, mode, precond):
+    banner(f"schur solve {mode} precond={precond}")
+    prob, V = sa.make_config(1)
+    V = np.concatenate([V, sa.rhs_random(prob, 2, np.random.default_rng(11))])
+    plan, elem = _pair(tp, prob, precond=precond)
+    plan.schur_create(elem, mode=mode, tol=1e-11, precond=precond)
+    x, info = plan.schur_solve(to_dev(V), mode=mode, tol=1e-8, precond=precond)
+    X = x.cpu().numpy()
+    rr = oracle.relres(prob, X, V)
+    assert all(i["status"] == 0 for i in info), info
+    assert np.all(rr <= 1e-8), rr
+    # the library's reported residual is the true one
+    assert np.allclose([i["relres"] for i in info], rr, rtol=1e-3, atol=1e-14)
+    Xlu = oracle.lu_solve(oracle.assemble(prob), V)
+    assert rel_err(X, Xlu) <= 1e-6
+
+
+def test_schur_solve_nonreciprocal_rim(tp):
+    banner("schur solve non-reciprocal rim")
+    prob = sa.make_problem(5, 3, 12, 10, 61)
+    rim_er = random_rim_er(prob, 62)
+    V = sa.rhs_random(prob, 3, np.random.default_rng(63))
+    plan, elem = _pair(tp, prob, rim_er=rim_er)
+    plan.schur_create(elem, tol=1e-11, precond=True)
+    x, info = plan.schur_solve(to_dev(V), tol=1e-8, precond=True)
+    op = oracle.Operator(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, rim_er)
+    rr = oracle.relres(op, x.cpu().numpy(), V)
+    assert all(i["status"] == 0 for i in info) and np.all(rr <= 1e-8), (info, rr)
+
+
+def test_schur_errors(tp):
+    banner("schur argument errors")
+    prob, V = sa.make_config(1)
+    plan, elem = _pair(tp, prob, precond=False)
+    with pytest.raises(tp.ToeplitzError):        # no elimination built yet
+        plan.schur_solve(to_dev(V))
+    other = tp.Plan.create(prob.Nx, prob.Ny, 8, 0, np.zeros((2 * prob.Ny - 1, 2 * prob.Nx - 1, 8, 8), complex),
+                           prec="mixed", max_rhs=2, restart=4)
+    with pytest.raises(tp.ToeplitzError):        # element plan of another shape
+        plan.schur_create(other)
+    with pytest.raises(tp.ToeplitzError):        # element plan with a rim
+        plan.schur_create(plan)
