@@ -14,10 +14,18 @@ with it, so these workloads replace each basis function by a point dipole:
   offset (0, 0) gets 10 + 5j added on its diagonal.  Evaluating the offsets in
   exactly this order makes Z_{-m,-n}[q, p] == Z_{m,n}[p, q] bit for bit, the
   reciprocity of Sec. II-A;
-* Nr rim basis functions stand for the margin components of Sec. II-B.  They sit
-  equally spaced in arc length, starting at (i + 1/2) L / Nr from the
-  bottom-left corner and running counter-clockwise, on the rectangle that lies
-  d/2 outside the array's cell hull, with seeded tangents and the same kernel;
+* Nr rim basis functions stand for the margin components of Sec. II-B: the
+  array is an element plus eight margin components (four sides, four corners),
+  each repeated by translation.  The margin is the band d/2 wide outside the
+  cell hull.  Margin parts in the part order of eqs. submatrixB12/B34: side 1
+  (left, Ny parts at cells (0, iy) shifted by -d/2 in x), side 2 (right, cells
+  (Nx, iy)), side 3 (bottom, Nx parts at cells (ix, 0) shifted by -d/2 in y),
+  side 4 (top, cells (ix, Ny)), then the four corners (bottom-left,
+  bottom-right, top-left, top-right).  Each side part carries bm = Nr //
+  (2 (Nx + Ny)) functions, the same offsets and tangents for every part of a
+  side; the remainder goes to the corners (as evenly as possible, first corners
+  first).  Every pair is evaluated as (cell difference) d + (local offset
+  difference), so the side blocks of B and C are block Toeplitz bit for bit;
   the rim-rim diagonal gets 10 + 5j as well.
 
 Global vector ordering (Sec. II-C, part ordering and eq. matrixForm): element
@@ -29,7 +37,8 @@ Rim layout: ``rim_re[r, e*b+p]`` (rim row, element column) and ``rim_rr[r, t]``;
 the element-rim block is rim_re transposed (reciprocal).
 
 All draws come from numpy's PCG64 seeded with SEED_BASE + config index, in the
-order: basis offsets, basis angles, rim angles, then right-hand sides.
+order: basis offsets, basis angles, then per margin component (sides 1-4,
+corners 1-4) its offsets and angles, then right-hand sides.
 """
 from __future__ import annotations
 
@@ -81,23 +90,29 @@ def _kernel(dx, dy, tdot, k):
     return np.exp(-1j * k * r) / (4.0 * np.pi * r) * tdot
 
 
-def _rim_positions(Nx, Ny, Nr, d):
-    """Arc-length-uniform points on the rectangle d/2 outside the cell hull."""
-    x0, y0 = -0.5 * d, -0.5 * d
-    W, H = Nx * d + d, Ny * d + d
-    L = 2.0 * (W + H)
-    s = (np.arange(Nr) + 0.5) * (L / Nr)
-    pos = np.zeros((Nr, 3))
-    for i, si in enumerate(s):
-        if si < W:
-            pos[i, 0], pos[i, 1] = x0 + si, y0
-        elif si < W + H:
-            pos[i, 0], pos[i, 1] = x0 + W, y0 + (si - W)
-        elif si < 2 * W + H:
-            pos[i, 0], pos[i, 1] = x0 + W - (si - W - H), y0 + H
-        else:
-            pos[i, 0], pos[i, 1] = x0, y0 + H - (si - 2 * W - H)
-    return pos
+def margin_counts(Nx: int, Ny: int, Nr: int):
+    """Functions per side part (bm) and per corner (four counts) for Nr rim functions."""
+    per = 2 * (Nx + Ny)
+    bm = Nr // per
+    rem = Nr - bm * per
+    return bm, [rem // 4 + (1 if i < rem % 4 else 0) for i in range(4)]
+
+
+def _margin_components(Nx, Ny, Nr, d):
+    """(cells [(cx, cy)], local box origin, box size, functions per part) per
+    margin component, in the rim's unknown order."""
+    bm, bc = margin_counts(Nx, Ny, Nr)
+    h = 0.5 * d
+    return [
+        ([(0, iy) for iy in range(Ny)], (-h, 0.0), (h, d), bm),        # side 1: left
+        ([(Nx, iy) for iy in range(Ny)], (0.0, 0.0), (h, d), bm),      # side 2: right
+        ([(ix, 0) for ix in range(Nx)], (0.0, -h), (d, h), bm),        # side 3: bottom
+        ([(ix, Ny) for ix in range(Nx)], (0.0, 0.0), (d, h), bm),      # side 4: top
+        ([(0, 0)], (-h, -h), (h, h), bc[0]),                           # corners
+        ([(Nx, 0)], (0.0, -h), (h, h), bc[1]),
+        ([(0, Ny)], (-h, 0.0), (h, h), bc[2]),
+        ([(Nx, Ny)], (0.0, 0.0), (h, h), bc[3]),
+    ]
 
 
 def make_problem(Nx: int, Ny: int, b: int, Nr: int, seed: int | list) -> Problem:
@@ -108,7 +123,6 @@ def make_problem(Nx: int, Ny: int, b: int, Nr: int, seed: int | list) -> Problem
     d, k = PERIOD, WAVENUMBER
     u = rng.uniform(0.0, 0.5, size=(b, 2))          # basis offsets inside the cell
     alpha = rng.uniform(0.0, 2.0 * np.pi, size=b)    # basis tangent angles
-    alpha_rim = rng.uniform(0.0, 2.0 * np.pi, size=Nr)
     tx, ty = np.cos(alpha), np.sin(alpha)
 
     dux = u[:, 0][:, None] - u[:, 0][None, :]        # (u_p.x - u_q.x)
@@ -135,21 +149,37 @@ def make_problem(Nx: int, Ny: int, b: int, Nr: int, seed: int | list) -> Problem
     tangents[:N, 0] = np.tile(tx, Nx * Ny)
     tangents[:N, 1] = np.tile(ty, Nx * Ny)
 
+    # rim functions: integer cell, local offset and tangent per unknown
+    rcell = np.zeros((Nr, 2))
+    roff = np.zeros((Nr, 2))
+    rtan = np.zeros((Nr, 2))
+    r0 = 0
+    for cells, org, size, nf in _margin_components(Nx, Ny, Nr, d):
+        w = rng.uniform(0.0, 1.0, size=(nf, 2)) * np.asarray(size) + np.asarray(org)
+        a = rng.uniform(0.0, 2.0 * np.pi, size=nf)
+        for c in cells:
+            rcell[r0:r0 + nf] = c
+            roff[r0:r0 + nf] = w
+            rtan[r0:r0 + nf, 0], rtan[r0:r0 + nf, 1] = np.cos(a), np.sin(a)
+            r0 += nf
+    assert r0 == Nr
     rim_re = np.zeros((Nr, N), dtype=np.complex128)
     rim_rr = np.zeros((Nr, Nr), dtype=np.complex128)
     if Nr:
-        rpos = _rim_positions(Nx, Ny, Nr, d)
-        rtx, rty = np.cos(alpha_rim), np.sin(alpha_rim)
-        centres[N:] = rpos
-        tangents[N:, 0], tangents[N:, 1] = rtx, rty
+        centres[N:, 0] = rcell[:, 0] * d + roff[:, 0]
+        centres[N:, 1] = rcell[:, 1] * d + roff[:, 1]
+        tangents[N:, 0], tangents[N:, 1] = rtan[:, 0], rtan[:, 1]
+        ecx = np.repeat(ix, b).astype(float)
+        ecy = np.repeat(iy, b).astype(float)
+        eox, eoy = np.tile(u[:, 0], Nx * Ny), np.tile(u[:, 1], Nx * Ny)
         for r in range(Nr):
-            dx = rpos[r, 0] - centres[:N, 0]
-            dy = rpos[r, 1] - centres[:N, 1]
-            td = rtx[r] * tangents[:N, 0] + rty[r] * tangents[:N, 1]
+            dx = (rcell[r, 0] - ecx) * d + (roff[r, 0] - eox)
+            dy = (rcell[r, 1] - ecy) * d + (roff[r, 1] - eoy)
+            td = rtan[r, 0] * tangents[:N, 0] + rtan[r, 1] * tangents[:N, 1]
             rim_re[r] = _kernel(dx, dy, td, k)
-        dx = rpos[:, 0][:, None] - rpos[:, 0][None, :]
-        dy = rpos[:, 1][:, None] - rpos[:, 1][None, :]
-        td = rtx[:, None] * rtx[None, :] + rty[:, None] * rty[None, :]
+        dx = (rcell[:, 0][:, None] - rcell[:, 0][None, :]) * d + (roff[:, 0][:, None] - roff[:, 0][None, :])
+        dy = (rcell[:, 1][:, None] - rcell[:, 1][None, :]) * d + (roff[:, 1][:, None] - roff[:, 1][None, :])
+        td = rtan[:, 0][:, None] * rtan[:, 0][None, :] + rtan[:, 1][:, None] * rtan[:, 1][None, :]
         rim_rr[:] = _kernel(dx, dy, td, k)
         rim_rr[np.arange(Nr), np.arange(Nr)] += DIAG_SHIFT
     return Problem(Nx, Ny, b, Nr, gen, rim_re, rim_rr, centres, tangents,
