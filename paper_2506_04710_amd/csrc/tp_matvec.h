@@ -53,16 +53,31 @@ __global__ void __launch_bounds__(256) k_fwd_x(Cols<const In> x, int R, int Nx, 
     const int CC = 1 << lgCC, C = b * R, P = fx.P;
     const int c0 = blockIdx.x * CC, iy = blockIdx.y;
     if (!cols_live((const void *const *)x.tab, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
-    load_twiddles<T>(twl, fx);
-    zero_lds<T>(buf, P * CC);
-    __syncthreads();
-    for (int i = threadIdx.x; i < Nx * CC; i += kBlock) {
-        const int ix = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
+    auto fetch = [&](int i, bool &ok) {
+        const int ix = i >> lgCC, c = c0 + (i & (CC - 1));
+        ok = false;
         if (c < C) {
             const int r = c / b, p = c - r * b;
             const In *xc = x.col(r);
-            if (xc) buf[(fx.perm[ix] << lgCC) + cl] = cvt<T>(xc[(long)(iy * Nx + ix) * b + p]);
+            if (xc) {
+                ok = true;
+                return cvt<T>(xc[(long)(iy * Nx + ix) * b + p]);
+            }
         }
+        return mk<T>(0, 0);
+    };
+    // the first value per thread is fetched before the twiddles and the
+    // zero fill, so its round trip overlaps theirs
+    bool ok0;
+    const cpx<T> v0 = threadIdx.x < Nx * CC ? fetch(threadIdx.x, ok0) : (ok0 = false, mk<T>(0, 0));
+    load_twiddles<T>(twl, fx);
+    zero_lds<T>(buf, P * CC);
+    __syncthreads();
+    if (ok0) buf[(fx.perm[threadIdx.x >> lgCC] << lgCC) + (threadIdx.x & (CC - 1))] = v0;
+    for (int i = threadIdx.x + kBlock; i < Nx * CC; i += kBlock) {
+        bool ok;
+        const cpx<T> v = fetch(i, ok);
+        if (ok) buf[(fx.perm[i >> lgCC] << lgCC) + (i & (CC - 1))] = v;
     }
     __syncthreads();
     lds_fft<T, false>(buf, lgCC, fx, twl);
@@ -882,20 +897,42 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
     const int CC = 1 << lgCC, C = b * R, P = fx.P;
     const int iy = blk / nchunk, c0 = (blk - iy * nchunk) * CC;
     if (!cols_live((const void *const *)y.tab, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
-    load_twiddles<T>(twl, fx);
-    for (int i = threadIdx.x; i < P * CC; i += kBlock) {
-        const int kx = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
+    auto gather = [&](int i) {
+        const int kx = i >> lgCC, c = c0 + (i & (CC - 1));
         cpx<T> v = mk<T>(0, 0);
         if (c < C) {
             if (mp.yp && kx >= mp.kxh) {
+                // all parts in flight at once (nch <= 8: rows of at most 64),
+                // then added in part order
                 const cpx<T> *src = mp.yp + ((long)iy * mp.nmir + (kx - mp.kxh)) * b + c;
-                for (int h = 0; h < mp.nch; ++h) v = v + src[h * mp.hstride];
+                cpx<T> pv[8];
+#pragma unroll
+                for (int h = 0; h < 8; ++h) pv[h] = h < mp.nch ? src[h * mp.hstride] : mk<T>(0, 0);
+#pragma unroll
+                for (int h = 0; h < 8; ++h)
+                    if (h < mp.nch) v = v + pv[h];
             } else {
                 v = in[((long)iy * P + kx) * C + c];
             }
         }
-        buf[(fx.perm[kx] << lgCC) + cl] = v;
+        return v;
+    };
+    // the first two values per thread are fetched before the twiddles, so
+    // both round trips overlap
+    cpx<T> pre[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int i = threadIdx.x + j * kBlock;
+        pre[j] = i < P * CC ? gather(i) : mk<T>(0, 0);
     }
+    load_twiddles<T>(twl, fx);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int i = threadIdx.x + j * kBlock;
+        if (i < P * CC) buf[(fx.perm[i >> lgCC] << lgCC) + (i & (CC - 1))] = pre[j];
+    }
+    for (int i = threadIdx.x + 2 * kBlock; i < P * CC; i += kBlock)
+        buf[(fx.perm[i >> lgCC] << lgCC) + (i & (CC - 1))] = gather(i);
     __syncthreads();
     lds_fft<T, true>(buf, lgCC, fx, twl);
     for (int i = threadIdx.x; i < Nx * CC; i += kBlock) {
