@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true",
                     help="headline workload only (no multi-RHS, precision or serving sections)")
+    ap.add_argument("--solves-only", action="store_true",
+                    help="only the headline solves (warmup + steps), for a kernel trace of the solve alone")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device-to-device copies of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -194,6 +196,22 @@ def precision(dev, K=2):
             "max_relres": max(i["relres"] for i in inf), "max_rel_diff_vs_fp64": err}
 
 
+def solves_only(K, W):
+    """The headline solve alone (mixed + preconditioner, one RHS), K timed after W."""
+    import torch
+    import paper_2506_04710_amd as tp
+    from synth import arrays as sa
+    tp.load()
+    prob, V = sa.make_config(2)
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=1, restart=40).precond_create()
+    v = torch.from_numpy(V).to("cuda:0")
+    total, _, (_, inf) = timed_solves(plan, v, K, W, mode="mixed", precond=True)
+    assert inf[0]["status"] == 0 and inf[0]["relres"] <= 1e-8, inf
+    print(json.dumps({"solves_per_s": round(K / total, 2), "steps": K, "warmup": W, "iters": inf[0]["iters"],
+                      "outer": inf[0]["outer_iters"]}), flush=True)
+    plan.close()
+
+
 def schur(dev, K):
     """The headline workload solved through the rim's Schur complement: setup
     (F = A^-1 B_er, S = C - B F, S^-1) once, then K solves of one RHS."""
@@ -273,6 +291,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.solves_only:
+        solves_only(args.steps, args.warmup)
         return
     import numpy as np
     import torch

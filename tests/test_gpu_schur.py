@@ -71,3 +71,29 @@ def test_schur_errors(tp):
         plan.schur_create(other)
     with pytest.raises(tp.ToeplitzError):        # element plan with a rim
         plan.schur_create(plan)
+
+
+def test_schur_one_rim_function_strided_columns(tp):
+    banner("schur solve Nr=1, ldv > Nt")
+    prob = sa.make_problem(3, 2, 4, 1, 71)          # the single rim function sits in a corner
+    V = sa.rhs_random(prob, 2, np.random.default_rng(72))
+    plan, elem = _pair(tp, prob, max_rhs=2, precond=False)
+    plan.schur_create(elem, mode="fp64", tol=1e-12)
+    import torch
+    wide = torch.zeros((2, prob.Nt + 3), dtype=torch.complex128, device="cuda:0")
+    wide[:, :prob.Nt] = to_dev(V)
+    x, info = plan.schur_solve(wide[:, :prob.Nt], mode="fp64", tol=1e-10)
+    X = x.cpu().numpy()
+    assert all(i["status"] == 0 for i in info), info
+    Xlu = oracle.lu_solve(oracle.assemble(prob), V)
+    assert rel_err(X, Xlu) <= 1e-8
+
+
+def test_schur_needs_fp64_operator(tp):
+    banner("schur rejects an FP32-only plan")
+    prob, _ = sa.make_config(1)
+    plan = tp.Plan.create(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, prec="fp32",
+                          max_rhs=1, restart=8)
+    elem = tp.Plan.create(prob.Nx, prob.Ny, prob.b, 0, prob.gen, prec="mixed", max_rhs=1, restart=8)
+    with pytest.raises(tp.ToeplitzError):
+        plan.schur_create(elem)
