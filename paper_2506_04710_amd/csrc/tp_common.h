@@ -277,7 +277,7 @@ struct tp_plan_s {
     // Schur-complement elimination of the rim, built on request into a third
     // caller buffer: F = A^-1 B_er [Nr][N], S^-1 = (C - B F)^-1 [Nr][Nr], and
     // scratch columns for the solves
-    tp::c128 *schurF = nullptr, *schurSinv = nullptr, *schurT = nullptr, *schurY = nullptr;
+    tp::c128 *schurF = nullptr, *schurSinv = nullptr, *schurPart = nullptr, *schurY = nullptr;
     double *schurRed = nullptr;
     int *schurFlag = nullptr;
     int has_schur = 0;

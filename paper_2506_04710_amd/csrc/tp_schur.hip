@@ -6,8 +6,7 @@
 //   solve:  w = A^-1 v_A,  x_r = S^-1 (v_r - B w),  x_A = w - F x_r.
 // The Toeplitz solves run on a second plan of the same array without rim
 // (the element operator alone), so the iterated operator is purely two-level
-// block Toeplitz; B applied to a vector is the rim part of the full
-// operator's FP64 application to [w; 0].
+// block Toeplitz; B w is one FP64 pass over the dense block B.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -18,29 +17,78 @@ namespace tp {
 
 static size_t al(size_t n) { return (n + 255) & ~(size_t)255; }
 
-// T[r] = [src_r[0..N); 0], columns of length Nt
-__global__ void k_schur_pad(const c128 *__restrict__ src, long lds, long N, long Nt, c128 *__restrict__ T) {
-    const int r = blockIdx.y;
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < Nt; e += (long)gridDim.x * blockDim.x)
-        T[(long)r * Nt + e] = e < N ? src[(long)r * lds + e] : c128{0, 0};
+// B w for up to kSchurCols columns per launch: workgroup (s, t) sums row t
+// of B against slab s of every column; the slab sums are added, in slab
+// order, by their consumer.  part[(c * Nr + t) * kSchurSlabs + s].
+constexpr int kSchurSlabs = 16;
+constexpr int kSchurCols = 8;
+__global__ void __launch_bounds__(256) k_schur_Bw(const c128 *__restrict__ B, long N, int Nr,
+                                                  const c128 *__restrict__ w, long ldw, int ncols, int c0,
+                                                  c128 *__restrict__ part) {
+    __shared__ double red[2][kSchurCols][4];
+    const int s = blockIdx.x, t = blockIdx.y;
+    const long L = (N + kSchurSlabs - 1) / kSchurSlabs, e0 = (long)s * L, e1 = min(N, e0 + L);
+    const int nc = min(kSchurCols, ncols - c0);
+    c128 acc[kSchurCols];
+#pragma unroll
+    for (int c = 0; c < kSchurCols; ++c) acc[c] = c128{0, 0};
+    const c128 *Bt = B + (long)t * N;
+    for (long e = e0 + threadIdx.x; e < e1; e += kBlock) {
+        const c128 bv = Bt[e];
+#pragma unroll
+        for (int c = 0; c < kSchurCols; ++c)
+            if (c < nc) acc[c] = cmac(acc[c], bv, w[(long)(c0 + c) * ldw + e]);
+    }
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < kSchurCols; ++c) {
+        if (c >= nc) break;
+        const double re = wave_allsum(acc[c].x), im = wave_allsum(acc[c].y);
+        if ((threadIdx.x & 63) == 0) {
+            red[0][c][wv] = re;
+            red[1][c][wv] = im;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+        const int c = threadIdx.x;
+        const c128 v{((red[0][c][0] + red[0][c][1]) + red[0][c][2]) + red[0][c][3],
+                     ((red[1][c][0] + red[1][c][1]) + red[1][c][2]) + red[1][c][3]};
+        part[((long)(c0 + c) * Nr + t) * kSchurSlabs + s] = v;
+    }
 }
 
-// S[i][r0 + c] = C[i][r0 + c] - Y_c[N + i]  (Y_c = rim part of Z [F_c; 0] = B F_c)
-__global__ void k_schur_S(const c128 *__restrict__ Cm, const c128 *__restrict__ Y, long N, long Nt, int Nr, int r0,
+__device__ __forceinline__ c128 slab_sum(const c128 *__restrict__ part, long i) {
+    c128 v = part[i * kSchurSlabs];
+#pragma unroll
+    for (int s = 1; s < kSchurSlabs; ++s) v = v + part[i * kSchurSlabs + s];
+    return v;
+}
+
+static hipError_t launch_Bw(const c128 *B, long N, int Nr, const c128 *w, long ldw, int ncols, c128 *part,
+                            hipStream_t st) {
+    for (int c0 = 0; c0 < ncols; c0 += kSchurCols)
+        hipLaunchKernelGGL(k_schur_Bw, dim3(kSchurSlabs, Nr), dim3(256), 0, st, B, N, Nr, w, ldw, ncols, c0, part);
+    return hipGetLastError();
+}
+
+// S[i][r0 + c] = C[i][r0 + c] - (B F_c)[i]
+__global__ void k_schur_S(const c128 *__restrict__ Cm, const c128 *__restrict__ part, int Nr, int r0,
                           c128 *__restrict__ S) {
     const int c = blockIdx.y, r = r0 + c;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Nr; i += gridDim.x * blockDim.x)
-        S[(long)i * Nr + r] = Cm[(long)i * Nr + r] - Y[(long)c * Nt + N + i];
+        S[(long)i * Nr + r] = Cm[(long)i * Nr + r] - slab_sum(part, (long)c * Nr + i);
 }
 
-// x_r = S^-1 (v_r - Y_r) for column blockIdx.x (Y = Z [w; 0])
+// x_r = S^-1 (v_r - B w) for column blockIdx.x
 __global__ void __launch_bounds__(256) k_schur_xr(const c128 *__restrict__ Sinv, const c128 *__restrict__ v, long ldv,
-                                                  const c128 *__restrict__ Y, long N, long Nt, int Nr,
+                                                  const c128 *__restrict__ part, long N, int Nr,
                                                   c128 *__restrict__ x, long ldx) {
     extern __shared__ char smem_raw[];
     c128 *g = reinterpret_cast<c128 *>(smem_raw);   // [Nr]
     const int r = blockIdx.x;
-    for (int t = threadIdx.x; t < Nr; t += blockDim.x) g[t] = v[(long)r * ldv + N + t] - Y[(long)r * Nt + N + t];
+    for (int t = threadIdx.x; t < Nr; t += blockDim.x)
+        g[t] = v[(long)r * ldv + N + t] - slab_sum(part, (long)r * Nr + t);
     __syncthreads();
     for (int i = threadIdx.x; i < Nr; i += blockDim.x) {
         c128 s = c128{0, 0};
@@ -96,7 +144,7 @@ __global__ void __launch_bounds__(1024) k_schur_norms(const c128 *__restrict__ v
 }
 
 struct SchurLayout {
-    size_t F, Sinv, T, Y, red, flag, total;
+    size_t F, Sinv, part, Y, red, flag, total;
 };
 static SchurLayout schur_layout(tp_plan p) {
     SchurLayout L;
@@ -108,7 +156,7 @@ static SchurLayout schur_layout(tp_plan p) {
     };
     L.F = take((size_t)p->Nr * p->N * 16);
     L.Sinv = take((size_t)p->Nr * p->Nr * 16);
-    L.T = take((size_t)p->max_rhs * p->Nt * 16);
+    L.part = take((size_t)p->max_rhs * p->Nr * kSchurSlabs * 16);
     L.Y = take((size_t)p->max_rhs * p->Nt * 16);
     L.red = take((size_t)p->max_rhs * 2 * 8);
     L.flag = take(sizeof(int));
@@ -154,7 +202,7 @@ tp_status toeplitz_schur_create(tp_plan p, tp_plan a, void *dev_buf, size_t dev_
     p->has_schur = 0;
     p->schurF = reinterpret_cast<c128 *>(base + L.F);
     p->schurSinv = reinterpret_cast<c128 *>(base + L.Sinv);
-    p->schurT = reinterpret_cast<c128 *>(base + L.T);
+    p->schurPart = reinterpret_cast<c128 *>(base + L.part);
     p->schurY = reinterpret_cast<c128 *>(base + L.Y);
     p->schurRed = reinterpret_cast<double *>(base + L.red);
     p->schurFlag = reinterpret_cast<int *>(base + L.flag);
@@ -173,17 +221,13 @@ tp_status toeplitz_schur_create(tp_plan p, tp_plan a, void *dev_buf, size_t dev_
         s = toeplitz_solve(a, Ber + (long)r0 * N, N, p->schurF + (long)r0 * N, N, R, &o, info.data(), hip_stream);
         if (s != TP_OK) return s == TP_E_NOCONV ? fail(s, "a solve with the element operator missed its tolerance") : s;
     }
-    // S = C - B F, p->max_rhs columns at a time: B F_c is the rim part of Z [F_c; 0]
+    // S = C - B F, p->max_rhs columns at a time
     hipError_t e = hipSuccess;
     for (int r0 = 0; r0 < Nr && e == hipSuccess; r0 += p->max_rhs) {
         const int R = std::min(p->max_rhs, Nr - r0);
-        hipLaunchKernelGGL(k_schur_pad, dim3((unsigned)((Nt + 255) / 256), R), dim3(256), 0, st,
-                           p->schurF + (long)r0 * N, N, N, Nt, p->schurT);
-        if ((e = hipGetLastError())) break;
-        if ((e = matvec_fp64(p, Cols<const c128>{p->schurT, Nt, nullptr}, Cols<c128>{p->schurY, Nt, nullptr}, R, st)))
-            break;
-        hipLaunchKernelGGL(k_schur_S, dim3((unsigned)((Nr + 255) / 256), R), dim3(256), 0, st, p->C64, p->schurY, N,
-                           Nt, Nr, r0, p->schurSinv);
+        if ((e = launch_Bw(p->B64, N, Nr, p->schurF + (long)r0 * N, N, R, p->schurPart, st))) break;
+        hipLaunchKernelGGL(k_schur_S, dim3((unsigned)((Nr + 255) / 256), R), dim3(256), 0, st, p->C64, p->schurPart, Nr,
+                           r0, p->schurSinv);
         e = hipGetLastError();
     }
     int hflag = 0;
@@ -229,13 +273,9 @@ tp_status toeplitz_schur_solve(tp_plan p, tp_plan a, const void *v, long ldv, vo
     if (s != TP_OK && s != TP_E_NOCONV) return s;
     hipError_t e;
     // x_r = S^-1 (v_r - B w), x_A = w - F x_r
-    hipLaunchKernelGGL(k_schur_pad, dim3((unsigned)((Nt + 255) / 256), nrhs), dim3(256), 0, st, xc, ldx, N, Nt,
-                       p->schurT);
-    if ((e = hipGetLastError()) ||
-        (e = matvec_fp64(p, Cols<const c128>{p->schurT, Nt, nullptr}, Cols<c128>{p->schurY, Nt, nullptr}, nrhs, st)))
-        return hip_fail(e, "rim elimination solve");
+    if ((e = launch_Bw(p->B64, N, Nr, xc, ldx, nrhs, p->schurPart, st))) return hip_fail(e, "rim elimination solve");
     hipLaunchKernelGGL(k_schur_xr, dim3(nrhs), dim3(256), (size_t)Nr * sizeof(c128), st, p->schurSinv, vc, ldv,
-                       p->schurY, N, Nt, Nr, xc, ldx);
+                       p->schurPart, N, Nr, xc, ldx);
     hipLaunchKernelGGL(k_schur_xa, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), (size_t)Nr * sizeof(c128), st,
                        p->schurF, N, Nr, xc, ldx);
     // the true residual of the full system
