@@ -648,7 +648,9 @@ static hipError_t solver_resources(tp_plan pl) {
     if (!pl->cs && (e = hipStreamCreateWithFlags(&pl->cs, hipStreamNonBlocking))) return e;
     for (hipEvent_t &ev : pl->ev)
         if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming))) return e;
-    if (!pl->host_status && (e = hipHostMalloc(&pl->host_status, 2 * sizeof(SlotState) * pl->max_rhs)))
+    // [2][max_rhs] slot states, then [2][max_rhs] Arnoldi decisions
+    if (!pl->host_status &&
+        (e = hipHostMalloc(&pl->host_status, 2 * (sizeof(SlotState) + sizeof(SlotDec)) * pl->max_rhs)))
         return e;
     return e;
 }
@@ -763,6 +765,7 @@ tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int 
     if ((e = solver_resources(pl))) return hip_fail(e, "solver resources");
     hipStream_t cs = pl->cs;
     SlotState *hstat = (SlotState *)pl->host_status;     // [2][max_rhs], pinned
+    SlotDec *hdec = reinterpret_cast<SlotDec *>(hstat + 2 * (size_t)pl->max_rhs);
 
     // the first super-step (parity 0) commits from the parity-1 copy
     std::vector<SlotState> hs(2 * (size_t)nrhs, initial_state(o.x0_given));
@@ -780,26 +783,54 @@ tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int 
 
     hipGraphExec_t gexec = nullptr;
     if ((e = step_graph(pl, E, &gexec))) return hip_fail(e, "solver graph capture");
+    // Without a starting guess the first super-step only turns INIT into the
+    // initial residual r = v: its operator and CGS2 launches would all find no
+    // column of their phase. Run just its commit and tail, as parity 1, so
+    // that the first replayed super-step (parity 0) starts from that residual.
+    if (!o.x0_given) {
+        const dim3 gv(E.nb, E.nslots), blk(kThreads);
+        hipLaunchKernelGGL(k_commit, gv, blk, 0, cs, E, 1);
+        hipLaunchKernelGGL(k_tail, gv, blk, 0, cs, E, 1);
+        if ((e = hipGetLastError())) return hip_fail(e, "solver initial residual");
+    }
 
     // replay with one graph of lookahead; the state after a graph is the
-    // parity-1 copy (the second super-step's commit)
+    // parity-1 copy (the second super-step's commit). When that state is a
+    // residual step, or an Arnoldi step that ended its cycle, the graph in
+    // flight may finish every column: the host then waits for it before
+    // launching another, so no idle graph runs after convergence.
     const long max_launch = ((long)o.max_iter * 2 + (long)o.max_outer * 4 + 16) / kStepsPerGraph + 2;
-    const size_t sbytes = sizeof(SlotState) * nrhs;
+    const size_t sbytes = sizeof(SlotState) * nrhs, dbytes = sizeof(SlotDec) * nrhs;
     const SlotState *dev_last = E.st + nrhs;
+    auto all_done = [&](int b) {
+        for (int r = 0; r < nrhs; ++r)
+            if (hstat[b * pl->max_rhs + r].phase != PH_DONE) return false;
+        return true;
+    };
+    auto may_finish = [&](int b) {
+        for (int r = 0; r < nrhs; ++r) {
+            const SlotState &S = hstat[b * pl->max_rhs + r];
+            if (S.phase == PH_RES || (S.phase == PH_ARN && hdec[b * pl->max_rhs + r].end)) return true;
+        }
+        return false;
+    };
     long k = 0;
     bool done = false;
     while (!done && k < max_launch) {
         const int buf = (int)(k & 1);
         if ((e = hipGraphLaunch(gexec, cs)) ||
             (e = hipMemcpyAsync(hstat + buf * pl->max_rhs, dev_last, sbytes, hipMemcpyDeviceToHost, cs)) ||
+            (e = hipMemcpyAsync(hdec + buf * pl->max_rhs, E.dec, dbytes, hipMemcpyDeviceToHost, cs)) ||
             (e = hipEventRecord(pl->ev[1 + buf], cs)))
             return hip_fail(e, "solver replay");
         if (k > 0) {
             const int pb = 1 - buf;
             if ((e = hipEventSynchronize(pl->ev[1 + pb]))) return hip_fail(e, "solver poll");
-            done = true;
-            for (int r = 0; r < nrhs; ++r)
-                if (hstat[pb * pl->max_rhs + r].phase != PH_DONE) done = false;
+            done = all_done(pb);
+            if (!done && may_finish(pb)) {
+                if ((e = hipEventSynchronize(pl->ev[1 + buf]))) return hip_fail(e, "solver poll");
+                done = all_done(buf);
+            }
         }
         ++k;
     }
