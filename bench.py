@@ -31,8 +31,8 @@ METRIC = "solves/s at rel-residual 1e-8 (32x32,b=64) vs FP64 plain; matvec GB/s;
 # HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the same counters on a plain copy of known size),
 # valid only for the kernel source it was measured on.
-TRAFFIC = {"source_sha256": "68a19964de2abbe4e5893cb35be8b06a055387f57a2d46ecef3438d8f20015a6",
-           "bytes": 211265222, "fetch_factor": 0.500009, "write_factor": 1.0}
+TRAFFIC = {"source_sha256": "05905eaa96f44caeaeb4fc83e68f291b7535bc1055187d6cac6694f86ed1ed6b",
+           "bytes": 211212425, "fetch_factor": 0.500009, "write_factor": 1.0}
 
 
 def parse():
