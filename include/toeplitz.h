@@ -124,7 +124,8 @@ tp_status toeplitz_gen_symmetric(int Nx, int Ny, int b, const double *gen, int *
  *           aligned; owned by the caller, who must keep it alive until
  *           toeplitz_plan_destroy and free it afterwards.
  *   out     receives the plan handle.
- * Errors: TP_E_INVAL (shapes, NULL pointers, misaligned buffer), TP_E_NOMEM
+ * Errors: TP_E_INVAL (shapes, NULL pointers, misaligned buffer, a NaN or Inf
+ * in gen or a rim block), TP_E_NOMEM
  * (dev_bytes below toeplitz_plan_bytes with the sym bits this call implies),
  * TP_E_HIP.
  */
@@ -140,10 +141,17 @@ tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *desc);
  * y = Z x for nrhs columns (eq. MoMMatrixEq operator): embed, forward 2-D DFT,
  * per-frequency b x b block product with the stored spectrum, inverse DFT, crop,
  * plus the dense rim terms y_A += B_er x_r, y_r = B x_A + C x_r.
- * x, y: device, column-major Nt x nrhs, leading dimensions ldx, ldy >= Nt;
- * complex128 if which == TP_FP64, complex64 if which == TP_FP32.  x and y must
- * not overlap.  1 <= nrhs <= max_rhs.  Asynchronous on hip_stream; uses the
- * plan's workspace, so calls on one plan must not run concurrently.
+ * x, y: device, column-major Nt x nrhs, leading dimensions ldx, ldy >= Nt.
+ * which selects the operator copy and the vector type:
+ *   TP_FP64   FP64 operator, complex128 vectors;
+ *   TP_FP32   FP32 operator (FP32 accumulation), complex64 vectors;
+ *   TP_MIXED  FP32 operator on complex128 vectors (inputs rounded to FP32 as
+ *             they are read, results widened as they are written): the inner
+ *             operator of a TP_MIXED solve.
+ * x and y must not overlap.  1 <= nrhs <= max_rhs.  Asynchronous on
+ * hip_stream; uses the plan's workspace, so calls on one plan must not run
+ * concurrently, and the call is refused (TP_E_INVAL) while a continuous batch
+ * runs on the plan.
  * Errors: TP_E_INVAL, TP_E_UNSUPPORTED (the plan lacks that precision copy),
  * TP_E_HIP.
  */
@@ -199,8 +207,12 @@ void toeplitz_solve_opts_default(tp_solve_opts *opts);
  * opts NULL = defaults.  The call synchronises hip_stream (the host reads the
  * convergence scalars).  Returns TP_OK if every column met tol, TP_E_NOCONV /
  * TP_E_BREAKDOWN otherwise (x then holds each column's best iterate and info is
- * filled), TP_E_INVAL / TP_E_UNSUPPORTED / TP_E_HIP on errors.  Solves are
- * limited to Nt <= 262144 unknowns (TP_E_UNSUPPORTED beyond).
+ * filled), TP_E_INVAL / TP_E_UNSUPPORTED / TP_E_HIP on errors.  A column
+ * whose right-hand side holds NaN or Inf stops at its first residual with
+ * status TP_E_INVAL (the call then returns TP_E_INVAL with info filled; the
+ * other columns run to their own end).  Solves are limited to Nt <= 262144
+ * unknowns (TP_E_UNSUPPORTED beyond; the Krylov kernels keep two rounds of 256
+ * elements per thread in registers for 512 element ranges).
  */
 tp_status toeplitz_solve(tp_plan p, const void *v, long ldv, void *x, long ldx, int nrhs,
                          const tp_solve_opts *opts, tp_solve_info *info, void *hip_stream);
@@ -267,6 +279,7 @@ tp_status toeplitz_schur_create(tp_plan p, tp_plan a, void *dev_buf, size_t dev_
  * true ||v - Z x|| / ||v|| of the full system from an FP64 application, and
  * status TP_OK when it is <= opts->tol (else TP_E_NOCONV, x holds the result);
  * iters and outer_iters are those of the element solve.  Synchronises hip_stream.
+ * Refused (TP_E_INVAL) while a continuous batch runs on either plan.
  */
 tp_status toeplitz_schur_solve(tp_plan p, tp_plan a, const void *v, long ldv, void *x, long ldx, int nrhs,
                                const tp_solve_opts *opts, tp_solve_info *info, void *hip_stream);
@@ -296,12 +309,19 @@ tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void 
  *   every b x b frequency block in FP64 (Gauss-Jordan, partial pivoting).
  *   Needs a plan with the FP64 copy (TP_FP64 or TP_MIXED; else
  *   TP_E_UNSUPPORTED).  Synchronises hip_stream; a singular block or a zero
- *   diagonal entry of C returns TP_E_BREAKDOWN.  A second call rebuilds.
+ *   diagonal entry of C returns TP_E_BREAKDOWN.  A second call rebuilds (and
+ *   drops the plan's captured solver graphs, which hold the old pointers);
+ *   refused while a continuous batch runs on the plan.
+ * toeplitz_precond_bytes_for: the same count before a plan exists (for
+ *   admission), from the arguments of toeplitz_plan_bytes (sym as there;
+ *   prec TP_FP64 or TP_MIXED, else TP_E_UNSUPPORTED).
  * toeplitz_precond_apply: y = M^-1 x for nrhs columns (same conventions as
- *   toeplitz_matvec; x and y must not overlap).  TP_E_INVAL without a
- *   preconditioner.  Asynchronous on hip_stream.
+ *   toeplitz_matvec, including which = TP_MIXED: the FP32 copy on complex128
+ *   vectors, as a mixed solve applies it; x and y must not overlap).
+ *   TP_E_INVAL without a preconditioner.  Asynchronous on hip_stream.
  */
 tp_status toeplitz_precond_bytes(tp_plan p, size_t *bytes);
+tp_status toeplitz_precond_bytes_for(int Nx, int Ny, int b, int Nr, int sym, tp_prec prec, size_t *bytes);
 tp_status toeplitz_precond_create(tp_plan p, void *dev_buf, size_t dev_bytes, void *hip_stream);
 tp_status toeplitz_precond_apply(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int nrhs,
                                  void *hip_stream);

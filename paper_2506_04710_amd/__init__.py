@@ -50,32 +50,14 @@ def gen_symmetric(Nx, Ny, b, gen) -> bool:
     return bool(out.value)
 
 
-def precond_bytes(Nx, Ny, b, Nr, prec="mixed", symmetric=False) -> int:
-    """Device bytes of the block-circulant preconditioner of such a plan: the
-    inverted spectrum per precision held (the plan's stored blocks: Px Py, or
-    (Px / 2 + 1) Py for symmetric generators, of b^2 values), 1/diag(C), a
-    status word, each region 256-byte aligned (as toeplitz_precond_bytes)."""
-    px, py = _grid(Nx), _grid(Ny)
-    nblk = (px // 2 + 1) * py if symmetric else px * py
-    al = lambda v: (v + 255) // 256 * 256
-    per = {"fp64": (16,), "fp32": (8,), "mixed": (16, 8)}[prec]
-    total = sum(al(nblk * b * b * s) for s in per)
-    if Nr:
-        total += sum(al(Nr * s) for s in per)
-    return total + 256
-
-
-def _grid(n):
-    """Smallest 2, 3, 5, 7-smooth size >= 2n - 1 (the plan's embedding)."""
-    m = 2 * n - 1
-    while True:
-        k = m
-        for f in (2, 3, 5, 7):
-            while k % f == 0:
-                k //= f
-        if k == 1:
-            return m
-        m += 1
+def precond_bytes(Nx, Ny, b, Nr, prec="mixed", symmetric=False, reciprocal=True) -> int:
+    """Device bytes of the block-circulant preconditioner of such a plan (the
+    library's own count, toeplitz_precond_bytes_for), for HBM admission before
+    the plan exists."""
+    n = ctypes.c_size_t(0)
+    sym = (_lib.TP_SYM_RIM if reciprocal else 0) | (_lib.TP_SYM_GEN if symmetric else 0)
+    check(_lib.lib().toeplitz_precond_bytes_for(Nx, Ny, b, Nr, sym, PREC[prec], ctypes.byref(n)))
+    return n.value
 
 
 def _host_c128(a, shape):
@@ -150,11 +132,13 @@ class Plan:
         return t, t.shape[0], t.stride(0) if t.shape[0] > 1 else self.Nt
 
     def matvec(self, x, which=None, out=None, stream=None):
-        """y = Z x on the device (which: 'fp64' for complex128 x, 'fp32' for complex64)."""
+        """y = Z x on the device.  which: 'fp64' (complex128 x, FP64 operator),
+        'fp32' (complex64 x, FP32 operator) or 'mixed' (complex128 x, FP32
+        operator: the inner operator of a mixed solve)."""
         import torch
         if which is None:
             which = "fp64" if x.dtype == torch.complex128 else "fp32"
-        dt = torch.complex128 if which == "fp64" else torch.complex64
+        dt = torch.complex64 if which == "fp32" else torch.complex128
         x2, R, ldx = self._cols(x, dt)
         y = torch.empty((R, self.Nt), dtype=dt, device=x.device) if out is None else out
         y2, Ry, ldy = self._cols(y, dt)
@@ -171,19 +155,21 @@ class Plan:
         L = _lib.lib()
         n = ctypes.c_size_t(0)
         check(L.toeplitz_precond_bytes(self._h, ctypes.byref(n)))
-        self.pbuf = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
-        base = self.pbuf.data_ptr()
+        buf = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        base = buf.data_ptr()
         off = (-base) % 256
         with torch.cuda.device(self.device):
             check(L.toeplitz_precond_create(self._h, ctypes.c_void_p(base + off), n.value, _stream_handle(stream)))
+        self.pbuf = buf           # only now: a refused rebuild keeps the old buffer in use
         return self
 
     def precond_apply(self, x, which=None, stream=None):
-        """y = M^-1 x with the plan's preconditioner (complex128 'fp64' or complex64 'fp32')."""
+        """y = M^-1 x with the plan's preconditioner ('fp64': complex128, 'fp32':
+        complex64, 'mixed': complex128 vectors with the FP32 copy)."""
         import torch
         if which is None:
             which = "fp64" if x.dtype == torch.complex128 else "fp32"
-        dt = torch.complex128 if which == "fp64" else torch.complex64
+        dt = torch.complex64 if which == "fp32" else torch.complex128
         x2, R, ldx = self._cols(x, dt)
         y = torch.empty((R, self.Nt), dtype=dt, device=x.device)
         check(_lib.lib().toeplitz_precond_apply(self._h, PREC[which], ctypes.c_void_p(x2.data_ptr()), ldx,
@@ -197,7 +183,7 @@ class Plan:
         import torch
         if which is None:
             which = "fp64" if x.dtype == torch.complex128 else "fp32"
-        dt = torch.complex128 if which == "fp64" else torch.complex64
+        dt = torch.complex64 if which == "fp32" else torch.complex128
         x2, R, ldx = self._cols(x, dt)
         y = torch.empty((R, self.Nt), dtype=dt, device=x.device)
         ms = (ctypes.c_double * 7)()

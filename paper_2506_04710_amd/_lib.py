@@ -27,7 +27,7 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_last_error", "toeplitz_batch_begin", "toeplitz_batch_admit", "toeplitz_batch_release",
            "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end", "toeplitz_port_smatrix",
            "toeplitz_far_field", "toeplitz_precond_bytes", "toeplitz_precond_create", "toeplitz_precond_apply",
-           "toeplitz_gen_symmetric", "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve")
+           "toeplitz_precond_bytes_for", "toeplitz_gen_symmetric", "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve")
 TP_SYM_RIM, TP_SYM_GEN = 1, 2
 
 
@@ -94,6 +94,7 @@ def lib():
         L.toeplitz_port_smatrix.argtypes = [ci, cl, vp, cl, vp, vp, cd, vp, cl, vp, sz, vp]
         L.toeplitz_far_field.argtypes = [ci, ci, ci, ci, cd, cd, vp, vp, vp, vp, vp, cl, ci, vp, ci, cd, cd, vp, vp]
         L.toeplitz_precond_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.toeplitz_precond_bytes_for.argtypes = [ci, ci, ci, ci, ci, ci, ctypes.POINTER(sz)]
         L.toeplitz_precond_create.argtypes = [vp, vp, sz, vp]
         L.toeplitz_precond_apply.argtypes = [vp, ci, vp, cl, vp, cl, ci, vp]
         L.toeplitz_plan_destroy.argtypes = [vp]
@@ -104,7 +105,7 @@ def lib():
                      "toeplitz_solve", "toeplitz_plan_spectrum", "toeplitz_batch_begin", "toeplitz_batch_admit",
                      "toeplitz_batch_release", "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end",
                      "toeplitz_port_smatrix", "toeplitz_far_field", "toeplitz_precond_bytes",
-                     "toeplitz_precond_create", "toeplitz_precond_apply", "toeplitz_gen_symmetric",
+                     "toeplitz_precond_bytes_for", "toeplitz_precond_create", "toeplitz_precond_apply", "toeplitz_gen_symmetric",
                      "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve"):
             getattr(L, name).restype = ci
         _lib = L

@@ -209,6 +209,25 @@ tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
     if (!dev_buf) return fail(TP_E_INVAL, "dev_buf is NULL");
     if (((uintptr_t)dev_buf) & 255) return fail(TP_E_INVAL, "dev_buf must be 256-byte aligned");
     const int reciprocal = (rim_er == nullptr) ? 1 : 0;
+    {
+        // non-finite operator entries would only surface as a Krylov breakdown
+        // much later; refuse them here (shapes are checked by make_layout
+        // below, so only scan once they are known to be sane)
+        Layout L0;
+        tp_status s0 = make_layout(Nx, Ny, b, Nr, reciprocal ? TP_SYM_RIM : 0, prec, max_rhs, restart, &L0);
+        if (s0 != TP_OK) return s0;
+        const long N = (long)Nx * Ny * b;
+        auto finite = [](const double *a, size_t n) {
+            for (size_t i = 0; i < n; ++i)
+                if (!std::isfinite(a[i])) return false;
+            return true;
+        };
+        if (!finite(gen, 2 * (size_t)(2 * Ny - 1) * (2 * Nx - 1) * b * b))
+            return fail(TP_E_INVAL, "gen holds a non-finite value");
+        if (Nr > 0 && (!finite(rim_re, 2 * (size_t)Nr * N) || !finite(rim_rr, 2 * (size_t)Nr * Nr) ||
+                       (rim_er && !finite(rim_er, 2 * (size_t)Nr * N))))
+            return fail(TP_E_INVAL, "a rim block holds a non-finite value");
+    }
     int gsym = 0;
     toeplitz_gen_symmetric(Nx, Ny, b, gen, &gsym);
     Layout L;
@@ -339,29 +358,42 @@ tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *d) {
     return TP_OK;
 }
 
-tp_status toeplitz_matvec(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int nrhs,
-                          void *hip_stream) {
+// Argument checks shared by the operator and preconditioner applications:
+// element size of the vectors (complex128 for TP_FP64 and TP_MIXED, complex64
+// for TP_FP32), shapes, overlap, and no continuous batch on the plan (its
+// graphs use the same workspace on the plan's own stream).
+static tp_status check_apply(tp_plan p, tp_prec which, const void *x, long ldx, const void *y, long ldy, int nrhs) {
     if (!p) return fail(TP_E_INVAL, "plan is NULL");
     if (!x || !y) return fail(TP_E_INVAL, "x or y is NULL");
+    if (which != TP_FP64 && which != TP_FP32 && which != TP_MIXED)
+        return fail(TP_E_INVAL, "precision must be TP_FP64, TP_FP32 or TP_MIXED");
     if (nrhs < 1 || nrhs > p->max_rhs) return fail(TP_E_INVAL, "nrhs must be in [1, max_rhs]");
     if (ldx < p->Nt || ldy < p->Nt) return fail(TP_E_INVAL, "leading dimension smaller than Nt");
-    const size_t es = which == TP_FP64 ? 16 : 8;
+    const size_t es = which == TP_FP32 ? 8 : 16;
     const char *xa = (const char *)x, *ya = (const char *)y;
     const size_t xb = ((size_t)ldx * (nrhs - 1) + p->Nt) * es, yb = ((size_t)ldy * (nrhs - 1) + p->Nt) * es;
     if (xa < ya + yb && ya < xa + xb) return fail(TP_E_INVAL, "x and y overlap");
+    if (p->batch && solver_batch_active(p)) return fail(TP_E_INVAL, "a continuous batch is active on this plan");
+    if (which != TP_FP64 && !p->G32) return fail(TP_E_UNSUPPORTED, "plan holds no FP32 operator");
+    if (which == TP_FP64 && !p->G64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 operator");
+    return TP_OK;
+}
+
+tp_status toeplitz_matvec(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int nrhs,
+                          void *hip_stream) {
+    tp_status s = check_apply(p, which, x, ldx, y, ldy, nrhs);
+    if (s != TP_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
     hipError_t e;
-    if (which == TP_FP64) {
-        if (!p->G64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 operator");
+    if (which == TP_FP64)
         e = matvec_fp64(p, Cols<const c128>{(const c128 *)x, ldx, nullptr}, Cols<c128>{(c128 *)y, ldy, nullptr},
                         nrhs, st);
-    } else if (which == TP_FP32) {
-        if (!p->G32) return fail(TP_E_UNSUPPORTED, "plan holds no FP32 operator");
+    else if (which == TP_FP32)
         e = matvec_fp32(p, Cols<const c64>{(const c64 *)x, ldx, nullptr}, Cols<c64>{(c64 *)y, ldy, nullptr}, nrhs,
                         st);
-    } else {
-        return fail(TP_E_INVAL, "matvec precision must be TP_FP64 or TP_FP32");
-    }
+    else   // FP32 operator on complex128 vectors: the inner operator of a mixed solve
+        e = matvec_fp32_wide(p, Cols<const c128>{(const c128 *)x, ldx, nullptr}, Cols<c128>{(c128 *)y, ldy, nullptr},
+                             nrhs, st);
     if (e != hipSuccess) return hip_fail(e, "matvec launch");
     return TP_OK;
 }
@@ -385,9 +417,12 @@ tp_status toeplitz_matvec_profile(tp_plan p, tp_prec which, const void *x, long 
         if (which == TP_FP64)
             e = matvec_fp64_timed(p, Cols<const c128>{(const c128 *)x, ldx, nullptr}, Cols<c128>{(c128 *)y, ldy, nullptr},
                                   nrhs, st, ev);
-        else
+        else if (which == TP_FP32)
             e = matvec_fp32_timed(p, Cols<const c64>{(const c64 *)x, ldx, nullptr}, Cols<c64>{(c64 *)y, ldy, nullptr},
                                   nrhs, st, ev);
+        else
+            e = matvec_fp32_wide_timed(p, Cols<const c128>{(const c128 *)x, ldx, nullptr},
+                                       Cols<c128>{(c128 *)y, ldy, nullptr}, nrhs, st, ev);
         if (e == hipSuccess) e = hipEventSynchronize(ev[kMatvecStages]);
         for (int i = 0; i < kMatvecStages && e == hipSuccess; ++i) {
             float ms = 0.f;
@@ -434,26 +469,45 @@ tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void 
     return TP_OK;
 }
 
-static size_t precond_layout(tp_plan p, size_t *s64, size_t *s32, size_t *d64, size_t *d32, size_t *flag) {
-    const size_t P = (size_t)p->kxh * p->Py, bb = (size_t)p->b * p->b;   // stored blocks
+// Preconditioner buffer: the inverted stored spectrum blocks per precision the
+// plan holds, 1 / diag(C) per precision when there is a rim, a status word.
+static size_t precond_layout(size_t nblk, int b, int Nr, bool f64, bool f32, size_t *s64, size_t *s32, size_t *d64,
+                             size_t *d32, size_t *flag) {
+    const size_t bb = (size_t)b * b;
     size_t off = 0;
     auto take = [&](bool on, size_t bytes) {
         const size_t o = off;
         if (on) off += al(bytes);
         return on ? o : (size_t)-1;
     };
-    *s64 = take(p->G64 != nullptr, P * bb * 16);
-    *s32 = take(p->G32 != nullptr, P * bb * 8);
-    *d64 = take(p->G64 != nullptr && p->Nr > 0, (size_t)p->Nr * 16);
-    *d32 = take(p->G32 != nullptr && p->Nr > 0, (size_t)p->Nr * 8);
+    *s64 = take(f64, nblk * bb * 16);
+    *s32 = take(f32, nblk * bb * 8);
+    *d64 = take(f64 && Nr > 0, (size_t)Nr * 16);
+    *d32 = take(f32 && Nr > 0, (size_t)Nr * 8);
     *flag = take(true, 256);
     return off;
+}
+static size_t precond_layout(tp_plan p, size_t *s64, size_t *s32, size_t *d64, size_t *d32, size_t *flag) {
+    return precond_layout((size_t)p->kxh * p->Py, p->b, p->Nr, p->G64 != nullptr, p->G32 != nullptr, s64, s32, d64,
+                          d32, flag);
 }
 
 tp_status toeplitz_precond_bytes(tp_plan p, size_t *bytes) {
     if (!p || !bytes) return fail(TP_E_INVAL, "plan or bytes is NULL");
     size_t a, b, c, d, f;
     *bytes = precond_layout(p, &a, &b, &c, &d, &f);
+    return TP_OK;
+}
+
+tp_status toeplitz_precond_bytes_for(int Nx, int Ny, int b, int Nr, int sym, tp_prec prec, size_t *bytes) {
+    if (!bytes) return fail(TP_E_INVAL, "bytes is NULL");
+    if (sym & ~(TP_SYM_RIM | TP_SYM_GEN)) return fail(TP_E_INVAL, "sym holds unknown bits");
+    if (prec == TP_FP32) return fail(TP_E_UNSUPPORTED, "the preconditioner is built from the FP64 spectrum");
+    Layout L;
+    tp_status s = make_layout(Nx, Ny, b, Nr, sym, prec, 1, 1, &L);
+    if (s != TP_OK) return s;
+    size_t a, c, d, e, f;
+    *bytes = precond_layout((size_t)L.kxh * L.Py, b, Nr, true, prec == TP_MIXED, &a, &c, &d, &e, &f);
     return TP_OK;
 }
 
@@ -468,6 +522,9 @@ tp_status toeplitz_precond_create(tp_plan p, void *dev_buf, size_t dev_bytes, vo
     char *base = static_cast<char *>(dev_buf);
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t nS = (size_t)p->kxh * p->Py * p->b * p->b;
+    // captured solver graphs hold the previous S and D pointers as kernel
+    // arguments: drop them before repointing
+    solver_drop_graphs(p);
     p->has_precond = 0;
     p->S64 = reinterpret_cast<c128 *>(base + o64);
     p->S32 = o32 != (size_t)-1 ? reinterpret_cast<c64 *>(base + o32) : nullptr;
@@ -493,25 +550,22 @@ tp_status toeplitz_precond_apply(tp_plan p, tp_prec which, const void *x, long l
                                  void *hip_stream) {
     if (!p) return fail(TP_E_INVAL, "plan is NULL");
     if (!p->has_precond) return fail(TP_E_INVAL, "the plan has no preconditioner (toeplitz_precond_create)");
-    if (!x || !y) return fail(TP_E_INVAL, "x or y is NULL");
-    if (nrhs < 1 || nrhs > p->max_rhs) return fail(TP_E_INVAL, "nrhs must be in [1, max_rhs]");
-    if (ldx < p->Nt || ldy < p->Nt) return fail(TP_E_INVAL, "leading dimension smaller than Nt");
-    const size_t es = which == TP_FP64 ? 16 : 8;
-    const char *xa = (const char *)x, *ya = (const char *)y;
-    const size_t xb = ((size_t)ldx * (nrhs - 1) + p->Nt) * es, yb = ((size_t)ldy * (nrhs - 1) + p->Nt) * es;
-    if (xa < ya + yb && ya < xa + xb) return fail(TP_E_INVAL, "x and y overlap");
+    tp_status s = check_apply(p, which, x, ldx, y, ldy, nrhs);
+    if (s != TP_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
     hipError_t e;
     if (which == TP_FP64) {
         if (!p->S64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 preconditioner");
         e = precond_fp64(p, Cols<const c128>{(const c128 *)x, ldx, nullptr}, Cols<c128>{(c128 *)y, ldy, nullptr},
                          Cols<const c128>{nullptr, 0, nullptr}, nrhs, st);
-    } else if (which == TP_FP32) {
-        if (!p->S32) return fail(TP_E_UNSUPPORTED, "plan holds no FP32 preconditioner");
-        e = precond_fp32(p, Cols<const c64>{(const c64 *)x, ldx, nullptr}, Cols<c64>{(c64 *)y, ldy, nullptr},
-                         Cols<const c64>{nullptr, 0, nullptr}, nrhs, st);
     } else {
-        return fail(TP_E_INVAL, "precision must be TP_FP64 or TP_FP32");
+        if (!p->S32) return fail(TP_E_UNSUPPORTED, "plan holds no FP32 preconditioner");
+        if (which == TP_FP32)
+            e = precond_fp32(p, Cols<const c64>{(const c64 *)x, ldx, nullptr}, Cols<c64>{(c64 *)y, ldy, nullptr},
+                             Cols<const c64>{nullptr, 0, nullptr}, nrhs, st);
+        else
+            e = precond_fp32_wide(p, Cols<const c128>{(const c128 *)x, ldx, nullptr},
+                                  Cols<c128>{(c128 *)y, ldy, nullptr}, Cols<const c128>{nullptr, 0, nullptr}, nrhs, st);
     }
     if (e != hipSuccess) return hip_fail(e, "preconditioner launch");
     return TP_OK;

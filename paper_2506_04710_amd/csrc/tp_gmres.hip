@@ -26,6 +26,7 @@
 // residual columns (iterative refinement); each inner cycle stops when the
 // estimate drops below inner_tol * ||r||.  Krylov vectors, inner products,
 // norms and the small least-squares problem are FP64 throughout.
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -333,12 +334,17 @@ __device__ __forceinline__ Next transition(const Eng &E, int s, const SlotState 
         const double *pr = E.PR + (long)s * 2 * E.nb;
         const double rr = reduce_d(pr, E.nb, red), vv = reduce_d(pr + E.nb, E.nb, red);
         const double beta = sqrt(rr), vn = sqrt(vv);
-        const double rel = vn > 0 ? beta / vn : (beta > 0 ? INFINITY : 0.0);
+        // a non-finite ||v|| or ||r|| (NaN compares false) decides before rel
+        const bool vbad = !(vv <= DBL_MAX), rbad = !(rr <= DBL_MAX);
+        const double rel = (vbad || rbad) ? INFINITY : vn > 0 ? beta / vn : (beta > 0 ? INFINITY : 0.0);
         nx.S.vnorm = vn;
         nx.S.relres = rel;
         if (!P.first) nx.S.outer = P.outer + 1;
         nx.S.first = 0;
-        if (rel <= C.tol) {
+        if (vbad) {                  // the right-hand side holds NaN or Inf
+            nx.S.phase = PH_DONE;
+            nx.S.status = TP_E_INVAL;
+        } else if (rel <= C.tol) {
             nx.S.phase = PH_DONE;
             nx.S.status = TP_OK;
         } else if (!(rel == rel) || rel == INFINITY) {
@@ -619,9 +625,13 @@ struct BatchEngine {
     long nstep = 0;                  // batch_step calls since batch_begin
 };
 
-void solver_release(tp_plan pl) {
+void solver_drop_graphs(tp_plan pl) {
     for (int i = 0; i < pl->ngraphs; ++i) hipGraphExecDestroy(pl->graphs[i].exec);
     pl->ngraphs = 0;
+}
+
+void solver_release(tp_plan pl) {
+    solver_drop_graphs(pl);
     for (hipEvent_t &e : pl->ev)
         if (e) {
             hipEventDestroy(e);
@@ -845,6 +855,7 @@ tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int 
     }
     if (ret == TP_E_NOCONV) set_error("at least one column missed the tolerance");
     if (ret == TP_E_BREAKDOWN) set_error("Krylov breakdown or non-finite residual");
+    if (ret == TP_E_INVAL) set_error("a right-hand side holds a non-finite value");
     return ret;
 }
 

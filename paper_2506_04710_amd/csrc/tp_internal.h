@@ -20,6 +20,8 @@ hipError_t matvec_fp32_wide(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R,
 constexpr int kMatvecStages = 7;   // rim pass, x DFT, y DFT, product, inverse y, inverse x, rim finish
 hipError_t matvec_fp64_timed(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st, hipEvent_t *ev);
 hipError_t matvec_fp32_timed(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStream_t st, hipEvent_t *ev);
+hipError_t matvec_fp32_wide_timed(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st,
+                                  hipEvent_t *ev);
 hipError_t spectrum_build(tp_plan pl, const c128 *gen_dev, c128 *tmp, hipStream_t st);
 // block-circulant preconditioner: y = base + M^-1 x (base columns optional)
 hipError_t precond_fp64(tp_plan pl, Cols<const c128> x, Cols<c128> y, Cols<const c128> base, int R, hipStream_t st);
@@ -43,6 +45,7 @@ int rim_slab_width(long N);
 // solver (tp_gmres.hip)
 size_t solver_ws_bytes(long Nt, int restart, int max_rhs);
 void solver_release(tp_plan pl);
+void solver_drop_graphs(tp_plan pl);      // captured super-step graphs (they bake operator pointers)
 tp_status solve_run(tp_plan pl, const c128 *v, long ldv, c128 *x, long ldx, int nrhs,
                     const tp_solve_opts &o, tp_solve_info *info, hipStream_t st);
 long solver_max_nt();

@@ -247,6 +247,8 @@ tp_status toeplitz_schur_solve(tp_plan p, tp_plan a, const void *v, long ldv, vo
     if (s != TP_OK) return s;
     if (!p->has_schur) return fail(TP_E_INVAL, "the plan has no rim elimination (toeplitz_schur_create)");
     if (!v || !x || !info) return fail(TP_E_INVAL, "v, x or info is NULL");
+    if ((p->batch && solver_batch_active(p)) || (a->batch && solver_batch_active(a)))
+        return fail(TP_E_INVAL, "a continuous batch is active on one of the plans");
     if (nrhs < 1 || nrhs > p->max_rhs || nrhs > a->max_rhs)
         return fail(TP_E_INVAL, "nrhs must be in [1, max_rhs] of both plans");
     if (ldv < p->Nt || ldx < p->Nt) return fail(TP_E_INVAL, "leading dimension smaller than Nt");

@@ -122,11 +122,47 @@ def test_plan_create_validates_before_device_work(L):
     assert L.toeplitz_plan_create(4, 4, 1, 0, gen, None, None, None, 0, 1, 8, fake, 16, None,
                                   ctypes.byref(h)) == _lib.TP_E_NOMEM
     assert h.value is None
+    # a non-finite generator or rim entry
+    for bad in (float("nan"), float("inf")):
+        g = np.zeros((7, 7, 1, 1), dtype=np.complex128)
+        g[3, 2, 0, 0] = complex(0.0, bad)
+        assert L.toeplitz_plan_create(4, 4, 1, 0, g.ctypes.data_as(ctypes.c_void_p), None, None, None, 0, 1, 8, fake,
+                                      1 << 30, None, ctypes.byref(h)) == _lib.TP_E_INVAL
+        assert b"non-finite" in L.toeplitz_last_error()
+        rim = np.zeros((2, 16), dtype=np.complex128)
+        rim[1, 5] = bad
+        rr = np.eye(2, dtype=np.complex128)
+        ok = np.zeros((7, 7, 1, 1), dtype=np.complex128)
+        assert L.toeplitz_plan_create(4, 4, 1, 2, ok.ctypes.data_as(ctypes.c_void_p),
+                                      rim.ctypes.data_as(ctypes.c_void_p), None, rr.ctypes.data_as(ctypes.c_void_p),
+                                      0, 1, 8, fake, 1 << 30, None, ctypes.byref(h)) == _lib.TP_E_INVAL
+    assert h.value is None
+
+
+def test_precond_bytes_for_matches_layout(L):
+    """The admission size of the preconditioner before a plan exists: the
+    inverted stored spectrum blocks per precision, 1/diag(C) per precision,
+    a status word, each region 256-byte aligned."""
+    from paper_2506_04710_amd import _lib, precond_bytes
+    al = lambda v: (v + 255) // 256 * 256
+    for (Nx, Ny, b, Nr), (px, py) in (((32, 32, 64, 256), (63, 63)), ((9, 9, 96, 72), (18, 18)),
+                                      ((8, 5, 16, 0), (15, 9))):
+        for sym in (False, True):
+            nblk = ((px // 2 + 1) if sym else px) * py
+            for prec, sizes in (("fp64", (16,)), ("mixed", (16, 8))):
+                want = sum(al(nblk * b * b * s) for s in sizes) + (sum(al(Nr * s) for s in sizes) if Nr else 0) + 256
+                assert precond_bytes(Nx, Ny, b, Nr, prec, symmetric=sym) == want, (Nx, Ny, b, Nr, sym, prec)
+    n = ctypes.c_size_t(0)
+    assert L.toeplitz_precond_bytes_for(4, 4, 8, 0, 0, _lib.TP_FP32, ctypes.byref(n)) == _lib.TP_E_UNSUPPORTED
+    assert L.toeplitz_precond_bytes_for(4, 4, 8, 0, 8, _lib.TP_FP64, ctypes.byref(n)) == _lib.TP_E_INVAL
+    assert L.toeplitz_precond_bytes_for(0, 4, 8, 0, 0, _lib.TP_FP64, ctypes.byref(n)) == _lib.TP_E_INVAL
 
 
 def test_null_plan_calls_fail_cleanly(L):
     from paper_2506_04710_amd import _lib
-    assert L.toeplitz_matvec(None, 0, None, 1, None, 1, 1, None) == _lib.TP_E_INVAL
+    for which in (_lib.TP_FP64, _lib.TP_FP32, _lib.TP_MIXED):
+        assert L.toeplitz_matvec(None, which, None, 1, None, 1, 1, None) == _lib.TP_E_INVAL
+        assert L.toeplitz_precond_apply(None, which, None, 1, None, 1, 1, None) == _lib.TP_E_INVAL
     assert L.toeplitz_solve(None, None, 1, None, 1, 1, None, None, None) == _lib.TP_E_INVAL
     assert L.toeplitz_plan_info(None, None) == _lib.TP_E_INVAL
     n = ctypes.c_size_t(0)

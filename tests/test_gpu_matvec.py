@@ -5,10 +5,19 @@ import pytest
 
 import oracle
 from synth import arrays as sa
-from helpers import banner, random_rim_er, rel_err, to_dev
+from helpers import assert_parity, banner, random_rim_er, rel_err, to_dev
 
 pytestmark = pytest.mark.gpu
 TOL64, TOL32 = 1e-10, 1e-5
+TOL = {"fp64": TOL64, "fp32": TOL32, "mixed": TOL32}
+WHICH = ["fp64", "fp32", "mixed"]
+
+
+def _input(X, which):
+    """The exact input a path reads: complex64 vectors for 'fp32'; 'fp64' and
+    'mixed' take complex128 (the mixed path rounds them to FP32 itself, so its
+    comparison against the oracle on the unrounded X includes that rounding)."""
+    return X.astype(np.complex64).astype(np.complex128) if which == "fp32" else X
 
 
 @pytest.fixture(scope="module")
@@ -25,7 +34,7 @@ def _matvec_case(torch, prob, X, rim_er=None, which="fp64", ld_pad=0):
     R = X.shape[0]
     plan = tp.Plan.create(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, rim_er=rim_er,
                           prec="mixed", max_rhs=R, restart=4)
-    dt = torch.complex128 if which == "fp64" else torch.complex64
+    dt = torch.complex64 if which == "fp32" else torch.complex128
     xd = torch.zeros((R, prob.Nt + ld_pad), dtype=dt, device="cuda:0")
     xd[:, :prob.Nt] = to_dev(X, dt)
     yd = torch.zeros((R, prob.Nt + ld_pad), dtype=dt, device="cuda:0")
@@ -46,18 +55,14 @@ CASES = [  # (Nx, Ny, b, Nr, R): ragged b against the 64-lane rows, prime and pa
 
 
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}b{c[2]}r{c[3]}R{c[4]}" for c in CASES])
-@pytest.mark.parametrize("which", ["fp64", "fp32"])
+@pytest.mark.parametrize("which", WHICH)
 def test_matvec_parity(torch_cuda, case, which):
     Nx, Ny, b, Nr, R = case
     banner(f"matvec {which} {case}")
     prob = sa.make_problem(Nx, Ny, b, Nr, 3000 + Nx * 100 + Ny * 10 + b)
-    X = sa.rhs_random(prob, R)
-    if which == "fp32":
-        X = X.astype(np.complex64).astype(np.complex128)     # the exact input the kernel sees
+    X = _input(sa.rhs_random(prob, R), which)
     Y, _ = _matvec_case(torch_cuda, prob, X, which=which, ld_pad=3 if R > 1 else 0)
-    ref = oracle.matvec(prob, X)
-    err = rel_err(Y, ref)
-    assert err <= (TOL64 if which == "fp64" else TOL32), err
+    assert_parity(Y, oracle.matvec(prob, X), TOL[which], N=prob.N, what=f"{which} {case}")
 
 
 def _general_problem(Nx, Ny, b, Nr, seed):
@@ -74,18 +79,16 @@ GENERAL_CASES = [(4, 4, 16, 24, 1), (7, 2, 3, 0, 1), (9, 8, 8, 0, 1), (5, 3, 33,
 
 
 @pytest.mark.parametrize("case", GENERAL_CASES, ids=[f"{c[0]}x{c[1]}b{c[2]}r{c[3]}R{c[4]}" for c in GENERAL_CASES])
-@pytest.mark.parametrize("which", ["fp64", "fp32"])
+@pytest.mark.parametrize("which", WHICH)
 def test_matvec_parity_general_generators(torch_cuda, case, which):
     """Generators without the symmetry: whole spectrum, every kernel path."""
     Nx, Ny, b, Nr, R = case
     banner(f"matvec general generators {which} {case}")
     prob = _general_problem(Nx, Ny, b, Nr, 5000 + Nx * 100 + Ny * 10 + b)
-    X = sa.rhs_random(prob, R)
-    if which == "fp32":
-        X = X.astype(np.complex64).astype(np.complex128)
+    X = _input(sa.rhs_random(prob, R), which)
     Y, plan = _matvec_case(torch_cuda, prob, X, which=which)
     assert plan.info()["half_spectrum"] == 0
-    assert rel_err(Y, oracle.matvec(prob, X)) <= (TOL64 if which == "fp64" else TOL32)
+    assert_parity(Y, oracle.matvec(prob, X), TOL[which], N=prob.N, what=f"{which} {case}")
 
 
 def test_half_spectrum_storage(torch_cuda):
@@ -107,17 +110,16 @@ def test_half_spectrum_storage(torch_cuda):
         gplan.close()
 
 
-@pytest.mark.parametrize("which", ["fp64", "fp32"])
-def test_matvec_nonreciprocal_rim(torch_cuda, which):
-    banner(f"matvec non-reciprocal {which}")
+@pytest.mark.parametrize("R", [1, 2])
+@pytest.mark.parametrize("which", WHICH)
+def test_matvec_nonreciprocal_rim(torch_cuda, which, R):
+    banner(f"matvec non-reciprocal {which} R={R}")
     prob = sa.make_problem(6, 5, 12, 9, 41)
     rim_er = random_rim_er(prob, 5)
-    X = sa.rhs_random(prob, 2)
-    if which == "fp32":
-        X = X.astype(np.complex64).astype(np.complex128)
+    X = _input(sa.rhs_random(prob, R), which)
     Y, _ = _matvec_case(torch_cuda, prob, X, rim_er=rim_er, which=which)
     op = oracle.Operator(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, rim_er)
-    assert rel_err(Y, oracle.matvec(op, X)) <= (TOL64 if which == "fp64" else TOL32)
+    assert_parity(Y, oracle.matvec(op, X), TOL[which], N=prob.N, what=which)
 
 
 def test_matvec_batch_invariant(torch_cuda):
@@ -150,17 +152,15 @@ def test_matvec_batch_invariant_mfma(torch_cuda):
         assert np.array_equal(Yb, Ya[3:21]) and np.array_equal(Yc, Ya[5:21]), which
 
 
-@pytest.mark.parametrize("which", ["fp64", "fp32"])
+@pytest.mark.parametrize("which", WHICH)
 def test_matvec_nonreciprocal_rim_mfma(torch_cuda, which):
     banner(f"matvec non-reciprocal MFMA {which}")
     prob = sa.make_problem(6, 5, 12, 40, 45)
     rim_er = random_rim_er(prob, 6)
-    X = sa.rhs_random(prob, 19)
-    if which == "fp32":
-        X = X.astype(np.complex64).astype(np.complex128)
+    X = _input(sa.rhs_random(prob, 19), which)
     Y, _ = _matvec_case(torch_cuda, prob, X, rim_er=rim_er, which=which)
     op = oracle.Operator(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, rim_er)
-    assert rel_err(Y, oracle.matvec(op, X)) <= (TOL64 if which == "fp64" else TOL32)
+    assert_parity(Y, oracle.matvec(op, X), TOL[which], N=prob.N, what=which)
 
 
 def test_matvec_repeat_bitwise(torch_cuda):
@@ -220,21 +220,77 @@ def test_spectrum_parity_config2_sampled(torch_cuda):
 
 
 @pytest.mark.parametrize("cfg", [2, 3, 4])
-@pytest.mark.parametrize("which", ["fp64", "fp32"])
+@pytest.mark.parametrize("which", WHICH)
 def test_matvec_full_size_sampled(torch_cuda, cfg, which):
-    """Benchmark-size arrays: sampled output rows against the oracle's row sums."""
+    """Benchmark-size arrays with as many columns as the workload (config 3:
+    81, the matrix-core path; config 4: 8), seeded random inputs: sampled
+    output rows (element and rim) against the oracle's row sums."""
     banner(f"matvec full size config {cfg} {which}")
     import paper_2506_04710_amd as tp
     torch = torch_cuda
     prob, V = sa.make_config(cfg)
-    if which == "fp32":
-        V = V.astype(np.complex64).astype(np.complex128)
     R = V.shape[0]
+    X = _input(sa.rhs_random(prob, R, rng=np.random.default_rng(700 + cfg)), which)
     plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=R, restart=4)
-    dt = torch.complex128 if which == "fp64" else torch.complex64
-    Y = plan.matvec(to_dev(V, dt)).cpu().numpy().astype(np.complex128).reshape(R, prob.Nt)
+    dt = torch.complex64 if which == "fp32" else torch.complex128
+    Y = plan.matvec(to_dev(X, dt), which=which).cpu().numpy().astype(np.complex128).reshape(R, prob.Nt)
     rng = np.random.default_rng(cfg)
     rows = np.unique(np.concatenate([[0, prob.N - 1, prob.Nt - 1], rng.integers(0, prob.Nt, 40),
-                                     prob.N + np.arange(min(prob.Nr, 4))]))
-    ref = oracle.matvec(prob, V, rows=rows)
-    assert rel_err(Y[:, rows], ref) <= (TOL64 if which == "fp64" else TOL32)
+                                     prob.N + np.arange(min(prob.Nr, 8))]))
+    ref = oracle.matvec(prob, X, rows=rows)
+    assert_parity(Y[:, rows], ref, TOL[which], N=prob.N, rows=rows, what=f"config {cfg} {which}")
+    plan.close()
+
+
+@pytest.fixture(scope="module")
+def config2_full():
+    """The 32 x 32, b = 64, 256-rim operator on one seeded random input
+    (rounded to complex64, so every path reads the same values) and the
+    oracle's product over all 65,792 rows."""
+    prob, _ = sa.make_config(2)
+    X = sa.rhs_random(prob, 1, rng=np.random.default_rng(7002)).astype(np.complex64).astype(np.complex128)
+    return prob, X, oracle.matvec(prob, X)
+
+
+@pytest.mark.parametrize("which", WHICH)
+def test_matvec_config2_every_row(torch_cuda, config2_full, which):
+    """Headline operator (fused single-column half-spectrum path with the rim
+    pass) checked on every output row, element and rim parts separately."""
+    banner(f"matvec config 2 every row {which}")
+    import paper_2506_04710_amd as tp
+    torch = torch_cuda
+    prob, X, ref = config2_full
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=1, restart=4)
+    dt = torch.complex64 if which == "fp32" else torch.complex128
+    Y = plan.matvec(to_dev(X, dt), which=which).cpu().numpy().astype(np.complex128).reshape(1, prob.Nt)
+    e = assert_parity(Y, ref, TOL[which], N=prob.N, what=f"config 2 {which}")
+    print(f"config 2 {which}: {e}")
+    plan.close()
+
+
+# Arrays with N >= 131072 use rim slabs of 256 columns (4 per lane): the
+# fused single-column launch (b <= 64, half spectrum) and the multi-column
+# rim pass, on seeded random inputs, sampled rows.
+WIDE_SLAB_CASES = [(46, 46, 64, 184, 1), (64, 64, 32, 64, 3)]
+
+
+@pytest.mark.parametrize("case", WIDE_SLAB_CASES, ids=[f"{c[0]}x{c[1]}b{c[2]}r{c[3]}R{c[4]}"
+                                                       for c in WIDE_SLAB_CASES])
+@pytest.mark.parametrize("which", WHICH)
+def test_matvec_wide_rim_slabs(torch_cuda, case, which):
+    Nx, Ny, b, Nr, R = case
+    banner(f"matvec wide rim slabs {which} {case}")
+    import paper_2506_04710_amd as tp
+    torch = torch_cuda
+    prob = sa.make_problem(Nx, Ny, b, Nr, 8000 + Nx + b)
+    assert prob.N >= 131072
+    X = _input(sa.rhs_random(prob, R, rng=np.random.default_rng(Nx * b)), which)
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=R, restart=4)
+    dt = torch.complex64 if which == "fp32" else torch.complex128
+    Y = plan.matvec(to_dev(X, dt), which=which).cpu().numpy().astype(np.complex128).reshape(R, prob.Nt)
+    rng = np.random.default_rng(b)
+    rows = np.unique(np.concatenate([[0, prob.N - 1, prob.Nt - 1], rng.integers(0, prob.N, 40),
+                                     prob.N + rng.integers(0, prob.Nr, 16)]))
+    assert_parity(Y[:, rows], oracle.matvec(prob, X, rows=rows), TOL[which], N=prob.N, rows=rows,
+                  what=f"{which} {case}")
+    plan.close()

@@ -60,17 +60,61 @@ def test_serving_mix_matches_alone(server_cls, mode):
         p = GEOMS[r.key]
         X = np.stack([x.cpu().numpy() for x in r.X])
         assert np.all(oracle.relres(p, X, r.V) <= 1e-8), r.id
-    # the same requests one at a time on a fresh server
+    # The same requests one at a time on a fresh server with the same slot
+    # count: every engine step runs the same kernels on a column whatever
+    # the other slots hold and whichever slot it sits in (per-column sums in
+    # a fixed order), so each result is the same bit for bit.
     alone = server_cls(geometry, slots=6, mode=mode, tol=1e-8, restart=20, hbm_budget=8 << 30)
-    for r in reqs[:6]:
+    for r in reqs[:8]:
         from paper_2506_04710_amd.serve import Request
         r1 = Request(id=r.id, t=0.0, key=r.key, V=r.V)
         alone.run([r1], realtime=False)
         for c in range(r.R):
-            assert rel_err(r1.X[c].cpu().numpy(), r.X[c].cpu().numpy()) <= 1e-6
+            assert np.array_equal(r1.X[c].cpu().numpy(), r.X[c].cpu().numpy()), (r.id, c)
+            assert r1.info[c]["iters"] == r.info[c]["iters"], (r.id, c)
     srv.close()
     alone.close()
     print(f"serving {mode}: {stats}")
+
+
+def test_serving_mix_sample_against_oracle(server_cls):
+    """The serving workload's own geometries (Nx, Ny in {8, ..., 48}, b in
+    {32, 64}, 1-16 ports, mixed + preconditioner, 16 slots): a seeded sample
+    of its request stream, chosen to cover every array size and both b, is
+    served in one run, and the first port column of every request is checked
+    against the oracle's FP64 residual over all rows."""
+    banner("serving mix sample vs oracle")
+    from paper_2506_04710_amd.serve import Request
+    stream = sa.serving_stream(512)
+    pick, seen = [], set()
+    for r in stream:
+        tags = {("n", r["Nx"]), ("n", r["Ny"]), ("b", r["b"])}
+        if not tags <= seen:
+            pick.append(r)
+            seen |= tags
+    assert {t[1] for t in seen if t[0] == "n"} == set(sa.SERVE_SIZES)
+    assert {t[1] for t in seen if t[0] == "b"} == set(sa.SERVE_B)
+    G = {}
+
+    def geom(key):
+        if key not in G:
+            G[key] = sa.serving_geometry(*key)
+        p = G[key]
+        return p.Nx, p.Ny, p.b, p.Nr, p.gen, p.rim_re, p.rim_rr
+
+    reqs = []
+    for i, r in enumerate(pick):
+        key = (r["Nx"], r["Ny"], r["b"])
+        geom(key)
+        reqs.append(Request(id=r["id"], t=0.002 * i, key=key, V=sa.rhs_ports(G[key], r["elements"])))
+    srv = server_cls(geom, slots=16, mode="mixed", tol=1e-8, restart=40, hbm_budget=64 << 30, precond=True)
+    stats = srv.run(reqs, realtime=True)
+    assert stats["all_ok"], stats
+    for r in reqs:
+        rr = oracle.relres(G[r.key], r.X[0].cpu().numpy()[None], r.V[:1])[0]
+        print(f"request {r.id} {r.key} R={r.R}: oracle relres {rr:.2e}, library {r.info[0]['relres']:.2e}")
+        assert rr <= 1e-8, (r.id, r.key, rr)
+    srv.close()
 
 
 def test_serving_hbm_budget_evicts_idle_plans(server_cls):
@@ -121,6 +165,14 @@ def test_batch_api_direct():
     assert L.toeplitz_batch_step(plan._h, 0) == _lib.TP_E_INVAL
     with pytest.raises(_lib.ToeplitzError):
         plan.solve(v)
+    # applications share the engine's workspace: refused while it runs
+    for which in ("fp64", "mixed"):
+        with pytest.raises(_lib.ToeplitzError) as ei:
+            plan.matvec(v, which=which)
+        assert ei.value.status == _lib.TP_E_INVAL
+    with pytest.raises(_lib.ToeplitzError) as ei:
+        plan.precond_create()
+    assert ei.value.status == _lib.TP_E_INVAL
     _lib.check(L.toeplitz_batch_admit(plan._h, 1, vp(v.data_ptr()), vp(x.data_ptr()), 1e-9, 0, sh))
     done = False
     for _ in range(200):

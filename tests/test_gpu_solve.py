@@ -102,19 +102,26 @@ def test_solve_rejects_bad_requests(tp):
 
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
 def test_solve_batch_matches_single(tp, mode):
-    """Independent Krylov spaces: a column solved in a batch matches it solved
-    alone within the tolerance (a single column runs the fused operator path,
-    a batch the multi-column one, so the two agree to rounding, not bitwise)."""
+    """Independent Krylov spaces.  Batches of two or more columns run the same
+    kernels whatever the batch holds, so a column's iterates, and its solution,
+    are the same bit for bit in any such batch.  A single column runs the
+    fused single-column operator, whose sums run in another order: its
+    solution is a different iterate meeting the same tolerance, so the two
+    differ by at most the residual bound ||Z (x1 - xb)|| <= 2 tol ||v||."""
     banner(f"solve batch vs single {mode}")
     prob = sa.make_problem(6, 5, 16, 20, 77)
     V = sa.rhs_random(prob, 4)
     Xb, ib, _ = _solve(tp, prob, V, mode)
     assert np.all(oracle.relres(prob, Xb, V) <= 1e-8)
+    X2, i2, _ = _solve(tp, prob, V[[3, 0]], mode)
+    assert np.array_equal(X2[0], Xb[3]) and np.array_equal(X2[1], Xb[0])
+    assert [i["iters"] for i in i2] == [ib[3]["iters"], ib[0]["iters"]]
     for r in (0, 3):
         X1, i1, _ = _solve(tp, prob, V[r:r + 1], mode)
-        assert abs(i1[0]["iters"] - ib[r]["iters"]) <= 2
         assert oracle.relres(prob, X1, V[r:r + 1])[0] <= 1e-8
-        assert rel_err(X1[0], Xb[r]) <= 1e-7
+        # ||Z (x1 - xb)|| / ||v|| by the oracle's product (v cancels)
+        D = oracle.matvec(prob, X1 - Xb[r:r + 1])
+        assert np.linalg.norm(D) / np.linalg.norm(V[r]) <= 2e-8
 
 
 def test_solve_config3_ports_batched(tp):
@@ -179,8 +186,39 @@ def test_config4_mixed_to_1e10_against_fp64():
     print(f"config 4: mixed iters {[i['iters'] for i in info]} outer {[i['outer_iters'] for i in info]}, "
           f"fp64 iters {[i['iters'] for i in info64]}, max rel diff mixed vs fp64 {max(errs):.2e}")
     assert max(errs) <= 1e-8
-    rows = np.linspace(0, prob.Nt - 1, 64).astype(np.int64)
-    Y = oracle.matvec(prob, X, rows=rows)
-    for r in range(R):
-        assert np.max(np.abs(V[r, rows] - Y[r])) <= 1e-10 * np.linalg.norm(V[r])
+    # the oracle's FP64 residual over all 196,608 rows, for the first and the
+    # last scan angle
+    for r in (0, R - 1):
+        rr = oracle.relres(prob, X[r:r + 1], V[r:r + 1])[0]
+        print(f"config 4 column {r}: oracle relres {rr:.3e}, library {info[r]['relres']:.3e}")
+        assert rr <= 1e-10
+    plan.close()
+
+
+def test_solve_nonfinite_rhs_stops():
+    """A right-hand side holding NaN or Inf ends its column at the first
+    residual with TP_E_INVAL; a finite column in the same call still solves."""
+    banner("solve non-finite right-hand side")
+    import ctypes
+    import torch
+    import paper_2506_04710_amd as tp
+    from paper_2506_04710_amd import _lib
+    prob, V = sa.make_config(1)
+    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=3, restart=40)
+    V3 = np.vstack([V, V, V])
+    V3[1, 7] = np.nan
+    V3[2, 3] = np.inf
+    v = to_dev(V3)
+    x = torch.empty_like(v)
+    o = _lib.SolveOpts()
+    _lib.lib().toeplitz_solve_opts_default(ctypes.byref(o))
+    o.mode = _lib.PREC["mixed"]
+    info = (_lib.SolveInfo * 3)()
+    st = _lib.lib().toeplitz_solve(plan._h, ctypes.c_void_p(v.data_ptr()), prob.Nt, ctypes.c_void_p(x.data_ptr()),
+                                   prob.Nt, 3, ctypes.byref(o), info, None)
+    assert st == _lib.TP_E_INVAL
+    assert info[0].status == 0 and info[0].relres <= 1e-8
+    assert info[1].status == _lib.TP_E_INVAL and info[1].iters == 0
+    assert info[2].status == _lib.TP_E_INVAL and info[2].iters == 0
+    assert oracle.relres(prob, x[:1].cpu().numpy(), V)[0] <= 1e-8
     plan.close()
