@@ -159,6 +159,29 @@ tp_status toeplitz_matvec(tp_plan p, tp_prec which, const void *x, long ldx, voi
                           int nrhs, void *hip_stream);
 
 /*
+ * For callers that cannot allocate or hand over workspace (code under HIP graph
+ * capture, serving loops that forbid allocation): the same y = Z x as
+ * toeplitz_matvec, same arguments, checks and kernels, but the transform grids,
+ * rim slab partial sums and mirror parts live in a static device array of
+ * toeplitz_static_scratch_bytes() bytes (64 MiB) that the library holds on each
+ * device it runs on until the process ends, not in the plan's workspace.  The
+ * call allocates nothing.  The workspace one call needs is
+ * 2 * max(Ny*Px, Px*Py) * b * nrhs * 16 bytes of grids, plus
+ * nslab * max(Nr, 1) * nrhs * 16 bytes of rim partials, plus, for a half
+ * spectrum, (b/8) * Ny * (Px - kxh) * b * 16 bytes of mirror parts (each rounded
+ * up to 256 bytes); a call that needs more returns TP_E_INVAL before any device
+ * work.  Every call on a device shares that device's array and leaves its last
+ * contents there: calls that overlap in time on one device (on any streams,
+ * from any threads or plans) race and give wrong results; order them on one
+ * stream.  The device of p must be current.
+ * Errors: as toeplitz_matvec, plus TP_E_INVAL for a workspace beyond the limit.
+ */
+tp_status toeplitz_matvec_static(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy,
+                                 int nrhs, void *hip_stream);
+/* Size in bytes of the static workspace of toeplitz_matvec_static. */
+size_t toeplitz_static_scratch_bytes(void);
+
+/*
  * Instrumentation: run the operator application of toeplitz_matvec `reps`
  * times on hip_stream with HIP events between its kernels and write the mean
  * duration in milliseconds of each stage to stage_ms[7]: 0 rim pass over B,

@@ -148,6 +148,24 @@ class Plan:
                                          ctypes.c_void_p(y2.data_ptr()), ldy, R, _stream_handle(stream)))
         return y.reshape(x.shape) if out is None else out
 
+    def matvec_static(self, x, which=None, out=None, stream=None):
+        """y = Z x like matvec, through toeplitz_matvec_static: the workspace is
+        the library's static device array (no allocation by the library; calls
+        that overlap in time on one device race)."""
+        import torch
+        if which is None:
+            which = "fp64" if x.dtype == torch.complex128 else "fp32"
+        dt = torch.complex64 if which == "fp32" else torch.complex128
+        x2, R, ldx = self._cols(x, dt)
+        y = torch.empty((R, self.Nt), dtype=dt, device=x.device) if out is None else out
+        y2, Ry, ldy = self._cols(y, dt)
+        if Ry != R:
+            raise ValueError("out has a different number of columns")
+        with torch.cuda.device(x.device):
+            check(_lib.lib().toeplitz_matvec_static(self._h, PREC[which], ctypes.c_void_p(x2.data_ptr()), ldx,
+                                                    ctypes.c_void_p(y2.data_ptr()), ldy, R, _stream_handle(stream)))
+        return y.reshape(x.shape) if out is None else out
+
     def precond_create(self, stream=None):
         """Build the block-circulant preconditioner into a second device buffer
         owned by this plan object (needs an FP64 or mixed plan)."""

@@ -27,7 +27,8 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_last_error", "toeplitz_batch_begin", "toeplitz_batch_admit", "toeplitz_batch_release",
            "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end", "toeplitz_port_smatrix",
            "toeplitz_far_field", "toeplitz_precond_bytes", "toeplitz_precond_create", "toeplitz_precond_apply",
-           "toeplitz_precond_bytes_for", "toeplitz_gen_symmetric", "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve")
+           "toeplitz_precond_bytes_for", "toeplitz_gen_symmetric", "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve",
+           "toeplitz_matvec_static", "toeplitz_static_scratch_bytes")
 TP_SYM_RIM, TP_SYM_GEN = 1, 2
 
 
@@ -78,6 +79,9 @@ def lib():
                                            ctypes.POINTER(vp)]
         L.toeplitz_plan_info.argtypes = [vp, ctypes.POINTER(PlanDesc)]
         L.toeplitz_matvec.argtypes = [vp, ci, vp, cl, vp, cl, ci, vp]
+        L.toeplitz_matvec_static.argtypes = [vp, ci, vp, cl, vp, cl, ci, vp]
+        L.toeplitz_static_scratch_bytes.argtypes = []
+        L.toeplitz_static_scratch_bytes.restype = sz
         L.toeplitz_matvec_profile.argtypes = [vp, ci, vp, cl, vp, cl, ci, ci, vp, ctypes.POINTER(ctypes.c_double)]
         L.toeplitz_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
         L.toeplitz_solve_opts_default.restype = None
@@ -106,7 +110,8 @@ def lib():
                      "toeplitz_batch_release", "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end",
                      "toeplitz_port_smatrix", "toeplitz_far_field", "toeplitz_precond_bytes",
                      "toeplitz_precond_bytes_for", "toeplitz_precond_create", "toeplitz_precond_apply", "toeplitz_gen_symmetric",
-                     "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve"):
+                     "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve",
+           "toeplitz_matvec_static", "toeplitz_static_scratch_bytes"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib

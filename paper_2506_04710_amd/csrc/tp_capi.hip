@@ -358,11 +358,15 @@ tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *d) {
     return TP_OK;
 }
 
+}  // extern "C"
+
+namespace tp {
+
 // Argument checks shared by the operator and preconditioner applications:
 // element size of the vectors (complex128 for TP_FP64 and TP_MIXED, complex64
 // for TP_FP32), shapes, overlap, and no continuous batch on the plan (its
 // graphs use the same workspace on the plan's own stream).
-static tp_status check_apply(tp_plan p, tp_prec which, const void *x, long ldx, const void *y, long ldy, int nrhs) {
+tp_status check_apply(tp_plan p, tp_prec which, const void *x, long ldx, const void *y, long ldy, int nrhs) {
     if (!p) return fail(TP_E_INVAL, "plan is NULL");
     if (!x || !y) return fail(TP_E_INVAL, "x or y is NULL");
     if (which != TP_FP64 && which != TP_FP32 && which != TP_MIXED)
@@ -378,6 +382,10 @@ static tp_status check_apply(tp_plan p, tp_prec which, const void *x, long ldx, 
     if (which == TP_FP64 && !p->G64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 operator");
     return TP_OK;
 }
+
+}  // namespace tp
+
+extern "C" {
 
 tp_status toeplitz_matvec(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int nrhs,
                           void *hip_stream) {

@@ -12,6 +12,9 @@ void set_error(const std::string &msg);
 tp_status fail(tp_status s, const std::string &msg);
 tp_status hip_fail(hipError_t e, const char *what);
 
+// argument checks of an operator or preconditioner application (tp_capi.hip)
+tp_status check_apply(tp_plan p, tp_prec which, const void *x, long ldx, const void *y, long ldy, int nrhs);
+
 // operator application (tp_matvec.h; instances in tp_apply_f64/f32/wide.hip)
 hipError_t matvec_fp64(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st);
 hipError_t matvec_fp32(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStream_t st);
