@@ -66,6 +66,8 @@ typedef struct {
     size_t total_bytes;      /* == toeplitz_plan_bytes() */
     int reciprocal;          /* 1 if the element-rim block is rim_re transposed */
     int half_spectrum;       /* 1 if the generators are symmetric and half the spectrum is stored */
+    int nrc;                 /* rim channels per cell of a placed rim (toeplitz_plan_create_placed), else 0 */
+    int bc;                  /* channels per cell of the transforms and spectrum blocks: b + nrc */
 } tp_plan_desc;
 
 /*
@@ -133,6 +135,47 @@ tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
                                const double *rim_re, const double *rim_er, const double *rim_rr,
                                tp_prec prec, int max_rhs, int restart, void *dev_buf,
                                size_t dev_bytes, void *hip_stream, tp_plan *out);
+
+/*
+ * Structured rim (the margin decomposition of Sec. II-B and the one-level
+ * block-Toeplitz rim blocks of eqs. submatrixB12, submatrixB34, submatrixC123,
+ * submatrixC456): every rim function belongs to a margin part that repeats by
+ * translation with the elements, so it can be pinned to an element cell with
+ * a fixed local offset.  Then every coupling of Z, rim included, depends only
+ * on the difference of the two cells, and Z is the restriction, to the
+ * occupied (cell, channel) pairs, of one two-level block-Toeplitz operator with
+ * bc = b + nrc channels per cell.  A placed plan stores the spectrum of that
+ * operator (no dense B or C) and applies the whole of Z with the element
+ * kernels: the embedding scatters x_r into the rim channels of their cells and
+ * the crop gathers y_r from them.
+ *
+ * toeplitz_plan_bytes_placed: as toeplitz_plan_bytes for a placed rim with
+ *   nrc >= 1 rim channels per cell (TP_SYM_GEN when the extended generators
+ *   are symmetric, which holds for symmetric generators with a reciprocal rim
+ *   and a symmetric rim_rr).
+ * toeplitz_plan_create_placed: as toeplitz_plan_create, plus
+ *   rim_place  host int [Nr][3]: rim function r sits at element cell
+ *              (rim_place[r][0], rim_place[r][1]) in [0, Nx) x [0, Ny) as
+ *              channel b + rim_place[r][2], rim_place[r][2] in [0, nrc); no
+ *              two functions share a cell and channel.  (A margin part outside
+ *              the cell range is placed at the nearest cell: its whole
+ *              component moves with it, which changes no coupling.)
+ *   The extended generators are assembled on the host from gen, rim_re,
+ *   rim_er (or rim_re transposed) and rim_rr; every entry must receive the same
+ *   value, bit for bit, from every pair of rim/element functions whose cells
+ *   have that offset.  Errors: as toeplitz_plan_create, plus TP_E_INVAL when
+ *   the placement is out of range or shared, or the rim blocks are not block
+ *   Toeplitz in it (checked before any device work).  A placed plan has no
+ *   rim elimination (toeplitz_schur_* return TP_E_UNSUPPORTED); its
+ *   preconditioner inverts the extended spectrum blocks, rim channels included.
+ */
+tp_status toeplitz_plan_bytes_placed(int Nx, int Ny, int b, int Nr, int nrc, int sym, tp_prec prec,
+                                     int max_rhs, int restart, size_t *bytes);
+tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const double *gen,
+                                      const double *rim_re, const double *rim_er, const double *rim_rr,
+                                      const int *rim_place, int nrc, tp_prec prec, int max_rhs,
+                                      int restart, void *dev_buf, size_t dev_bytes, void *hip_stream,
+                                      tp_plan *out);
 
 /* Copy the plan's layout facts into *desc. */
 tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *desc);
@@ -308,8 +351,10 @@ tp_status toeplitz_schur_solve(tp_plan p, tp_plan a, const void *v, long ldv, vo
                                const tp_solve_opts *opts, tp_solve_info *info, void *hip_stream);
 
 /*
- * Copy one block of the stored spectrum to the host (the b x b matrix at
- * frequency (kx, ky), row-major; complex128 for TP_FP64, complex64 for TP_FP32).
+ * Copy one block of the stored spectrum to the host (the bc x bc matrix at
+ * frequency (kx, ky), row-major, bc = b, or b + nrc for a placed rim (the
+ * extended generators); host_out holds bc * bc complex128 for TP_FP64,
+ * complex64 for TP_FP32).
  * It equals (1/(Px Py)) sum_{m,n} Z_{m,n} exp(-2 pi i (kx m / Px + ky n / Py)).
  * Synchronous.  Errors: TP_E_INVAL, TP_E_UNSUPPORTED, TP_E_HIP.
  */

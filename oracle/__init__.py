@@ -232,6 +232,58 @@ def precond_apply(op, X, Px, Py) -> np.ndarray:
     return Y
 
 
+def placed_generator(op, place, nrc) -> np.ndarray:
+    """Generators of the structured rim (Sec. II-B margin parts, one-level
+    block-Toeplitz rim blocks of eqs. submatrixB12/B34/C123/C456): unknown i
+    sits at a cell (cx_i, cy_i) as channel ch_i (element basis p of element
+    (ix, iy): cell (ix, iy), channel p; rim function r: cell place[r][0:2],
+    channel b + place[r][2]).  The result gext [2Ny-1, 2Nx-1, b+nrc, b+nrc]
+    holds, at offset (m, n) and channels (p, q), the entry Z[i, j] of every
+    pair with cell_i - cell_j = (m, n), ch_i = p, ch_j = q (read off the
+    assembled Z); offsets and channels no pair reaches stay zero.  Raises
+    ValueError when two such pairs disagree (Z is then not the restriction
+    of a block-Toeplitz operator in this placement)."""
+    op = _op(op)
+    Nx, Ny, b, Nr, N = op.Nx, op.Ny, op.b, op.Nr, op.N
+    bc = b + nrc
+    place = np.asarray(place, dtype=np.int64).reshape(Nr, 3)
+    e = np.arange(N) // b
+    cx = np.concatenate([e % Nx, place[:, 0]])
+    cy = np.concatenate([e // Nx, place[:, 1]])
+    ch = np.concatenate([np.arange(N) % b, b + place[:, 2]])
+    Z = assemble(op)
+    m = cx[:, None] - cx[None, :] + (Nx - 1)
+    n = cy[:, None] - cy[None, :] + (Ny - 1)
+    flat = ((n * (2 * Nx - 1) + m) * bc + ch[:, None]) * bc + ch[None, :]
+    gext = np.zeros((2 * Ny - 1) * (2 * Nx - 1) * bc * bc, dtype=np.complex128)
+    gext[flat.ravel()] = Z.ravel()
+    if not np.array_equal(gext[flat.ravel()].view(np.uint64), Z.ravel().view(np.uint64)):
+        raise ValueError("Z is not block Toeplitz in this placement")
+    return gext.reshape(2 * Ny - 1, 2 * Nx - 1, bc, bc)
+
+
+def placed_precond_apply(op, X, place, nrc, Px, Py) -> np.ndarray:
+    """The block-circulant preconditioner of a structured-rim plan: with
+    gext = placed_generator(op, place, nrc), crop(C_P^-1 pad(x)) where pad puts
+    every unknown of x at its cell and channel on the Px x Py torus (zeros
+    elsewhere), C_P is the block circulant of gext (circulant_matrix) and crop
+    reads every unknown back from its cell and channel."""
+    op = _op(op)
+    X = _c128(np.atleast_2d(X))
+    R = X.shape[0]
+    Nx, Ny, b, Nr, N = op.Nx, op.Ny, op.b, op.Nr, op.N
+    bc = b + nrc
+    place = np.asarray(place, dtype=np.int64).reshape(Nr, 3)
+    ext = Operator(Nx, Ny, bc, 0, placed_generator(op, place, nrc))
+    e = np.arange(N) // b
+    slot = np.concatenate([((e // Nx) * Px + e % Nx) * bc + np.arange(N) % b,
+                           (place[:, 1] * Px + place[:, 0]) * bc + b + place[:, 2]])
+    rhs = np.zeros((R, Px * Py * bc), dtype=np.complex128)
+    rhs[:, slot] = X
+    Zg = lu_solve(circulant_matrix(ext, Px, Py), rhs)
+    return Zg[:, slot]
+
+
 def max_threads() -> int:
     return int(_lib().orc_max_threads())
 

@@ -21,7 +21,7 @@ import numpy as np
 from . import _lib
 from ._lib import PREC, ToeplitzError, check  # noqa: F401
 
-__all__ = ["Plan", "plan_bytes", "precond_bytes", "gen_symmetric", "port_smatrix", "far_field", "ToeplitzError",
+__all__ = ["Plan", "plan_bytes", "plan_bytes_placed", "precond_bytes", "gen_symmetric", "port_smatrix", "far_field", "ToeplitzError",
            "load"]
 
 
@@ -38,6 +38,29 @@ def plan_bytes(Nx, Ny, b, Nr, prec="mixed", max_rhs=1, restart=40, reciprocal=Tr
     sym = (_lib.TP_SYM_RIM if reciprocal else 0) | (_lib.TP_SYM_GEN if symmetric else 0)
     check(_lib.lib().toeplitz_plan_bytes(Nx, Ny, b, Nr, sym, PREC[prec], max_rhs, restart, ctypes.byref(n)))
     return n.value
+
+
+def plan_bytes_placed(Nx, Ny, b, Nr, nrc, prec="mixed", max_rhs=1, restart=40, reciprocal=True,
+                      symmetric=False) -> int:
+    """Device bytes of a plan with a placed rim of nrc channels per cell;
+    symmetric: the extended generators are symmetric (symmetric generators,
+    reciprocal rim, symmetric rim_rr)."""
+    n = ctypes.c_size_t(0)
+    sym = (_lib.TP_SYM_RIM if reciprocal else 0) | (_lib.TP_SYM_GEN if symmetric else 0)
+    check(_lib.lib().toeplitz_plan_bytes_placed(Nx, Ny, b, Nr, nrc, sym, PREC[prec], max_rhs, restart,
+                                                ctypes.byref(n)))
+    return n.value
+
+
+def placed_symmetric(gen_sym, rim_er, rim_rr) -> bool:
+    """Whether a placed plan's extended generators are symmetric (so that it
+    keeps half the spectrum): symmetric element generators, a reciprocal rim
+    (rim_er None) and rim_rr equal to its transpose bit for bit."""
+    if not gen_sym or rim_er is not None:
+        return False
+    rr = np.ascontiguousarray(rim_rr, dtype=np.complex128)
+    bits = rr.view(np.uint64).reshape(rr.shape[0], rr.shape[1], 2)
+    return bool(np.array_equal(bits, bits.transpose(1, 0, 2)))
 
 
 def gen_symmetric(Nx, Ny, b, gen) -> bool:
@@ -83,7 +106,10 @@ class Plan:
 
     @classmethod
     def create(cls, Nx, Ny, b, Nr, gen, rim_re=None, rim_rr=None, rim_er=None, prec="mixed", max_rhs=1,
-               restart=40, device="cuda:0", stream=None):
+               restart=40, device="cuda:0", stream=None, rim_place=None):
+        """rim_place: None (dense rim blocks), or (place, nrc) for a placed rim:
+        place an int array [Nr, 3] of (cell x, cell y, channel), nrc the rim
+        channels per cell (toeplitz_plan_create_placed)."""
         import torch
         L = _lib.lib()
         N = Nx * Ny * b
@@ -91,8 +117,15 @@ class Plan:
         rim_re = _host_c128(rim_re, (Nr, N)) if Nr else None
         rim_rr = _host_c128(rim_rr, (Nr, Nr)) if Nr else None
         rim_er = _host_c128(rim_er, (N, Nr)) if (Nr and rim_er is not None) else None
-        nbytes = plan_bytes(Nx, Ny, b, Nr, prec, max_rhs, restart, reciprocal=rim_er is None,
-                            symmetric=gen_symmetric(Nx, Ny, b, gen))
+        gsym = gen_symmetric(Nx, Ny, b, gen)
+        if rim_place is not None:
+            place = np.ascontiguousarray(rim_place[0], dtype=np.int32).reshape(Nr, 3)
+            nrc = int(rim_place[1])
+            xsym = placed_symmetric(gsym, rim_er, rim_rr)
+            nbytes = plan_bytes_placed(Nx, Ny, b, Nr, nrc, prec, max_rhs, restart, reciprocal=rim_er is None,
+                                       symmetric=xsym)
+        else:
+            nbytes = plan_bytes(Nx, Ny, b, Nr, prec, max_rhs, restart, reciprocal=rim_er is None, symmetric=gsym)
         self = cls()
         self.device = torch.device(device)
         self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -101,9 +134,15 @@ class Plan:
         h = ctypes.c_void_p()
         ptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
         with torch.cuda.device(self.device):
-            check(L.toeplitz_plan_create(Nx, Ny, b, Nr, ptr(gen), ptr(rim_re), ptr(rim_er), ptr(rim_rr),
-                                         PREC[prec], max_rhs, restart, ctypes.c_void_p(base + off), nbytes,
-                                         _stream_handle(stream), ctypes.byref(h)))
+            if rim_place is not None:
+                check(L.toeplitz_plan_create_placed(Nx, Ny, b, Nr, ptr(gen), ptr(rim_re), ptr(rim_er), ptr(rim_rr),
+                                                    ptr(place), nrc, PREC[prec], max_rhs, restart,
+                                                    ctypes.c_void_p(base + off), nbytes, _stream_handle(stream),
+                                                    ctypes.byref(h)))
+            else:
+                check(L.toeplitz_plan_create(Nx, Ny, b, Nr, ptr(gen), ptr(rim_re), ptr(rim_er), ptr(rim_rr),
+                                             PREC[prec], max_rhs, restart, ctypes.c_void_p(base + off), nbytes,
+                                             _stream_handle(stream), ctypes.byref(h)))
         self._h = h
         self.Nx, self.Ny, self.b, self.Nr = Nx, Ny, b, Nr
         self.N, self.Nt = N, N + Nr
@@ -283,7 +322,8 @@ class Plan:
 
     def spectrum(self, kx, ky, which="fp64") -> np.ndarray:
         dt = np.complex128 if which == "fp64" else np.complex64
-        out = np.empty((self.b, self.b), dtype=dt)
+        bc = self.info()["bc"]               # channels per cell (b, plus a placed rim's)
+        out = np.empty((bc, bc), dtype=dt)
         check(_lib.lib().toeplitz_plan_spectrum(self._h, PREC[which], kx, ky, out.ctypes.data_as(ctypes.c_void_p)))
         return out
 

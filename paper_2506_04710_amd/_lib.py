@@ -28,7 +28,8 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_batch_step", "toeplitz_batch_poll", "toeplitz_batch_end", "toeplitz_port_smatrix",
            "toeplitz_far_field", "toeplitz_precond_bytes", "toeplitz_precond_create", "toeplitz_precond_apply",
            "toeplitz_precond_bytes_for", "toeplitz_gen_symmetric", "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve",
-           "toeplitz_matvec_static", "toeplitz_static_scratch_bytes")
+           "toeplitz_matvec_static", "toeplitz_static_scratch_bytes", "toeplitz_plan_bytes_placed",
+           "toeplitz_plan_create_placed")
 TP_SYM_RIM, TP_SYM_GEN = 1, 2
 
 
@@ -38,7 +39,8 @@ class PlanDesc(ctypes.Structure):
                 ("max_rhs", ctypes.c_int), ("restart", ctypes.c_int), ("prec", ctypes.c_int),
                 ("spectrum_bytes", ctypes.c_size_t), ("rim_bytes", ctypes.c_size_t),
                 ("workspace_bytes", ctypes.c_size_t), ("total_bytes", ctypes.c_size_t),
-                ("reciprocal", ctypes.c_int), ("half_spectrum", ctypes.c_int)]
+                ("reciprocal", ctypes.c_int), ("half_spectrum", ctypes.c_int), ("nrc", ctypes.c_int),
+                ("bc", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -77,6 +79,9 @@ def lib():
                                            ctypes.POINTER(SolveInfo), vp]
         L.toeplitz_plan_create.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, ci, ci, ci, vp, sz, vp,
                                            ctypes.POINTER(vp)]
+        L.toeplitz_plan_bytes_placed.argtypes = [ci, ci, ci, ci, ci, ci, ci, ci, ci, ctypes.POINTER(sz)]
+        L.toeplitz_plan_create_placed.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, ci, ci, ci, ci, vp, sz, vp,
+                                                  ctypes.POINTER(vp)]
         L.toeplitz_plan_info.argtypes = [vp, ctypes.POINTER(PlanDesc)]
         L.toeplitz_matvec.argtypes = [vp, ci, vp, cl, vp, cl, ci, vp]
         L.toeplitz_matvec_static.argtypes = [vp, ci, vp, cl, vp, cl, ci, vp]

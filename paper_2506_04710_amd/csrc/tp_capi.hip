@@ -97,9 +97,11 @@ static bool overflow_mul(size_t a, size_t b, size_t *out) {
     return false;
 }
 
-// sym: TP_SYM_RIM (one dense rim block) | TP_SYM_GEN (half the spectrum)
-static tp_status make_layout(int Nx, int Ny, int b, int Nr, int sym, tp_prec prec, int max_rhs, int restart,
-                             Layout *L) {
+// sym: TP_SYM_RIM (one dense rim block) | TP_SYM_GEN (half the spectrum).
+// nrc > 0: a placed rim (the rim functions are nrc extra channels of the
+// element cells, no dense rim blocks); 0: dense rim blocks.
+static tp_status make_layout(int Nx, int Ny, int b, int Nr, int nrc, int sym, tp_prec prec, int max_rhs,
+                             int restart, Layout *L) {
     const bool reciprocal = (sym & TP_SYM_RIM) != 0, half = (sym & TP_SYM_GEN) != 0;
     if (Nx < 1 || Ny < 1 || b < 1 || Nr < 0 || max_rhs < 1 || restart < 1)
         return fail(TP_E_INVAL, "Nx, Ny, b, max_rhs, restart must be >= 1 and Nr >= 0");
@@ -107,19 +109,23 @@ static tp_status make_layout(int Nx, int Ny, int b, int Nr, int sym, tp_prec pre
     if (Nx > 256 || Ny > 256) return fail(TP_E_INVAL, "Nx and Ny are limited to 256 (transform length <= 512)");
     if (b > 256) return fail(TP_E_INVAL, "b is limited to 256");
     if (Nr > 2048) return fail(TP_E_INVAL, "Nr is limited to 2048");
+    if (nrc < 0 || (nrc > 0 && Nr < 1)) return fail(TP_E_INVAL, "rim channels need nrc >= 0 and, if nrc > 0, Nr >= 1");
+    if (b + nrc > 256) return fail(TP_E_INVAL, "b + nrc is limited to 256");
+    const int bc = b + nrc;                    // channels per cell
+    const bool dense_rim = Nr > 0 && nrc == 0;
     if (restart > 512) return fail(TP_E_INVAL, "restart is limited to 512");
     L->Px = choose_grid(Nx);
     L->Py = choose_grid(Ny);
     if (L->Px > kMaxP || L->Py > kMaxP) return fail(TP_E_INVAL, "transform length exceeds 512");
     const size_t N = (size_t)Nx * Ny * b, Nt = N + Nr, P = (size_t)L->Px * L->Py;
-    const size_t bb = (size_t)b * b;
+    const size_t bb = (size_t)bc * bc;
     // half spectrum: columns kx <= Px / 2 (Ghat(-k) = Ghat(k)^T)
     L->kxh = half ? L->Px / 2 + 1 : L->Px;
     const size_t nblk = (size_t)L->kxh * L->Py;
     size_t t;
     if (overflow_mul(nblk, bb, &t) || overflow_mul(t, 16, &L->spec1)) return fail(TP_E_INVAL, "size overflow");
     const size_t nrim = reciprocal ? 1 : 2;
-    L->rim1 = (nrim * (size_t)Nr * N + (size_t)Nr * Nr) * 16;
+    L->rim1 = dense_rim ? (nrim * (size_t)Nr * N + (size_t)Nr * Nr) * 16 : 0;
     const bool f64 = prec != TP_FP32, f32 = prec != TP_FP64;
     size_t off = 0;
     auto take = [&](bool present, size_t bytes) -> size_t {
@@ -130,27 +136,29 @@ static tp_status make_layout(int Nx, int Ny, int b, int Nr, int sym, tp_prec pre
     };
     L->G64 = take(f64, L->spec1);
     L->G32 = take(f32, L->spec1 / 2);
-    L->B64 = take(f64 && Nr, (size_t)Nr * N * 16);
-    L->BE64 = take(f64 && Nr && !reciprocal, (size_t)Nr * N * 16);
-    L->C64 = take(f64 && Nr, (size_t)Nr * Nr * 16);
-    L->B32 = take(f32 && Nr, (size_t)Nr * N * 8);
-    L->BE32 = take(f32 && Nr && !reciprocal, (size_t)Nr * N * 8);
-    L->C32 = take(f32 && Nr, (size_t)Nr * Nr * 8);
+    L->B64 = take(f64 && dense_rim, (size_t)Nr * N * 16);
+    L->BE64 = take(f64 && dense_rim && !reciprocal, (size_t)Nr * N * 16);
+    L->C64 = take(f64 && dense_rim, (size_t)Nr * Nr * 16);
+    L->B32 = take(f32 && dense_rim, (size_t)Nr * N * 8);
+    L->BE32 = take(f32 && dense_rim && !reciprocal, (size_t)Nr * N * 8);
+    L->C32 = take(f32 && dense_rim, (size_t)Nr * Nr * 8);
+    // tables: digit reversals, twiddles (FP64, FP32), the rim channel map
     const size_t tab_bytes = al((size_t)(L->Px + L->Py) * 4) + al((size_t)(L->Px + L->Py) * 16) +
-                             al((size_t)(L->Px + L->Py) * 8);
+                             al((size_t)(L->Px + L->Py) * 8) + al((size_t)Nx * Ny * nrc * 4);
     L->tab = take(true, tab_bytes);
     // workspace: two transform grids, rim partial sums, Krylov storage
     const size_t gpts = std::max((size_t)Ny * L->Px, P);
-    L->grid_bytes = al(gpts * (size_t)b * max_rhs * 16);
+    L->grid_bytes = al(gpts * (size_t)bc * max_rhs * 16);
     L->rim_te = rim_slab_width((long)N);
     L->rim_nslab = (int)((N + L->rim_te - 1) / L->rim_te);
-    L->rimpart_bytes = al((size_t)L->rim_nslab * (Nr ? Nr : 1) * max_rhs * 16);
+    L->rimpart_bytes = dense_rim ? al((size_t)L->rim_nslab * Nr * max_rhs * 16) : al(16);
     // single-column half-spectrum path: mirror parts per row chunk of 8
-    L->ypart_bytes = half ? al((size_t)((b + 7) / 8) * Ny * (L->Px - L->kxh) * b * 16) : 0;
+    L->ypart_bytes = half ? al((size_t)((bc + 7) / 8) * Ny * (L->Px - L->kxh) * bc * 16) : 0;
     L->solver_bytes = al(solver_ws_bytes((long)Nt, restart, max_rhs));
     // plan-time scratch: device copy of the generators + the x-transformed rows
+    // (+ a staging copy of one dense rim block)
     L->scratch_bytes = al((size_t)(2 * Ny - 1) * (2 * Nx - 1) * bb * 16) + al((size_t)(2 * Ny - 1) * L->Px * bb * 16) +
-                       al((size_t)Nr * std::max(N, (size_t)Nr) * 16);
+                       (dense_rim ? al((size_t)Nr * std::max(N, (size_t)Nr) * 16) : 0);
     L->ws_bytes =
         std::max(2 * L->grid_bytes + L->rimpart_bytes + L->ypart_bytes + L->solver_bytes, L->scratch_bytes);
     L->ws = take(true, L->ws_bytes);
@@ -193,46 +201,143 @@ tp_status toeplitz_plan_bytes(int Nx, int Ny, int b, int Nr, int sym, tp_prec pr
     if (!bytes) return fail(TP_E_INVAL, "bytes is NULL");
     if (sym & ~(TP_SYM_RIM | TP_SYM_GEN)) return fail(TP_E_INVAL, "sym holds unknown bits");
     Layout L;
-    tp_status s = make_layout(Nx, Ny, b, Nr, sym, prec, max_rhs, restart, &L);
+    tp_status s = make_layout(Nx, Ny, b, Nr, 0, sym, prec, max_rhs, restart, &L);
     if (s != TP_OK) return s;
     *bytes = L.total;
     return TP_OK;
 }
 
-tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen, const double *rim_re,
-                               const double *rim_er, const double *rim_rr, tp_prec prec, int max_rhs, int restart,
-                               void *dev_buf, size_t dev_bytes, void *hip_stream, tp_plan *out) {
+tp_status toeplitz_plan_bytes_placed(int Nx, int Ny, int b, int Nr, int nrc, int sym, tp_prec prec, int max_rhs,
+                                     int restart, size_t *bytes) {
+    if (!bytes) return fail(TP_E_INVAL, "bytes is NULL");
+    if (sym & ~(TP_SYM_RIM | TP_SYM_GEN)) return fail(TP_E_INVAL, "sym holds unknown bits");
+    if (nrc < 1) return fail(TP_E_INVAL, "a placed rim needs nrc >= 1");
+    Layout L;
+    tp_status s = make_layout(Nx, Ny, b, Nr, nrc, sym, prec, max_rhs, restart, &L);
+    if (s != TP_OK) return s;
+    *bytes = L.total;
+    return TP_OK;
+}
+
+}  // extern "C"
+
+namespace tp {
+
+static bool all_finite(const double *a, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+// Checks shared by both plan constructors, before any device work: pointers,
+// alignment, shapes (make_layout) and finite operator entries (a NaN or Inf
+// would only surface as a Krylov breakdown much later).
+static tp_status check_create_inputs(int Nx, int Ny, int b, int Nr, int nrc, const double *gen, const double *rim_re,
+                                     const double *rim_er, const double *rim_rr, tp_prec prec, int max_rhs,
+                                     int restart, void *dev_buf, tp_plan *out) {
     if (!out) return fail(TP_E_INVAL, "out is NULL");
     *out = nullptr;
     if (!gen) return fail(TP_E_INVAL, "gen is NULL");
     if (Nr > 0 && (!rim_re || !rim_rr)) return fail(TP_E_INVAL, "rim_re and rim_rr are required when Nr > 0");
     if (!dev_buf) return fail(TP_E_INVAL, "dev_buf is NULL");
     if (((uintptr_t)dev_buf) & 255) return fail(TP_E_INVAL, "dev_buf must be 256-byte aligned");
-    const int reciprocal = (rim_er == nullptr) ? 1 : 0;
-    {
-        // non-finite operator entries would only surface as a Krylov breakdown
-        // much later; refuse them here (shapes are checked by make_layout
-        // below, so only scan once they are known to be sane)
-        Layout L0;
-        tp_status s0 = make_layout(Nx, Ny, b, Nr, reciprocal ? TP_SYM_RIM : 0, prec, max_rhs, restart, &L0);
-        if (s0 != TP_OK) return s0;
-        const long N = (long)Nx * Ny * b;
-        auto finite = [](const double *a, size_t n) {
-            for (size_t i = 0; i < n; ++i)
-                if (!std::isfinite(a[i])) return false;
-            return true;
-        };
-        if (!finite(gen, 2 * (size_t)(2 * Ny - 1) * (2 * Nx - 1) * b * b))
-            return fail(TP_E_INVAL, "gen holds a non-finite value");
-        if (Nr > 0 && (!finite(rim_re, 2 * (size_t)Nr * N) || !finite(rim_rr, 2 * (size_t)Nr * Nr) ||
-                       (rim_er && !finite(rim_er, 2 * (size_t)Nr * N))))
-            return fail(TP_E_INVAL, "a rim block holds a non-finite value");
+    Layout L0;
+    tp_status s0 = make_layout(Nx, Ny, b, Nr, nrc, rim_er ? 0 : TP_SYM_RIM, prec, max_rhs, restart, &L0);
+    if (s0 != TP_OK) return s0;
+    const long N = (long)Nx * Ny * b;
+    if (!all_finite(gen, 2 * (size_t)(2 * Ny - 1) * (2 * Nx - 1) * b * b))
+        return fail(TP_E_INVAL, "gen holds a non-finite value");
+    if (Nr > 0 && (!all_finite(rim_re, 2 * (size_t)Nr * N) || !all_finite(rim_rr, 2 * (size_t)Nr * Nr) ||
+                   (rim_er && !all_finite(rim_er, 2 * (size_t)Nr * N))))
+        return fail(TP_E_INVAL, "a rim block holds a non-finite value");
+    return TP_OK;
+}
+
+// The generator of a placed rim: blocks of bc = b + nrc channels per cell,
+// gext[n + Ny - 1][m + Nx - 1][p][q] coupling channel p of cell (ix + m, iy + n)
+// (row) with channel q of cell (ix, iy).  Element channels (p, q < b) are the
+// element generators; a rim channel takes its couplings from the dense rim
+// blocks at every pair of cells they connect, and every value one block entry
+// receives must be the same bit for bit (else the rim is not block Toeplitz
+// in this placement: TP_E_INVAL).  Entries no pair of occupied cells reaches
+// stay zero; the restricted operator never reads them.  map[e * nrc + c]: the
+// rim function at channel b + c of cell e, or -1.
+static tp_status build_placed_gen(int Nx, int Ny, int b, int Nr, int nrc, const double *gen, const double *rim_re,
+                                  const double *rim_er, const double *rim_rr, const int *place,
+                                  std::vector<c128> &gext, std::vector<int> &map) {
+    const int bc = b + nrc, W = 2 * Nx - 1, H = 2 * Ny - 1;
+    const long N = (long)Nx * Ny * b;
+    const size_t bb = (size_t)bc * bc;
+    map.assign((size_t)Nx * Ny * nrc, -1);
+    for (int r = 0; r < Nr; ++r) {
+        const int cx = place[3 * r], cy = place[3 * r + 1], c = place[3 * r + 2];
+        if (cx < 0 || cx >= Nx || cy < 0 || cy >= Ny || c < 0 || c >= nrc)
+            return fail(TP_E_INVAL, "rim function " + std::to_string(r) + " is placed outside the cells or channels");
+        int &slot = map[((size_t)cy * Nx + cx) * nrc + c];
+        if (slot >= 0)
+            return fail(TP_E_INVAL, "rim functions " + std::to_string(slot) + " and " + std::to_string(r) +
+                                        " share a cell and channel");
+        slot = r;
     }
+    gext.assign((size_t)H * W * bb, c128{0.0, 0.0});
+    std::vector<unsigned char> set((size_t)H * W * bb, 0);
+    auto at = [&](int m, int n, int p, int q) {
+        return ((size_t)(n + Ny - 1) * W + (m + Nx - 1)) * bb + (size_t)p * bc + q;
+    };
+    auto put = [&](size_t o, const double *src) {
+        if (set[o]) return memcmp(&gext[o], src, sizeof(c128)) == 0;
+        memcpy(&gext[o], src, sizeof(c128));
+        set[o] = 1;
+        return true;
+    };
+    for (int n = 0; n < H; ++n)
+        for (int m = 0; m < W; ++m)
+            for (int p = 0; p < b; ++p)
+                memcpy(&gext[at(m - (Nx - 1), n - (Ny - 1), p, 0)], gen + 2 * (((size_t)n * W + m) * b * b + (size_t)p * b),
+                       (size_t)b * sizeof(c128));
+    auto not_toeplitz = [&](const char *block, int r) {
+        return fail(TP_E_INVAL, std::string("the rim is not block Toeplitz in this placement: ") + block +
+                                    " entries of rim function " + std::to_string(r) +
+                                    " differ between cell pairs of equal offset");
+    };
+    for (int r = 0; r < Nr; ++r) {
+        const int cx = place[3 * r], cy = place[3 * r + 1], c = place[3 * r + 2];
+        for (int ly = 0; ly < Ny; ++ly)
+            for (int lx = 0; lx < Nx; ++lx) {
+                const long e0 = ((long)ly * Nx + lx) * b;
+                // rim row (channel b + c of cell (cx, cy)), element column
+                const size_t o = at(cx - lx, cy - ly, b + c, 0);
+                for (int q = 0; q < b; ++q)
+                    if (!put(o + q, rim_re + 2 * ((size_t)r * N + e0 + q))) return not_toeplitz("rim-element", r);
+                // element row, rim column
+                const size_t oe = at(lx - cx, ly - cy, 0, b + c);
+                for (int p = 0; p < b; ++p) {
+                    const double *src = rim_er ? rim_er + 2 * ((size_t)(e0 + p) * Nr + r) : rim_re + 2 * ((size_t)r * N + e0 + p);
+                    if (!put(oe + (size_t)p * bc, src)) return not_toeplitz("element-rim", r);
+                }
+            }
+        for (int t = 0; t < Nr; ++t) {
+            const int tx = place[3 * t], ty = place[3 * t + 1], d = place[3 * t + 2];
+            if (!put(at(cx - tx, cy - ty, b + c, b + d), rim_rr + 2 * ((size_t)r * Nr + t)))
+                return not_toeplitz("rim-rim", r);
+        }
+    }
+    return TP_OK;
+}
+
+// Plan construction once the generators are final: gen holds blocks of
+// bc = b + nrc channels; the dense rim blocks only when nrc = 0; map_host
+// ([Nx Ny][nrc]) only when nrc > 0.
+static tp_status create_plan(int Nx, int Ny, int b, int Nr, int nrc, const double *gen, const int *map_host,
+                             const double *rim_re, const double *rim_er, const double *rim_rr, int reciprocal,
+                             tp_prec prec, int max_rhs, int restart, void *dev_buf, size_t dev_bytes,
+                             void *hip_stream, tp_plan *out) {
+    const int bc = b + nrc;
     int gsym = 0;
-    toeplitz_gen_symmetric(Nx, Ny, b, gen, &gsym);
+    toeplitz_gen_symmetric(Nx, Ny, bc, gen, &gsym);
     Layout L;
-    tp_status s = make_layout(Nx, Ny, b, Nr, (reciprocal ? TP_SYM_RIM : 0) | (gsym ? TP_SYM_GEN : 0), prec, max_rhs,
-                              restart, &L);
+    tp_status s = make_layout(Nx, Ny, b, Nr, nrc, (reciprocal ? TP_SYM_RIM : 0) | (gsym ? TP_SYM_GEN : 0), prec,
+                              max_rhs, restart, &L);
     if (s != TP_OK) return s;
     if (dev_bytes < L.total)
         return fail(TP_E_NOMEM, "device buffer holds " + std::to_string(dev_bytes) + " bytes, plan needs " +
@@ -243,6 +348,7 @@ tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
     char *base = (char *)dev_buf;
     auto at = [&](size_t off) -> char * { return off == SIZE_MAX ? nullptr : base + off; };
     pl->Nx = Nx; pl->Ny = Ny; pl->b = b; pl->Nr = Nr;
+    pl->bc = bc; pl->nrc = nrc; pl->rim_map = nullptr;
     pl->Px = L.Px; pl->Py = L.Py;
     pl->N = (long)Nx * Ny * b; pl->Nt = pl->N + Nr;
     pl->max_rhs = max_rhs; pl->restart = restart; pl->prec = prec; pl->reciprocal = reciprocal;
@@ -266,6 +372,10 @@ tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
     int *perm_x = (int *)tab, *perm_y = perm_x + Px;
     c128 *tw64_x = (c128 *)(tab + al((size_t)(Px + Py) * 4)), *tw64_y = tw64_x + Px;
     c64 *tw32_x = (c64 *)(tab + al((size_t)(Px + Py) * 4) + al((size_t)(Px + Py) * 16)), *tw32_y = tw32_x + Px;
+    int *map_dev = nrc ? (int *)(tab + al((size_t)(Px + Py) * 4) + al((size_t)(Px + Py) * 16) +
+                                 al((size_t)(Px + Py) * 8))
+                       : nullptr;
+    pl->rim_map = map_dev;
     std::vector<int> hperm(Px + Py);
     std::vector<c128> htw64(Px + Py);
     std::vector<c64> htw32(Px + Py);
@@ -289,12 +399,14 @@ tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
     hipError_t e;
     if ((e = hipMemcpyAsync(perm_x, hperm.data(), sizeof(int) * (Px + Py), hipMemcpyHostToDevice, st)) ||
         (e = hipMemcpyAsync(tw64_x, htw64.data(), sizeof(c128) * (Px + Py), hipMemcpyHostToDevice, st)) ||
-        (e = hipMemcpyAsync(tw32_x, htw32.data(), sizeof(c64) * (Px + Py), hipMemcpyHostToDevice, st))) {
+        (e = hipMemcpyAsync(tw32_x, htw32.data(), sizeof(c64) * (Px + Py), hipMemcpyHostToDevice, st)) ||
+        (nrc && (e = hipMemcpyAsync(map_dev, map_host, sizeof(int) * (size_t)Nx * Ny * nrc, hipMemcpyHostToDevice,
+                                    st)))) {
         delete pl;
         return hip_fail(e, "plan tables upload");
     }
     // spectrum: generators -> scratch, two transform passes -> G64 / G32
-    const size_t bb = (size_t)b * b;
+    const size_t bb = (size_t)bc * bc;
     const size_t gen_bytes = (size_t)(2 * Ny - 1) * (2 * Nx - 1) * bb * 16;
     c128 *gen_dev = (c128 *)pl->ws;
     c128 *tmp = (c128 *)(pl->ws + al(gen_bytes));
@@ -308,7 +420,7 @@ tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
         return hip_fail(e, "spectrum build");
     }
     // rim blocks: complex128 copies and/or complex64 casts
-    if (Nr > 0) {
+    if (Nr > 0 && nrc == 0) {
         const size_t nN = (size_t)Nr * pl->N, nC = (size_t)Nr * Nr;
         std::vector<c128> ber;
         if (!reciprocal) {      // store B_er transposed, [Nr][N], like B
@@ -346,6 +458,43 @@ tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen,
     return TP_OK;
 }
 
+}  // namespace tp
+
+extern "C" {
+
+tp_status toeplitz_plan_create(int Nx, int Ny, int b, int Nr, const double *gen, const double *rim_re,
+                               const double *rim_er, const double *rim_rr, tp_prec prec, int max_rhs, int restart,
+                               void *dev_buf, size_t dev_bytes, void *hip_stream, tp_plan *out) {
+    tp_status s = check_create_inputs(Nx, Ny, b, Nr, 0, gen, rim_re, rim_er, rim_rr, prec, max_rhs, restart, dev_buf,
+                                      out);
+    if (s != TP_OK) return s;
+    return create_plan(Nx, Ny, b, Nr, 0, gen, nullptr, rim_re, rim_er, rim_rr, rim_er == nullptr, prec, max_rhs,
+                       restart, dev_buf, dev_bytes, hip_stream, out);
+}
+
+tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const double *gen, const double *rim_re,
+                                      const double *rim_er, const double *rim_rr, const int *rim_place, int nrc,
+                                      tp_prec prec, int max_rhs, int restart, void *dev_buf, size_t dev_bytes,
+                                      void *hip_stream, tp_plan *out) {
+    if (out) *out = nullptr;
+    if (Nr < 1 || nrc < 1) return fail(TP_E_INVAL, "a placed rim needs Nr >= 1 and nrc >= 1");
+    if (!rim_place) return fail(TP_E_INVAL, "rim_place is NULL");
+    tp_status s = check_create_inputs(Nx, Ny, b, Nr, nrc, gen, rim_re, rim_er, rim_rr, prec, max_rhs, restart,
+                                      dev_buf, out);
+    if (s != TP_OK) return s;
+    std::vector<c128> gext;
+    std::vector<int> map;
+    try {
+        s = build_placed_gen(Nx, Ny, b, Nr, nrc, gen, rim_re, rim_er, rim_rr, rim_place, gext, map);
+    } catch (const std::bad_alloc &) {
+        return fail(TP_E_NOMEM, "host allocation of the placed generators failed");
+    }
+    if (s != TP_OK) return s;
+    return create_plan(Nx, Ny, b, Nr, nrc, reinterpret_cast<const double *>(gext.data()), map.data(), nullptr,
+                       nullptr, nullptr, rim_er == nullptr, prec, max_rhs, restart, dev_buf, dev_bytes, hip_stream,
+                       out);
+}
+
 tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *d) {
     if (!p || !d) return fail(TP_E_INVAL, "NULL argument");
     d->Nx = p->Nx; d->Ny = p->Ny; d->b = p->b; d->Nr = p->Nr;
@@ -355,6 +504,8 @@ tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *d) {
     d->workspace_bytes = p->workspace_bytes; d->total_bytes = p->total;
     d->reciprocal = p->reciprocal;
     d->half_spectrum = p->half;
+    d->nrc = p->nrc;
+    d->bc = p->bc;
     return TP_OK;
 }
 
@@ -445,7 +596,7 @@ tp_status toeplitz_matvec_profile(tp_plan p, tp_prec which, const void *x, long 
 tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void *host_out) {
     if (!p || !host_out) return fail(TP_E_INVAL, "NULL argument");
     if (kx < 0 || kx >= p->Px || ky < 0 || ky >= p->Py) return fail(TP_E_INVAL, "frequency out of range");
-    const size_t bb = (size_t)p->b * p->b;
+    const size_t bb = (size_t)p->bc * p->bc;
     // a column the plan does not store is the transpose of the block at (-kx, -ky)
     const bool tr = kx >= p->kxh;
     const size_t k = tr ? (size_t)(p->Px - kx) * p->Py + (ky ? p->Py - ky : 0) : (size_t)kx * p->Py + ky;
@@ -465,7 +616,7 @@ tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void 
     if (e != hipSuccess) return hip_fail(e, "spectrum copy");
     if (tr) {
         char *o = static_cast<char *>(host_out), tmp[16];
-        const int b = p->b;
+        const int b = p->bc;
         for (int i = 0; i < b; ++i)
             for (int j = i + 1; j < b; ++j) {
                 char *a = o + ((size_t)i * b + j) * es, *c = o + ((size_t)j * b + i) * es;
@@ -496,7 +647,8 @@ static size_t precond_layout(size_t nblk, int b, int Nr, bool f64, bool f32, siz
     return off;
 }
 static size_t precond_layout(tp_plan p, size_t *s64, size_t *s32, size_t *d64, size_t *d32, size_t *flag) {
-    return precond_layout((size_t)p->kxh * p->Py, p->b, p->Nr, p->G64 != nullptr, p->G32 != nullptr, s64, s32, d64,
+    // a placed rim's channels are inverted with the element channels (no D)
+    return precond_layout((size_t)p->kxh * p->Py, p->bc, p->nrc ? 0 : p->Nr, p->G64 != nullptr, p->G32 != nullptr, s64, s32, d64,
                           d32, flag);
 }
 
@@ -512,7 +664,7 @@ tp_status toeplitz_precond_bytes_for(int Nx, int Ny, int b, int Nr, int sym, tp_
     if (sym & ~(TP_SYM_RIM | TP_SYM_GEN)) return fail(TP_E_INVAL, "sym holds unknown bits");
     if (prec == TP_FP32) return fail(TP_E_UNSUPPORTED, "the preconditioner is built from the FP64 spectrum");
     Layout L;
-    tp_status s = make_layout(Nx, Ny, b, Nr, sym, prec, 1, 1, &L);
+    tp_status s = make_layout(Nx, Ny, b, Nr, 0, sym, prec, 1, 1, &L);
     if (s != TP_OK) return s;
     size_t a, c, d, e, f;
     *bytes = precond_layout((size_t)L.kxh * L.Py, b, Nr, true, prec == TP_MIXED, &a, &c, &d, &e, &f);
@@ -529,7 +681,7 @@ tp_status toeplitz_precond_create(tp_plan p, void *dev_buf, size_t dev_bytes, vo
     if (dev_bytes < need) return fail(TP_E_NOMEM, "dev_buf smaller than toeplitz_precond_bytes()");
     char *base = static_cast<char *>(dev_buf);
     hipStream_t st = (hipStream_t)hip_stream;
-    const size_t nS = (size_t)p->kxh * p->Py * p->b * p->b;
+    const size_t nS = (size_t)p->kxh * p->Py * p->bc * p->bc;
     // captured solver graphs hold the previous S and D pointers as kernel
     // arguments: drop them before repointing
     solver_drop_graphs(p);

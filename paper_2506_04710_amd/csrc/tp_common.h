@@ -238,6 +238,25 @@ struct FFTDesc {
 
 constexpr int kMaxP = 512;
 
+// Placed rim: the rim functions are extra channels of element cells (a margin
+// part sits at a cell with a fixed local offset, so every coupling depends only
+// on the cell difference and the whole operator is the restriction of one
+// two-level block-Toeplitz operator with b + nrc channels per cell).  Channel
+// p of cell e is element basis p for p < be, and for p >= be rim function
+// idx[e * nrc + p - be] (unknown N + that), or no unknown when that is -1.
+// idx == nullptr: every channel is an element basis function.
+struct RimMap {
+    const int *idx;
+    int be, nrc;
+    long N;
+};
+// Index into a column of cell e's channel p, or -1 (unoccupied rim channel).
+__device__ __forceinline__ long cell_unknown(const RimMap &m, int e, int p) {
+    if (p < m.be) return (long)e * m.be + p;
+    const int r = m.idx[(long)e * m.nrc + (p - m.be)];
+    return r < 0 ? -1 : m.N + r;
+}
+
 // Stored spectrum block of frequency k = kx Py + ky.  With half the spectrum
 // stored (columns kx < kxh), a column kx >= kxh is read as the transpose of
 // the block at (Px - kx, -ky mod Py).
@@ -252,6 +271,10 @@ __device__ __forceinline__ long spec_src(long k, int Px, int Py, int kxh, bool &
 // Plan record (host memory; every pointer is into the caller's device buffer).
 struct tp_plan_s {
     int Nx, Ny, b, Nr;
+    // channels per cell of the transforms and spectrum blocks: b, or b + nrc
+    // with a placed rim (rim_map: [Nx Ny][nrc] rim function or -1, device)
+    int bc, nrc;
+    const int *rim_map;
     int Px, Py;
     long N, Nt;
     int max_rhs, restart;

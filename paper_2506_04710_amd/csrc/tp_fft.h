@@ -237,19 +237,20 @@ __device__ __forceinline__ void fft_stage(cpx<T> *buf, int lgCC, int P, int L, c
 // order (slot perm[k] holds X[k]).  The transposed stage takes the radix-R
 // DFT first and then multiplies output q by w^(q j stride).
 //
-// fft_stage2 runs one stage (DIT or DIF) over two tiles at once, b1 with
-// 2^lg1 channels and b2 (may be null) with 2^lg2, so that the two transforms
-// share the stage's barrier.
+// fft_stage2 runs one stage (DIT or DIF) over two tiles at once, b1 with a
+// channel stride of 2^lg1 and b2 (may be null) with 2^lg2, so that the two
+// transforms share the stage's barrier.  Only the first nc1 (nc2) channels of
+// a tile are transformed (the rest of its stride is padding).
 template <typename T, int R, bool INV, bool DIF, int NT = kBlock>
-__device__ __forceinline__ void fft_stage2(cpx<T> *b1, int lg1, cpx<T> *b2, int lg2, int P, int L,
+__device__ __forceinline__ void fft_stage2(cpx<T> *b1, int lg1, int nc1, cpx<T> *b2, int lg2, int nc2, int P, int L,
                                            const cpx<T> *twl) {
     // NI butterflies per thread and round: their LDS reads issue together
     // (indices past the end are clamped; such a duplicate is not stored)
     constexpr int NI = sizeof(T) == 4 ? 2 : 1;
     const int nb = P / R;
     const int stride = P / (L * R);
-    const int n1 = nb << lg1, total = n1 + (b2 ? (nb << lg2) : 0);
-    const float rL = 1.0f / (float)L;
+    const int n1 = nb * nc1, total = n1 + (b2 ? nb * nc2 : 0);
+    const float rL = 1.0f / (float)L, rc1 = 1.0f / (float)nc1, rc2 = 1.0f / (float)nc2;
     for (int it0 = threadIdx.x; it0 < total; it0 += NI * NT) {
         cpx<T> a[NI][R], w[NI][R];
         cpx<T> *b0[NI];
@@ -259,7 +260,8 @@ __device__ __forceinline__ void fft_stage2(cpx<T> *b1, int lg1, cpx<T> *b2, int 
             const int it = min(it0 + ii * NT, total - 1);
             const bool sec = it >= n1;
             const int lg = sec ? lg2 : lg1, i2 = sec ? it - n1 : it;
-            const int ch = i2 & ((1 << lg) - 1), bf = i2 >> lg;
+            int ch;
+            const int bf = small_divmod(i2, sec ? nc2 : nc1, sec ? rc2 : rc1, ch);
             int j;
             const int grp = small_divmod(bf, L, rL, j);
             base[ii] = grp * L * R + j;
@@ -292,20 +294,22 @@ __device__ __forceinline__ void fft_stage2(cpx<T> *b1, int lg1, cpx<T> *b2, int 
 }
 
 // Two tiles transformed together (b2 may be null; barrier done before) by NT
-// threads.  DIT: input in digit-reversed order, output natural.  DIF: input
-// natural, output digit-reversed.
+// threads: nc1 of b1's 2^lg1 channel slots, nc2 of b2's 2^lg2.  DIT: input in
+// digit-reversed order, output natural.  DIF: input natural, output
+// digit-reversed.
 template <typename T, bool INV, bool DIF, int NT = kBlock>
-__device__ void lds_fft2(cpx<T> *b1, int lg1, cpx<T> *b2, int lg2, const FFTDesc &d, const cpx<T> *twl) {
+__device__ void lds_fft2(cpx<T> *b1, int lg1, int nc1, cpx<T> *b2, int lg2, int nc2, const FFTDesc &d,
+                         const cpx<T> *twl) {
     for (int t = 0; t < d.nst; ++t) {
         const int s = DIF ? d.nst - 1 - t : t;
         switch (d.radix[s]) {
-            case 2: fft_stage2<T, 2, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
-            case 3: fft_stage2<T, 3, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
-            case 4: fft_stage2<T, 4, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
-            case 5: fft_stage2<T, 5, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
-            case 7: fft_stage2<T, 7, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
-            case 8: fft_stage2<T, 8, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
-            case 9: fft_stage2<T, 9, INV, DIF, NT>(b1, lg1, b2, lg2, d.P, d.L[s], twl); break;
+            case 2: fft_stage2<T, 2, INV, DIF, NT>(b1, lg1, nc1, b2, lg2, nc2, d.P, d.L[s], twl); break;
+            case 3: fft_stage2<T, 3, INV, DIF, NT>(b1, lg1, nc1, b2, lg2, nc2, d.P, d.L[s], twl); break;
+            case 4: fft_stage2<T, 4, INV, DIF, NT>(b1, lg1, nc1, b2, lg2, nc2, d.P, d.L[s], twl); break;
+            case 5: fft_stage2<T, 5, INV, DIF, NT>(b1, lg1, nc1, b2, lg2, nc2, d.P, d.L[s], twl); break;
+            case 7: fft_stage2<T, 7, INV, DIF, NT>(b1, lg1, nc1, b2, lg2, nc2, d.P, d.L[s], twl); break;
+            case 8: fft_stage2<T, 8, INV, DIF, NT>(b1, lg1, nc1, b2, lg2, nc2, d.P, d.L[s], twl); break;
+            case 9: fft_stage2<T, 9, INV, DIF, NT>(b1, lg1, nc1, b2, lg2, nc2, d.P, d.L[s], twl); break;
             default: break;
         }
     }

@@ -46,7 +46,7 @@ __device__ __forceinline__ void zero_lds(cpx<T> *buf, int n, int nt = kBlock) {
 // ------------------------------------------------------------ FFT passes
 template <typename T, typename In>
 __global__ void __launch_bounds__(256) k_fwd_x(Cols<const In> x, int R, int Nx, int b, FFTDesc fx,
-                                               int lgCC, cpx<T> *__restrict__ out) {
+                                               int lgCC, cpx<T> *__restrict__ out, RimMap rm) {
     extern __shared__ char smem_raw[];
     cpx<T> *twl = reinterpret_cast<cpx<T> *>(smem_raw);
     cpx<T> *buf = twl + fx.P;
@@ -59,9 +59,10 @@ __global__ void __launch_bounds__(256) k_fwd_x(Cols<const In> x, int R, int Nx, 
         if (c < C) {
             const int r = c / b, p = c - r * b;
             const In *xc = x.col(r);
-            if (xc) {
+            const long j = xc ? cell_unknown(rm, iy * Nx + ix, p) : -1;
+            if (j >= 0) {
                 ok = true;
-                return cvt<T>(xc[(long)(iy * Nx + ix) * b + p]);
+                return cvt<T>(xc[j]);
             }
         }
         return mk<T>(0, 0);
@@ -590,7 +591,8 @@ __device__ __forceinline__ void spec_block_half(const cpx<T> *__restrict__ G, co
         batched<8, cpx<T>>(
             nxm - NT, [&](int i) { return mload(i + NT); }, [&](int i, cpx<T> v) { mstore(i + NT, v); }, NT);
     __syncthreads();
-    lds_fft2<T, false, true, NT>(xs, lgCC, mir ? xm : nullptr, 3, fy, twl);
+    // (only the b real channels of the CC-wide rows are transformed)
+    lds_fft2<T, false, true, NT>(xs, lgCC, b, mir ? xm : nullptr, 3, TP, fy, twl);
     load(gc, w);
     bool qok[VPL];
     int qi[VPL];
@@ -673,7 +675,7 @@ __device__ __forceinline__ void spec_block_half(const cpx<T> *__restrict__ G, co
         reduce(gc, w + tb * bstep);
     }
     __syncthreads();
-    lds_fft2<T, true, false, NT>(ys, 3, mir ? xs : nullptr, lgCC, fy, twl);
+    lds_fft2<T, true, false, NT>(ys, 3, TP, mir ? xs : nullptr, lgCC, b, fy, twl);
     for (int i = threadIdx.x; i < Ny * TP; i += NT) {
         const int iy = i >> 3, pr = i & 7, pp = p0 + pr;
         if (pp < b) Y1[((long)iy * Px + kx) * b + pp] = ys[i];
@@ -848,10 +850,10 @@ __global__ void __launch_bounds__(NT) k_spec_rim(const cpx<T> *__restrict__ G, c
     if (spec_id >= 0) {
         if (!cols_live((const void *const *)x.tab, 0, 0)) return;
         // without the rim pass the spectrum stream alone must keep HBM busy:
-        // two pairs per register buffer (FP32)
+        // two pairs per register buffer (FP32, 8-wave workgroups)
         if constexpr (HALF)
-            spec_block_half<T, VPL, (E == 0 && sizeof(T) == 4) ? 2 : 1, NT>(G, X1, Y1, Yp, b, Ny, Px, kxh, fy,
-                                                                         lgCC, spec_id, smem_raw);
+            spec_block_half<T, VPL, (E == 0 && sizeof(T) == 4 && NT == 512) ? 2 : 1, NT>(
+                G, X1, Y1, Yp, b, Ny, Px, kxh, fy, lgCC, spec_id, smem_raw);
         else
             spec_block<T, VPL, U>(G, X1, Y1, b, Ny, Px, fy, lgCC, spec_id, smem_raw);
     } else if constexpr (E > 0) {
@@ -879,7 +881,8 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
                                                    int lgCC, int nchunk, Cols<Out> y, int accumulate,
                                                    Cols<const Out> acc, int ninv, const cpx<T> *__restrict__ part,
                                                    const cpx<T> *__restrict__ Cm, const cpx<T> *__restrict__ D,
-                                                   Cols<const In> x, long N, int Nr, int nslab, MirrorParts<T> mp) {
+                                                   Cols<const In> x, long N, int Nr, int nslab, MirrorParts<T> mp,
+                                                   RimMap rm) {
     extern __shared__ char smem_raw[];
     const int blk = blockIdx.x;
     if (blk >= ninv) {
@@ -902,14 +905,14 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
         cpx<T> v = mk<T>(0, 0);
         if (c < C) {
             if (mp.yp && kx >= mp.kxh) {
-                // all parts in flight at once (nch <= 8: rows of at most 64),
+                // all parts in flight at once (nch <= 12: rows of at most 96),
                 // then added in part order
                 const cpx<T> *src = mp.yp + ((long)iy * mp.nmir + (kx - mp.kxh)) * b + c;
-                cpx<T> pv[8];
+                cpx<T> pv[12];
 #pragma unroll
-                for (int h = 0; h < 8; ++h) pv[h] = h < mp.nch ? src[h * mp.hstride] : mk<T>(0, 0);
+                for (int h = 0; h < 12; ++h) pv[h] = h < mp.nch ? src[h * mp.hstride] : mk<T>(0, 0);
 #pragma unroll
-                for (int h = 0; h < 8; ++h)
+                for (int h = 0; h < 12; ++h)
                     if (h < mp.nch) v = v + pv[h];
             } else {
                 v = in[((long)iy * P + kx) * C + c];
@@ -941,7 +944,8 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
             const int r = c / b, p = c - r * b;
             Out *yc = y.col(r);
             if (!yc) continue;
-            const long e = (long)(iy * Nx + ix) * b + p;
+            const long e = cell_unknown(rm, iy * Nx + ix, p);
+            if (e < 0) continue;
             // the added term keeps the output's precision (an FP64 solution
             // vector updated by an FP32 preconditioner stays FP64)
             Out v = cvt<typename Out::value_type>(buf[i]);
@@ -964,7 +968,8 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
 // Tile layout: value (x, y, channel) at (x Py + y) CC + channel.
 template <typename T, typename In>
 __global__ void __launch_bounds__(256) k_fft2_fwd(Cols<const In> x, int R, int Nx, int Ny, int b, FFTDesc fx,
-                                                  FFTDesc fy, int lgCC, int XS, cpx<T> *__restrict__ out) {
+                                                  FFTDesc fy, int lgCC, int XS, cpx<T> *__restrict__ out,
+                                                  RimMap rm) {
     extern __shared__ char smem_raw[];
     cpx<T> *twx = reinterpret_cast<cpx<T> *>(smem_raw);
     cpx<T> *twy = twx + fx.P;
@@ -984,13 +989,24 @@ __global__ void __launch_bounds__(256) k_fft2_fwd(Cols<const In> x, int R, int N
         const int cl = threadIdx.x & (CC - 1), c = c0 + cl;
         const In *xc = c < C ? x.col(c / b) : nullptr;
         __syncthreads();
-        if (xc) {
-            xc += c % b;
+        const int p = c % b;
+        if (xc && p >= rm.be) {
+            // a rim channel: the rim functions placed at this channel's cells
+            const int es = kBlock >> lgCC, ne = Nx * Ny;
+            for (int e = threadIdx.x >> lgCC; e < ne; e += es) {
+                const long j = cell_unknown(rm, e, p);
+                if (j >= 0) {
+                    const int iy = e / Nx, ix = e - iy * Nx;
+                    buf[px[ix] * XS + (py[iy] << lgCC) + cl] = cvt<T>(ldg(xc + j));
+                }
+            }
+        } else if (xc) {
+            xc += p;
             const int es = kBlock >> lgCC, ne = Nx * Ny;
             for (int eb = threadIdx.x >> lgCC; eb < ne; eb += 8 * es) {
                 In v[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = ldg(xc + (long)min(eb + u * es, ne - 1) * b);
+                for (int u = 0; u < 8; ++u) v[u] = ldg(xc + (long)min(eb + u * es, ne - 1) * rm.be);
 #pragma unroll
                 for (int u = 0; u < 8; ++u) pin(v[u]);
 #pragma unroll
@@ -1020,7 +1036,7 @@ __global__ void __launch_bounds__(256) k_fft2_inv_fin(const cpx<T> *__restrict__
                                                       int accumulate, Cols<const Out> acc, int ninv,
                                                       const cpx<T> *__restrict__ part,
                                                       const cpx<T> *__restrict__ Cm, const cpx<T> *__restrict__ D,
-                                                      Cols<const In> x, long N, int Nr, int nslab) {
+                                                      Cols<const In> x, long N, int Nr, int nslab, RimMap rm) {
     extern __shared__ char smem_raw[];
     const int blk = blockIdx.x;
     if (blk >= ninv) {
@@ -1058,15 +1074,29 @@ __global__ void __launch_bounds__(256) k_fft2_inv_fin(const cpx<T> *__restrict__
     const int cl = threadIdx.x & (CC - 1), c = c0 + cl;
     Out *yc = c < C ? y.col(c / b) : nullptr;
     if (!yc) return;
-    yc += c % b;
+    const int p = c % b;
     const Out *ac = accumulate ? acc.col(c / b) : nullptr;
-    if (ac) ac += c % b;
     const int es = kBlock >> lgCC, ne = Nx * Ny;
+    if (p >= rm.be) {
+        // a rim channel: results of the rim functions placed at its cells
+        for (int e = threadIdx.x >> lgCC; e < ne; e += es) {
+            const long j = cell_unknown(rm, e, p);
+            if (j >= 0) {
+                const int iy = e / Nx, ix = e - iy * Nx;
+                Out v = cvt<typename Out::value_type>(buf[ix * XS + (iy << lgCC) + cl]);
+                if (ac) v = v + ldg(ac + j);
+                stg(yc + j, v);
+            }
+        }
+        return;
+    }
+    yc += p;
+    if (ac) ac += p;
     for (int eb = threadIdx.x >> lgCC; eb < ne; eb += 8 * es) {
         Out old[8];
         if (ac) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) old[u] = ldg(ac + (long)min(eb + u * es, ne - 1) * b);
+            for (int u = 0; u < 8; ++u) old[u] = ldg(ac + (long)min(eb + u * es, ne - 1) * rm.be);
 #pragma unroll
             for (int u = 0; u < 8; ++u) pin(old[u]);
         }
@@ -1077,7 +1107,7 @@ __global__ void __launch_bounds__(256) k_fft2_inv_fin(const cpx<T> *__restrict__
                 const int iy = e / Nx, ix = e - iy * Nx;
                 Out v = cvt<typename Out::value_type>(buf[ix * XS + (iy << lgCC) + cl]);
                 if (ac) v = v + old[u];
-                stg(yc + (long)e * b, v);
+                stg(yc + (long)e * rm.be, v);
             }
         }
     }
@@ -1152,7 +1182,7 @@ static int next_pow2(int v) {
 
 // Fused single-column path: LDS bytes.
 static size_t spec_lds(tp_plan pl, size_t es) {
-    const int P = pl->Py, CC = next_pow2(pl->b);
+    const int P = pl->Py, CC = next_pow2(pl->bc);
     const size_t xm = pl->half ? (size_t)P * 8 : 0;   // mirror column channels
     return ((size_t)P + (size_t)P * CC + (size_t)P * 8 + xm) * es + (size_t)P * sizeof(int);
 }
@@ -1180,26 +1210,39 @@ static void launch_spec_rim(tp_plan pl, const cpx<T> *G, Cols<const In> x, Cols<
 #endif
     constexpr int U = sizeof(T) == 8 ? TP_SPEC_U64 : VPL > 8 ? 1 : (E == 0 ? TP_SPEC_U32_NORIM : TP_SPEC_U32);
     // half spectrum: one workgroup per stored column and row chunk
-    const int nchunk = (pl->b + 7) / 8, nspec = pl->kxh * nchunk;
+    const int nchunk = (pl->bc + 7) / 8, nspec = pl->kxh * nchunk;
     const int nrim = E > 0 ? pl->rim_nslab : 0;
-    const int lgCC = ilog2(next_pow2(pl->b));
+    const int lgCC = ilog2(next_pow2(pl->bc));
     cpx<T> *yp = reinterpret_cast<cpx<T> *>(pl->ypart);
     // (the half-spectrum form holds two panels per register buffer: rows of at
-    // most 64 values, VPL <= 8)
+    // most 96 values, VPL <= 12)
     // Without the rim pass (E = 0) the spectrum workgroups have the GPU to
     // themselves: 8 waves each (FP32), so a column's stream and transforms
     // use a whole compute unit.
-    if constexpr (VPL <= 8)
+    // With more spectrum tasks than compute units (rows of more than 64
+    // values), 8-wave workgroups (one per CU) would run in two rounds; 4-wave
+    // ones fit two per CU, so every task is resident at once.
+    if constexpr (VPL <= 12)
         if (pl->half) {
-            constexpr int NT = (E == 0 && sizeof(T) == 4) ? 512 : kBlock;
-            hipLaunchKernelGGL((k_spec_rim<T, In, Out, VPL, U, E, NBE, true, NT>), dim3(nspec + nrim), dim3(NT), sh,
-                               st, G, gA, gB, pl->b, pl->Ny, pl->Px, pl->fy, lgCC, nspec, OpPtrs<T>::B(pl),
-                               OpPtrs<T>::BE(pl), x, y, pl->N, pl->Nr, reinterpret_cast<cpx<T> *>(pl->rim_part), nrim,
-                               yp, pl->kxh);
+            if constexpr (E == 0 && sizeof(T) == 4) {
+                if (nspec <= 256) {
+                    hipLaunchKernelGGL((k_spec_rim<T, In, Out, VPL, U, E, NBE, true, 512>), dim3(nspec + nrim),
+                                       dim3(512), sh, st, G, gA, gB, pl->bc, pl->Ny, pl->Px, pl->fy, lgCC, nspec,
+                                       OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl), x, y, pl->N, pl->Nr,
+                                       reinterpret_cast<cpx<T> *>(pl->rim_part), nrim, yp, pl->kxh);
+                    return;
+                }
+            }
+            {
+                hipLaunchKernelGGL((k_spec_rim<T, In, Out, VPL, U, E, NBE, true, kBlock>), dim3(nspec + nrim),
+                                   dim3(kBlock), sh, st, G, gA, gB, pl->bc, pl->Ny, pl->Px, pl->fy, lgCC, nspec,
+                                   OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl), x, y, pl->N, pl->Nr,
+                                   reinterpret_cast<cpx<T> *>(pl->rim_part), nrim, yp, pl->kxh);
+            }
             return;
         }
         hipLaunchKernelGGL((k_spec_rim<T, In, Out, VPL, U, E, NBE, false>), dim3(nspec + nrim), dim3(256), sh, st, G,
-                           gA, gB, pl->b, pl->Ny, pl->Px, pl->fy, lgCC, nspec, OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl),
+                           gA, gB, pl->bc, pl->Ny, pl->Px, pl->fy, lgCC, nspec, OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl),
                            x, y, pl->N, pl->Nr, reinterpret_cast<cpx<T> *>(pl->rim_part), nrim, yp, pl->kxh);
 }
 
@@ -1288,8 +1331,11 @@ static void launch_rim_general(tp_plan pl, Cols<const In> x, Cols<Out> y, int R,
 template <typename T, typename In, typename Out, bool PRE = false>
 hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipStream_t st,
                          hipEvent_t *ev = nullptr, Cols<const Out> base = Cols<const Out>{nullptr, 0, nullptr}) {
-    const int Nx = pl->Nx, Ny = pl->Ny, b = pl->b, Nr = pl->Nr;
+    // b: channels per cell (element basis functions, plus the rim channels of
+    // a placed rim); the embedding and crop map channels to unknowns
+    const int Nx = pl->Nx, Ny = pl->Ny, b = pl->bc, Nr = pl->Nr;
     const int Px = pl->Px, Py = pl->Py, C = b * R;
+    const RimMap rm{pl->rim_map, pl->b, pl->nrc, pl->N};
     cpx<T> *gA = reinterpret_cast<cpx<T> *>(pl->gridA);
     cpx<T> *gB = reinterpret_cast<cpx<T> *>(pl->gridB);
     const size_t es = sizeof(cpx<T>);
@@ -1299,10 +1345,10 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         if (ev) hipEventRecord(ev[i], st);
     };
     const cpx<T> *G = PRE ? OpPtrs<T>::S(pl) : OpPtrs<T>::G(pl);
-    const bool rim = !PRE && Nr > 0;         // dense rim pass
+    const bool rim = !PRE && Nr > 0 && pl->nrc == 0;   // dense rim pass
     const size_t sh_fused = std::max(spec_lds(pl, es), rim ? rim_lds(pl, 1, es) : (size_t)0);
-    // one column: the fused path (for a half spectrum, rows of at most 64)
-    const bool fused = R == 1 && sh_fused <= kLdsLimit && !(pl->half && b > 64);
+    // one column: the fused path (for a half spectrum, rows of at most 96)
+    const bool fused = R == 1 && sh_fused <= kLdsLimit && !(pl->half && b > 96);
 
     // many columns: the product and the rim run on the matrix cores
     const bool mfma = !fused && R >= kMfmaMinR;
@@ -1324,12 +1370,12 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     const size_t sh2 = ((size_t)Px * xs2 + Px + Py) * es + (size_t)(Px + Py) * sizeof(int);
     if (lg2 >= 0) {
         hipLaunchKernelGGL((k_fft2_fwd<T, In>), dim3((C + (1 << lg2) - 1) >> lg2), blk, sh2, st, x, R, Nx, Ny, b,
-                           pl->fx, pl->fy, lg2, xs2, gB);
+                           pl->fx, pl->fy, lg2, xs2, gB, rm);
     } else {
         const int lg = fft_lgcc(Px, C, es, 8);
         const size_t sh = ((size_t)Px * (1 << lg) + Px) * es;
         dim3 grid((C + (1 << lg) - 1) >> lg, Ny);
-        hipLaunchKernelGGL((k_fwd_x<T, In>), grid, blk, sh, st, x, R, Nx, b, pl->fx, lg, gA);
+        hipLaunchKernelGGL((k_fwd_x<T, In>), grid, blk, sh, st, x, R, Nx, b, pl->fx, lg, gA, rm);
     }
     mark(2);
     if (!fused && lg2 < 0) {
@@ -1345,6 +1391,7 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         else if (vpl <= 4) launch_spec_rim_e<T, In, Out, 4>(pl, G, rim, x, y, gA, gB, sh_fused, st);
         else if (vpl <= 6) launch_spec_rim_e<T, In, Out, 6>(pl, G, rim, x, y, gA, gB, sh_fused, st);
         else if (vpl <= 8) launch_spec_rim_e<T, In, Out, 8>(pl, G, rim, x, y, gA, gB, sh_fused, st);
+        else if (vpl <= 9) launch_spec_rim_e<T, In, Out, 9>(pl, G, rim, x, y, gA, gB, sh_fused, st);
         else if (vpl <= 12) launch_spec_rim_e<T, In, Out, 12>(pl, G, rim, x, y, gA, gB, sh_fused, st);
         else if (vpl <= 16) launch_spec_rim_e<T, In, Out, 16>(pl, G, rim, x, y, gA, gB, sh_fused, st);
         else launch_spec_rim_e<T, In, Out, 32>(pl, G, rim, x, y, gA, gB, sh_fused, st);
@@ -1372,13 +1419,15 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     const Cols<const Out> acc = PRE ? base : Cols<const Out>{y.base, y.ld, y.tab};
     const int accumulate = PRE ? (base.base || base.tab ? 1 : 0) : (rim ? 1 : 0);
     const cpx<T> *D = PRE ? OpPtrs<T>::D(pl) : nullptr;
-    const int nfin = Nr > 0 ? ((Nr + 3) / 4) * R : 0;
+    // rim rows of a dense rim (C x_r and the slab partials, or D x_r) are
+    // finished by extra waves; a placed rim's rows come out of the crop
+    const int nfin = (Nr > 0 && pl->nrc == 0) ? ((Nr + 3) / 4) * R : 0;
     if (lg2 >= 0) {
         const int ninv = (C + (1 << lg2) - 1) >> lg2;
         hipLaunchKernelGGL((k_fft2_inv_fin<T, In, Out>), dim3(ninv + nfin), blk, sh2, st, gA, R, Nx, Ny, b, pl->fx,
                            pl->fy, lg2, xs2, y, accumulate, acc, ninv,
                            reinterpret_cast<const cpx<T> *>(pl->rim_part), OpPtrs<T>::C(pl), D, x, pl->N, Nr,
-                           pl->rim_nslab);
+                           pl->rim_nslab, rm);
     } else {
         // the fused path leaves Y1 in gB with channel count b (R = 1), the
         // general path in gB with b * R channels: the same layout
@@ -1397,7 +1446,7 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         }
         hipLaunchKernelGGL((k_inv_x_fin<T, In, Out>), dim3(ninv + nfin), blk, sh, st, gB, R, Nx, b, pl->fx, lg,
                            nchunk, y, accumulate, acc, ninv, reinterpret_cast<const cpx<T> *>(pl->rim_part),
-                           OpPtrs<T>::C(pl), D, x, pl->N, Nr, pl->rim_nslab, mp);
+                           OpPtrs<T>::C(pl), D, x, pl->N, Nr, pl->rim_nslab, mp, rm);
     }
     mark(6);
     mark(7);

@@ -80,7 +80,7 @@ __global__ void k_cast_c64(const c128 *__restrict__ in, c64 *__restrict__ out, l
 
 hipError_t spectrum_build(tp_plan pl, const c128 *gen_dev, c128 *tmp, hipStream_t st) {
     const int Nx = pl->Nx, Ny = pl->Ny, Px = pl->Px, Py = pl->Py;
-    const long bb = (long)pl->b * pl->b;
+    const long bb = (long)pl->bc * pl->bc;
     const size_t es = sizeof(c128);
     {
         const int lg = fft_lgcc(Px, (int)std::min<long>(bb, 64), es);
@@ -199,11 +199,11 @@ hipError_t dense_inverse(c128 *A, int n, int *flag, hipStream_t st) {
 hipError_t precond_build(tp_plan pl, c128 *S, int *flag, hipStream_t st) {
     const long P = (long)pl->Px * pl->Py;
     const double scl = 1.0 / ((double)P * (double)P);
-    const size_t sh = (size_t)pl->b * (sizeof(c128) + sizeof(int));
+    const size_t sh = (size_t)pl->bc * (sizeof(c128) + sizeof(int));
     // the stored blocks only: the inverse of a transposed block is the
     // transposed inverse, so a half spectrum gives a half preconditioner
     const long nblk = (long)pl->kxh * pl->Py;
-    hipLaunchKernelGGL(k_block_inv, dim3((unsigned)nblk), dim3(256), sh, st, S, pl->b, scl, flag);
+    hipLaunchKernelGGL(k_block_inv, dim3((unsigned)nblk), dim3(256), sh, st, S, pl->bc, scl, flag);
     hipError_t e = hipGetLastError();
     if (e) return e;
     if (pl->Nr > 0 && pl->D64) {

@@ -168,6 +168,7 @@ static SchurLayout schur_layout(tp_plan p) {
 static tp_status check_pair(tp_plan p, tp_plan a) {
     if (!p || !a) return fail(TP_E_INVAL, "plan is NULL");
     if (p->Nr < 1) return fail(TP_E_INVAL, "the plan has no rim to eliminate");
+    if (p->nrc) return fail(TP_E_UNSUPPORTED, "the rim elimination needs the dense rim blocks (the plan holds a placed rim)");
     if (!p->G64 || !p->B64 || !p->C64) return fail(TP_E_UNSUPPORTED, "the rim elimination needs the FP64 operator");
     if (a->Nx != p->Nx || a->Ny != p->Ny || a->b != p->b || a->Nr != 0)
         return fail(TP_E_INVAL, "the element plan must have the same Nx, Ny, b and no rim");
@@ -184,6 +185,7 @@ extern "C" {
 tp_status toeplitz_schur_bytes(tp_plan p, size_t *bytes) {
     if (!p || !bytes) return fail(TP_E_INVAL, "plan or bytes is NULL");
     if (p->Nr < 1) return fail(TP_E_INVAL, "the plan has no rim to eliminate");
+    if (p->nrc) return fail(TP_E_UNSUPPORTED, "the rim elimination needs the dense rim blocks (the plan holds a placed rim)");
     *bytes = schur_layout(p).total;
     return TP_OK;
 }

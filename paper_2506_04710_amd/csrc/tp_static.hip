@@ -43,18 +43,18 @@ static tp_status scratch_address(void **out) {
 static size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 // Workspace of one application to nrhs columns, as toeplitz_matvec uses it in
-// the plan: two transform grids [max(Ny Px, Px Py)][b nrhs] (complex128 slots),
-// the rim slab partials [nslab][Nr][nrhs], and for a half spectrum the mirror
-// parts [b / 8][Ny][Px - kxh][b].
+// the plan: two transform grids [max(Ny Px, Px Py)][bc nrhs] (complex128
+// slots; bc channels per cell), the rim slab partials [nslab][Nr][nrhs], and
+// for a half spectrum the mirror parts [bc / 8][Ny][Px - kxh][bc].
 struct StaticLayout {
     size_t grid, rimpart, ypart, total;
 };
 static StaticLayout static_layout(tp_plan p, int nrhs) {
     StaticLayout L;
     const size_t gpts = std::max((size_t)p->Ny * p->Px, (size_t)p->Px * p->Py);
-    L.grid = al256(gpts * (size_t)p->b * nrhs * 16);
+    L.grid = al256(gpts * (size_t)p->bc * nrhs * 16);
     L.rimpart = al256((size_t)p->rim_nslab * (p->Nr ? p->Nr : 1) * nrhs * 16);
-    L.ypart = p->half ? al256((size_t)((p->b + 7) / 8) * p->Ny * (p->Px - p->kxh) * p->b * 16) : 0;
+    L.ypart = p->half ? al256((size_t)((p->bc + 7) / 8) * p->Ny * (p->Px - p->kxh) * p->bc * 16) : 0;
     L.total = 2 * L.grid + L.rimpart + L.ypart;
     return L;
 }

@@ -260,3 +260,31 @@ def serving_stream(n_requests: int = 512, rate_hz: float = 100.0, seed: int = SE
 def serving_geometry(Nx: int, Ny: int, b: int, Nr: int = 0, seed: int = SEED_BASE + 5) -> Problem:
     """One cached geometry of the serving mix (seed derived from its key)."""
     return make_problem(Nx, Ny, b, Nr, [seed, Nx, Ny, b, Nr])
+
+
+def rim_placement(prob: Problem):
+    """Where each rim function sits as a channel of an element cell, for a
+    plan that takes the rim in its one-level block-Toeplitz form: an int32
+    array [Nr, 3] of (cell x, cell y, channel) and the channel count nrc.
+
+    Every part of a margin component is a translate of the component's first
+    part, so a component can be pinned to any column (row) of cells as long
+    as all its parts move together: side 2 (cells (Nx, iy)) is placed at
+    column Nx - 1, side 4 at row Ny - 1, the corners at the corner cells.
+    Side s takes channels [s bm, (s + 1) bm); each corner its own channels
+    after the sides'.  (This is metadata of the margin decomposition, not an
+    evaluation of any coupling.)"""
+    Nx, Ny, Nr = prob.Nx, prob.Ny, prob.Nr
+    bm, bc = margin_counts(Nx, Ny, Nr)
+    comps = _margin_components(Nx, Ny, Nr, prob.d)
+    place = np.zeros((Nr, 3), dtype=np.int32)
+    r0 = 0
+    ch0 = 0
+    for cells, _org, _size, nf in comps:
+        for (cx, cy) in cells:
+            for j in range(nf):
+                place[r0] = (min(cx, Nx - 1), min(cy, Ny - 1), ch0 + j)
+                r0 += 1
+        ch0 += nf
+    assert r0 == Nr
+    return place, ch0
