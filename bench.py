@@ -47,6 +47,12 @@ def parse():
                     help="only the headline solves (warmup + steps), for a kernel trace of the solve alone")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device-to-device copies of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--apply-only", choices=["mixed", "fp32", "fp64", "precond", "multi"], default=None,
+                    help="only 20 applications of one operator form on the headline plan (precond: the FP32 "
+                         "preconditioner on complex128 vectors; multi: the FP32 operator on the 81 port columns "
+                         "of the 9x9 array), for kernel traces and counters")
+    ap.add_argument("--placed", action="store_true",
+                    help="with --solves-only / --apply-only: the plan with the rim as placed channels")
     return ap.parse_args()
 
 
@@ -65,7 +71,7 @@ def copy_calibration(mib):
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("tp_matvec.h", "tp_apply_f32.hip", "tp_fft.h", "tp_common.h"):
+    for f in ("tp_matvec.h", "tp_apply_wide.hip", "tp_fft.h", "tp_common.h"):
         with open(os.path.join(ROOT, "paper_2506_04710_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -83,22 +89,48 @@ def algorithmic_bytes(prob, R, s, half):
     return s * (spectrum_blocks(prob, half) * prob.b ** 2 + prob.Nr * prob.N + prob.Nr ** 2 + 2 * prob.Nt * R)
 
 
-def spec_rim_bytes(prob, Px, s, half):
+def spec_rim_bytes(prob, Px, s, half, sv=None):
     """Algorithmic bytes of one launch of the fused spectrum+rim kernel: the
     spectrum stream, the rim block, the x-transformed input grid and the
-    output grid (rows iy < Ny), x_A in and the rim term out."""
+    output grid (rows iy < Ny), all of s bytes per value, and x_A in and the
+    rim term out, of sv bytes per value (the solve's FP32 operator works on
+    complex128 vectors: s = 8, sv = 16)."""
+    sv = s if sv is None else sv
     grid = prob.Ny * Px * prob.b
-    return s * (spectrum_blocks(prob, half) * prob.b ** 2 + prob.Nr * prob.N + 2 * grid + 2 * prob.N)
+    return s * (spectrum_blocks(prob, half) * prob.b ** 2 + prob.Nr * prob.N + 2 * grid) + sv * 2 * prob.N
+
+
+def cpu_model():
+    """CPU model name and the threads this process may use (the GPU machine's host)."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, len(os.sched_getaffinity(0))
 
 
 def cpu_baseline(prob, V, lu_shape=(8, 8)):
-    """The plain FP64 oracle on a bounded sample of the same workload."""
-    import numpy as np
+    """The plain FP64 oracle on the host cores: the headline operator's dense
+    matvec (on-the-fly rows, every row) on all threads and on one thread, and
+    a dense GEPP solve at the largest size run here (the same generators on an
+    lu_shape sub-array, n = lu_shape[0] lu_shape[1] b unknowns).  The oracle
+    has no iterative solver: its solve is the LU, so its solves/s at the full
+    size is the measured LU time scaled by (Nt / n)^3 (labelled as such)."""
     import oracle
     from synth import arrays as sa
     cores = oracle.max_threads()
-    # dense GEPP solve of the same generator family on an 8 x 8 sub-array
-    # (n = 4096 unknowns), scaled by (Nt / n)^3 to the full system
+    model, nproc = cpu_model()
+    t0 = time.perf_counter()
+    oracle.matvec(prob, V)
+    t_mv = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.matvec(prob, V, nthreads=1)
+    t_mv1 = time.perf_counter() - t0
     sub, Vs = sa.make_config(2, reduced=dict(Nx=lu_shape[0], Ny=lu_shape[1], Nr=0))
     Z = oracle.assemble(sub)
     n = Z.shape[0]
@@ -106,18 +138,15 @@ def cpu_baseline(prob, V, lu_shape=(8, 8)):
     oracle.lu_solve(Z, Vs)
     t_lu = time.perf_counter() - t0
     t_full = t_lu * (prob.Nt / n) ** 3
-    # one dense matvec by rows, on a row sample, scaled to all Nt rows
-    nrow = 512
-    rows = np.linspace(0, prob.Nt - 1, nrow).astype(np.int64)
-    t0 = time.perf_counter()
-    oracle.matvec(prob, V, rows=rows)
-    t_mv = (time.perf_counter() - t0) * prob.Nt / nrow
     return {
         "value": 1.0 / t_full, "unit": "solves/s", "cores": cores, "kind": "oracle",
-        "sample": f"GEPP LU + solve of the same generators on a {lu_shape[0]}x{lu_shape[1]} sub-array "
-                  f"(n={n}, {t_lu:.2f} s), scaled by (Nt/n)^3 to Nt={prob.Nt}: {t_full / 3600:.1f} h per "
-                  f"solve; dense FP64 matvec by rows on {nrow} rows scaled to all rows: {t_mv:.1f} s",
-        "matvec_s": round(t_mv, 2),
+        "sample": f"dense FP64 matvec of the headline operator over all {prob.Nt} rows, measured: {t_mv:.2f} s on "
+                  f"{cores} threads, {t_mv1:.2f} s on 1 thread; GEPP LU + solve measured at n={n} (the same "
+                  f"generators on a {lu_shape[0]}x{lu_shape[1]} sub-array): {t_lu:.2f} s on {cores} threads; value "
+                  f"= that LU time scaled by (Nt/n)^3 to Nt={prob.Nt} ({t_full / 3600:.1f} h per solve, "
+                  f"extrapolated, not run)",
+        "matvec_s_all_threads": round(t_mv, 3), "matvec_s_1_thread": round(t_mv1, 3),
+        "lu_n": n, "lu_s_measured": round(t_lu, 3), "cpu_model": model, "nproc": nproc,
     }
 
 
@@ -152,8 +181,12 @@ def multi_rhs(dev, K=3):
     total, lat, (x, inf) = timed_solves(plan, v, K, 1, mode="mixed", precond=True)
     assert all(i["status"] == 0 and i["relres"] <= 1e-8 for i in inf), inf
     st = plan.matvec_profile(v.to(torch.complex64), which="fp32", reps=20)
-    Pg = plan.info()["Px"] * plan.info()["Py"]
-    flops = 8.0 * Pg * prob.b ** 2 * R
+    # algorithmic work at the minimal embedding (2Nx - 1)(2Ny - 1) = 17 x 17,
+    # not the padded 18 x 18 grid the kernels run on
+    Pa = (2 * prob.Nx - 1) * (2 * prob.Ny - 1)
+    flops = 8.0 * Pa * prob.b ** 2 * R
+    flops_rim = 16.0 * prob.Nr * prob.N * R + 8.0 * prob.Nr ** 2 * R
+    whole_us = sum(st.values()) * 1e3
     rows = np.nonzero(V)[1]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -168,7 +201,10 @@ def multi_rhs(dev, K=3):
            "prod_mfma": {"tflops": round(flops / (st["prod"] * 1e-3) / 1e12, 1),
                          "peak_tflops_fp32_mfma": 157.3,
                          "frac": round(flops / (st["prod"] * 1e-3) / 1e12 / 157.3, 3),
-                         "flops_per_launch": flops},
+                         "flops_per_launch": flops, "grid": "algorithmic 17x17"},
+           "whole_matvec": {"us": round(whole_us, 2), "flops": flops + flops_rim,
+                            "frac_fp32_mfma": round((flops + flops_rim) / (whole_us * 1e-6) / 1e12 / 157.3, 3),
+                            "note": "sum of the stage intervals (HIP events, each with its recording overhead)"},
            "smatrix_ms": round(1e3 * t_s, 2), "smatrix_max_asymmetry": float(np.abs(S - S.T).max())}
     plan.close()
     return out
@@ -196,19 +232,59 @@ def precision(dev, K=2):
             "max_relres": max(i["relres"] for i in inf), "max_rel_diff_vs_fp64": err}
 
 
-def solves_only(K, W):
+def headline_plan(tp, prob, placed, max_rhs=1, device="cuda:0"):
+    """The headline plan: dense rim blocks, or the rim as placed channels."""
+    from synth import arrays as sa
+    kw = {"rim_place": sa.rim_placement(prob)} if placed else {}
+    return tp.Plan.create(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, prec="mixed",
+                          max_rhs=max_rhs, restart=40, device=device, **kw)
+
+
+def apply_only(which, placed, K=20):
+    """K applications of one operator form on the headline plan (kernel traces
+    and HBM counters of its launches): mixed / fp32 / fp64 operator, the FP32
+    preconditioner on complex128 vectors, or the FP32 operator on the 81 port
+    columns of the 9 x 9 array (multi)."""
+    import torch
+    import paper_2506_04710_amd as tp
+    from synth import arrays as sa
+    tp.load()
+    if which == "multi":
+        prob, V = sa.make_config(3)
+        plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=V.shape[0], restart=4)
+        xv = torch.from_numpy(V).to("cuda:0").to(torch.complex64)
+        for _ in range(K):
+            plan.matvec(xv, which="fp32")
+    else:
+        prob, V = sa.make_config(2)
+        plan = headline_plan(tp, prob, placed)
+        dt = torch.complex64 if which == "fp32" else torch.complex128
+        xv = torch.from_numpy(V).to("cuda:0").to(dt)
+        if which == "precond":
+            plan.precond_create()
+            for _ in range(K):
+                plan.precond_apply(xv, which="mixed")
+        else:
+            for _ in range(K):
+                plan.matvec(xv, which=which)
+    torch.cuda.synchronize()
+    print(json.dumps({"apply_only": which, "placed": placed, "applications": K}), flush=True)
+    plan.close()
+
+
+def solves_only(K, W, placed=False):
     """The headline solve alone (mixed + preconditioner, one RHS), K timed after W."""
     import torch
     import paper_2506_04710_amd as tp
     from synth import arrays as sa
     tp.load()
     prob, V = sa.make_config(2)
-    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=1, restart=40).precond_create()
+    plan = headline_plan(tp, prob, placed).precond_create()
     v = torch.from_numpy(V).to("cuda:0")
     total, _, (_, inf) = timed_solves(plan, v, K, W, mode="mixed", precond=True)
     assert inf[0]["status"] == 0 and inf[0]["relres"] <= 1e-8, inf
     print(json.dumps({"solves_per_s": round(K / total, 2), "steps": K, "warmup": W, "iters": inf[0]["iters"],
-                      "outer": inf[0]["outer_iters"]}), flush=True)
+                      "outer": inf[0]["outer_iters"], "placed": placed}), flush=True)
     plan.close()
 
 
@@ -247,13 +323,48 @@ def schur(dev, K):
             "outer": inf[0]["outer_iters"], "relres": inf[0]["relres"], "rel_diff_vs_direct": diff}
 
 
-def serving(dev, n_requests=512):
-    """Seeded Poisson stream of 512 requests over the serving mix of geometries."""
+def structured_rim(dev, K):
+    """The headline workload on a plan that holds the rim as placed channels
+    of the element cells (one extended spectrum, no dense B or C): the same
+    preconditioned mixed and plain FP64 solves, and its operator launches."""
     import numpy as np
+    import torch
+    import paper_2506_04710_amd as tp
+    from synth import arrays as sa
+    prob, V = sa.make_config(2)
+    plan = headline_plan(tp, prob, True, device=dev).precond_create()
+    info = plan.info()
+    v = torch.from_numpy(V).to(dev)
+    total, lat, (_, inf) = timed_solves(plan, v, K, 3, mode="mixed", precond=True)
+    assert inf[0]["status"] == 0 and inf[0]["relres"] <= 1e-8, inf
+    total64, _, (_, inf64) = timed_solves(plan, v, max(3, K // 3), 1, mode="fp64")
+    assert inf64[0]["status"] == 0 and inf64[0]["relres"] <= 1e-8, inf64
+    stages = {w: plan.matvec_profile(v.to(dt), which=w, reps=30)
+              for w, dt in (("mixed", torch.complex128), ("fp64", torch.complex128))}
+    plan.close()
+    s_bytes = (prob.Nx * (2 * prob.Ny - 1)) * info["bc"] ** 2       # stored half spectrum at 2N - 1
+    return {"workload": "as the headline, rim as 8 placed channels per cell (72 channels, extended spectrum)",
+            "solves_per_s": round(K / total, 2), "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+            "iters": inf[0]["iters"], "outer": inf[0]["outer_iters"], "relres": inf[0]["relres"],
+            "fp64_plain_solves_per_s": round(max(3, K // 3) / total64, 2),
+            "spectrum_bytes_fp32": s_bytes * 8,
+            "fused_launch_us": {w: round(st["prod"] * 1e3, 2) for w, st in stages.items()},
+            "matvec_us": {w: round(sum(st.values()) * 1e3, 2) for w, st in stages.items()}}
+
+
+def serving(dev, n_requests=512):
+    """Seeded Poisson stream of 512 requests over the serving mix of geometries
+    (the arrival rate is not given by the paper): the continuous-batching
+    server (mixed + preconditioner, 16 slots per plan) at saturation, then the
+    same stream re-timed to 0.5x and 0.9x of that saturation rate; the same
+    stream through a plain FP64 single-RHS server (one slot per plan, no
+    preconditioner) at saturation; and the batched server under an HBM budget
+    small enough to force admission waits and evictions."""
     import torch
     from paper_2506_04710_amd.serve import Server, Request
     from synth import arrays as sa
-    stream = sa.serving_stream(n_requests)
+    base_rate = 100.0
+    stream = sa.serving_stream(n_requests, rate_hz=base_rate)
     keys = sorted({(r["Nx"], r["Ny"], r["b"]) for r in stream})
     G = {k: sa.serving_geometry(*k) for k in keys}
 
@@ -261,26 +372,48 @@ def serving(dev, n_requests=512):
         p = G[k]
         return p.Nx, p.Ny, p.b, p.Nr, p.gen, p.rim_re, p.rim_rr
 
-    def reqs():
-        return [Request(id=r["id"], t=r["t"], key=(r["Nx"], r["Ny"], r["b"]),
+    def reqs(rate=None):
+        scale = 1.0 if rate is None else base_rate / rate
+        return [Request(id=r["id"], t=r["t"] * scale, key=(r["Nx"], r["Ny"], r["b"]),
                         V=sa.rhs_ports(G[(r["Nx"], r["Ny"], r["b"])], r["elements"])) for r in stream]
 
+    keep = ("requests", "columns", "wall_s", "requests_per_s", "solves_per_s", "p50_ms", "p99_ms", "max_relres",
+            "all_ok", "plans_created", "plans_evicted")
+    rnd = lambda d: {k: (round(d[k], 4) if isinstance(d[k], float) and k != "max_relres" else d[k]) for k in keep}
     srv = Server(geometry, slots=16, mode="mixed", tol=1e-8, restart=40, hbm_budget=160 << 30, precond=True,
                  device=dev)
     t0 = time.perf_counter()
     srv.warm(keys)
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
+    hbm_all = srv.used
     sat = srv.run(reqs(), realtime=False)
-    live = srv.run(reqs(), realtime=True)
+    lam = sat["requests_per_s"]
+    at = {f"{f}x_saturation": rnd(dict(srv.run(reqs(f * lam), realtime=True), offered_rate=round(f * lam, 1)))
+          for f in (0.5, 0.9)}
     srv.close()
-    keep = ("requests", "columns", "wall_s", "requests_per_s", "solves_per_s", "p50_ms", "p99_ms", "max_relres",
-            "all_ok")
-    r = lambda d: {k: (round(d[k], 4) if isinstance(d[k], float) and k != "max_relres" else d[k]) for k in keep}
-    return {"workload": f"{n_requests} requests, Poisson arrivals at 100/s, {len(keys)} geometries (Nx, Ny in "
-                        "{8..48}, b in {32, 64}), 1-16 ports each, mixed + preconditioner, tol 1e-8, 16 slots per "
-                        "plan", "plans_warm_s": round(t_warm, 2), "hbm_used_gib": round(sat["hbm_used"] / 2 ** 30, 2),
-            "saturation": r(sat), "at_stream_rate": r(live)}
+    # plain FP64, one right-hand side at a time per geometry
+    plain = Server(geometry, slots=1, mode="fp64", tol=1e-8, restart=40, hbm_budget=160 << 30, precond=False,
+                   device=dev)
+    plain.warm(keys)
+    torch.cuda.synchronize()
+    sat64 = plain.run(reqs(), realtime=False)
+    plain.close()
+    # HBM pressure: a budget of 8 GiB (all plans warm need about 27 GiB), at
+    # least 1.5x the largest single plan so that every request can be admitted
+    tight = Server(geometry, slots=16, mode="mixed", tol=1e-8, restart=40, hbm_budget=8 << 30, precond=True,
+                   device=dev)
+    tight.budget = max(tight.budget, int(1.5 * max(tight._need(k) for k in keys)))
+    press = tight.run(reqs(), realtime=False)
+    tight.close()
+    return {"workload": f"{n_requests} requests, Poisson arrivals (seeded), {len(keys)} geometries (Nx, Ny in "
+                        "{8..48}, b in {32, 64}), 1-16 ports each, tol 1e-8",
+            "batched": "mixed + preconditioner, 16 slots per plan, continuous batching",
+            "plans_warm_s": round(t_warm, 2), "hbm_all_plans_gib": round(hbm_all / 2 ** 30, 2),
+            "saturation": rnd(sat), **at,
+            "fp64_plain_single_rhs_saturation": rnd(sat64),
+            "speedup_vs_fp64_plain_single_rhs": round(sat["solves_per_s"] / sat64["solves_per_s"], 2),
+            "hbm_budget_saturation": dict(rnd(press), budget_gib=round(tight.budget / 2 ** 30, 2))}
 
 
 def main():
@@ -293,7 +426,10 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.solves_only:
-        solves_only(args.steps, args.warmup)
+        solves_only(args.steps, args.warmup, args.placed)
+        return
+    if args.apply_only:
+        apply_only(args.apply_only, args.placed)
         return
     import numpy as np
     import torch
@@ -336,28 +472,31 @@ def main():
     gbs = {}
     stage = {}
     stage_warm = {}
-    for which, dt, s in (("fp32", torch.complex64, 8), ("fp64", torch.complex128, 16)):
+    # mixed: the FP32 operator on complex128 vectors, the instance the solve runs
+    for which, dt, s in (("mixed", torch.complex128, 8), ("fp32", torch.complex64, 8),
+                         ("fp64", torch.complex128, 16)):
         xv = v.to(dt)
         for _ in range(3):
-            plan.matvec(xv)
+            plan.matvec(xv, which=which)
         torch.cuda.synchronize()
         reps = 30
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for e0, e1 in ev:
             flush.sum()
             e0.record()
-            plan.matvec(xv)
+            plan.matvec(xv, which=which)
             e1.record()
         torch.cuda.synchronize()
         ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
         for _ in range(reps):
-            plan.matvec(xv)
+            plan.matvec(xv, which=which)
         ev1.record()
         torch.cuda.synchronize()
         ms_warm = ev0.elapsed_time(ev1) / reps
-        nb = algorithmic_bytes(prob, 1, s, half)
+        # vectors in and out are complex128 in the mixed form
+        nb = algorithmic_bytes(prob, 1, s, half) + (2 * prob.Nt * 8 if which == "mixed" else 0)
         gbs[which] = {"us": round(ms * 1e3, 2), "GB_s": round(nb / (ms * 1e-3) / 1e9, 1),
                       "us_warm": round(ms_warm * 1e3, 2), "GB_s_warm": round(nb / (ms_warm * 1e-3) / 1e9, 1)}
         cold = []
@@ -368,11 +507,12 @@ def main():
         stage_warm[which] = plan.matvec_profile(xv, which=which, reps=50)
     del flush
     # dominant kernel of the timed solve: the fused spectrum+rim launch of the
-    # FP32 operator (it carries both HBM streams); its duration from HIP events
-    # recorded on the stream it is launched on, after the MALL flush
-    k_ms = stage["fp32"]["prod"]
-    k_ms_warm = stage_warm["fp32"]["prod"]
-    k_bytes = spec_rim_bytes(prob, Px, 8, half)
+    # FP32 operator on complex128 vectors (it carries both HBM streams); its
+    # duration from HIP events recorded on the stream it is launched on, after
+    # the MALL flush
+    k_ms = stage["mixed"]["prod"]
+    k_ms_warm = stage_warm["mixed"]["prod"]
+    k_bytes = spec_rim_bytes(prob, Px, 8, half, sv=16)
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     sha = kernel_source_sha()
     traffic = TRAFFIC["bytes"] if TRAFFIC["source_sha256"] == sha else None
@@ -412,7 +552,9 @@ def main():
         "matvec_stages_us_warm": {w: {k: round(v_ * 1e3, 2) for k, v_ in st.items()} for w, st in stage_warm.items()},
         "plan_create_s": round(t_plan, 3),
         "precond_create_s": round(t_pc, 3),
-        "roofline": {"kernel": "k_spec_rim<float> (stored spectrum half, mirror parts + rim pass, fused)", "bound": "hbm",
+        "roofline": {"kernel": "k_spec_rim<float, cpx<double>, cpx<double>> (FP32 operator on complex128 "
+                               "vectors, as in the mixed solve: stored spectrum half, mirror parts + rim pass, "
+                               "fused)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": int(k_bytes), "launch_us": round(k_ms * 1e3, 2),
@@ -425,6 +567,7 @@ def main():
         line["precision"] = precision(dev)
         line["serving"] = serving(dev)
         line["schur"] = schur(dev, args.steps)
+        line["structured_rim"] = structured_rim(dev, args.steps)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, V)
     print(json.dumps(line), flush=True)

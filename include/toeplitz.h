@@ -177,6 +177,30 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
                                       int restart, void *dev_buf, size_t dev_bytes, void *hip_stream,
                                       tp_plan *out);
 
+/*
+ * Launch options of a plan: kernel variants that compute the same result
+ * (bit for bit within one option value) at different speeds on different
+ * shapes; the tuner (toeplitz_tune) measures them and sets the fastest.
+ *   TP_OPT_SPECTRUM_PASS  one column without a dense rim pass over a half
+ *     spectrum (the preconditioner, and the operator of a placed rim):
+ *     TP_PASS_FUSED  one launch per column chunk that transforms along y,
+ *                    streams the stored blocks and transforms back;
+ *     TP_PASS_PAIRS  y transforms in passes of their own and a stream that
+ *                    reads each stored block once in its own workgroup and
+ *                    applies it to its frequency and, transposed, to the
+ *                    mirror frequency;
+ *     TP_PASS_AUTO   (default) the fused launch.
+ * Setting an option drops the plan's captured solver graphs.  Errors:
+ * TP_E_INVAL (unknown option or value, NULL pointers, a continuous batch is
+ * active on the plan).
+ */
+#define TP_OPT_SPECTRUM_PASS 1
+#define TP_PASS_AUTO 0
+#define TP_PASS_FUSED 1
+#define TP_PASS_PAIRS 2
+tp_status toeplitz_plan_set_option(tp_plan p, int option, int value);
+tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value);
+
 /* Copy the plan's layout facts into *desc. */
 tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *desc);
 

@@ -153,6 +153,16 @@ class Plan:
     def from_problem(cls, prob, **kw):
         return cls.create(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, **kw)
 
+    def set_option(self, option, value):
+        """Launch option (toeplitz_plan_set_option), e.g. spectrum pass."""
+        check(_lib.lib().toeplitz_plan_set_option(self._h, option, value))
+        return self
+
+    def get_option(self, option) -> int:
+        v = ctypes.c_int(0)
+        check(_lib.lib().toeplitz_plan_get_option(self._h, option, ctypes.byref(v)))
+        return v.value
+
     def info(self) -> dict:
         d = _lib.PlanDesc()
         check(_lib.lib().toeplitz_plan_info(self._h, ctypes.byref(d)))

@@ -29,8 +29,10 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_far_field", "toeplitz_precond_bytes", "toeplitz_precond_create", "toeplitz_precond_apply",
            "toeplitz_precond_bytes_for", "toeplitz_gen_symmetric", "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve",
            "toeplitz_matvec_static", "toeplitz_static_scratch_bytes", "toeplitz_plan_bytes_placed",
-           "toeplitz_plan_create_placed")
+           "toeplitz_plan_create_placed", "toeplitz_plan_set_option", "toeplitz_plan_get_option")
 TP_SYM_RIM, TP_SYM_GEN = 1, 2
+TP_OPT_SPECTRUM_PASS = 1
+TP_PASS_AUTO, TP_PASS_FUSED, TP_PASS_PAIRS = 0, 1, 2
 
 
 class PlanDesc(ctypes.Structure):
@@ -82,6 +84,8 @@ def lib():
         L.toeplitz_plan_bytes_placed.argtypes = [ci, ci, ci, ci, ci, ci, ci, ci, ci, ctypes.POINTER(sz)]
         L.toeplitz_plan_create_placed.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, ci, ci, ci, ci, vp, sz, vp,
                                                   ctypes.POINTER(vp)]
+        L.toeplitz_plan_set_option.argtypes = [vp, ci, ci]
+        L.toeplitz_plan_get_option.argtypes = [vp, ci, ctypes.POINTER(ci)]
         L.toeplitz_plan_info.argtypes = [vp, ctypes.POINTER(PlanDesc)]
         L.toeplitz_matvec.argtypes = [vp, ci, vp, cl, vp, cl, ci, vp]
         L.toeplitz_matvec_static.argtypes = [vp, ci, vp, cl, vp, cl, ci, vp]

@@ -495,6 +495,29 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
                        out);
 }
 
+tp_status toeplitz_plan_set_option(tp_plan p, int option, int value) {
+    if (!p) return fail(TP_E_INVAL, "plan is NULL");
+    if (p->batch && solver_batch_active(p)) return fail(TP_E_INVAL, "a continuous batch is active on this plan");
+    switch (option) {
+        case TP_OPT_SPECTRUM_PASS:
+            if (value != TP_PASS_AUTO && value != TP_PASS_FUSED && value != TP_PASS_PAIRS)
+                return fail(TP_E_INVAL, "unknown spectrum pass");
+            solver_drop_graphs(p);     // captured graphs hold the launch shapes
+            p->opt_spectrum_pass = value;
+            return TP_OK;
+        default:
+            return fail(TP_E_INVAL, "unknown option");
+    }
+}
+
+tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value) {
+    if (!p || !value) return fail(TP_E_INVAL, "plan or value is NULL");
+    switch (option) {
+        case TP_OPT_SPECTRUM_PASS: *value = p->opt_spectrum_pass; return TP_OK;
+        default: return fail(TP_E_INVAL, "unknown option");
+    }
+}
+
 tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *d) {
     if (!p || !d) return fail(TP_E_INVAL, "NULL argument");
     d->Nx = p->Nx; d->Ny = p->Ny; d->b = p->b; d->Nr = p->Nr;

@@ -317,6 +317,8 @@ struct tp_plan_s {
     char *ws;
     size_t ws_bytes;
     size_t workspace_bytes;
+    // launch options (toeplitz_plan_set_option; the tuner sets them)
+    int opt_spectrum_pass = TP_PASS_AUTO;
     // solver launch resources, created on the first solve and released by
     // toeplitz_plan_destroy: a stream for graph capture and replay (default
     // priority), events ordering it against the caller's stream, pinned host

@@ -494,6 +494,76 @@ __device__ __forceinline__ void rs8(cpx<T> (&v)[V], int lane) {
 
 constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 1) / 2); }
 
+// ------------------------------------ one column, half spectrum: pair stream
+// The per-frequency product of one column over a half spectrum with the y
+// transforms in passes of their own (no transform work inside): workgroup =
+// one stored block s = (kx, ky), kx < kxh.  The block is read once and applied
+// to its own frequency, yhat(kx, ky) = G xhat(kx, ky), and, when its mirror
+// frequency (Px - kx, -ky) is not stored, transposed to it: yhat(-k) =
+// G^T xhat(-k).  Wave w takes rows p = 8 w .. 8 w + 7 with 8 lanes per row;
+// lane l holds G[p][q] for q in [(l & 7) VPL, (l & 7) VPL + VPL).  Row sums
+// add the 8 lanes of a row (DPP); column sums add the 8 rows of a wave (rs8)
+// and then the waves, in wave order, in LDS.  One workgroup per stored block
+// keeps the stream balanced over the compute units whatever the block width;
+// every block's loads issue before anything else.
+template <typename T, int VPL>
+__global__ void __launch_bounds__(1024) k_pair_prod(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ in,
+                                                    int b, int Px, int Py, int kxh, cpx<T> *__restrict__ out,
+                                                    const void *const *act) {
+    constexpr int VP = pow2_at_least(VPL), S = RS8<VP>::S, NV = RS8<VP>::NV;
+    extern __shared__ char smem_raw[];
+    if (!cols_live(act, 0, 0)) return;                 // an idle column (solver phases)
+    const int nw = blockDim.x >> 6;
+    cpx<T> *xk = reinterpret_cast<cpx<T> *>(smem_raw);   // [b] xhat(k)
+    cpx<T> *xm = xk + b;                                   // [b] xhat(-k)
+    cpx<T> *zp = xm + b;                                   // [nw][b] column sums per wave
+    const int s = blockIdx.x;
+    const int kx = s / Py, ky = s - kx * Py;
+    const bool mir = kx > 0 && Px - kx >= kxh;
+    const long k = (long)kx * Py + ky;
+    const long km = (long)(Px - kx) * Py + (ky == 0 ? 0 : Py - ky);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int pl = lane >> 3, qs = (lane & 7) * VPL, p = w * 8 + pl;
+    const bool prow = p < b;
+    const cpx<T> *Grow = G + (long)s * b * b + (long)min(p, b - 1) * b;
+    cpx<T> g[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) g[v] = Grow[min(qs + v, b - 1)];
+    for (int i = threadIdx.x; i < b; i += blockDim.x) {
+        xk[i] = in[k * b + i];
+        if (mir) xm[i] = in[km * b + i];
+    }
+    __syncthreads();
+    bool qok[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) qok[v] = prow && qs + v < b;
+    cpx<T> acc = mk<T>(0, 0);
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) acc = cmac(acc, keep(g[v], qok[v]), xk[min(qs + v, b - 1)]);
+    acc = sum8(acc);
+    if ((lane & 7) == 0 && prow) out[k * b + p] = acc;
+    if (!mir) return;                                  // uniform over the workgroup
+    const cpx<T> xv = xm[min(p, b - 1)];
+    cpx<T> m[VP];
+#pragma unroll
+    for (int v = 0; v < VP; ++v) m[v] = v < VPL ? keep(g[v], qok[v]) * xv : mk<T>(0, 0);
+    rs8<T, VP>(m, lane);
+    const int grp = pl >> (3 - S);
+    const bool writer = (pl & ((1 << (3 - S)) - 1)) == 0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int v = i + (VP >> S) * grp;
+        if (writer && v < VPL && qs + v < b) zp[w * b + qs + v] = m[i];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < b; q += blockDim.x) {
+        cpx<T> t = zp[q];
+        for (int u = 1; u < nw; ++u) t = t + zp[u * b + q];
+        out[km * b + q] = t;
+    }
+}
+
+
 // Fused single-column path over half the spectrum.  A symmetric operator
 // (Z_{-m,-n} = Z_{m,n}^T, Sec. II-B) has Ghat(-k) = Ghat(k)^T, and the plan
 // stores the columns kx < kxh = Px / 2 + 1 only.  Workgroup = stored column kx
@@ -1246,6 +1316,23 @@ static void launch_spec_rim(tp_plan pl, const cpx<T> *G, Cols<const In> x, Cols<
                            x, y, pl->N, pl->Nr, reinterpret_cast<cpx<T> *>(pl->rim_part), nrim, yp, pl->kxh);
 }
 
+// Pair stream over the stored half spectrum, one column (gB -> gA).
+template <typename T>
+static void launch_pair_prod(tp_plan pl, const cpx<T> *G, const cpx<T> *in, cpx<T> *out, const void *const *act,
+                             hipStream_t st) {
+    const int b = pl->bc, nw = (b + 7) / 8, vpl = (b + 7) / 8;
+    const size_t sh = (size_t)(2 + nw) * b * sizeof(cpx<T>);
+    const dim3 grid((unsigned)(pl->kxh * pl->Py)), blk((unsigned)(64 * nw));
+    const int Px = pl->Px, Py = pl->Py, kxh = pl->kxh;
+    if (vpl <= 2) hipLaunchKernelGGL((k_pair_prod<T, 2>), grid, blk, sh, st, G, in, b, Px, Py, kxh, out, act);
+    else if (vpl <= 4) hipLaunchKernelGGL((k_pair_prod<T, 4>), grid, blk, sh, st, G, in, b, Px, Py, kxh, out, act);
+    else if (vpl <= 6) hipLaunchKernelGGL((k_pair_prod<T, 6>), grid, blk, sh, st, G, in, b, Px, Py, kxh, out, act);
+    else if (vpl <= 8) hipLaunchKernelGGL((k_pair_prod<T, 8>), grid, blk, sh, st, G, in, b, Px, Py, kxh, out, act);
+    else if (vpl <= 9) hipLaunchKernelGGL((k_pair_prod<T, 9>), grid, blk, sh, st, G, in, b, Px, Py, kxh, out, act);
+    else if (vpl <= 12) hipLaunchKernelGGL((k_pair_prod<T, 12>), grid, blk, sh, st, G, in, b, Px, Py, kxh, out, act);
+    else hipLaunchKernelGGL((k_pair_prod<T, 16>), grid, blk, sh, st, G, in, b, Px, Py, kxh, out, act);
+}
+
 // rim: whether the launch carries the rim pass (the operator with Nr > 0)
 template <typename T, typename In, typename Out, int VPL>
 static void launch_spec_rim_e(tp_plan pl, const cpx<T> *G, bool rim, Cols<const In> x, Cols<Out> y, cpx<T> *gA,
@@ -1347,8 +1434,12 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     const cpx<T> *G = PRE ? OpPtrs<T>::S(pl) : OpPtrs<T>::G(pl);
     const bool rim = !PRE && Nr > 0 && pl->nrc == 0;   // dense rim pass
     const size_t sh_fused = std::max(spec_lds(pl, es), rim ? rim_lds(pl, 1, es) : (size_t)0);
+    // one column without a rim pass over a half spectrum: the fused path or the
+    // pair stream (y transforms in passes of their own), as the plan's option
+    // says (the tuner picks it; without a choice the fused path)
+    const bool pairs = R == 1 && !rim && pl->half && b <= 128 && pl->opt_spectrum_pass == TP_PASS_PAIRS;
     // one column: the fused path (for a half spectrum, rows of at most 96)
-    const bool fused = R == 1 && sh_fused <= kLdsLimit && !(pl->half && b > 96);
+    const bool fused = !pairs && R == 1 && sh_fused <= kLdsLimit && !(pl->half && b > 96);
 
     // many columns: the product and the rim run on the matrix cores
     const bool mfma = !fused && R >= kMfmaMinR;
@@ -1395,6 +1486,8 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         else if (vpl <= 12) launch_spec_rim_e<T, In, Out, 12>(pl, G, rim, x, y, gA, gB, sh_fused, st);
         else if (vpl <= 16) launch_spec_rim_e<T, In, Out, 16>(pl, G, rim, x, y, gA, gB, sh_fused, st);
         else launch_spec_rim_e<T, In, Out, 32>(pl, G, rim, x, y, gA, gB, sh_fused, st);
+    } else if (pairs) {
+        launch_pair_prod<T>(pl, G, gB, gA, act, st);
     } else if (mfma) {
         prod_mfma<T>(G, gB, b, R, Px, Py, pl->kxh, gA, act, st);
     } else {
