@@ -3,10 +3,11 @@
 broadside plane-wave excitation, on one MI355X.
 
 One step = one complete solve of Z x = v to ||v - Z x|| / ||v|| <= 1e-8
-(FP64 residual), in the fastest form (FP32 operator and block-circulant
-preconditioner inside FP64 iterative refinement, all Krylov arithmetic FP64),
-with the plan (generator spectrum, rim blocks, preconditioner) resident in HBM
-and the right-hand side on the device.  The same GPU's plain FP64 GMRES is
+(FP64 residual), in the fastest form (the rim as placed channels of the
+element cells, FP32 operator and block-circulant preconditioner inside FP64
+iterative refinement, all Krylov arithmetic FP64, launch options tuned), with
+the plan (extended generator spectrum, preconditioner) resident in HBM and the
+right-hand side on the device.  The same GPU's plain FP64 GMRES is
 timed beside it ("vs FP64 plain"), together with the operator's achieved
 bandwidth, per-solve latency percentiles, the roofline fraction of the
 dominant kernel and the plain FP64 CPU oracle on a bounded sample.  Unless
@@ -256,12 +257,16 @@ def apply_only(which, placed, K=20):
         for _ in range(K):
             plan.matvec(xv, which="fp32")
     else:
+        from paper_2506_04710_amd import tune
         prob, V = sa.make_config(2)
         plan = headline_plan(tp, prob, placed)
         dt = torch.complex64 if which == "fp32" else torch.complex128
         xv = torch.from_numpy(V).to("cuda:0").to(dt)
         if which == "precond":
             plan.precond_create()
+        if placed or which == "precond":
+            tune.tune(plan, "mixed", 1)
+        if which == "precond":
             for _ in range(K):
                 plan.precond_apply(xv, which="mixed")
         else:
@@ -280,6 +285,8 @@ def solves_only(K, W, placed=False):
     tp.load()
     prob, V = sa.make_config(2)
     plan = headline_plan(tp, prob, placed).precond_create()
+    from paper_2506_04710_amd import tune
+    tune.tune(plan, "mixed", 1)
     v = torch.from_numpy(V).to("cuda:0")
     total, _, (_, inf) = timed_solves(plan, v, K, W, mode="mixed", precond=True)
     assert inf[0]["status"] == 0 and inf[0]["relres"] <= 1e-8, inf
@@ -321,35 +328,6 @@ def schur(dev, K):
                         "through C - B A^-1 B_er, element solves mixed + preconditioner",
             "setup_s": round(t_setup, 3), "solves_per_s": round(K / total, 2), "iters": inf[0]["iters"],
             "outer": inf[0]["outer_iters"], "relres": inf[0]["relres"], "rel_diff_vs_direct": diff}
-
-
-def structured_rim(dev, K):
-    """The headline workload on a plan that holds the rim as placed channels
-    of the element cells (one extended spectrum, no dense B or C): the same
-    preconditioned mixed and plain FP64 solves, and its operator launches."""
-    import numpy as np
-    import torch
-    import paper_2506_04710_amd as tp
-    from synth import arrays as sa
-    prob, V = sa.make_config(2)
-    plan = headline_plan(tp, prob, True, device=dev).precond_create()
-    info = plan.info()
-    v = torch.from_numpy(V).to(dev)
-    total, lat, (_, inf) = timed_solves(plan, v, K, 3, mode="mixed", precond=True)
-    assert inf[0]["status"] == 0 and inf[0]["relres"] <= 1e-8, inf
-    total64, _, (_, inf64) = timed_solves(plan, v, max(3, K // 3), 1, mode="fp64")
-    assert inf64[0]["status"] == 0 and inf64[0]["relres"] <= 1e-8, inf64
-    stages = {w: plan.matvec_profile(v.to(dt), which=w, reps=30)
-              for w, dt in (("mixed", torch.complex128), ("fp64", torch.complex128))}
-    plan.close()
-    s_bytes = (prob.Nx * (2 * prob.Ny - 1)) * info["bc"] ** 2       # stored half spectrum at 2N - 1
-    return {"workload": "as the headline, rim as 8 placed channels per cell (72 channels, extended spectrum)",
-            "solves_per_s": round(K / total, 2), "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
-            "iters": inf[0]["iters"], "outer": inf[0]["outer_iters"], "relres": inf[0]["relres"],
-            "fp64_plain_solves_per_s": round(max(3, K // 3) / total64, 2),
-            "spectrum_bytes_fp32": s_bytes * 8,
-            "fused_launch_us": {w: round(st["prod"] * 1e3, 2) for w, st in stages.items()},
-            "matvec_us": {w: round(sum(st.values()) * 1e3, 2) for w, st in stages.items()}}
 
 
 def serving(dev, n_requests=512):
@@ -439,42 +417,56 @@ def main():
     tp.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    from paper_2506_04710_amd import tune
     prob, V = sa.make_config(2)
+    # headline plan: the rim as placed channels of the element cells (one
+    # extended spectrum, no dense B or C), its preconditioner, tuned options
     t0 = time.perf_counter()
-    plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=1, restart=40, device=dev)
+    plan = headline_plan(tp, prob, True, device=dev)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     t0 = time.perf_counter()
     plan.precond_create()
     t_pc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tuned = tune.tune(plan, "mixed", 1)
+    t_tune = time.perf_counter() - t0
     info = plan.info()
-    Px, Py = info["Px"], info["Py"]
+    Px, Py, bc = info["Px"], info["Py"], info["bc"]
     half = bool(info["half_spectrum"])       # symmetric generators: half the spectrum is stored
     v = torch.from_numpy(V).to(dev)
 
     # headline: the fastest form (FP32 operator and preconditioner inside FP64
-    # refinement); then the same GPU's plain FP64 GMRES and two intermediate forms
+    # refinement) on the headline plan; then the same GPU's plain FP64 GMRES on
+    # a plan with the dense rim blocks (no structure beyond the element
+    # Toeplitz blocks, no preconditioner), and intermediate forms
     total, lat, (x, inf) = timed_solves(plan, v, args.steps, args.warmup, mode="mixed", precond=True)
     assert inf[0]["status"] == 0 and inf[0]["relres"] <= 1e-8, inf
-    total64, lat64, (_, inf64) = timed_solves(plan, v, args.steps, args.warmup, mode="fp64")
+    dense = headline_plan(tp, prob, False, device=dev)
+    total64, lat64, (_, inf64) = timed_solves(dense, v, args.steps, args.warmup, mode="fp64")
     assert inf64[0]["status"] == 0 and inf64[0]["relres"] <= 1e-8, inf64
     kb = max(3, args.steps // 3)
+    dense.precond_create()
+    totd, _, (_, infd) = timed_solves(dense, v, kb, 1, mode="mixed", precond=True)
+    dense.close()
+    del dense
     totm, _, (_, infm) = timed_solves(plan, v, kb, 1, mode="mixed")
     totp, _, (_, infp) = timed_solves(plan, v, kb, 1, mode="fp64", precond=True)
+    tot64s, _, (_, inf64s) = timed_solves(plan, v, kb, 1, mode="fp64")
 
     # operator bandwidth (whole matvec) and the dominant kernel's duration.
-    # The half-spectrum operator (203 MB in FP32) fits the 256 MB MALL, so
-    # back-to-back repeats could be served partly from it: every timed
-    # application follows a 512 MB read that evicts the operator with clean
-    # lines (a write would leave dirty lines whose write-back lands in the
-    # timed region); the back-to-back figure is reported beside it as "warm".
+    # Every timed application follows a 512 MB read that evicts the operator
+    # from the 256 MB MALL with clean lines (a write would leave dirty lines
+    # whose write-back lands in the timed region); the back-to-back figure is
+    # reported beside it as "warm".
     flush = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+    sblk = (prob.Nx if half else 2 * prob.Nx - 1) * (2 * prob.Ny - 1)      # stored blocks at 2N - 1
     gbs = {}
     stage = {}
     stage_warm = {}
     # mixed: the FP32 operator on complex128 vectors, the instance the solve runs
-    for which, dt, s in (("mixed", torch.complex128, 8), ("fp32", torch.complex64, 8),
-                         ("fp64", torch.complex128, 16)):
+    for which, dt, s, sv in (("mixed", torch.complex128, 8, 16), ("fp32", torch.complex64, 8, 8),
+                             ("fp64", torch.complex128, 16, 16)):
         xv = v.to(dt)
         for _ in range(3):
             plan.matvec(xv, which=which)
@@ -495,10 +487,12 @@ def main():
         ev1.record()
         torch.cuda.synchronize()
         ms_warm = ev0.elapsed_time(ev1) / reps
-        # vectors in and out are complex128 in the mixed form
-        nb = algorithmic_bytes(prob, 1, s, half) + (2 * prob.Nt * 8 if which == "mixed" else 0)
+        # what the placed operator must move: its stored extended spectrum and
+        # the vectors in and out
+        nb = s * sblk * bc * bc + sv * 2 * prob.Nt
         gbs[which] = {"us": round(ms * 1e3, 2), "GB_s": round(nb / (ms * 1e-3) / 1e9, 1),
-                      "us_warm": round(ms_warm * 1e3, 2), "GB_s_warm": round(nb / (ms_warm * 1e-3) / 1e9, 1)}
+                      "us_warm": round(ms_warm * 1e3, 2), "GB_s_warm": round(nb / (ms_warm * 1e-3) / 1e9, 1),
+                      "bytes": int(nb)}
         cold = []
         for _ in range(reps):
             flush.sum()
@@ -506,13 +500,15 @@ def main():
         stage[which] = {k: sum(c[k] for c in cold) / reps for k in cold[0]}
         stage_warm[which] = plan.matvec_profile(xv, which=which, reps=50)
     del flush
-    # dominant kernel of the timed solve: the fused spectrum+rim launch of the
-    # FP32 operator on complex128 vectors (it carries both HBM streams); its
-    # duration from HIP events recorded on the stream it is launched on, after
-    # the MALL flush
+    # dominant kernel of the timed solve: the pair-stream launch of the FP32
+    # extended spectrum (k_pair_prod<float>; the preconditioner launches the
+    # same kernel on its inverted blocks); its duration from HIP events recorded
+    # on the stream it is launched on, after the MALL flush.  Its bytes: the
+    # stored blocks and the transformed grid in and out.
+    pair = tuned["spectrum_pass"] == 2
     k_ms = stage["mixed"]["prod"]
     k_ms_warm = stage_warm["mixed"]["prod"]
-    k_bytes = spec_rim_bytes(prob, Px, 8, half, sv=16)
+    k_bytes = 8 * (sblk * bc * bc + 2 * (2 * prob.Nx - 1) * (2 * prob.Ny - 1) * bc)
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     sha = kernel_source_sha()
     traffic = TRAFFIC["bytes"] if TRAFFIC["source_sha256"] == sha else None
@@ -534,40 +530,44 @@ def main():
         "data": "synthetic",
         "config": {"workload": "32x32 array, b=64, 256 rim functions (N=65,536, Nt=65,792), broadside plane "
                                "wave, tol 1e-8, one RHS", "Nx": 32, "Ny": 32, "b": 64, "Nr": 256,
-                   "grid": [Px, Py], "restart": 40,
-                   "solve": "mixed GMRES-IR, right block-circulant preconditioner"},
+                   "grid": [Px, Py], "restart": 40, "rim": f"placed, {bc - prob.b} channels per cell",
+                   "solve": "mixed GMRES-IR, right block-circulant preconditioner",
+                   "tuned": {k: tuned[k] for k in ("spectrum_pass", "source")}},
         "fp64_plain_solves_per_s": round(args.steps / total64, 2),
         "speedup_vs_fp64_plain": round(total64 / total, 3),
-        "other_forms_solves_per_s": {"mixed_no_precond": round(kb / totm, 2), "fp64_precond": round(kb / totp, 2)},
+        "other_forms_solves_per_s": {"mixed_no_precond": round(kb / totm, 2), "fp64_precond": round(kb / totp, 2),
+                                     "fp64_plain_on_placed_plan": round(kb / tot64s, 2),
+                                     "dense_rim_mixed_precond": round(kb / totd, 2)},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3),
                        "fp64_plain_p50": round(1e3 * float(np.percentile(lat64, 50)), 3),
                        "fp64_plain_p99": round(1e3 * float(np.percentile(lat64, 99)), 3)},
         "iters": {"mixed_precond": inf[0]["iters"], "mixed_precond_outer": inf[0]["outer_iters"],
                   "fp64_plain": inf64[0]["iters"], "mixed_no_precond": infm[0]["iters"],
-                  "fp64_precond": infp[0]["iters"]},
+                  "fp64_precond": infp[0]["iters"], "dense_rim_mixed_precond": infd[0]["iters"]},
         "relres": {"mixed_precond": inf[0]["relres"], "fp64_plain": inf64[0]["relres"]},
         "matvec": gbs,
         "matvec_stages_us": {w: {k: round(v_ * 1e3, 2) for k, v_ in st.items()} for w, st in stage.items()},
         "matvec_stages_us_warm": {w: {k: round(v_ * 1e3, 2) for k, v_ in st.items()} for w, st in stage_warm.items()},
         "plan_create_s": round(t_plan, 3),
         "precond_create_s": round(t_pc, 3),
-        "roofline": {"kernel": "k_spec_rim<float, cpx<double>, cpx<double>> (FP32 operator on complex128 "
-                               "vectors, as in the mixed solve: stored spectrum half, mirror parts + rim pass, "
-                               "fused)", "bound": "hbm",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "tune_s": round(t_tune, 3),
+        "roofline": {"kernel": ("k_pair_prod<float, 9> (pair stream over the stored half of the extended "
+                                "spectrum, 72 x 72 blocks)") if pair else
+                               "k_spec_rim<float, cpx<double>, cpx<double>, 9, 1, 0, false, true, 256> (fused "
+                               "spectrum-only pass over the extended spectrum)",
+                     "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": int(k_bytes), "launch_us": round(k_ms * 1e3, 2),
                      "launch_us_warm": round(k_ms_warm * 1e3, 2),
                      "note": "launch_us after a 512 MB read that evicts the operator from the 256 MB MALL; "
-                             "launch_us_warm back to back"},
+                             "launch_us_warm back to back; HIP events on the launch stream around the launch"},
     }
     if not args.quick:
         line["multi_rhs"] = multi_rhs(dev)
         line["precision"] = precision(dev)
         line["serving"] = serving(dev)
         line["schur"] = schur(dev, args.steps)
-        line["structured_rim"] = structured_rim(dev, args.steps)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, V)
     print(json.dumps(line), flush=True)

@@ -190,16 +190,47 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
  *                    applies it to its frequency and, transposed, to the
  *                    mirror frequency;
  *     TP_PASS_AUTO   (default) the fused launch.
+ *   TP_OPT_MFMA_COLS  columns per workgroup of the matrix-core product (16,
+ *     32 or 64, FP64 products take at most 32; 0 = default: 32 FP32, 16 FP64).
+ *   TP_OPT_MFMA_MIN_R  number of columns from which products and the dense rim
+ *     pass run on the matrix cores (2..max_rhs; 0 = default 16).
  * Setting an option drops the plan's captured solver graphs.  Errors:
  * TP_E_INVAL (unknown option or value, NULL pointers, a continuous batch is
  * active on the plan).
  */
 #define TP_OPT_SPECTRUM_PASS 1
+#define TP_OPT_MFMA_COLS 2
+#define TP_OPT_MFMA_MIN_R 3
 #define TP_PASS_AUTO 0
 #define TP_PASS_FUSED 1
 #define TP_PASS_PAIRS 2
 tp_status toeplitz_plan_set_option(tp_plan p, int option, int value);
 tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value);
+
+/* Result of toeplitz_tune: the options it set and the time they gave. */
+typedef struct {
+    int spectrum_pass;   /* TP_PASS_FUSED or TP_PASS_PAIRS (TP_PASS_AUTO when no launch depends on it) */
+    int mfma_cols;       /* 16, 32, 64 (0 when nrhs is below the matrix-core threshold) */
+    int candidates;      /* option combinations timed */
+    double ms;           /* mean milliseconds of the timed work with the chosen options */
+    double ms_default;   /* the same with every option at its default */
+} tp_tune_result;
+
+/*
+ * Autotuner: time every combination of the launch options that changes a
+ * kernel on this plan at nrhs columns (the spectrum pass for one column over
+ * a half spectrum without a dense rim pass: placed-rim operators and the
+ * preconditioner; the matrix-core column tile from the threshold on), each
+ * for reps applications after two untimed ones, with HIP events on
+ * hip_stream, and set the fastest.  The timed work is what a solve applies:
+ * the operator `which` (TP_FP64, TP_FP32 or TP_MIXED, as toeplitz_matvec) and,
+ * if the plan has a preconditioner, its application in the same precision.
+ * x, y: device work vectors as for toeplitz_matvec (any content; y is
+ * overwritten).  Synchronises hip_stream.  Errors: as toeplitz_matvec,
+ * TP_E_INVAL for reps < 1 or a NULL result.
+ */
+tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int nrhs,
+                        int reps, void *hip_stream, tp_tune_result *result);
 
 /* Copy the plan's layout facts into *desc. */
 tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *desc);

@@ -29,9 +29,9 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_far_field", "toeplitz_precond_bytes", "toeplitz_precond_create", "toeplitz_precond_apply",
            "toeplitz_precond_bytes_for", "toeplitz_gen_symmetric", "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve",
            "toeplitz_matvec_static", "toeplitz_static_scratch_bytes", "toeplitz_plan_bytes_placed",
-           "toeplitz_plan_create_placed", "toeplitz_plan_set_option", "toeplitz_plan_get_option")
+           "toeplitz_plan_create_placed", "toeplitz_plan_set_option", "toeplitz_plan_get_option", "toeplitz_tune")
 TP_SYM_RIM, TP_SYM_GEN = 1, 2
-TP_OPT_SPECTRUM_PASS = 1
+TP_OPT_SPECTRUM_PASS, TP_OPT_MFMA_COLS, TP_OPT_MFMA_MIN_R = 1, 2, 3
 TP_PASS_AUTO, TP_PASS_FUSED, TP_PASS_PAIRS = 0, 1, 2
 
 
@@ -49,6 +49,11 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("mode", ctypes.c_int), ("x0_given", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("precond", ctypes.c_int)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("spectrum_pass", ctypes.c_int), ("mfma_cols", ctypes.c_int), ("candidates", ctypes.c_int),
+                ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -85,6 +90,7 @@ def lib():
         L.toeplitz_plan_create_placed.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, ci, ci, ci, ci, vp, sz, vp,
                                                   ctypes.POINTER(vp)]
         L.toeplitz_plan_set_option.argtypes = [vp, ci, ci]
+        L.toeplitz_tune.argtypes = [vp, ci, vp, cl, vp, cl, ci, ci, vp, ctypes.POINTER(TuneResult)]
         L.toeplitz_plan_get_option.argtypes = [vp, ci, ctypes.POINTER(ci)]
         L.toeplitz_plan_info.argtypes = [vp, ctypes.POINTER(PlanDesc)]
         L.toeplitz_matvec.argtypes = [vp, ci, vp, cl, vp, cl, ci, vp]

@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libtoeplitz.so")
 SOURCES = ["tp_capi.hip", "tp_plan.hip", "tp_apply_f64.hip", "tp_apply_f32.hip", "tp_apply_wide.hip", "tp_gmres.hip",
-           "tp_post.hip", "tp_mfma.hip", "tp_schur.hip", "tp_static.hip"]
+           "tp_post.hip", "tp_mfma.hip", "tp_schur.hip", "tp_static.hip",
+           "tp_tune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # keep the compiler from forming packed FP32 instructions

@@ -505,6 +505,17 @@ tp_status toeplitz_plan_set_option(tp_plan p, int option, int value) {
             solver_drop_graphs(p);     // captured graphs hold the launch shapes
             p->opt_spectrum_pass = value;
             return TP_OK;
+        case TP_OPT_MFMA_COLS:
+            if (value != 0 && value != 16 && value != 32 && value != 64)
+                return fail(TP_E_INVAL, "matrix-core columns must be 0, 16, 32 or 64");
+            solver_drop_graphs(p);
+            p->opt_mfma_cols = value;
+            return TP_OK;
+        case TP_OPT_MFMA_MIN_R:
+            if (value != 0 && (value < 2 || value > 4096)) return fail(TP_E_INVAL, "threshold must be 0 or 2..4096");
+            solver_drop_graphs(p);
+            p->opt_mfma_min_r = value;
+            return TP_OK;
         default:
             return fail(TP_E_INVAL, "unknown option");
     }
@@ -514,6 +525,8 @@ tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value) {
     if (!p || !value) return fail(TP_E_INVAL, "plan or value is NULL");
     switch (option) {
         case TP_OPT_SPECTRUM_PASS: *value = p->opt_spectrum_pass; return TP_OK;
+        case TP_OPT_MFMA_COLS: *value = p->opt_mfma_cols; return TP_OK;
+        case TP_OPT_MFMA_MIN_R: *value = p->opt_mfma_min_r; return TP_OK;
         default: return fail(TP_E_INVAL, "unknown option");
     }
 }

@@ -64,7 +64,7 @@ bool solver_batch_active(tp_plan pl);
 // matrix-core kernels for many right-hand sides (tp_mfma.hip)
 template <typename T>
 hipError_t prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, int Px, int Py, int kxh, cpx<T> *out,
-                     const void *const *act, hipStream_t st);
+                     const void *const *act, hipStream_t st, int cols);   // cols: columns per workgroup, 0 = default
 template <typename T, typename In, typename Out>
 hipError_t rim_mfma(const cpx<T> *B, const cpx<T> *BE, Cols<const In> x, Cols<Out> y, int R, long N, int Nr,
                     int nslab, cpx<T> *part, hipStream_t st);

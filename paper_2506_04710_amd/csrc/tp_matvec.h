@@ -1441,8 +1441,9 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     // one column: the fused path (for a half spectrum, rows of at most 96)
     const bool fused = !pairs && R == 1 && sh_fused <= kLdsLimit && !(pl->half && b > 96);
 
-    // many columns: the product and the rim run on the matrix cores
-    const bool mfma = !fused && R >= kMfmaMinR;
+    // many columns: the product and the rim run on the matrix cores (from the
+    // plan's threshold, else kMfmaMinR columns)
+    const bool mfma = !fused && !pairs && R >= (pl->opt_mfma_min_r ? pl->opt_mfma_min_r : kMfmaMinR);
     const bool rim_mma =
         mfma && rim && pl->rim_te == 64 && rim_mfma_lds<T>(OpPtrs<T>::BE(pl) != nullptr) <= kLdsLimit;
 
@@ -1489,7 +1490,7 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     } else if (pairs) {
         launch_pair_prod<T>(pl, G, gB, gA, act, st);
     } else if (mfma) {
-        prod_mfma<T>(G, gB, b, R, Px, Py, pl->kxh, gA, act, st);
+        prod_mfma<T>(G, gB, b, R, Px, Py, pl->kxh, gA, act, st, pl->opt_mfma_cols);
     } else {
         // columns per workgroup: up to 16 (the spectrum block is re-read from
         // cache by each column block of a frequency)

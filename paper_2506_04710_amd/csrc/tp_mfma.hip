@@ -196,13 +196,11 @@ __global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G
     }
 }
 
-template <typename T>
-static constexpr int prod_nt() { return sizeof(T) == 4 ? 2 : 1; }
-
-template <typename T>
-hipError_t prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, int Px, int Py, int kxh, cpx<T> *out,
-                     const void *const *act, hipStream_t st) {
-    constexpr int NT = prod_nt<T>();
+// Column tiles of 16 per workgroup: the launch option (16, 32 or 64 columns;
+// 0 = 32 for f32, 16 for f64).
+template <typename T, int NT>
+static void launch_prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, int Px, int Py, int kxh, cpx<T> *out,
+                             const void *const *act, hipStream_t st) {
     const int KP = (b + 7) >> 3;
     const size_t sh = (size_t)16 * NT * (8 * KP + 2) * sizeof(cpx<T>);
     const int waves = (b + 15) / 16;
@@ -214,12 +212,24 @@ hipError_t prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, int Px, in
     else
         hipLaunchKernelGGL((k_prod_mfma<T, NT, 4, false>), grid, dim3(64 * waves), sh, st, G, in, b, R, Px, Py, kxh,
                            out, act);
+}
+
+template <typename T>
+hipError_t prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, int Px, int Py, int kxh, cpx<T> *out,
+                     const void *const *act, hipStream_t st, int cols) {
+    if (cols == 0) cols = sizeof(T) == 4 ? 32 : 16;
+    if (cols >= 64 && sizeof(T) == 4)
+        launch_prod_mfma<T, 4>(G, in, b, R, Px, Py, kxh, out, act, st);
+    else if (cols >= 32)
+        launch_prod_mfma<T, 2>(G, in, b, R, Px, Py, kxh, out, act, st);
+    else
+        launch_prod_mfma<T, 1>(G, in, b, R, Px, Py, kxh, out, act, st);
     return hipGetLastError();
 }
 template hipError_t prod_mfma<float>(const c64 *, const c64 *, int, int, int, int, int, c64 *, const void *const *,
-                                     hipStream_t);
+                                     hipStream_t, int);
 template hipError_t prod_mfma<double>(const c128 *, const c128 *, int, int, int, int, int, c128 *,
-                                      const void *const *, hipStream_t);
+                                      const void *const *, hipStream_t, int);
 
 // ---------------------------------------------------------------- rim
 // One slab of 64 element columns e0 .. e0 + 63 and a block of 16 NT

@@ -1,0 +1,116 @@
+// Autotuner: times the launch options that change a kernel of this plan at a
+// given column count and keeps the fastest.  The candidates are kernel
+// variants with the same results; the timed work is what a solve applies (the
+// operator and, when the plan has one, the preconditioner).
+#include <vector>
+
+#include "tp_internal.h"
+
+namespace tp {
+
+#ifndef TP_MFMA_MIN_R
+#define TP_MFMA_MIN_R 16
+#endif
+
+// One application of the timed work (operator, then preconditioner).
+static hipError_t tune_apply(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int R,
+                             hipStream_t st) {
+    hipError_t e;
+    if (which == TP_FP64) {
+        const Cols<const c128> xc{(const c128 *)x, ldx, nullptr};
+        const Cols<c128> yc{(c128 *)y, ldy, nullptr};
+        if ((e = matvec_fp64(p, xc, yc, R, st))) return e;
+        if (p->has_precond && p->S64) return precond_fp64(p, xc, yc, Cols<const c128>{nullptr, 0, nullptr}, R, st);
+    } else if (which == TP_FP32) {
+        const Cols<const c64> xc{(const c64 *)x, ldx, nullptr};
+        const Cols<c64> yc{(c64 *)y, ldy, nullptr};
+        if ((e = matvec_fp32(p, xc, yc, R, st))) return e;
+        if (p->has_precond && p->S32) return precond_fp32(p, xc, yc, Cols<const c64>{nullptr, 0, nullptr}, R, st);
+    } else {
+        const Cols<const c128> xc{(const c128 *)x, ldx, nullptr};
+        const Cols<c128> yc{(c128 *)y, ldy, nullptr};
+        if ((e = matvec_fp32_wide(p, xc, yc, R, st))) return e;
+        if (p->has_precond && p->S32)
+            return precond_fp32_wide(p, xc, yc, Cols<const c128>{nullptr, 0, nullptr}, R, st);
+    }
+    return hipSuccess;
+}
+
+}  // namespace tp
+
+using namespace tp;
+
+extern "C" {
+
+tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int nrhs, int reps,
+                        void *hip_stream, tp_tune_result *res) {
+    if (!res || reps < 1) return fail(TP_E_INVAL, "result is NULL or reps < 1");
+    tp_status s = check_apply(p, which, x, ldx, y, ldy, nrhs);
+    if (s != TP_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    // options that change a kernel here
+    const bool pass_matters = nrhs == 1 && p->half && p->bc <= 128 && (p->nrc > 0 || p->has_precond);
+    const int min_r = p->opt_mfma_min_r ? p->opt_mfma_min_r : TP_MFMA_MIN_R;
+    const bool mfma_matters = nrhs >= min_r;
+    std::vector<int> passes = pass_matters ? std::vector<int>{TP_PASS_FUSED, TP_PASS_PAIRS}
+                                           : std::vector<int>{p->opt_spectrum_pass};
+    std::vector<int> cols = mfma_matters ? (which == TP_FP64 ? std::vector<int>{16, 32} : std::vector<int>{16, 32, 64})
+                                         : std::vector<int>{p->opt_mfma_cols};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(TP_E_HIP, "event create");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(TP_E_HIP, "event create");
+    }
+    hipError_t e = hipSuccess;
+    auto time_it = [&](double &ms) {
+        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = tune_apply(p, which, x, ldx, y, ldy, nrhs, st);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = tune_apply(p, which, x, ldx, y, ldy, nrhs, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float f = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+        ms = (double)f / reps;
+    };
+    const int keep_pass = p->opt_spectrum_pass, keep_cols = p->opt_mfma_cols;
+    // every option at its default first
+    p->opt_spectrum_pass = TP_PASS_AUTO;
+    p->opt_mfma_cols = 0;
+    double ms_def = 0.0;
+    time_it(ms_def);
+    double best = -1.0;
+    int bp = keep_pass, bc = keep_cols, n = 0;
+    for (int pv : passes)
+        for (int cv : cols) {
+            if (e != hipSuccess) break;
+            p->opt_spectrum_pass = pv;
+            p->opt_mfma_cols = cv;
+            double ms = 0.0;
+            time_it(ms);
+            ++n;
+            if (e == hipSuccess && (best < 0.0 || ms < best)) {
+                best = ms;
+                bp = pv;
+                bc = cv;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    solver_drop_graphs(p);      // captured graphs hold the launch shapes
+    if (e != hipSuccess) {
+        p->opt_spectrum_pass = keep_pass;
+        p->opt_mfma_cols = keep_cols;
+        return hip_fail(e, "tune");
+    }
+    p->opt_spectrum_pass = bp;
+    p->opt_mfma_cols = bc;
+    res->spectrum_pass = pass_matters ? bp : TP_PASS_AUTO;
+    res->mfma_cols = mfma_matters ? bc : 0;
+    res->candidates = n;
+    res->ms = best;
+    res->ms_default = ms_def;
+    return TP_OK;
+}
+
+}  // extern "C"
