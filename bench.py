@@ -52,6 +52,9 @@ def parse():
                     help="only 20 applications of one operator form on the headline plan (precond: the FP32 "
                          "preconditioner on complex128 vectors; multi: the FP32 operator on the 81 port columns "
                          "of the 9x9 array), for kernel traces and counters")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="only tune the headline plan's launch options (placed rim, preconditioner) into the "
+                         "cache, so that later runs, profiled or not, take the same choice")
     ap.add_argument("--placed", action="store_true",
                     help="with --solves-only / --apply-only: the plan with the rim as placed channels")
     return ap.parse_args()
@@ -178,6 +181,8 @@ def multi_rhs(dev, K=3):
     prob, V = sa.make_config(3)
     R = V.shape[0]
     plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=R, restart=40, device=dev).precond_create()
+    from paper_2506_04710_amd import tune
+    tuned = tune.tune(plan, "mixed", R)
     v = torch.from_numpy(V).to(dev)
     total, lat, (x, inf) = timed_solves(plan, v, K, 1, mode="mixed", precond=True)
     assert all(i["status"] == 0 and i["relres"] <= 1e-8 for i in inf), inf
@@ -187,7 +192,17 @@ def multi_rhs(dev, K=3):
     Pa = (2 * prob.Nx - 1) * (2 * prob.Ny - 1)
     flops = 8.0 * Pa * prob.b ** 2 * R
     flops_rim = 16.0 * prob.Nr * prob.N * R + 8.0 * prob.Nr ** 2 * R
-    whole_us = sum(st.values()) * 1e3
+    # the whole operator application, 20 back to back between two events
+    xv = v.to(torch.complex64)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.matvec(xv, which="fp32")
+    e0.record()
+    for _ in range(20):
+        plan.matvec(xv, which="fp32")
+    e1.record()
+    torch.cuda.synchronize()
+    whole_us = e0.elapsed_time(e1) / 20 * 1e3
+    prod_us = plan.stage_time(xv, 3, "fp32", reps=50) * 1e3
     rows = np.nonzero(V)[1]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -199,14 +214,16 @@ def multi_rhs(dev, K=3):
            "solves_per_s": round(R * K / total, 1), "ms_per_81": round(1e3 * total / K, 2),
            "iters_max": max(i["iters"] for i in inf), "outer_max": max(i["outer_iters"] for i in inf),
            "fp32_matvec_stages_us": {k: round(t * 1e3, 2) for k, t in st.items()},
-           "prod_mfma": {"tflops": round(flops / (st["prod"] * 1e-3) / 1e12, 1),
+           "prod_mfma": {"us": round(prod_us, 2), "tflops": round(flops / (prod_us * 1e-6) / 1e12, 1),
                          "peak_tflops_fp32_mfma": 157.3,
-                         "frac": round(flops / (st["prod"] * 1e-3) / 1e12 / 157.3, 3),
-                         "flops_per_launch": flops, "grid": "algorithmic 17x17"},
+                         "frac": round(flops / (prod_us * 1e-6) / 1e12 / 157.3, 3),
+                         "flops_per_launch": flops, "grid": "algorithmic 17x17",
+                         "timing": "launch repeated back to back between two events"},
            "whole_matvec": {"us": round(whole_us, 2), "flops": flops + flops_rim,
                             "frac_fp32_mfma": round((flops + flops_rim) / (whole_us * 1e-6) / 1e12 / 157.3, 3),
-                            "note": "sum of the stage intervals (HIP events, each with its recording overhead)"},
-           "smatrix_ms": round(1e3 * t_s, 2), "smatrix_max_asymmetry": float(np.abs(S - S.T).max())}
+                            "timing": "20 applications back to back between two events"},
+           "smatrix_ms": round(1e3 * t_s, 2), "smatrix_max_asymmetry": float(np.abs(S - S.T).max()),
+           "tuned_mfma_cols": tuned["mfma_cols"]}
     plan.close()
     return out
 
@@ -241,6 +258,26 @@ def headline_plan(tp, prob, placed, max_rhs=1, device="cuda:0"):
                           max_rhs=max_rhs, restart=40, device=device, **kw)
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON result stays the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def tune_only():
+    """Tune the headline plan (placed rim, preconditioner, mixed, one column)
+    and print the record."""
+    import torch
+    import paper_2506_04710_amd as tp
+    from paper_2506_04710_amd import tune
+    from synth import arrays as sa
+    tp.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prob, _ = sa.make_config(2)
+    plan = headline_plan(tp, prob, True).precond_create()
+    print(json.dumps({"tune": tune.tune(plan, "mixed", 1)}), flush=True)
+    plan.close()
+
+
 def apply_only(which, placed, K=20):
     """K applications of one operator form on the headline plan (kernel traces
     and HBM counters of its launches): mixed / fp32 / fp64 operator, the FP32
@@ -265,7 +302,7 @@ def apply_only(which, placed, K=20):
         if which == "precond":
             plan.precond_create()
         if placed or which == "precond":
-            tune.tune(plan, "mixed", 1)
+            progress(f"tuning: {tune.tune(plan, 'mixed', 1)}")
         if which == "precond":
             for _ in range(K):
                 plan.precond_apply(xv, which="mixed")
@@ -286,7 +323,8 @@ def solves_only(K, W, placed=False):
     prob, V = sa.make_config(2)
     plan = headline_plan(tp, prob, placed).precond_create()
     from paper_2506_04710_amd import tune
-    tune.tune(plan, "mixed", 1)
+    rec = tune.tune(plan, "mixed", 1)
+    progress(f"tuning: {rec}")
     v = torch.from_numpy(V).to("cuda:0")
     total, _, (_, inf) = timed_solves(plan, v, K, W, mode="mixed", precond=True)
     assert inf[0]["status"] == 0 and inf[0]["relres"] <= 1e-8, inf
@@ -357,7 +395,8 @@ def serving(dev, n_requests=512):
 
     keep = ("requests", "columns", "wall_s", "requests_per_s", "solves_per_s", "p50_ms", "p99_ms", "max_relres",
             "all_ok", "plans_created", "plans_evicted")
-    rnd = lambda d: {k: (round(d[k], 4) if isinstance(d[k], float) and k != "max_relres" else d[k]) for k in keep}
+    rnd = lambda d: {k: (round(d[k], 4) if isinstance(d.get(k), float) and k != "max_relres" else d.get(k))
+                     for k in keep + (("error",) if "error" in d else ())}
     srv = Server(geometry, slots=16, mode="mixed", tol=1e-8, restart=40, hbm_budget=160 << 30, precond=True,
                  device=dev)
     t0 = time.perf_counter()
@@ -367,6 +406,7 @@ def serving(dev, n_requests=512):
     hbm_all = srv.used
     sat = srv.run(reqs(), realtime=False)
     lam = sat["requests_per_s"]
+    progress(f"serving saturation: {lam:.1f} requests/s")
     at = {f"{f}x_saturation": rnd(dict(srv.run(reqs(f * lam), realtime=True), offered_rate=round(f * lam, 1)))
           for f in (0.5, 0.9)}
     srv.close()
@@ -377,13 +417,22 @@ def serving(dev, n_requests=512):
     torch.cuda.synchronize()
     sat64 = plain.run(reqs(), realtime=False)
     plain.close()
-    # HBM pressure: a budget of 8 GiB (all plans warm need about 27 GiB), at
-    # least 1.5x the largest single plan so that every request can be admitted
-    tight = Server(geometry, slots=16, mode="mixed", tol=1e-8, restart=40, hbm_budget=8 << 30, precond=True,
+    progress(f"plain FP64 single-RHS server: {sat64['wall_s']:.1f} s")
+    # HBM pressure: a budget of half what every plan warm needs (at least 1.5x
+    # the largest single plan, so that every request can be admitted): plans
+    # are created on demand, requests wait for memory, idle plans are evicted
+    tight = Server(geometry, slots=16, mode="mixed", tol=1e-8, restart=40, hbm_budget=hbm_all // 2, precond=True,
                    device=dev)
     tight.budget = max(tight.budget, int(1.5 * max(tight._need(k) for k in keys)))
-    press = tight.run(reqs(), realtime=False)
+    try:
+        press = tight.run(reqs(), realtime=False, max_seconds=120.0,
+                          progress=lambda d, n, t: progress(f"budgeted serving: {d}/{n} requests at {t:.1f} s, "
+                                                            f"{tight.stats['plans_created']} plans created"))
+    except RuntimeError as ex:
+        press = {k: None for k in keep}
+        press["error"] = str(ex)
     tight.close()
+    progress("serving under an HBM budget done")
     return {"workload": f"{n_requests} requests, Poisson arrivals (seeded), {len(keys)} geometries (Nx, Ny in "
                         "{8..48}, b in {32, 64}), 1-16 ports each, tol 1e-8",
             "batched": "mixed + preconditioner, 16 slots per plan, continuous batching",
@@ -391,7 +440,8 @@ def serving(dev, n_requests=512):
             "saturation": rnd(sat), **at,
             "fp64_plain_single_rhs_saturation": rnd(sat64),
             "speedup_vs_fp64_plain_single_rhs": round(sat["solves_per_s"] / sat64["solves_per_s"], 2),
-            "hbm_budget_saturation": dict(rnd(press), budget_gib=round(tight.budget / 2 ** 30, 2))}
+            "hbm_budget_saturation": dict(rnd(press), budget_gib=round(tight.budget / 2 ** 30, 2),
+                                          note="plans created on demand, idle plans evicted")}
 
 
 def main():
@@ -408,6 +458,9 @@ def main():
         return
     if args.apply_only:
         apply_only(args.apply_only, args.placed)
+        return
+    if args.tune_only:
+        tune_only()
         return
     import numpy as np
     import torch
@@ -431,6 +484,7 @@ def main():
     t0 = time.perf_counter()
     tuned = tune.tune(plan, "mixed", 1)
     t_tune = time.perf_counter() - t0
+    progress(f"headline plan, preconditioner and tuning: {tuned}")
     info = plan.info()
     Px, Py, bc = info["Px"], info["Py"], info["bc"]
     half = bool(info["half_spectrum"])       # symmetric generators: half the spectrum is stored
@@ -442,6 +496,7 @@ def main():
     # Toeplitz blocks, no preconditioner), and intermediate forms
     total, lat, (x, inf) = timed_solves(plan, v, args.steps, args.warmup, mode="mixed", precond=True)
     assert inf[0]["status"] == 0 and inf[0]["relres"] <= 1e-8, inf
+    progress(f"headline solves: {args.steps / total:.1f}/s")
     dense = headline_plan(tp, prob, False, device=dev)
     total64, lat64, (_, inf64) = timed_solves(dense, v, args.steps, args.warmup, mode="fp64")
     assert inf64[0]["status"] == 0 and inf64[0]["relres"] <= 1e-8, inf64
@@ -500,14 +555,18 @@ def main():
         stage[which] = {k: sum(c[k] for c in cold) / reps for k in cold[0]}
         stage_warm[which] = plan.matvec_profile(xv, which=which, reps=50)
     del flush
+    progress("operator timings done")
     # dominant kernel of the timed solve: the pair-stream launch of the FP32
     # extended spectrum (k_pair_prod<float>; the preconditioner launches the
     # same kernel on its inverted blocks); its duration from HIP events recorded
     # on the stream it is launched on, after the MALL flush.  Its bytes: the
     # stored blocks and the transformed grid in and out.
     pair = tuned["spectrum_pass"] == 2
-    k_ms = stage["mixed"]["prod"]
-    k_ms_warm = stage_warm["mixed"]["prod"]
+    # launch duration: the launch repeated back to back between two events on
+    # its stream (no event between the repeats); the per-stage intervals of
+    # matvec_profile carry an event's own few microseconds each
+    k_ms = plan.stage_time(v, 3, "mixed", reps=100)
+    k_ms_cold = stage["mixed"]["prod"]
     k_bytes = 8 * (sblk * bc * bc + 2 * (2 * prob.Nx - 1) * (2 * prob.Ny - 1) * bc)
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     sha = kernel_source_sha()
@@ -559,17 +618,24 @@ def main():
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": int(k_bytes), "launch_us": round(k_ms * 1e3, 2),
-                     "launch_us_warm": round(k_ms_warm * 1e3, 2),
-                     "note": "launch_us after a 512 MB read that evicts the operator from the 256 MB MALL; "
-                             "launch_us_warm back to back; HIP events on the launch stream around the launch"},
+                     "launch_us_event_interval_after_mall_flush": round(k_ms_cold * 1e3, 2),
+                     "note": "launch_us: the launch repeated 100 times back to back between two HIP events on its "
+                             "stream (toeplitz_stage_time); the second figure is the interval between events "
+                             "recorded right before and after one launch, after a 512 MB read that evicts the "
+                             "256 MB MALL (it includes the events' own overhead)"},
     }
     if not args.quick:
         line["multi_rhs"] = multi_rhs(dev)
+        progress("multi-RHS done")
         line["precision"] = precision(dev)
+        progress("precision done")
         line["serving"] = serving(dev)
+        progress("serving done")
         line["schur"] = schur(dev, args.steps)
+        progress("rim elimination done")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, V)
+        progress("CPU oracle done")
     print(json.dumps(line), flush=True)
 
 

@@ -259,6 +259,21 @@ class Plan:
                                                  _stream_handle(stream), ms))
         return dict(zip(self.STAGES, list(ms)))
 
+    def stage_time(self, x, stage=3, which=None, reps=50, stream=None) -> float:
+        """Mean milliseconds of one stage of the application launched reps
+        times back to back (toeplitz_stage_time)."""
+        import torch
+        if which is None:
+            which = "fp64" if x.dtype == torch.complex128 else "fp32"
+        dt = torch.complex64 if which == "fp32" else torch.complex128
+        x2, R, ldx = self._cols(x, dt)
+        y = torch.empty((R, self.Nt), dtype=dt, device=x.device)
+        ms = ctypes.c_double(0.0)
+        check(_lib.lib().toeplitz_stage_time(self._h, PREC[which], ctypes.c_void_p(x2.data_ptr()), ldx,
+                                             ctypes.c_void_p(y.data_ptr()), self.Nt, R, stage, reps,
+                                             _stream_handle(stream), ctypes.byref(ms)))
+        return ms.value
+
     def solve(self, v, mode="mixed", tol=1e-8, restart=0, max_iter=2000, max_outer=50, inner_tol=1e-4, x0=None,
               stream=None, raise_on_noconv=False, precond=False):
         """Solve Z x = v for the columns of v (complex128 cuda tensor (Nt,) or (R, Nt))."""

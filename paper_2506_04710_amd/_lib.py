@@ -29,7 +29,8 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_far_field", "toeplitz_precond_bytes", "toeplitz_precond_create", "toeplitz_precond_apply",
            "toeplitz_precond_bytes_for", "toeplitz_gen_symmetric", "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve",
            "toeplitz_matvec_static", "toeplitz_static_scratch_bytes", "toeplitz_plan_bytes_placed",
-           "toeplitz_plan_create_placed", "toeplitz_plan_set_option", "toeplitz_plan_get_option", "toeplitz_tune")
+           "toeplitz_plan_create_placed", "toeplitz_plan_set_option", "toeplitz_plan_get_option", "toeplitz_tune",
+           "toeplitz_stage_time")
 TP_SYM_RIM, TP_SYM_GEN = 1, 2
 TP_OPT_SPECTRUM_PASS, TP_OPT_MFMA_COLS, TP_OPT_MFMA_MIN_R = 1, 2, 3
 TP_PASS_AUTO, TP_PASS_FUSED, TP_PASS_PAIRS = 0, 1, 2
@@ -76,6 +77,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        # torch first: it loads the HIP runtime the library then shares (the
+        # library loaded first would bring its own copy in ahead of torch's)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, ci, cl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_size_t
         L.toeplitz_plan_bytes.argtypes = [ci, ci, ci, ci, ci, ci, ci, ci, ctypes.POINTER(sz)]
@@ -90,6 +94,7 @@ def lib():
         L.toeplitz_plan_create_placed.argtypes = [ci, ci, ci, ci, vp, vp, vp, vp, vp, ci, ci, ci, ci, vp, sz, vp,
                                                   ctypes.POINTER(vp)]
         L.toeplitz_plan_set_option.argtypes = [vp, ci, ci]
+        L.toeplitz_stage_time.argtypes = [vp, ci, vp, cl, vp, cl, ci, ci, ci, vp, ctypes.POINTER(ctypes.c_double)]
         L.toeplitz_tune.argtypes = [vp, ci, vp, cl, vp, cl, ci, ci, vp, ctypes.POINTER(TuneResult)]
         L.toeplitz_plan_get_option.argtypes = [vp, ci, ctypes.POINTER(ci)]
         L.toeplitz_plan_info.argtypes = [vp, ctypes.POINTER(PlanDesc)]

@@ -629,6 +629,45 @@ tp_status toeplitz_matvec_profile(tp_plan p, tp_prec which, const void *x, long 
     return e == hipSuccess ? TP_OK : hip_fail(e, "matvec profile");
 }
 
+tp_status toeplitz_stage_time(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy, int nrhs,
+                              int stage, int reps, void *hip_stream, double *ms) {
+    if (!ms || reps < 1 || stage < 0 || stage > 5) return fail(TP_E_INVAL, "ms is NULL, reps < 1 or stage not in 0..5");
+    // a full application first: it checks the arguments and leaves every
+    // stage's input in the workspace
+    tp_status s = toeplitz_matvec(p, which, x, ldx, y, ldy, nrhs, hip_stream);
+    if (s != TP_OK) return s;
+    tp_plan_s q = *p;
+    q.only_stage = stage;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(TP_E_HIP, "event create");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(TP_E_HIP, "event create");
+    }
+    hipError_t e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        if (which == TP_FP64)
+            e = matvec_fp64(&q, Cols<const c128>{(const c128 *)x, ldx, nullptr}, Cols<c128>{(c128 *)y, ldy, nullptr},
+                            nrhs, st);
+        else if (which == TP_FP32)
+            e = matvec_fp32(&q, Cols<const c64>{(const c64 *)x, ldx, nullptr}, Cols<c64>{(c64 *)y, ldy, nullptr},
+                            nrhs, st);
+        else
+            e = matvec_fp32_wide(&q, Cols<const c128>{(const c128 *)x, ldx, nullptr},
+                                 Cols<c128>{(c128 *)y, ldy, nullptr}, nrhs, st);
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float f = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "stage timing");
+    *ms = (double)f / reps;
+    return TP_OK;
+}
+
 tp_status toeplitz_plan_spectrum(tp_plan p, tp_prec which, int kx, int ky, void *host_out) {
     if (!p || !host_out) return fail(TP_E_INVAL, "NULL argument");
     if (kx < 0 || kx >= p->Px || ky < 0 || ky >= p->Py) return fail(TP_E_INVAL, "frequency out of range");

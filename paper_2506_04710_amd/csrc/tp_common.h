@@ -321,6 +321,8 @@ struct tp_plan_s {
     int opt_spectrum_pass = TP_PASS_AUTO;
     int opt_mfma_cols = 0;        // columns per workgroup of the matrix-core product (0 = default)
     int opt_mfma_min_r = 0;       // columns from which the matrix-core kernels run (0 = default)
+    // instrumentation only, on a copy of the record: launch this stage alone
+    int only_stage = -1;
     // solver launch resources, created on the first solve and released by
     // toeplitz_plan_destroy: a stream for graph capture and replay (default
     // priority), events ordering it against the caller's stream, pinned host

@@ -501,9 +501,11 @@ constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 
 // to its own frequency, yhat(kx, ky) = G xhat(kx, ky), and, when its mirror
 // frequency (Px - kx, -ky) is not stored, transposed to it: yhat(-k) =
 // G^T xhat(-k).  Wave w takes rows p = 8 w .. 8 w + 7 with 8 lanes per row;
-// lane l holds G[p][q] for q in [(l & 7) VPL, (l & 7) VPL + VPL).  Row sums
-// add the 8 lanes of a row (DPP); column sums add the 8 rows of a wave (rs8)
-// and then the waves, in wave order, in LDS.  One workgroup per stored block
+// lane l holds G[p][q] for q = (l & 7) + 8 v, v < VPL, so that each load
+// instruction of a wave reads 8 contiguous runs of 8 values (whole cache
+// lines for FP64, half lines for FP32).  Row sums add the 8 lanes of a row
+// (DPP); column sums add the 8 rows of a wave (rs8) and then the waves, in
+// wave order, in LDS.  One workgroup per stored block
 // keeps the stream balanced over the compute units whatever the block width;
 // every block's loads issue before anything else.
 template <typename T, int VPL>
@@ -523,12 +525,12 @@ __global__ void __launch_bounds__(1024) k_pair_prod(const cpx<T> *__restrict__ G
     const long k = (long)kx * Py + ky;
     const long km = (long)(Px - kx) * Py + (ky == 0 ? 0 : Py - ky);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int pl = lane >> 3, qs = (lane & 7) * VPL, p = w * 8 + pl;
+    const int pl = lane >> 3, qj = lane & 7, p = w * 8 + pl;
     const bool prow = p < b;
     const cpx<T> *Grow = G + (long)s * b * b + (long)min(p, b - 1) * b;
     cpx<T> g[VPL];
 #pragma unroll
-    for (int v = 0; v < VPL; ++v) g[v] = Grow[min(qs + v, b - 1)];
+    for (int v = 0; v < VPL; ++v) g[v] = Grow[min(qj + 8 * v, b - 1)];
     for (int i = threadIdx.x; i < b; i += blockDim.x) {
         xk[i] = in[k * b + i];
         if (mir) xm[i] = in[km * b + i];
@@ -536,10 +538,10 @@ __global__ void __launch_bounds__(1024) k_pair_prod(const cpx<T> *__restrict__ G
     __syncthreads();
     bool qok[VPL];
 #pragma unroll
-    for (int v = 0; v < VPL; ++v) qok[v] = prow && qs + v < b;
+    for (int v = 0; v < VPL; ++v) qok[v] = prow && qj + 8 * v < b;
     cpx<T> acc = mk<T>(0, 0);
 #pragma unroll
-    for (int v = 0; v < VPL; ++v) acc = cmac(acc, keep(g[v], qok[v]), xk[min(qs + v, b - 1)]);
+    for (int v = 0; v < VPL; ++v) acc = cmac(acc, keep(g[v], qok[v]), xk[min(qj + 8 * v, b - 1)]);
     acc = sum8(acc);
     if ((lane & 7) == 0 && prow) out[k * b + p] = acc;
     if (!mir) return;                                  // uniform over the workgroup
@@ -553,7 +555,7 @@ __global__ void __launch_bounds__(1024) k_pair_prod(const cpx<T> *__restrict__ G
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         const int v = i + (VP >> S) * grp;
-        if (writer && v < VPL && qs + v < b) zp[w * b + qs + v] = m[i];
+        if (writer && v < VPL && qj + 8 * v < b) zp[w * b + qj + 8 * v] = m[i];
     }
     __syncthreads();
     for (int q = threadIdx.x; q < b; q += blockDim.x) {
@@ -1431,6 +1433,9 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     auto mark = [&](int i) {
         if (ev) hipEventRecord(ev[i], st);
     };
+    // instrumentation (a copy of the plan record with only_stage set): launch
+    // one stage alone, on the workspace a full application left behind
+    auto on = [&](int stage) { return pl->only_stage < 0 || pl->only_stage == stage; };
     const cpx<T> *G = PRE ? OpPtrs<T>::S(pl) : OpPtrs<T>::G(pl);
     const bool rim = !PRE && Nr > 0 && pl->nrc == 0;   // dense rim pass
     const size_t sh_fused = std::max(spec_lds(pl, es), rim ? rim_lds(pl, 1, es) : (size_t)0);
@@ -1448,7 +1453,7 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         mfma && rim && pl->rim_te == 64 && rim_mfma_lds<T>(OpPtrs<T>::BE(pl) != nullptr) <= kLdsLimit;
 
     mark(0);
-    if (rim && !fused) {
+    if (rim && !fused && on(0)) {
         if (rim_mma)
             rim_mfma<T, In, Out>(OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl), x, y, R, pl->N, Nr, pl->rim_nslab,
                                  reinterpret_cast<cpx<T> *>(pl->rim_part), st);
@@ -1460,7 +1465,8 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     const int lg2 = fused ? -1 : fft2_lgcc(Px, Py, C, es);
     const int xs2 = lg2 >= 0 ? fft2_xstride(Py, lg2, es) : 0;
     const size_t sh2 = ((size_t)Px * xs2 + Px + Py) * es + (size_t)(Px + Py) * sizeof(int);
-    if (lg2 >= 0) {
+    if (!on(1)) {
+    } else if (lg2 >= 0) {
         hipLaunchKernelGGL((k_fft2_fwd<T, In>), dim3((C + (1 << lg2) - 1) >> lg2), blk, sh2, st, x, R, Nx, Ny, b,
                            pl->fx, pl->fy, lg2, xs2, gB, rm);
     } else {
@@ -1470,14 +1476,15 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         hipLaunchKernelGGL((k_fwd_x<T, In>), grid, blk, sh, st, x, R, Nx, b, pl->fx, lg, gA, rm);
     }
     mark(2);
-    if (!fused && lg2 < 0) {
+    if (!fused && lg2 < 0 && on(2)) {
         const int lg = fft_lgcc(Py, C, es, 16);
         const size_t sh = ((size_t)Py * (1 << lg) + Py) * es;
         dim3 grid((C + (1 << lg) - 1) >> lg, Px);
         hipLaunchKernelGGL((k_fwd_y<T>), grid, blk, sh, st, gA, C, Ny, Px, pl->fy, lg, gB, act, b);
     }
     mark(3);
-    if (fused) {
+    if (!on(3)) {
+    } else if (fused) {
         const int vpl = (b + 7) / 8;
         if (vpl <= 2) launch_spec_rim_e<T, In, Out, 2>(pl, G, rim, x, y, gA, gB, sh_fused, st);
         else if (vpl <= 4) launch_spec_rim_e<T, In, Out, 4>(pl, G, rim, x, y, gA, gB, sh_fused, st);
@@ -1501,7 +1508,7 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         launch_prod<T>(pl, vpl, RC, grid, sh, st, G, gB, b, R, gA, act);
     }
     mark(4);
-    if (!fused && lg2 < 0) {
+    if (!fused && lg2 < 0 && on(4)) {
         const int lg = fft_lgcc(Py, C, es, 16);
         const size_t sh = ((size_t)Py * (1 << lg) + Py) * es;
         dim3 grid((C + (1 << lg) - 1) >> lg, Px);
@@ -1516,7 +1523,8 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     // rim rows of a dense rim (C x_r and the slab partials, or D x_r) are
     // finished by extra waves; a placed rim's rows come out of the crop
     const int nfin = (Nr > 0 && pl->nrc == 0) ? ((Nr + 3) / 4) * R : 0;
-    if (lg2 >= 0) {
+    if (!on(5)) {
+    } else if (lg2 >= 0) {
         const int ninv = (C + (1 << lg2) - 1) >> lg2;
         hipLaunchKernelGGL((k_fft2_inv_fin<T, In, Out>), dim3(ninv + nfin), blk, sh2, st, gA, R, Nx, Ny, b, pl->fx,
                            pl->fy, lg2, xs2, y, accumulate, acc, ninv,

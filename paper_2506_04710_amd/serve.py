@@ -79,16 +79,23 @@ class Server:
         self.budget = hbm_budget
         self.device = torch.device(device)
         self.plans: "collections.OrderedDict[tuple, _PlanState]" = collections.OrderedDict()
+        self._needs = {}
         self.used = 0
         self.stats = dict(plans_created=0, plans_evicted=0, steps=0, plan_create_s=0.0)
 
     # ----------------------------------------------------------- plans
     def _need(self, key):
-        Nx, Ny, b, Nr, gen = self.geometry(key)[:5]
-        sym = gen_symmetric(Nx, Ny, b, gen)
-        need = plan_bytes(Nx, Ny, b, Nr, "mixed", self.slots, self.restart, symmetric=sym)
-        if self.precond:
-            need += precond_bytes(Nx, Ny, b, Nr, "mixed", symmetric=sym)
+        """Device bytes of a geometry's plan (and preconditioner), computed once
+        per geometry: the symmetry test reads every generator entry, and a
+        request waiting for memory asks again on every pass of the loop."""
+        need = self._needs.get(key)
+        if need is None:
+            Nx, Ny, b, Nr, gen = self.geometry(key)[:5]
+            sym = gen_symmetric(Nx, Ny, b, gen)
+            need = plan_bytes(Nx, Ny, b, Nr, "mixed", self.slots, self.restart, symmetric=sym)
+            if self.precond:
+                need += precond_bytes(Nx, Ny, b, Nr, "mixed", symmetric=sym)
+            self._needs[key] = need
         return need
 
     def _get_plan(self, key, now):
@@ -139,10 +146,11 @@ class Server:
                 break
 
     # ------------------------------------------------------------- run
-    def run(self, requests, realtime=True, max_seconds=600.0):
+    def run(self, requests, realtime=True, max_seconds=600.0, progress=None):
         """Serve the requests (sorted by arrival).  With realtime, requests are
         admitted when the wall clock passes their arrival time; otherwise all
-        are admitted as fast as slots allow (saturation)."""
+        are admitted as fast as slots allow (saturation).  progress(done,
+        total, seconds) is called after every 64 finished requests."""
         torch = self.torch
         L = _lib.lib()
         pending = collections.deque(sorted(requests, key=lambda r: r.t))
@@ -215,6 +223,8 @@ class Server:
                         if r.done_cols == r.R:
                             r.t_done = now
                             remaining -= 1
+                            if progress and (len(requests) - remaining) % 64 == 0:
+                                progress(len(requests) - remaining, len(requests), now)
             for ps in self.plans.values():
                 if not ps.busy:
                     ps.stepped = False

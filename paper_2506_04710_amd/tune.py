@@ -10,7 +10,9 @@ sets the stored options without timing again.
     tune.tune(plan, which="mixed", nrhs=1)   # after plan.precond_create(), if any
 
 The cache file is $TOEPLITZ_TUNE_CACHE, else
-~/.cache/paper_2506_04710_amd/tune.json.
+~/.cache/paper_2506_04710_amd/tune.json.  Tune without a profiler attached: a
+kernel-trace profiler adds a cost per dispatch and so favours the variants
+with fewer launches; a later profiled run then takes the stored choice.
 """
 from __future__ import annotations
 
@@ -38,10 +40,12 @@ def _bucket(nrhs: int) -> int:
 
 
 def device_key(device) -> str:
+    """Architecture, compute-unit count and HIP version (not the marketing
+    name: it is empty in some environments, e.g. under a profiler)."""
     import torch
     props = torch.cuda.get_device_properties(device)
     arch = getattr(props, "gcnArchName", "")
-    return f"{props.name}|{arch}|hip {torch.version.hip}"
+    return f"{arch}|cu{props.multi_processor_count}|hip {torch.version.hip}"
 
 
 def plan_key(plan, which: str, nrhs: int) -> str:
