@@ -194,6 +194,9 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
  *     32 or 64, FP64 products take at most 32; 0 = default: 32 FP32, 16 FP64).
  *   TP_OPT_MFMA_MIN_R  number of columns from which products and the dense rim
  *     pass run on the matrix cores (2..max_rhs; 0 = default 16).
+ *   TP_OPT_FFT2_LDS  LDS bytes a workgroup of the 2-D transform tiles may take
+ *     (16384..163840; 0 = default 49152): grids whose tile of 4 channels fits
+ *     run both transform directions in one launch instead of two passes.
  * Setting an option drops the plan's captured solver graphs.  Errors:
  * TP_E_INVAL (unknown option or value, NULL pointers, a continuous batch is
  * active on the plan).
@@ -201,6 +204,7 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
 #define TP_OPT_SPECTRUM_PASS 1
 #define TP_OPT_MFMA_COLS 2
 #define TP_OPT_MFMA_MIN_R 3
+#define TP_OPT_FFT2_LDS 4
 #define TP_PASS_AUTO 0
 #define TP_PASS_FUSED 1
 #define TP_PASS_PAIRS 2
@@ -211,6 +215,7 @@ tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value);
 typedef struct {
     int spectrum_pass;   /* TP_PASS_FUSED or TP_PASS_PAIRS (TP_PASS_AUTO when no launch depends on it) */
     int mfma_cols;       /* 16, 32, 64 (0 when nrhs is below the matrix-core threshold) */
+    int fft2_lds;        /* 0 (48 KB tiles) or 163840 (where larger tiles would change the path) */
     int candidates;      /* option combinations timed */
     double ms;           /* mean milliseconds of the timed work with the chosen options */
     double ms_default;   /* the same with every option at its default */
@@ -220,7 +225,9 @@ typedef struct {
  * Autotuner: time every combination of the launch options that changes a
  * kernel on this plan at nrhs columns (the spectrum pass for one column over
  * a half spectrum without a dense rim pass: placed-rim operators and the
- * preconditioner; the matrix-core column tile from the threshold on), each
+ * preconditioner; the matrix-core column tile from the threshold on; the 2-D
+ * transform tile size where a 160 KB tile of 4 channels would hold a grid
+ * that a 48 KB one does not), each
  * for reps applications after two untimed ones, with HIP events on
  * hip_stream, and set the fastest.  The timed work is what a solve applies:
  * the operator `which` (TP_FP64, TP_FP32 or TP_MIXED, as toeplitz_matvec) and,
@@ -290,6 +297,21 @@ size_t toeplitz_static_scratch_bytes(void);
  */
 tp_status toeplitz_matvec_profile(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy,
                                   int nrhs, int reps, void *hip_stream, double *stage_ms);
+
+/*
+ * Instrumentation: the mean duration in milliseconds of one stage of the
+ * operator application (numbered as in toeplitz_matvec_profile; 3 is the
+ * per-frequency product, or the fused pass that includes it), launched reps
+ * times back to back between two HIP events on hip_stream, after one full
+ * application that leaves every stage's input in the plan's workspace (each
+ * stage rewrites the same output from the same input, so the repeats are
+ * alike).  No event sits between the repeats.  A stage the plan's path does
+ * not have launches nothing.  Same arguments and errors as toeplitz_matvec,
+ * plus TP_E_INVAL for a NULL ms, reps < 1 or a stage outside 0..5;
+ * synchronises hip_stream.
+ */
+tp_status toeplitz_stage_time(tp_plan p, tp_prec which, const void *x, long ldx, void *y, long ldy,
+                              int nrhs, int stage, int reps, void *hip_stream, double *ms);
 
 /* Solver options (all fields are read; see toeplitz_solve_opts_default). */
 typedef struct {

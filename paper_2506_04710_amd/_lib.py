@@ -32,7 +32,7 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_plan_create_placed", "toeplitz_plan_set_option", "toeplitz_plan_get_option", "toeplitz_tune",
            "toeplitz_stage_time")
 TP_SYM_RIM, TP_SYM_GEN = 1, 2
-TP_OPT_SPECTRUM_PASS, TP_OPT_MFMA_COLS, TP_OPT_MFMA_MIN_R = 1, 2, 3
+TP_OPT_SPECTRUM_PASS, TP_OPT_MFMA_COLS, TP_OPT_MFMA_MIN_R, TP_OPT_FFT2_LDS = 1, 2, 3, 4
 TP_PASS_AUTO, TP_PASS_FUSED, TP_PASS_PAIRS = 0, 1, 2
 
 
@@ -53,8 +53,8 @@ class SolveOpts(ctypes.Structure):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("spectrum_pass", ctypes.c_int), ("mfma_cols", ctypes.c_int), ("candidates", ctypes.c_int),
-                ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
+    _fields_ = [("spectrum_pass", ctypes.c_int), ("mfma_cols", ctypes.c_int), ("fft2_lds", ctypes.c_int),
+                ("candidates", ctypes.c_int), ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -516,6 +516,12 @@ tp_status toeplitz_plan_set_option(tp_plan p, int option, int value) {
             solver_drop_graphs(p);
             p->opt_mfma_min_r = value;
             return TP_OK;
+        case TP_OPT_FFT2_LDS:
+            if (value != 0 && (value < 16384 || value > 160 * 1024))
+                return fail(TP_E_INVAL, "2-D tile LDS must be 0 or 16384..163840 bytes");
+            solver_drop_graphs(p);
+            p->opt_fft2_lds = value;
+            return TP_OK;
         default:
             return fail(TP_E_INVAL, "unknown option");
     }
@@ -527,6 +533,7 @@ tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value) {
         case TP_OPT_SPECTRUM_PASS: *value = p->opt_spectrum_pass; return TP_OK;
         case TP_OPT_MFMA_COLS: *value = p->opt_mfma_cols; return TP_OK;
         case TP_OPT_MFMA_MIN_R: *value = p->opt_mfma_min_r; return TP_OK;
+        case TP_OPT_FFT2_LDS: *value = p->opt_fft2_lds; return TP_OK;
         default: return fail(TP_E_INVAL, "unknown option");
     }
 }

@@ -1206,12 +1206,12 @@ static int fft2_xstride(int Py, int lgCC, size_t elem) {
 #ifndef TP_FFT2_MAXLG
 #define TP_FFT2_MAXLG 4
 #endif
-static int fft2_lgcc(int Px, int Py, int C, size_t elem) {
+static int fft2_lgcc(int Px, int Py, int C, size_t elem, size_t lds_cap = 48 * 1024) {
     auto bytes = [&](int lg) {
         return ((size_t)Px * fft2_xstride(Py, lg, elem) + Px + Py) * elem + (size_t)(Px + Py) * sizeof(int);
     };
     int lg = TP_FFT2_MAXLG;
-    while (lg >= 2 && bytes(lg) > 48 * 1024) --lg;
+    while (lg >= 2 && bytes(lg) > lds_cap) --lg;
     if (lg < 2) return -1;
     while (lg > 2 && (1 << (lg - 1)) >= C) --lg;
     return lg;
@@ -1462,7 +1462,9 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     }
     mark(1);
     // small grids with several columns: both transform directions per launch
-    const int lg2 = fused ? -1 : fft2_lgcc(Px, Py, C, es);
+    // (the plan's option may let the 2-D tiles take more LDS: larger grids
+    // then run both transform directions in one launch, on fewer workgroups)
+    const int lg2 = fused ? -1 : fft2_lgcc(Px, Py, C, es, pl->opt_fft2_lds ? (size_t)pl->opt_fft2_lds : 48 * 1024);
     const int xs2 = lg2 >= 0 ? fft2_xstride(Py, lg2, es) : 0;
     const size_t sh2 = ((size_t)Px * xs2 + Px + Py) * es + (size_t)(Px + Py) * sizeof(int);
     if (!on(1)) {

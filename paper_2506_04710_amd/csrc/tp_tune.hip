@@ -56,6 +56,12 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
                                            : std::vector<int>{p->opt_spectrum_pass};
     std::vector<int> cols = mfma_matters ? (which == TP_FP64 ? std::vector<int>{16, 32} : std::vector<int>{16, 32, 64})
                                          : std::vector<int>{p->opt_mfma_cols};
+    // the 2-D tiles: only where a 160 KB tile of 4 channels of the timed
+    // operator's values holds the grid and a 48 KB one does not
+    const size_t es = which == TP_FP64 ? 16 : 8;
+    const size_t tile4 = ((size_t)p->Px * (p->Py * 4 + 16) + p->Px + p->Py) * es + (size_t)(p->Px + p->Py) * 4;
+    const bool fft2_matters = tile4 > 48 * 1024 && tile4 <= 160 * 1024;
+    std::vector<int> tiles = fft2_matters ? std::vector<int>{0, 160 * 1024} : std::vector<int>{p->opt_fft2_lds};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(TP_E_HIP, "event create");
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -73,40 +79,47 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
         if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
         ms = (double)f / reps;
     };
-    const int keep_pass = p->opt_spectrum_pass, keep_cols = p->opt_mfma_cols;
+    const int keep_pass = p->opt_spectrum_pass, keep_cols = p->opt_mfma_cols, keep_tile = p->opt_fft2_lds;
     // every option at its default first
     p->opt_spectrum_pass = TP_PASS_AUTO;
     p->opt_mfma_cols = 0;
+    p->opt_fft2_lds = 0;
     double ms_def = 0.0;
     time_it(ms_def);
     double best = -1.0;
-    int bp = keep_pass, bc = keep_cols, n = 0;
+    int bp = keep_pass, bc = keep_cols, bt = keep_tile, n = 0;
     for (int pv : passes)
-        for (int cv : cols) {
-            if (e != hipSuccess) break;
-            p->opt_spectrum_pass = pv;
-            p->opt_mfma_cols = cv;
-            double ms = 0.0;
-            time_it(ms);
-            ++n;
-            if (e == hipSuccess && (best < 0.0 || ms < best)) {
-                best = ms;
-                bp = pv;
-                bc = cv;
+        for (int cv : cols)
+            for (int tv : tiles) {
+                if (e != hipSuccess) break;
+                p->opt_spectrum_pass = pv;
+                p->opt_mfma_cols = cv;
+                p->opt_fft2_lds = tv;
+                double ms = 0.0;
+                time_it(ms);
+                ++n;
+                if (e == hipSuccess && (best < 0.0 || ms < best)) {
+                    best = ms;
+                    bp = pv;
+                    bc = cv;
+                    bt = tv;
+                }
             }
-        }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     solver_drop_graphs(p);      // captured graphs hold the launch shapes
     if (e != hipSuccess) {
         p->opt_spectrum_pass = keep_pass;
         p->opt_mfma_cols = keep_cols;
+        p->opt_fft2_lds = keep_tile;
         return hip_fail(e, "tune");
     }
     p->opt_spectrum_pass = bp;
     p->opt_mfma_cols = bc;
+    p->opt_fft2_lds = bt;
     res->spectrum_pass = pass_matters ? bp : TP_PASS_AUTO;
     res->mfma_cols = mfma_matters ? bc : 0;
+    res->fft2_lds = fft2_matters ? bt : 0;
     res->candidates = n;
     res->ms = best;
     res->ms_default = ms_def;

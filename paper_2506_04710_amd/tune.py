@@ -92,7 +92,8 @@ def tune(plan, which: str = "mixed", nrhs: int = 1, reps: int = 10, path: str | 
             check(_lib.lib().toeplitz_tune(plan._h, PREC[which], ctypes.c_void_p(x.data_ptr()), plan.Nt,
                                            ctypes.c_void_p(y.data_ptr()), plan.Nt, nrhs, reps,
                                            ctypes.c_void_p(stream.cuda_stream), ctypes.byref(r)))
-        rec = dict(spectrum_pass=r.spectrum_pass, mfma_cols=r.mfma_cols, candidates=r.candidates,
+        rec = dict(spectrum_pass=r.spectrum_pass, mfma_cols=r.mfma_cols, fft2_lds=r.fft2_lds,
+                   candidates=r.candidates,
                    ms=r.ms, ms_default=r.ms_default, nrhs=nrhs, source="measured")
         data.setdefault(dkey, {})[pkey] = rec
         _store(path, data)
@@ -102,4 +103,6 @@ def tune(plan, which: str = "mixed", nrhs: int = 1, reps: int = 10, path: str | 
             plan.set_option(_lib.TP_OPT_SPECTRUM_PASS, rec["spectrum_pass"])
         if rec["mfma_cols"]:
             plan.set_option(_lib.TP_OPT_MFMA_COLS, rec["mfma_cols"])
+        if rec.get("fft2_lds"):
+            plan.set_option(_lib.TP_OPT_FFT2_LDS, rec["fft2_lds"])
     return rec

@@ -87,24 +87,30 @@ def config2():
     return prob, V, X, oracle.matvec(prob, X)
 
 
+@pytest.mark.parametrize("tile", [0, 163840])
 @pytest.mark.parametrize("which", WHICH)
-def test_pairs_config2_every_row(tp, config2, which):
-    """The headline grid (63 x 63, separate x and y transform passes), placed
-    rim with 72 channels: every output row."""
-    banner(f"pairs placed config 2 every row {which}")
+def test_pairs_config2_every_row(tp, config2, which, tile):
+    """The headline grid (63 x 63: separate x and y transform passes, or with
+    160 KB tiles both directions in one launch for FP32), placed rim with 72
+    channels: every output row."""
+    from paper_2506_04710_amd import _lib
+    banner(f"pairs placed config 2 every row {which} tile={tile}")
     prob, _, X, ref = config2
     plan = _plan(tp, prob, True)
+    plan.set_option(_lib.TP_OPT_FFT2_LDS, tile)
     assert_parity(_apply(plan, X, which, "matvec"), ref, TOL[which], N=prob.N, what=f"config 2 {which}")
     plan.close()
 
 
-@pytest.mark.parametrize("placed", [False, True])
-def test_pairs_config2_solve(tp, config2, placed):
+@pytest.mark.parametrize("placed,tile", [(False, 0), (True, 0), (True, 163840)])
+def test_pairs_config2_solve(tp, config2, placed, tile):
     """The headline preconditioned mixed solve with the pair-stream pass (the
     dense plan uses it for its preconditioner, the placed plan for both)."""
-    banner(f"pairs config 2 solve placed={placed}")
+    from paper_2506_04710_amd import _lib
+    banner(f"pairs config 2 solve placed={placed} tile={tile}")
     prob, V, _, _ = config2
     plan = _plan(tp, prob, placed, restart=40)
+    plan.set_option(_lib.TP_OPT_FFT2_LDS, tile)
     plan.precond_create()
     x, info = plan.solve(to_dev(V), mode="mixed", tol=1e-8, precond=True)
     rr = oracle.relres(prob, x.cpu().numpy().reshape(1, -1), V)[0]
@@ -123,4 +129,6 @@ def test_option_checks(tp):
         plan.set_option(_lib.TP_OPT_SPECTRUM_PASS, 7)
     with pytest.raises(tp.ToeplitzError):
         plan.set_option(99, 0)
+    with pytest.raises(tp.ToeplitzError):
+        plan.set_option(_lib.TP_OPT_FFT2_LDS, 200000)
     plan.close()
