@@ -197,6 +197,12 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
  *   TP_OPT_FFT2_LDS  LDS bytes a workgroup of the 2-D transform tiles may take
  *     (16384..163840; 0 = default 49152): grids whose tile of 4 channels fits
  *     run both transform directions in one launch instead of two passes.
+ *   TP_OPT_MULTI_FUSED  1: 16+ columns on a grid of 2-D tiles run every stage
+ *     (dense reciprocal rim slabs, forward tiles, matrix-core products,
+ *     inverse tiles, rim finish) in one persistent launch whose workgroups
+ *     take tasks from a queue in dependency order (same results bit for bit);
+ *     0 (default): one launch per stage.  Applies with even b, the default
+ *     column tile and no separate B_er.
  * Setting an option drops the plan's captured solver graphs.  Errors:
  * TP_E_INVAL (unknown option or value, NULL pointers, a continuous batch is
  * active on the plan).
@@ -205,17 +211,44 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
 #define TP_OPT_MFMA_COLS 2
 #define TP_OPT_MFMA_MIN_R 3
 #define TP_OPT_FFT2_LDS 4
+#define TP_OPT_MULTI_FUSED 5
 #define TP_PASS_AUTO 0
 #define TP_PASS_FUSED 1
 #define TP_PASS_PAIRS 2
 tp_status toeplitz_plan_set_option(tp_plan p, int option, int value);
 tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value);
 
+/*
+ * Which launches an application takes (a description, for tuning and tests):
+ * the operator (precond = 0) or the preconditioner (precond = 1) in precision
+ * `which` (as toeplitz_matvec) at nrhs columns, with the plan's current
+ * options.  Sets *flags to an OR of
+ *   TP_PATH_FUSED       one column, fused spectrum pass (transforms in it)
+ *   TP_PATH_PAIRS       one column, pair-stream spectrum pass
+ *   TP_PATH_MFMA        products on the matrix cores (many columns)
+ *   TP_PATH_DENSE_RIM   a dense rim pass (operator of a plan without a placed rim)
+ *   TP_PATH_RIM_MFMA    that rim pass on the matrix cores
+ *   TP_PATH_TILES2D     both transform directions per launch on 2-D tiles
+ *   TP_PATH_PERSISTENT  every stage in one persistent launch (TP_OPT_MULTI_FUSED)
+ * Launches nothing.  Errors: TP_E_INVAL (NULL plan or flags, bad precision,
+ * nrhs outside [1, max_rhs], precond without a preconditioner),
+ * TP_E_UNSUPPORTED (the plan lacks the copy `which` needs).
+ */
+#define TP_PATH_FUSED 1
+#define TP_PATH_PAIRS 2
+#define TP_PATH_MFMA 4
+#define TP_PATH_DENSE_RIM 8
+#define TP_PATH_RIM_MFMA 16
+#define TP_PATH_TILES2D 32
+#define TP_PATH_PERSISTENT 64
+tp_status toeplitz_plan_path(tp_plan p, tp_prec which, int precond, int nrhs, int *flags);
+
 /* Result of toeplitz_tune: the options it set and the time they gave. */
 typedef struct {
     int spectrum_pass;   /* TP_PASS_FUSED or TP_PASS_PAIRS (TP_PASS_AUTO when no launch depends on it) */
     int mfma_cols;       /* 16, 32, 64 (0 when nrhs is below the matrix-core threshold) */
     int fft2_lds;        /* 0 (48 KB tiles) or 163840 (where larger tiles would change the path) */
+    int multi_fused;     /* 1 where the persistent multi-column launch was timed and fastest, else 0 */
     int candidates;      /* option combinations timed */
     double ms;           /* mean milliseconds of the timed work with the chosen options */
     double ms_default;   /* the same with every option at its default */
@@ -227,7 +260,8 @@ typedef struct {
  * a half spectrum without a dense rim pass: placed-rim operators and the
  * preconditioner; the matrix-core column tile from the threshold on; the 2-D
  * transform tile size where a 160 KB tile of 4 channels would hold a grid
- * that a 48 KB one does not), each
+ * that a 48 KB one does not; the persistent multi-column launch where a
+ * combination at the default column tile takes it), each
  * for reps applications after two untimed ones, with HIP events on
  * hip_stream, and set the fastest.  The timed work is what a solve applies:
  * the operator `which` (TP_FP64, TP_FP32 or TP_MIXED, as toeplitz_matvec) and,

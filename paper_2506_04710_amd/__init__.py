@@ -163,6 +163,13 @@ class Plan:
         check(_lib.lib().toeplitz_plan_get_option(self._h, option, ctypes.byref(v)))
         return v.value
 
+    def path(self, which="mixed", nrhs=1, precond=False) -> set:
+        """Names of the launches an application of the operator (or the
+        preconditioner) takes at nrhs columns (toeplitz_plan_path)."""
+        v = ctypes.c_int(0)
+        check(_lib.lib().toeplitz_plan_path(self._h, PREC[which], int(precond), nrhs, ctypes.byref(v)))
+        return {k for k, bit in _lib.PATH_BITS.items() if v.value & bit}
+
     def info(self) -> dict:
         d = _lib.PlanDesc()
         check(_lib.lib().toeplitz_plan_info(self._h, ctypes.byref(d)))

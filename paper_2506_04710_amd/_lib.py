@@ -30,10 +30,11 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_precond_bytes_for", "toeplitz_gen_symmetric", "toeplitz_schur_bytes", "toeplitz_schur_create", "toeplitz_schur_solve",
            "toeplitz_matvec_static", "toeplitz_static_scratch_bytes", "toeplitz_plan_bytes_placed",
            "toeplitz_plan_create_placed", "toeplitz_plan_set_option", "toeplitz_plan_get_option", "toeplitz_tune",
-           "toeplitz_stage_time")
+           "toeplitz_stage_time", "toeplitz_plan_path")
 TP_SYM_RIM, TP_SYM_GEN = 1, 2
-TP_OPT_SPECTRUM_PASS, TP_OPT_MFMA_COLS, TP_OPT_MFMA_MIN_R, TP_OPT_FFT2_LDS = 1, 2, 3, 4
+TP_OPT_SPECTRUM_PASS, TP_OPT_MFMA_COLS, TP_OPT_MFMA_MIN_R, TP_OPT_FFT2_LDS, TP_OPT_MULTI_FUSED = 1, 2, 3, 4, 5
 TP_PASS_AUTO, TP_PASS_FUSED, TP_PASS_PAIRS = 0, 1, 2
+PATH_BITS = {"fused": 1, "pairs": 2, "mfma": 4, "dense_rim": 8, "rim_mfma": 16, "tiles2d": 32, "persistent": 64}
 
 
 class PlanDesc(ctypes.Structure):
@@ -54,7 +55,8 @@ class SolveOpts(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("spectrum_pass", ctypes.c_int), ("mfma_cols", ctypes.c_int), ("fft2_lds", ctypes.c_int),
-                ("candidates", ctypes.c_int), ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
+                ("multi_fused", ctypes.c_int), ("candidates", ctypes.c_int), ("ms", ctypes.c_double),
+                ("ms_default", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -95,6 +97,7 @@ def lib():
                                                   ctypes.POINTER(vp)]
         L.toeplitz_plan_set_option.argtypes = [vp, ci, ci]
         L.toeplitz_stage_time.argtypes = [vp, ci, vp, cl, vp, cl, ci, ci, ci, vp, ctypes.POINTER(ctypes.c_double)]
+        L.toeplitz_plan_path.argtypes = [vp, ci, ci, ci, ctypes.POINTER(ci)]
         L.toeplitz_tune.argtypes = [vp, ci, vp, cl, vp, cl, ci, ci, vp, ctypes.POINTER(TuneResult)]
         L.toeplitz_plan_get_option.argtypes = [vp, ci, ctypes.POINTER(ci)]
         L.toeplitz_plan_info.argtypes = [vp, ctypes.POINTER(PlanDesc)]

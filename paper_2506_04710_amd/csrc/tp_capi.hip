@@ -160,7 +160,7 @@ static tp_status make_layout(int Nx, int Ny, int b, int Nr, int nrc, int sym, tp
     L->scratch_bytes = al((size_t)(2 * Ny - 1) * (2 * Nx - 1) * bb * 16) + al((size_t)(2 * Ny - 1) * L->Px * bb * 16) +
                        (dense_rim ? al((size_t)Nr * std::max(N, (size_t)Nr) * 16) : 0);
     L->ws_bytes =
-        std::max(2 * L->grid_bytes + L->rimpart_bytes + L->ypart_bytes + L->solver_bytes, L->scratch_bytes);
+        std::max(2 * L->grid_bytes + L->rimpart_bytes + L->ypart_bytes + 256 + L->solver_bytes, L->scratch_bytes);
     L->ws = take(true, L->ws_bytes);
     L->total = off;
     return TP_OK;
@@ -363,7 +363,9 @@ static tp_status create_plan(int Nx, int Ny, int b, int Nr, int nrc, const doubl
     pl->gridB = pl->ws + L.grid_bytes;
     pl->rim_part = pl->ws + 2 * L.grid_bytes;
     pl->ypart = L.ypart_bytes ? pl->ws + 2 * L.grid_bytes + L.rimpart_bytes : nullptr;
-    pl->solver_ws = pl->ws + 2 * L.grid_bytes + L.rimpart_bytes + L.ypart_bytes;
+    // the persistent multi-column launch's queue and counters (256 bytes)
+    pl->fctr = (int *)(pl->ws + 2 * L.grid_bytes + L.rimpart_bytes + L.ypart_bytes);
+    pl->solver_ws = pl->ws + 2 * L.grid_bytes + L.rimpart_bytes + L.ypart_bytes + 256;
     pl->rim_te = L.rim_te; pl->rim_nslab = L.rim_nslab;
 
     // transform tables
@@ -516,6 +518,11 @@ tp_status toeplitz_plan_set_option(tp_plan p, int option, int value) {
             solver_drop_graphs(p);
             p->opt_mfma_min_r = value;
             return TP_OK;
+        case TP_OPT_MULTI_FUSED:
+            if (value != 0 && value != 1) return fail(TP_E_INVAL, "persistent multi-column launch must be 0 or 1");
+            solver_drop_graphs(p);
+            p->opt_multi_fused = value;
+            return TP_OK;
         case TP_OPT_FFT2_LDS:
             if (value != 0 && (value < 16384 || value > 160 * 1024))
                 return fail(TP_E_INVAL, "2-D tile LDS must be 0 or 16384..163840 bytes");
@@ -534,8 +541,21 @@ tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value) {
         case TP_OPT_MFMA_COLS: *value = p->opt_mfma_cols; return TP_OK;
         case TP_OPT_MFMA_MIN_R: *value = p->opt_mfma_min_r; return TP_OK;
         case TP_OPT_FFT2_LDS: *value = p->opt_fft2_lds; return TP_OK;
+        case TP_OPT_MULTI_FUSED: *value = p->opt_multi_fused; return TP_OK;
         default: return fail(TP_E_INVAL, "unknown option");
     }
+}
+
+tp_status toeplitz_plan_path(tp_plan p, tp_prec which, int precond, int nrhs, int *flags) {
+    if (!p || !flags) return fail(TP_E_INVAL, "plan or flags is NULL");
+    if (which != TP_FP64 && which != TP_FP32 && which != TP_MIXED)
+        return fail(TP_E_INVAL, "precision must be TP_FP64, TP_FP32 or TP_MIXED");
+    if (nrhs < 1 || nrhs > p->max_rhs) return fail(TP_E_INVAL, "nrhs must be in [1, max_rhs]");
+    if (precond && !p->has_precond) return fail(TP_E_INVAL, "the plan has no preconditioner");
+    if (which != TP_FP64 && !p->G32) return fail(TP_E_UNSUPPORTED, "plan holds no FP32 operator");
+    if (which == TP_FP64 && !p->G64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 operator");
+    *flags = tp::path_flags(p, which == TP_FP64, precond != 0, nrhs);
+    return TP_OK;
 }
 
 tp_status toeplitz_plan_info(tp_plan p, tp_plan_desc *d) {

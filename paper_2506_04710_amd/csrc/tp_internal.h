@@ -14,6 +14,8 @@ tp_status hip_fail(hipError_t e, const char *what);
 
 // argument checks of an operator or preconditioner application (tp_capi.hip)
 tp_status check_apply(tp_plan p, tp_prec which, const void *x, long ldx, const void *y, long ldy, int nrhs);
+// TP_PATH_* bits of the launches an application takes at R columns
+int path_flags(tp_plan pl, bool fp64, bool pre, int R);
 
 // operator application (tp_matvec.h; instances in tp_apply_f64/f32/wide.hip)
 hipError_t matvec_fp64(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st);

@@ -28,6 +28,7 @@
 // a mirrored frequency's block transposed, and the fused single-column path
 // applies each stored block to both of its frequencies (spec_block_half).
 #include "tp_fft.h"
+#include "tp_mfma.h"
 #include "tp_internal.h"
 
 namespace tp {
@@ -1039,17 +1040,16 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
 // elements, adds the rim term and, in extra workgroups, finishes y_r.
 // Tile layout: value (x, y, channel) at (x Py + y) CC + channel.
 template <typename T, typename In>
-__global__ void __launch_bounds__(256) k_fft2_fwd(Cols<const In> x, int R, int Nx, int Ny, int b, FFTDesc fx,
-                                                  FFTDesc fy, int lgCC, int XS, cpx<T> *__restrict__ out,
-                                                  RimMap rm) {
-    extern __shared__ char smem_raw[];
+__device__ __forceinline__ void fft2_fwd_tile(Cols<const In> x, int R, int Nx, int Ny, int b, const FFTDesc &fx,
+                                              const FFTDesc &fy, int lgCC, int XS, cpx<T> *__restrict__ out,
+                                              const RimMap &rm, int blk, char *smem_raw) {
     cpx<T> *twx = reinterpret_cast<cpx<T> *>(smem_raw);
     cpx<T> *twy = twx + fx.P;
     cpx<T> *buf = twy + fy.P;
     int *px = reinterpret_cast<int *>(buf + fx.P * XS);   // digit-reversal tables
     int *py = px + fx.P;
     const int CC = 1 << lgCC, C = b * R, Px = fx.P, Py = fy.P;
-    const int c0 = blockIdx.x * CC;
+    const int c0 = blk * CC;
     if (!cols_live((const void *const *)x.tab, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
     load_twiddles<T>(twx, fx);
     load_twiddles<T>(twy, fy);
@@ -1102,15 +1102,21 @@ __global__ void __launch_bounds__(256) k_fft2_fwd(Cols<const In> x, int R, int N
     }
 }
 
-template <typename T, typename In, typename Out>
-__global__ void __launch_bounds__(256) k_fft2_inv_fin(const cpx<T> *__restrict__ in, int R, int Nx, int Ny, int b,
-                                                      FFTDesc fx, FFTDesc fy, int lgCC, int XS, Cols<Out> y,
-                                                      int accumulate, Cols<const Out> acc, int ninv,
-                                                      const cpx<T> *__restrict__ part,
-                                                      const cpx<T> *__restrict__ Cm, const cpx<T> *__restrict__ D,
-                                                      Cols<const In> x, long N, int Nr, int nslab, RimMap rm) {
+template <typename T, typename In>
+__global__ void __launch_bounds__(256) k_fft2_fwd(Cols<const In> x, int R, int Nx, int Ny, int b, FFTDesc fx,
+                                                  FFTDesc fy, int lgCC, int XS, cpx<T> *__restrict__ out,
+                                                  RimMap rm) {
     extern __shared__ char smem_raw[];
-    const int blk = blockIdx.x;
+    fft2_fwd_tile<T, In>(x, R, Nx, Ny, b, fx, fy, lgCC, XS, out, rm, blockIdx.x, smem_raw);
+}
+
+template <typename T, typename In, typename Out>
+__device__ __forceinline__ void fft2_inv_tile(const cpx<T> *__restrict__ in, int R, int Nx, int Ny, int b,
+                                              const FFTDesc &fx, const FFTDesc &fy, int lgCC, int XS, Cols<Out> y,
+                                              int accumulate, Cols<const Out> acc, int ninv,
+                                              const cpx<T> *__restrict__ part, const cpx<T> *__restrict__ Cm,
+                                              const cpx<T> *__restrict__ D, Cols<const In> x, long N, int Nr,
+                                              int nslab, const RimMap &rm, int blk, char *smem_raw) {
     if (blk >= ninv) {
         const int f = blk - ninv, w = threadIdx.x >> 6;
         const int nrowblk = (Nr + 3) >> 2;
@@ -1185,6 +1191,130 @@ __global__ void __launch_bounds__(256) k_fft2_inv_fin(const cpx<T> *__restrict__
     }
 }
 
+template <typename T, typename In, typename Out>
+__global__ void __launch_bounds__(256) k_fft2_inv_fin(const cpx<T> *__restrict__ in, int R, int Nx, int Ny, int b,
+                                                      FFTDesc fx, FFTDesc fy, int lgCC, int XS, Cols<Out> y,
+                                                      int accumulate, Cols<const Out> acc, int ninv,
+                                                      const cpx<T> *__restrict__ part,
+                                                      const cpx<T> *__restrict__ Cm, const cpx<T> *__restrict__ D,
+                                                      Cols<const In> x, long N, int Nr, int nslab, RimMap rm) {
+    extern __shared__ char smem_raw[];
+    fft2_inv_tile<T, In, Out>(in, R, Nx, Ny, b, fx, fy, lgCC, XS, y, accumulate, acc, ninv, part, Cm, D, x, N, Nr,
+                              nslab, rm, blockIdx.x, smem_raw);
+}
+
+// ------------------------------------ many columns: one persistent launch
+// The operator (or preconditioner) on 16+ columns of a grid small enough for
+// the 2-D transform tiles, in one persistent launch: every workgroup takes
+// tasks from a queue, in dependency order: the dense rim's matrix-core slabs,
+// the forward 2-D tiles, the per-frequency products (after every forward
+// tile), the inverse tiles (after every product and rim slab) and the rim
+// finish (after every rim slab).  A task is taken only by a running workgroup
+// and waits only on tasks earlier in the queue, which wait on nothing later,
+// so every wait ends whatever the number of resident workgroups.  A task
+// signals completion by its writes, a device-scope fence by every thread, a
+// barrier and one atomic increment; a waiter spins on an acquire load of the
+// counter and then fences before it reads (another XCD's L2 may hold stale
+// lines of the previous application's buffers).  Each task runs the same body
+// as its separate launch, so the results are the same bits.
+// Counters: [0] queue head, [1] rim slabs done, [2] forward tiles done,
+// [3] products done, [4] set when a wait gave up (it cannot happen unless
+// the device stops running the workgroups that hold earlier tasks).
+constexpr int kFusedCounters = 5;
+
+static __global__ void k_zero_ints(int *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+// Completion counters of the persistent launch.  The wait spins on relaxed
+// loads and takes one agent-scope acquire after the count is reached: an
+// acquire load in the loop would invalidate the caches on every spin.  The
+// signal makes each wave's writes visible at agent scope, then one thread
+// adds to the counter with release order.
+__device__ __forceinline__ void fused_wait(int *c, int target, int *err) {
+    if (threadIdx.x == 0) {
+        long spins = 0;
+        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1L << 22)) {    // seconds, far beyond any real wait: give up rather than hang
+                atomicOr(err, 1);
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void fused_signal(int *c) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(c, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct FusedDims {
+    int nslab, ncb_rim, nrim;     // rim slabs x column blocks
+    int nfwd;                     // forward 2-D tiles
+    int ncb, nprod;               // product column blocks, items (frequencies x column blocks)
+    int ninv, nfin;               // inverse tiles, rim finish blocks
+};
+
+// Every stage of a many-column application in one persistent launch.  The
+// workgroups take tasks from a queue in this order: dense rim slabs (slab x
+// column block), forward 2-D tiles, matrix-core products (frequency x column
+// block), inverse tiles, rim-row finish blocks.  A task depends only on tasks
+// earlier in the queue (products on every forward tile, inverse tiles on
+// every product and rim slab, finish blocks on the rim slabs), and a task is
+// taken only by a running workgroup, so every wait ends.  Each task body is
+// the device function of the separate launch, so results match it bit for
+// bit.  Counters: [0] queue, [1] rim slabs, [2] forward tiles, [3] products,
+// [4] set if a wait gave up (it never should).
+template <typename T, typename In, typename Out, bool RIM>
+__global__ void __launch_bounds__(256) k_fused_multi(
+    Cols<const In> x, Cols<Out> y, int R, int Nx, int Ny, int b, FFTDesc fx, FFTDesc fy, int lgCC, int XS,
+    cpx<T> *__restrict__ gA, cpx<T> *__restrict__ gB, const cpx<T> *__restrict__ G, int kxh,
+    const cpx<T> *__restrict__ B, cpx<T> *__restrict__ part, const cpx<T> *__restrict__ Cm,
+    const cpx<T> *__restrict__ D, int accumulate, Cols<const Out> acc, long N, int Nr, RimMap rm, FusedDims fd,
+    int *ctr) {
+    extern __shared__ char smem_raw[];
+    __shared__ int task;
+    constexpr int NTP = sizeof(T) == 4 ? 2 : 1;          // product column tiles (the default)
+    const int Px = fx.P, Py = fy.P;
+    const int e_rim = fd.nrim, e_fwd = e_rim + fd.nfwd, e_prod = e_fwd + fd.nprod,
+              e_all = e_prod + fd.ninv + fd.nfin;
+    const void *const *act = (const void *const *)x.tab;
+    for (;;) {
+        __syncthreads();                                  // LDS and `task` free again
+        if (threadIdx.x == 0) task = atomicAdd(&ctr[0], 1);
+        __syncthreads();
+        const int t = task;
+        if (t >= e_all) break;
+        if (t < e_rim) {
+            if constexpr (RIM) {
+                rim_mfma_tile<T, In, Out, rim_nt<T>(), rim_rch<T>(), false>(B, B, x, y, R, N, Nr, part,
+                                                                             t % fd.nslab, t / fd.nslab, smem_raw);
+                fused_signal(&ctr[1]);
+            }
+        } else if (t < e_fwd) {
+            fft2_fwd_tile<T, In>(x, R, Nx, Ny, b, fx, fy, lgCC, XS, gB, rm, t - e_rim, smem_raw);
+            fused_signal(&ctr[2]);
+        } else if (t < e_prod) {
+            fused_wait(&ctr[2], fd.nfwd, &ctr[4]);
+            const int item = t - e_fwd;
+            const long k = item / fd.ncb;
+            prod_mfma_item<T, NTP, 4, true>(G, gB, b, R, Px, Py, kxh, gA, act, k, (int)(item - k * fd.ncb),
+                                            smem_raw);
+            fused_signal(&ctr[3]);
+        } else {
+            const int blk = t - e_prod;
+            if (blk < fd.ninv) fused_wait(&ctr[3], fd.nprod, &ctr[4]);
+            if (RIM) fused_wait(&ctr[1], fd.nrim, &ctr[4]);
+            fft2_inv_tile<T, In, Out>(gA, R, Nx, Ny, b, fx, fy, lgCC, XS, y, accumulate, acc, fd.ninv, part, Cm, D, x,
+                                      N, Nr, fd.nslab, rm, blk, smem_raw);
+        }
+    }
+}
+
 // --------------------------------------------------------------- launcher
 static int ilog2(int v) {
     int l = 0;
@@ -1245,6 +1375,49 @@ struct OpPtrs<float> {
     static const c64 *S(tp_plan p) { return p->S32; }
     static const c64 *D(tp_plan p) { return p->D32; }
 };
+
+// LDS of the persistent multi-column launch: the largest task's
+template <typename T>
+static size_t fused_multi_lds(int b, size_t sh2, bool rim) {
+    constexpr int NTP = sizeof(T) == 4 ? 2 : 1;
+    const int KP = (b + 7) >> 3;
+    const size_t shp = (size_t)16 * NTP * (8 * KP + 2) * sizeof(cpx<T>);
+    return std::max(std::max(sh2, shp), rim ? rim_mfma_lds<T>(false) : (size_t)0);
+}
+
+template <typename T, typename In, typename Out>
+static void launch_fused_multi(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, const cpx<T> *G, bool rim, int lg2,
+                               int xs2, size_t sh2, int accumulate, Cols<const Out> acc, const cpx<T> *D, int nfin,
+                               const RimMap &rm, hipStream_t st) {
+    constexpr int NTP = sizeof(T) == 4 ? 2 : 1, NTR = rim_nt<T>();
+    const int b = pl->bc, C = b * R;
+    FusedDims fd;
+    fd.nslab = pl->rim_nslab;
+    fd.ncb_rim = (R + 16 * NTR - 1) / (16 * NTR);
+    fd.nrim = rim ? fd.nslab * fd.ncb_rim : 0;
+    fd.nfwd = (C + (1 << lg2) - 1) >> lg2;
+    fd.ncb = (R + 16 * NTP - 1) / (16 * NTP);
+    fd.nprod = pl->Px * pl->Py * fd.ncb;
+    fd.ninv = fd.nfwd;
+    fd.nfin = nfin;
+    const size_t sh = fused_multi_lds<T>(b, sh2, rim);
+    const int total = fd.nrim + fd.nfwd + fd.nprod + fd.ninv + fd.nfin;
+    const int grid = std::min(total, 512);
+    cpx<T> *gA = reinterpret_cast<cpx<T> *>(pl->gridA);
+    cpx<T> *gB = reinterpret_cast<cpx<T> *>(pl->gridB);
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, pl->fctr, kFusedCounters);
+    if (rim)
+        hipLaunchKernelGGL((k_fused_multi<T, In, Out, true>), dim3(grid), dim3(256), sh, st, x, y, R, pl->Nx, pl->Ny,
+                           b, pl->fx, pl->fy, lg2, xs2, gA, gB, G, pl->kxh, OpPtrs<T>::B(pl),
+                           reinterpret_cast<cpx<T> *>(pl->rim_part), OpPtrs<T>::C(pl), D, accumulate, acc, pl->N,
+                           pl->Nr, rm, fd, pl->fctr);
+    else
+        hipLaunchKernelGGL((k_fused_multi<T, In, Out, false>), dim3(grid), dim3(256), sh, st, x, y, R, pl->Nx, pl->Ny,
+                           b, pl->fx, pl->fy, lg2, xs2, gA, gB, G, pl->kxh, OpPtrs<T>::B(pl),
+                           reinterpret_cast<cpx<T> *>(pl->rim_part), OpPtrs<T>::C(pl), D, accumulate, acc, pl->N,
+                           pl->Nr, rm, fd, pl->fctr);
+}
+
 
 static int next_pow2(int v) {
     int p = 1;
@@ -1417,6 +1590,52 @@ static void launch_rim_general(tp_plan pl, Cols<const In> x, Cols<Out> y, int R,
 // PRE: apply the block-circulant preconditioner instead of the operator:
 // spectrum S, no rim pass, rim entries D x_r, and y = base + M^-1 x for the
 // columns whose base pointer is set (base.tab or base.base).
+// The launches an application takes at R columns (one choice for the
+// operator and its preconditioner alike; PRE picks the preconditioner).
+struct Path {
+    bool rim;          // dense rim pass (slabs; finished with the rim rows)
+    bool pairs;        // one column, pair-stream spectrum pass
+    bool fused;        // one column, fused spectrum pass
+    bool mfma;         // products (and a dense rim) on the matrix cores
+    bool rim_mma;      // the dense rim on the matrix cores
+    bool fusedm;       // every stage in one persistent launch
+    int lg2, xs2;      // 2-D tiles: log2 channels per tile (-1: separate x and y passes), row stride
+    size_t sh_fused, sh2;
+};
+
+template <typename T, bool PRE>
+static Path choose_path(tp_plan pl, int R) {
+    Path P;
+    const int b = pl->bc, Nr = pl->Nr, Px = pl->Px, Py = pl->Py, C = b * R;
+    const size_t es = sizeof(cpx<T>);
+    P.rim = !PRE && Nr > 0 && pl->nrc == 0;
+    P.sh_fused = std::max(spec_lds(pl, es), P.rim ? rim_lds(pl, 1, es) : (size_t)0);
+    // one column without a rim pass over a half spectrum: the fused path or the
+    // pair stream (y transforms in passes of their own), as the plan's option
+    // says (the tuner picks it; without a choice the fused path)
+    P.pairs = R == 1 && !P.rim && pl->half && b <= 128 && pl->opt_spectrum_pass == TP_PASS_PAIRS;
+    // one column: the fused path (for a half spectrum, rows of at most 96)
+    P.fused = !P.pairs && R == 1 && P.sh_fused <= kLdsLimit && !(pl->half && b > 96);
+    // many columns: the product and the rim run on the matrix cores (from the
+    // plan's threshold, else kMfmaMinR columns)
+    P.mfma = !P.fused && !P.pairs && R >= (pl->opt_mfma_min_r ? pl->opt_mfma_min_r : kMfmaMinR);
+    P.rim_mma = P.mfma && P.rim && pl->rim_te == 64 && rim_mfma_lds<T>(OpPtrs<T>::BE(pl) != nullptr) <= kLdsLimit;
+    // small grids with several columns: both transform directions per launch
+    // (the plan's option may let the 2-D tiles take more LDS: larger grids
+    // then run both transform directions in one launch, on fewer workgroups)
+    P.lg2 = P.fused ? -1 : fft2_lgcc(Px, Py, C, es, pl->opt_fft2_lds ? (size_t)pl->opt_fft2_lds : 48 * 1024);
+    P.xs2 = P.lg2 >= 0 ? fft2_xstride(Py, P.lg2, es) : 0;
+    P.sh2 = ((size_t)Px * P.xs2 + Px + Py) * es + (size_t)(Px + Py) * sizeof(int);
+    // many columns on the 2-D tiles and the matrix cores: optionally every
+    // stage in one persistent launch (default column tile, even b, a dense
+    // rim only when reciprocal)
+    P.fusedm = pl->opt_multi_fused == 1 && P.mfma && P.lg2 >= 0 && pl->fctr && b % 2 == 0 &&
+               (!P.rim || (P.rim_mma && OpPtrs<T>::BE(pl) == nullptr)) &&
+               (pl->opt_mfma_cols == 0 || pl->opt_mfma_cols == (sizeof(T) == 4 ? 32 : 16)) &&
+               fused_multi_lds<T>(b, P.sh2, P.rim) + 1024 <= kLdsLimit;
+    return P;
+}
+
 template <typename T, typename In, typename Out, bool PRE = false>
 hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipStream_t st,
                          hipEvent_t *ev = nullptr, Cols<const Out> base = Cols<const Out>{nullptr, 0, nullptr}) {
@@ -1437,20 +1656,31 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     // one stage alone, on the workspace a full application left behind
     auto on = [&](int stage) { return pl->only_stage < 0 || pl->only_stage == stage; };
     const cpx<T> *G = PRE ? OpPtrs<T>::S(pl) : OpPtrs<T>::G(pl);
-    const bool rim = !PRE && Nr > 0 && pl->nrc == 0;   // dense rim pass
-    const size_t sh_fused = std::max(spec_lds(pl, es), rim ? rim_lds(pl, 1, es) : (size_t)0);
-    // one column without a rim pass over a half spectrum: the fused path or the
-    // pair stream (y transforms in passes of their own), as the plan's option
-    // says (the tuner picks it; without a choice the fused path)
-    const bool pairs = R == 1 && !rim && pl->half && b <= 128 && pl->opt_spectrum_pass == TP_PASS_PAIRS;
-    // one column: the fused path (for a half spectrum, rows of at most 96)
-    const bool fused = !pairs && R == 1 && sh_fused <= kLdsLimit && !(pl->half && b > 96);
-
-    // many columns: the product and the rim run on the matrix cores (from the
-    // plan's threshold, else kMfmaMinR columns)
-    const bool mfma = !fused && !pairs && R >= (pl->opt_mfma_min_r ? pl->opt_mfma_min_r : kMfmaMinR);
-    const bool rim_mma =
-        mfma && rim && pl->rim_te == 64 && rim_mfma_lds<T>(OpPtrs<T>::BE(pl) != nullptr) <= kLdsLimit;
+    const Path P = choose_path<T, PRE>(pl, R);
+    const bool rim = P.rim, pairs = P.pairs, fused = P.fused, mfma = P.mfma, rim_mma = P.rim_mma;
+    const int lg2 = P.lg2, xs2 = P.xs2;
+    const size_t sh_fused = P.sh_fused, sh2 = P.sh2;
+    // the operator adds its rim term (already in y); the preconditioner adds
+    // the caller's base columns, if any
+    const Cols<const Out> acc = PRE ? base : Cols<const Out>{y.base, y.ld, y.tab};
+    const int accumulate = PRE ? (base.base || base.tab ? 1 : 0) : (rim ? 1 : 0);
+    const cpx<T> *D = PRE ? OpPtrs<T>::D(pl) : nullptr;
+    // rim rows of a dense rim (C x_r and the slab partials, or D x_r) are
+    // finished by extra waves; a placed rim's rows come out of the crop
+    const int nfin = (Nr > 0 && pl->nrc == 0) ? ((Nr + 3) / 4) * R : 0;
+    if (P.fusedm) {
+        mark(0);
+        mark(1);
+        mark(2);
+        mark(3);
+        if (on(3))
+            launch_fused_multi<T, In, Out>(pl, x, y, R, G, rim, lg2, xs2, sh2, accumulate, acc, D, nfin, rm, st);
+        mark(4);
+        mark(5);
+        mark(6);
+        mark(7);
+        return hipGetLastError();
+    }
 
     mark(0);
     if (rim && !fused && on(0)) {
@@ -1461,12 +1691,6 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
             launch_rim_general<T, In, Out>(pl, x, y, R, st);
     }
     mark(1);
-    // small grids with several columns: both transform directions per launch
-    // (the plan's option may let the 2-D tiles take more LDS: larger grids
-    // then run both transform directions in one launch, on fewer workgroups)
-    const int lg2 = fused ? -1 : fft2_lgcc(Px, Py, C, es, pl->opt_fft2_lds ? (size_t)pl->opt_fft2_lds : 48 * 1024);
-    const int xs2 = lg2 >= 0 ? fft2_xstride(Py, lg2, es) : 0;
-    const size_t sh2 = ((size_t)Px * xs2 + Px + Py) * es + (size_t)(Px + Py) * sizeof(int);
     if (!on(1)) {
     } else if (lg2 >= 0) {
         hipLaunchKernelGGL((k_fft2_fwd<T, In>), dim3((C + (1 << lg2) - 1) >> lg2), blk, sh2, st, x, R, Nx, Ny, b,
@@ -1517,14 +1741,6 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         hipLaunchKernelGGL((k_inv_y<T>), grid, blk, sh, st, gA, C, Ny, Px, pl->fy, lg, gB, act, b);
     }
     mark(5);
-    // the operator adds its rim term (already in y); the preconditioner adds
-    // the caller's base columns, if any
-    const Cols<const Out> acc = PRE ? base : Cols<const Out>{y.base, y.ld, y.tab};
-    const int accumulate = PRE ? (base.base || base.tab ? 1 : 0) : (rim ? 1 : 0);
-    const cpx<T> *D = PRE ? OpPtrs<T>::D(pl) : nullptr;
-    // rim rows of a dense rim (C x_r and the slab partials, or D x_r) are
-    // finished by extra waves; a placed rim's rows come out of the crop
-    const int nfin = (Nr > 0 && pl->nrc == 0) ? ((Nr + 3) / 4) * R : 0;
     if (!on(5)) {
     } else if (lg2 >= 0) {
         const int ninv = (C + (1 << lg2) - 1) >> lg2;

@@ -1,203 +1,8 @@
-// Matrix-core (MFMA) kernels for many right-hand sides, where the operator's
-// per-frequency product and its rim blocks become dense complex contractions.
-//
-// Both kernels are built from the 16 x 16 x 4 real MFMA (f32 or f64): lane l of
-// a wave supplies A[l % 16][l / 16] and B[l / 16][l % 16] and, after the
-// instruction, holds D[row(l / 16, v)][l % 16] for v = 0..3, with
-// row(g, v) = 4 g + v for f32 and g + 4 v for f64 (checked on gfx950 with
-// single-lane unit inputs).  A complex product takes four of them:
-//   D_re += A_re B_re + (-A_im) B_im,   D_im += A_re B_im + A_im B_re.
-// The contraction index k is free to be permuted, as long as A and B use the
-// same permutation; the kernels pick one that gives each lane a contiguous
-// run of memory.
-#include "tp_internal.h"
+// Launchers of the matrix-core kernels (bodies in tp_mfma.h).
+#include "tp_mfma.h"
 
 namespace tp {
 
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<float> {
-    typedef float v4 __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
-};
-template <>
-struct Mfma<double> {
-    typedef double v4 __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
-};
-
-// Stage n values into LDS with U loads in flight per thread: every load of a
-// round issues (addresses clamped by `ld`) before any value is stored, so the
-// round costs one memory latency rather than U.  Indices past the end are
-// clamped to n - 1 for the store as well: such a thread writes the same value
-// to the same slot as the thread that owns it, and no branch forms.
-template <int U, typename V, typename Load, typename Store>
-__device__ __forceinline__ void stage(int n, Load ld, Store st, int nt = kBlock) {
-    for (int base = threadIdx.x; base < n; base += U * nt) {
-        V v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = ld(min(base + u * nt, n - 1));
-#pragma unroll
-        for (int u = 0; u < U; ++u) st(min(base + u * nt, n - 1), v[u]);
-    }
-}
-
-template <typename T>
-struct CAcc {
-    typename Mfma<T>::v4 re, im;
-    __device__ __forceinline__ void zero() {
-        for (int v = 0; v < 4; ++v) re[v] = im[v] = 0;
-    }
-    __device__ __forceinline__ void mac(cpx<T> a, cpx<T> b) {
-        re = Mfma<T>::mac(a.x, b.x, re);
-        re = Mfma<T>::mac(-a.y, b.y, re);
-        im = Mfma<T>::mac(a.x, b.y, im);
-        im = Mfma<T>::mac(a.y, b.x, im);
-    }
-    __device__ __forceinline__ cpx<T> get(int v) const { return mk<T>(re[v], im[v]); }
-};
-
-// ------------------------------------------------ per-frequency product
-// yhat[k] = G[k] xhat[k] for every frequency k: (b x b) times (b x R).
-// Workgroup = frequency k and a block of 16 NT columns; wave w owns output rows
-// p in [16 w, 16 w + 16).  The contraction runs in pairs of k-steps: at pair t,
-// lane group g = l / 16 takes q = 8 t + 2 g + h for the two steps h = 0, 1, so
-// one load gives a lane the two consecutive values G[k][p][8t + 2g .. +1] and a
-// wave's load covers 16 rows x 64 contiguous bytes (f32).  Pairs are loaded in
-// chunks of KC, the next chunk's loads issued before the current chunk's
-// MFMAs.  The column block of xhat[k] is staged in LDS, row stride 8 KP + 2.
-// EVEN: b is even, so a value pair never straddles the end of a row and is
-// fetched with one aligned load.
-template <typename T>
-struct alignas(4 * sizeof(T)) cpair {
-    cpx<T> a, b;
-};
-
-template <typename T, int NT, int KC, bool EVEN>
-__global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ in,
-                                                    int b, int R, int Px, int Py, int kxh,
-                                                    cpx<T> *__restrict__ out, const void *const *act) {
-    extern __shared__ char smem_raw[];
-    cpx<T> *xs = reinterpret_cast<cpx<T> *>(smem_raw);
-    const int KP = (b + 7) >> 3, W = 8 * KP, bs = W + 2;
-    const long C = (long)b * R;
-    // XCD-aware order: workgroups are dealt to the 8 XCDs in turn, so XCD x
-    // receives ids x, x + 8, ...; it is given one contiguous range of
-    // (frequency, column block) items, and the column blocks of a frequency
-    // run back to back on the XCD whose L2 holds that frequency's G block
-    const int ncb = (R + 16 * NT - 1) / (16 * NT);
-    const long P = (long)Px * Py;
-    const long nitem = P * ncb, per = (long)gridDim.x >> 3;
-    const long item = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (item >= nitem) return;
-    const long k = item / ncb;
-    const int r0 = (int)(item - k * ncb) * 16 * NT, rn = min(16 * NT, R - r0);
-    if (!cols_live(act, r0, r0 + rn - 1)) return;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, i = l & 15;
-    const int nthr = blockDim.x;   // 64 per 16-row tile of the output
-    stage<4, cpx<T>>(
-        16 * NT * W,
-        [&](int idx) {
-            const int j = idx / W, q = idx - j * W;
-            return in[k * C + (long)(r0 + min(j, rn - 1)) * b + min(q, b - 1)];
-        },
-        [&](int idx, cpx<T> v) {
-            const int j = idx / W, q = idx - j * W;
-            xs[j * bs + q] = keep(v, j < rn && q < b);
-        },
-        nthr);
-    const int p = 16 * w + i;
-    const bool prow = p < b;
-    // a mirrored frequency (half spectrum) reads its stored block transposed
-    bool tr;
-    const cpx<T> *Gk = G + spec_src(k, Px, Py, kxh, tr) * (long)b * b;
-    // loads use clamped addresses, so they issue without branches; values
-    // outside the row are masked to zero only when they are used
-    const cpx<T> *arow = Gk + (long)min(p, b - 1) * b;
-    const cpx<T> *acol = Gk + min(p, b - 1);
-    auto load = [&](cpair<T>(&a)[KC], int t0) {
-#pragma unroll
-        for (int u = 0; u < KC; ++u) {
-            const int q = 8 * (t0 + u) + 2 * g;
-            if constexpr (EVEN) {
-                a[u] = *reinterpret_cast<const cpair<T> *>(arow + min(q, b - 2));
-            } else {
-                a[u].a = arow[min(q, b - 1)];
-                a[u].b = arow[min(q + 1, b - 1)];
-            }
-        }
-    };
-    // transposed: A[p][q] = stored[q][p], a column walk (16 lanes of a group
-    // read 16 consecutive values of one stored row)
-    auto load_tr = [&](cpair<T>(&a)[KC], int t0) {
-#pragma unroll
-        for (int u = 0; u < KC; ++u) {
-            const int q = 8 * (t0 + u) + 2 * g;
-            a[u].a = acol[(long)min(q, b - 1) * b];
-            a[u].b = acol[(long)min(q + 1, b - 1) * b];
-        }
-    };
-    CAcc<T> acc[NT];
-#pragma unroll
-    for (int n = 0; n < NT; ++n) acc[n].zero();
-    auto compute = [&](const cpair<T>(&a)[KC], int t0) {
-#pragma unroll
-        for (int u = 0; u < KC; ++u) {
-            const int t = t0 + u, q = 8 * t + 2 * g;
-            if (t < KP) {
-                // with b even and q clamped to b - 2, a pair past the row end
-                // holds the row's last two values: masked off here
-                const cpx<T> a0 = keep(a[u].a, prow && q < b), a1 = keep(a[u].b, prow && q + 1 < b);
-#pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    const cpair<T> bx = *reinterpret_cast<const cpair<T> *>(xs + (n * 16 + i) * bs + q);
-                    acc[n].mac(a0, bx.a);
-                    acc[n].mac(a1, bx.b);
-                }
-            }
-        }
-    };
-    // loads unconditional (clamped addresses): a load under a branch would
-    // make the wait before the other buffer's use cover it too.  The two
-    // orientations are two copies of the loop (tr is uniform).
-    auto run = [&](auto ld) {
-        cpair<T> a0[KC], a1[KC];
-        ld(a0, 0);
-        __syncthreads();
-        for (int t0 = 0; t0 < KP; t0 += 2 * KC) {
-            ld(a1, t0 + KC);
-            compute(a0, t0);
-            ld(a0, t0 + 2 * KC);
-            if (t0 + KC < KP) compute(a1, t0 + KC);
-        }
-    };
-    if (tr)
-        run(load_tr);
-    else
-        run(load);
-#pragma unroll
-    for (int n = 0; n < NT; ++n) {
-        const int j = n * 16 + i;
-        if (j < rn) {
-            cpx<T> *o = out + k * C + (long)(r0 + j) * b + 16 * w;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int rr = Mfma<T>::row(g, v);
-                if (16 * w + rr < b) o[rr] = acc[n].get(v);
-            }
-        }
-    }
-}
-
-// Column tiles of 16 per workgroup: the launch option (16, 32 or 64 columns;
-// 0 = 32 for f32, 16 for f64).
 template <typename T, int NT>
 static void launch_prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, int Px, int Py, int kxh, cpx<T> *out,
                              const void *const *act, hipStream_t st) {
@@ -231,124 +36,6 @@ template hipError_t prod_mfma<float>(const c64 *, const c64 *, int, int, int, in
 template hipError_t prod_mfma<double>(const c128 *, const c128 *, int, int, int, int, int, c128 *,
                                       const void *const *, hipStream_t, int);
 
-// ---------------------------------------------------------------- rim
-// One slab of 64 element columns e0 .. e0 + 63 and a block of 16 NT
-// right-hand sides, 4 waves:
-//   uA[e][j]   = sum_row BE[row][e] x_r[row][j]      (y_A, wave w: e in [16 w, 16 w + 16))
-//   part[row][j] = sum_{e in slab} B[row][e] x_A[e][j] (slab partial of y_r)
-// The x_A slab sits in LDS; the rim rows are taken in chunks of RCH, whose B
-// (and BE) rows and x_r entries are staged in LDS, so each B value is read from
-// memory once for both products.  The partials use the slab layout of the
-// general rim pass and are finished by the same kernel.
-template <typename T, typename In, typename Out, int NT, int RCH, bool NBE>
-__global__ void __launch_bounds__(256) k_rim_mfma(const cpx<T> *__restrict__ B, const cpx<T> *__restrict__ BE,
-                                                  Cols<const In> x, Cols<Out> y, int R, long N, int Nr,
-                                                  cpx<T> *__restrict__ part) {
-    constexpr int TE = 64, LS = TE + 1, NC = 16 * NT, XS = RCH + 1;
-    extern __shared__ char smem_raw[];
-    cpx<T> *xa = reinterpret_cast<cpx<T> *>(smem_raw);   // [NC][LS]
-    cpx<T> *xr = xa + NC * LS;                             // [NC][XS]
-    cpx<T> *bs = xr + NC * XS;                             // [RCH][LS]
-    cpx<T> *be = NBE ? bs + RCH * LS : bs;                 // [RCH][LS]
-    const int slab = blockIdx.x, rb = blockIdx.y * NC;
-    const long e0 = (long)slab * TE;
-    const int rn = min(NC, R - rb);
-    if (!cols_live((const void *const *)x.tab, rb, rb + rn - 1)) return;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, i = l & 15;
-    // column pointers of the block; idle and missing columns read a live one
-    // (their values are masked to zero)
-    __shared__ const In *colp[NC];
-    __shared__ int colok[NC];
-    if (threadIdx.x == 0) {
-        const In *live = nullptr;
-        for (int j = 0; j < rn && !live; ++j) live = x.col(rb + j);
-        for (int j = 0; j < NC; ++j) {
-            const In *c = j < rn ? x.col(rb + j) : nullptr;
-            colok[j] = c != nullptr;
-            colp[j] = c ? c : live;
-        }
-    }
-    __syncthreads();
-    const long elast = N - 1;
-    stage<4, In>(
-        NC * TE, [&](int idx) { return colp[idx / TE][min(e0 + idx % TE, elast)]; },
-        [&](int idx, In v) {
-            const int j = idx / TE, t = idx - j * TE;
-            xa[j * LS + t] = keep(cvt<T>(v), colok[j] && e0 + t < N);
-        });
-    CAcc<T> ua[NT];
-#pragma unroll
-    for (int n = 0; n < NT; ++n) ua[n].zero();
-    for (int rc = 0; rc < Nr; rc += RCH) {
-        __syncthreads();
-        auto boff = [&](int idx) {
-            return (long)min(rc + idx / TE, Nr - 1) * N + min(e0 + idx % TE, elast);
-        };
-        auto bok = [&](int idx) { return rc + idx / TE < Nr && e0 + idx % TE < N; };
-        stage<4, cpx<T>>(
-            RCH * TE, [&](int idx) { return B[boff(idx)]; },
-            [&](int idx, cpx<T> v) { bs[(idx / TE) * LS + idx % TE] = keep(v, bok(idx)); });
-        if constexpr (NBE)
-            stage<4, cpx<T>>(
-                RCH * TE, [&](int idx) { return BE[boff(idx)]; },
-                [&](int idx, cpx<T> v) { be[(idx / TE) * LS + idx % TE] = keep(v, bok(idx)); });
-        stage<4, In>(
-            NC * RCH, [&](int idx) { return colp[idx / RCH][N + min(rc + idx % RCH, Nr - 1)]; },
-            [&](int idx, In v) {
-                const int j = idx / RCH, u = idx - j * RCH;
-                xr[j * XS + u] = keep(cvt<T>(v), colok[j] && rc + u < Nr);
-            });
-        __syncthreads();
-        // y_A part: A[e][u] = BE[rc + u][e], k = u = 4 s + g (steps past the last rim row skipped)
-        const int ks1 = (min(RCH, Nr - rc) + 3) >> 2;
-#pragma unroll 4
-        for (int s = 0; s < ks1; ++s) {
-            const int u = 4 * s + g;
-            const cpx<T> a = be[u * LS + 16 * w + i];
-#pragma unroll
-            for (int n = 0; n < NT; ++n) ua[n].mac(a, xr[(n * 16 + i) * XS + u]);
-        }
-        // slab partials of y_r: A[row][t] = B[rc + row][e0 + t], k = t = 4 s + g
-        for (int mt = w; mt < RCH / 16 && rc + 16 * mt < Nr; mt += 4) {
-            CAcc<T> pa[NT];
-#pragma unroll
-            for (int n = 0; n < NT; ++n) pa[n].zero();
-#pragma unroll 4
-            for (int s = 0; s < TE / 4; ++s) {
-                const int t = 4 * s + g;
-                const cpx<T> a = bs[(16 * mt + i) * LS + t];
-#pragma unroll
-                for (int n = 0; n < NT; ++n) pa[n].mac(a, xa[(n * 16 + i) * LS + t]);
-            }
-#pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                const int j = n * 16 + i;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = rc + 16 * mt + Mfma<T>::row(g, v);
-                    if (row < Nr && j < rn) part[((long)slab * Nr + row) * R + rb + j] = pa[n].get(v);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int n = 0; n < NT; ++n) {
-        const int j = n * 16 + i;
-        Out *yc = j < rn ? y.col(rb + j) : nullptr;
-        if (yc) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const long e = e0 + 16 * w + Mfma<T>::row(g, v);
-                if (e < N) yc[e] = cvt<typename Out::value_type>(ua[n].get(v));
-            }
-        }
-    }
-}
-
-template <typename T>
-static constexpr int rim_nt() { return sizeof(T) == 4 ? 2 : 1; }
-template <typename T>
-static constexpr int rim_rch() { return sizeof(T) == 4 ? 64 : 32; }
 
 template <typename T>
 size_t rim_mfma_lds(bool nbe) {

@@ -221,4 +221,17 @@ hipError_t cast_to_c64(const c128 *in, c64 *out, long n, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <typename T, bool PRE>
+static int path_bits(tp_plan pl, int R) {
+    const Path P = choose_path<T, PRE>(pl, R);
+    return (P.fused ? TP_PATH_FUSED : 0) | (P.pairs ? TP_PATH_PAIRS : 0) | (P.mfma ? TP_PATH_MFMA : 0) |
+           (P.rim ? TP_PATH_DENSE_RIM : 0) | (P.rim_mma ? TP_PATH_RIM_MFMA : 0) |
+           (P.lg2 >= 0 ? TP_PATH_TILES2D : 0) | (P.fusedm ? TP_PATH_PERSISTENT : 0);
+}
+
+int path_flags(tp_plan pl, bool fp64, bool pre, int R) {
+    if (fp64) return pre ? path_bits<double, true>(pl, R) : path_bits<double, false>(pl, R);
+    return pre ? path_bits<float, true>(pl, R) : path_bits<float, false>(pl, R);
+}
+
 }  // namespace tp

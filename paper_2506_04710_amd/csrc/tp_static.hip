@@ -45,7 +45,8 @@ static size_t al256(size_t n) { return (n + 255) & ~(size_t)255; }
 // Workspace of one application to nrhs columns, as toeplitz_matvec uses it in
 // the plan: two transform grids [max(Ny Px, Px Py)][bc nrhs] (complex128
 // slots; bc channels per cell), the rim slab partials [nslab][Nr][nrhs], and
-// for a half spectrum the mirror parts [bc / 8][Ny][Px - kxh][bc].
+// for a half spectrum the mirror parts [bc / 8][Ny][Px - kxh][bc], and the
+// queue and counters of the persistent multi-column launch (256 bytes).
 struct StaticLayout {
     size_t grid, rimpart, ypart, total;
 };
@@ -55,7 +56,7 @@ static StaticLayout static_layout(tp_plan p, int nrhs) {
     L.grid = al256(gpts * (size_t)p->bc * nrhs * 16);
     L.rimpart = al256((size_t)p->rim_nslab * (p->Nr ? p->Nr : 1) * nrhs * 16);
     L.ypart = p->half ? al256((size_t)((p->bc + 7) / 8) * p->Ny * (p->Px - p->kxh) * p->bc * 16) : 0;
-    L.total = 2 * L.grid + L.rimpart + L.ypart;
+    L.total = 2 * L.grid + L.rimpart + L.ypart + 256;    // + the persistent launch's counters
     return L;
 }
 
@@ -85,6 +86,7 @@ tp_status toeplitz_matvec_static(tp_plan p, tp_prec which, const void *x, long l
     q.gridB = b + L.grid;
     q.rim_part = b + 2 * L.grid;
     q.ypart = L.ypart ? b + 2 * L.grid + L.rimpart : nullptr;
+    q.fctr = reinterpret_cast<int *>(b + 2 * L.grid + L.rimpart + L.ypart);
     hipStream_t st = (hipStream_t)hip_stream;
     hipError_t e;
     if (which == TP_FP64)

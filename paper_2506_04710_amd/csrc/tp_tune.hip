@@ -62,6 +62,14 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
     const size_t tile4 = ((size_t)p->Px * (p->Py * 4 + 16) + p->Px + p->Py) * es + (size_t)(p->Px + p->Py) * 4;
     const bool fft2_matters = tile4 > 48 * 1024 && tile4 <= 160 * 1024;
     std::vector<int> tiles = fft2_matters ? std::vector<int>{0, 160 * 1024} : std::vector<int>{p->opt_fft2_lds};
+    // the persistent launch: timed where a combination takes it (it applies
+    // at the default column tile only)
+    const int def_cols = which == TP_FP64 ? 16 : 32;
+    auto persistent = [&]() {
+        const bool f64 = which == TP_FP64;
+        return (path_flags(p, f64, false, nrhs) & TP_PATH_PERSISTENT) ||
+               (p->has_precond && (path_flags(p, f64, true, nrhs) & TP_PATH_PERSISTENT));
+    };
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(TP_E_HIP, "event create");
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -79,32 +87,40 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
         if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
         ms = (double)f / reps;
     };
-    const int keep_pass = p->opt_spectrum_pass, keep_cols = p->opt_mfma_cols, keep_tile = p->opt_fft2_lds;
+    const int keep_pass = p->opt_spectrum_pass, keep_cols = p->opt_mfma_cols, keep_tile = p->opt_fft2_lds,
+              keep_multi = p->opt_multi_fused;
     // every option at its default first
     p->opt_spectrum_pass = TP_PASS_AUTO;
     p->opt_mfma_cols = 0;
     p->opt_fft2_lds = 0;
+    p->opt_multi_fused = 0;
     double ms_def = 0.0;
     time_it(ms_def);
     double best = -1.0;
-    int bp = keep_pass, bc = keep_cols, bt = keep_tile, n = 0;
+    int bp = keep_pass, bc = keep_cols, bt = keep_tile, bm = keep_multi, n = 0;
+    bool multi_seen = false;
     for (int pv : passes)
         for (int cv : cols)
-            for (int tv : tiles) {
-                if (e != hipSuccess) break;
-                p->opt_spectrum_pass = pv;
-                p->opt_mfma_cols = cv;
-                p->opt_fft2_lds = tv;
-                double ms = 0.0;
-                time_it(ms);
-                ++n;
-                if (e == hipSuccess && (best < 0.0 || ms < best)) {
-                    best = ms;
-                    bp = pv;
-                    bc = cv;
-                    bt = tv;
+            for (int tv : tiles)
+                for (int mv = 0; mv < 2; ++mv) {
+                    if (e != hipSuccess) break;
+                    p->opt_spectrum_pass = pv;
+                    p->opt_mfma_cols = cv;
+                    p->opt_fft2_lds = tv;
+                    p->opt_multi_fused = mv;
+                    if (mv == 1 && (cv != def_cols || !persistent())) continue;
+                    multi_seen |= mv == 1;
+                    double ms = 0.0;
+                    time_it(ms);
+                    ++n;
+                    if (e == hipSuccess && (best < 0.0 || ms < best)) {
+                        best = ms;
+                        bp = pv;
+                        bc = cv;
+                        bt = tv;
+                        bm = mv;
+                    }
                 }
-            }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     solver_drop_graphs(p);      // captured graphs hold the launch shapes
@@ -112,14 +128,17 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
         p->opt_spectrum_pass = keep_pass;
         p->opt_mfma_cols = keep_cols;
         p->opt_fft2_lds = keep_tile;
+        p->opt_multi_fused = keep_multi;
         return hip_fail(e, "tune");
     }
     p->opt_spectrum_pass = bp;
     p->opt_mfma_cols = bc;
     p->opt_fft2_lds = bt;
+    p->opt_multi_fused = bm;
     res->spectrum_pass = pass_matters ? bp : TP_PASS_AUTO;
     res->mfma_cols = mfma_matters ? bc : 0;
     res->fft2_lds = fft2_matters ? bt : 0;
+    res->multi_fused = multi_seen ? bm : 0;
     res->candidates = n;
     res->ms = best;
     res->ms_default = ms_def;

@@ -71,5 +71,11 @@ def test_tune_many_columns(tp, tmp_path):
     prob = sa.make_problem(4, 4, 16, 24, 9802)
     plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=20, restart=4)
     rec = tune.tune(plan, "fp32", 20, reps=5, path=str(tmp_path / "t.json"))
-    assert rec["mfma_cols"] in (16, 32, 64) and rec["candidates"] == 3 and rec["spectrum_pass"] == 0
+    # three column tiles, and the persistent launch at the default tile (a
+    # small grid on 2-D tiles, even b, reciprocal dense rim)
+    assert rec["mfma_cols"] in (16, 32, 64) and rec["candidates"] == 4 and rec["spectrum_pass"] == 0
+    assert rec["multi_fused"] in (0, 1)
+    from paper_2506_04710_amd import _lib
+    assert plan.get_option(_lib.TP_OPT_MULTI_FUSED) == rec["multi_fused"]
+    assert ("persistent" in plan.path("fp32", 20)) == (rec["multi_fused"] == 1)
     plan.close()
