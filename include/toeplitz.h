@@ -202,7 +202,14 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
  *     inverse tiles, rim finish) in one persistent launch whose workgroups
  *     take tasks from a queue in dependency order (same results bit for bit);
  *     0 (default): one launch per stage.  Applies with even b, the default
- *     column tile and no separate B_er.
+ *     column tile, no separate B_er and TP_OPT_PROD_LDS off.
+ *   TP_OPT_PROD_LDS  FP32 per-frequency product with the spectrum block staged
+ *     in LDS and each wave's column tile of the transformed input held in
+ *     registers: value 16 * CG + RT, CG column tiles of 16 per workgroup
+ *     (1..16), RT row tiles of 16 per wave (2, 3 or 6); 0 (default): the
+ *     product that streams the block from memory.  Same results bit for bit;
+ *     applies from the matrix-core column threshold on, to b <= 128, where
+ *     CG * ceil(ceil(b / 16) / RT) <= 16 (else the default product runs).
  * Setting an option drops the plan's captured solver graphs.  Errors:
  * TP_E_INVAL (unknown option or value, NULL pointers, a continuous batch is
  * active on the plan).
@@ -212,6 +219,7 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
 #define TP_OPT_MFMA_MIN_R 3
 #define TP_OPT_FFT2_LDS 4
 #define TP_OPT_MULTI_FUSED 5
+#define TP_OPT_PROD_LDS 6
 #define TP_PASS_AUTO 0
 #define TP_PASS_FUSED 1
 #define TP_PASS_PAIRS 2
@@ -249,6 +257,7 @@ typedef struct {
     int mfma_cols;       /* 16, 32, 64 (0 when nrhs is below the matrix-core threshold) */
     int fft2_lds;        /* 0 (48 KB tiles) or 163840 (where larger tiles would change the path) */
     int multi_fused;     /* 1 where the persistent multi-column launch was timed and fastest, else 0 */
+    int prod_lds;        /* TP_OPT_PROD_LDS value chosen (0: the streaming product) */
     int candidates;      /* option combinations timed */
     double ms;           /* mean milliseconds of the timed work with the chosen options */
     double ms_default;   /* the same with every option at its default */
@@ -261,7 +270,9 @@ typedef struct {
  * preconditioner; the matrix-core column tile from the threshold on; the 2-D
  * transform tile size where a 160 KB tile of 4 channels would hold a grid
  * that a 48 KB one does not; the persistent multi-column launch where a
- * combination at the default column tile takes it), each
+ * combination at the default column tile takes it; for FP32 operators from
+ * the threshold on, the LDS-staged product in column-group and row-tile
+ * shapes whose workgroup fits), each
  * for reps applications after two untimed ones, with HIP events on
  * hip_stream, and set the fastest.  The timed work is what a solve applies:
  * the operator `which` (TP_FP64, TP_FP32 or TP_MIXED, as toeplitz_matvec) and,

@@ -1590,6 +1590,16 @@ static void launch_rim_general(tp_plan pl, Cols<const In> x, Cols<Out> y, int R,
 // PRE: apply the block-circulant preconditioner instead of the operator:
 // spectrum S, no rim pass, rim entries D x_r, and y = base + M^-1 x for the
 // columns whose base pointer is set (base.tab or base.base).
+// The FP32 product with the block in LDS, when the plan's option asks for it
+// and the block and the workgroup fit
+template <typename T>
+static bool prod_lds_ok(tp_plan pl, int b) {
+    if (sizeof(T) != 4 || pl->opt_prod_lds == 0 || b > 128 || prod_lds_bytes(b) > kLdsLimit) return false;
+    const int CG = pl->opt_prod_lds >> 4, RT = pl->opt_prod_lds & 15, nrt = (b + 15) >> 4;
+    const int rt = RT <= 2 ? 2 : RT <= 3 ? 3 : 6;
+    return CG >= 1 && CG * ((nrt + rt - 1) / rt) <= 16;
+}
+
 // The launches an application takes at R columns (one choice for the
 // operator and its preconditioner alike; PRE picks the preconditioner).
 struct Path {
@@ -1629,7 +1639,7 @@ static Path choose_path(tp_plan pl, int R) {
     // many columns on the 2-D tiles and the matrix cores: optionally every
     // stage in one persistent launch (default column tile, even b, a dense
     // rim only when reciprocal)
-    P.fusedm = pl->opt_multi_fused == 1 && P.mfma && P.lg2 >= 0 && pl->fctr && b % 2 == 0 &&
+    P.fusedm = pl->opt_multi_fused == 1 && pl->opt_prod_lds == 0 && P.mfma && P.lg2 >= 0 && pl->fctr && b % 2 == 0 &&
                (!P.rim || (P.rim_mma && OpPtrs<T>::BE(pl) == nullptr)) &&
                (pl->opt_mfma_cols == 0 || pl->opt_mfma_cols == (sizeof(T) == 4 ? 32 : 16)) &&
                fused_multi_lds<T>(b, P.sh2, P.rim) + 1024 <= kLdsLimit;
@@ -1722,6 +1732,9 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         else launch_spec_rim_e<T, In, Out, 32>(pl, G, rim, x, y, gA, gB, sh_fused, st);
     } else if (pairs) {
         launch_pair_prod<T>(pl, G, gB, gA, act, st);
+    } else if (mfma && prod_lds_ok<T>(pl, b)) {
+        prod_lds(reinterpret_cast<const c64 *>(G), reinterpret_cast<const c64 *>(gB), b, R, Px, Py, pl->kxh,
+                 reinterpret_cast<c64 *>(gA), act, st, pl->opt_prod_lds >> 4, pl->opt_prod_lds & 15);
     } else if (mfma) {
         prod_mfma<T>(G, gB, b, R, Px, Py, pl->kxh, gA, act, st, pl->opt_mfma_cols);
     } else {

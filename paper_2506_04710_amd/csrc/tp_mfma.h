@@ -58,9 +58,19 @@ struct CAcc {
         for (int v = 0; v < 4; ++v) re[v] = im[v] = 0;
     }
     __device__ __forceinline__ void mac(cpx<T> a, cpx<T> b) {
+        mac_a(a, b);
+        mac_b(a, b);
+    }
+    // the two halves of mac, each two independent instructions: callers with
+    // several accumulators issue the first half of every one before the
+    // second, so no instruction waits on the one just before it (each
+    // accumulator still sums in the order of mac)
+    __device__ __forceinline__ void mac_a(cpx<T> a, cpx<T> b) {
         re = Mfma<T>::mac(a.x, b.x, re);
-        re = Mfma<T>::mac(-a.y, b.y, re);
         im = Mfma<T>::mac(a.x, b.y, im);
+    }
+    __device__ __forceinline__ void mac_b(cpx<T> a, cpx<T> b) {
+        re = Mfma<T>::mac(-a.y, b.y, re);
         im = Mfma<T>::mac(a.y, b.x, im);
     }
     __device__ __forceinline__ cpx<T> get(int v) const { return mk<T>(re[v], im[v]); }
@@ -147,12 +157,17 @@ __device__ __forceinline__ void prod_mfma_item(const cpx<T> *__restrict__ G, con
                 // with b even and q clamped to b - 2, a pair past the row end
                 // holds the row's last two values: masked off here
                 const cpx<T> a0 = keep(a[u].a, prow && q < b), a1 = keep(a[u].b, prow && q + 1 < b);
+                cpair<T> bx[NT];
 #pragma unroll
-                for (int n = 0; n < NT; ++n) {
-                    const cpair<T> bx = *reinterpret_cast<const cpair<T> *>(xs + (n * 16 + i) * bs + q);
-                    acc[n].mac(a0, bx.a);
-                    acc[n].mac(a1, bx.b);
-                }
+                for (int n = 0; n < NT; ++n) bx[n] = *reinterpret_cast<const cpair<T> *>(xs + (n * 16 + i) * bs + q);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) acc[n].mac_a(a0, bx[n].a);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) acc[n].mac_b(a0, bx[n].a);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) acc[n].mac_a(a1, bx[n].b);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) acc[n].mac_b(a1, bx[n].b);
             }
         }
     };
@@ -228,6 +243,131 @@ __global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G
     prod_mfma_item<T, NT, KC, EVEN>(G, in, b, R, Px, Py, kxh, out, act, k, (int)(item - k * ncb), smem_raw);
 }
 
+// The same product with the frequency's spectrum block in LDS.  Workgroup =
+// frequency k and a group of CG column tiles of 16; wave w takes column tile
+// w % CG and the RT row tiles of group w / CG.  The block is staged once
+// (transposed as it is written when the frequency is a mirrored one, zero past
+// column b), each wave holds its column tile of xhat[k] in registers for the
+// whole contraction (loaded before the staging barrier), and the contraction
+// then reads only LDS and registers.  The contraction order (pairs t, lane
+// group g, step h) is that of k_prod_mfma, so both give the same bits.
+// LDS row stride 8 KP + 2 values: the 16 rows a 16-lane phase reads fall in
+// distinct 16-byte bank groups.  KPM: pairs held in registers (KP <= KPM).
+template <typename T, int RT, int KPM, bool EVEN>
+__global__ void __launch_bounds__(1024) k_prod_lds(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ in,
+                                                   int b, int R, int Px, int Py, int kxh, int CG,
+                                                   cpx<T> *__restrict__ out, const void *const *act) {
+    extern __shared__ char smem_raw[];
+    cpx<T> *gs = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int KP = (b + 7) >> 3, W = 8 * KP, S = W + 2;
+    const int ntc = (R + 15) >> 4, ncg = (ntc + CG - 1) / CG;
+    const long P = (long)Px * Py, nitem = P * ncg, per = (long)gridDim.x >> 3;
+    const long item = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (item >= nitem) return;
+    const long k = item / ncg;
+    const int cg = (int)(item - k * ncg);
+    const int cfirst = cg * CG * 16, clast = min(R, cfirst + CG * 16) - 1;
+    if (!cols_live(act, cfirst, clast)) return;
+    const long C = (long)b * R;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, i = l & 15;
+    const int ct = w % CG, rg = w / CG;
+    const int c0 = cfirst + ct * 16;
+    const bool wlive = c0 <= clast && cols_live(act, c0, min(c0 + 15, clast));
+    // this lane's column of the tile, its xhat values for every pair (zero
+    // past row b and past column R)
+    cpair<T> xr[KPM];
+    {
+        const int col = min(c0 + i, R - 1);
+        const bool cok = c0 + i < R;
+        const cpx<T> *xc = in + k * C + (long)col * b;
+#pragma unroll
+        for (int t = 0; t < KPM; ++t) {
+            if (t < KP) {
+                const int q = 8 * t + 2 * g;
+                if constexpr (EVEN) {
+                    xr[t] = *reinterpret_cast<const cpair<T> *>(xc + min(q, b - 2));
+                } else {
+                    xr[t].a = xc[min(q, b - 1)];
+                    xr[t].b = xc[min(q + 1, b - 1)];
+                }
+                xr[t].a = keep(xr[t].a, cok && q < b);
+                xr[t].b = keep(xr[t].b, cok && q + 1 < b);
+            }
+        }
+    }
+    // the spectrum block, transposed for a mirrored frequency
+    bool tr;
+    const cpx<T> *Gk = G + spec_src(k, Px, Py, kxh, tr) * (long)b * b;
+    const int nthr = blockDim.x;
+    if (tr) {
+        // LDS[p][q] = stored[q][p]: read stored rows (contiguous in p)
+        stage<4, cpx<T>>(
+            W * b,
+            [&](int idx) {
+                const int q = idx / b, p = idx - q * b;
+                return Gk[(long)min(q, b - 1) * b + p];
+            },
+            [&](int idx, cpx<T> v) {
+                const int q = idx / b, p = idx - q * b;
+                gs[p * S + q] = keep(v, q < b);
+            },
+            nthr);
+    } else {
+        stage<4, cpx<T>>(
+            W * b,
+            [&](int idx) {
+                const int p = idx / W, q = idx - p * W;
+                return Gk[(long)p * b + min(q, b - 1)];
+            },
+            [&](int idx, cpx<T> v) {
+                const int p = idx / W, q = idx - p * W;
+                gs[p * S + q] = keep(v, q < b);
+            },
+            nthr);
+    }
+    __syncthreads();
+    if (!wlive) return;
+    const int nrt = (b + 15) >> 4;
+    CAcc<T> acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) acc[r].zero();
+    // rows past b read the last row (results not stored)
+    const cpx<T> *arow[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) arow[r] = gs + min(16 * (rg * RT + r) + i, b - 1) * S + 2 * g;
+#pragma unroll
+    for (int t = 0; t < KPM; ++t) {
+        if (t < KP) {
+            // row tiles past the last are computed on the clamped rows and
+            // not stored (no branch between the instructions)
+            cpair<T> a[RT];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) a[r] = *reinterpret_cast<const cpair<T> *>(arow[r] + 8 * t);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r].mac_a(a[r].a, xr[t].a);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r].mac_b(a[r].a, xr[t].a);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r].mac_a(a[r].b, xr[t].b);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r].mac_b(a[r].b, xr[t].b);
+        }
+    }
+    const int j = c0 + i;
+    if (j <= clast) {
+        cpx<T> *o = out + k * C + (long)j * b;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            const int rt = rg * RT + r;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * rt + Mfma<T>::row(g, v);
+                if (rt < nrt && row < b) o[row] = acc[r].get(v);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- rim
 // One slab of 64 element columns e0 .. e0 + 63 and a block of 16 NT
 // right-hand sides, 4 waves:
@@ -301,8 +441,13 @@ __device__ __forceinline__ void rim_mfma_tile(const cpx<T> *__restrict__ B, cons
         for (int s = 0; s < ks1; ++s) {
             const int u = 4 * s + g;
             const cpx<T> a = be[u * LS + 16 * w + i];
+            cpx<T> bx[NT];
 #pragma unroll
-            for (int n = 0; n < NT; ++n) ua[n].mac(a, xr[(n * 16 + i) * XS + u]);
+            for (int n = 0; n < NT; ++n) bx[n] = xr[(n * 16 + i) * XS + u];
+#pragma unroll
+            for (int n = 0; n < NT; ++n) ua[n].mac_a(a, bx[n]);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) ua[n].mac_b(a, bx[n]);
         }
         // slab partials of y_r: A[row][t] = B[rc + row][e0 + t], k = t = 4 s + g
         for (int mt = w; mt < RCH / 16 && rc + 16 * mt < Nr; mt += 4) {
@@ -313,8 +458,13 @@ __device__ __forceinline__ void rim_mfma_tile(const cpx<T> *__restrict__ B, cons
             for (int s = 0; s < TE / 4; ++s) {
                 const int t = 4 * s + g;
                 const cpx<T> a = bs[(16 * mt + i) * LS + t];
+                cpx<T> bx[NT];
 #pragma unroll
-                for (int n = 0; n < NT; ++n) pa[n].mac(a, xa[(n * 16 + i) * LS + t]);
+                for (int n = 0; n < NT; ++n) bx[n] = xa[(n * 16 + i) * LS + t];
+#pragma unroll
+                for (int n = 0; n < NT; ++n) pa[n].mac_a(a, bx[n]);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) pa[n].mac_b(a, bx[n]);
             }
 #pragma unroll
             for (int n = 0; n < NT; ++n) {

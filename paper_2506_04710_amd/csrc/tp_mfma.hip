@@ -1,7 +1,14 @@
 // Launchers of the matrix-core kernels (bodies in tp_mfma.h).
+#include <type_traits>
+
 #include "tp_mfma.h"
 
 namespace tp {
+
+// pairs of contraction steps per prefetched chunk of the product
+#ifndef TP_PROD_KC
+#define TP_PROD_KC 4
+#endif
 
 template <typename T, int NT>
 static void launch_prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, int Px, int Py, int kxh, cpx<T> *out,
@@ -12,10 +19,10 @@ static void launch_prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, in
     const long nitem = (long)Px * Py * ((R + 16 * NT - 1) / (16 * NT));
     dim3 grid((unsigned)(((nitem + 7) / 8) * 8));
     if (b % 2 == 0)
-        hipLaunchKernelGGL((k_prod_mfma<T, NT, 4, true>), grid, dim3(64 * waves), sh, st, G, in, b, R, Px, Py, kxh,
+        hipLaunchKernelGGL((k_prod_mfma<T, NT, TP_PROD_KC, true>), grid, dim3(64 * waves), sh, st, G, in, b, R, Px, Py, kxh,
                            out, act);
     else
-        hipLaunchKernelGGL((k_prod_mfma<T, NT, 4, false>), grid, dim3(64 * waves), sh, st, G, in, b, R, Px, Py, kxh,
+        hipLaunchKernelGGL((k_prod_mfma<T, NT, TP_PROD_KC, false>), grid, dim3(64 * waves), sh, st, G, in, b, R, Px, Py, kxh,
                            out, act);
 }
 
@@ -36,6 +43,44 @@ template hipError_t prod_mfma<float>(const c64 *, const c64 *, int, int, int, in
 template hipError_t prod_mfma<double>(const c128 *, const c128 *, int, int, int, int, int, c128 *,
                                       const void *const *, hipStream_t, int);
 
+
+size_t prod_lds_bytes(int b) {
+    const int KP = (b + 7) >> 3;
+    return (size_t)b * (8 * KP + 2) * sizeof(c64);
+}
+
+template <int RT, int KPM>
+static void launch_prod_lds(const c64 *G, const c64 *in, int b, int R, int Px, int Py, int kxh, c64 *out,
+                            const void *const *act, hipStream_t st, int CG) {
+    const int nrt = (b + 15) >> 4, RG = (nrt + RT - 1) / RT;
+    const int ntc = (R + 15) >> 4, ncg = (ntc + CG - 1) / CG;
+    const long nitem = (long)Px * Py * ncg;
+    dim3 grid((unsigned)(((nitem + 7) / 8) * 8));
+    const size_t sh = prod_lds_bytes(b);
+    if (b % 2 == 0)
+        hipLaunchKernelGGL((k_prod_lds<float, RT, KPM, true>), grid, dim3(64 * CG * RG), sh, st, G, in, b, R, Px,
+                           Py, kxh, CG, out, act);
+    else
+        hipLaunchKernelGGL((k_prod_lds<float, RT, KPM, false>), grid, dim3(64 * CG * RG), sh, st, G, in, b, R, Px,
+                           Py, kxh, CG, out, act);
+}
+
+// FP32 product with the spectrum block in LDS (b <= 128): RT row tiles per
+// wave, CG column tiles per workgroup (CG x ceil(ceil(b / 16) / RT) waves).
+hipError_t prod_lds(const c64 *G, const c64 *in, int b, int R, int Px, int Py, int kxh, c64 *out,
+                    const void *const *act, hipStream_t st, int CG, int RT) {
+    const int KP = (b + 7) >> 3;
+    auto go = [&](auto rt) {
+        constexpr int RTc = decltype(rt)::value;
+        if (KP <= 8) launch_prod_lds<RTc, 8>(G, in, b, R, Px, Py, kxh, out, act, st, CG);
+        else if (KP <= 12) launch_prod_lds<RTc, 12>(G, in, b, R, Px, Py, kxh, out, act, st, CG);
+        else launch_prod_lds<RTc, 16>(G, in, b, R, Px, Py, kxh, out, act, st, CG);
+    };
+    if (RT <= 2) go(std::integral_constant<int, 2>());
+    else if (RT <= 3) go(std::integral_constant<int, 3>());
+    else go(std::integral_constant<int, 6>());
+    return hipGetLastError();
+}
 
 template <typename T>
 size_t rim_mfma_lds(bool nbe) {

@@ -65,6 +65,15 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
     // the persistent launch: timed where a combination takes it (it applies
     // at the default column tile only)
     const int def_cols = which == TP_FP64 ? 16 : 32;
+    // the FP32 product with the block in LDS: column-group and row-tile shapes
+    // whose workgroup fits (it replaces the column tile and the persistent launch)
+    std::vector<int> plds{0};
+    if (mfma_matters && which != TP_FP64 && p->bc <= 128) {
+        const int nrt = (p->bc + 15) / 16;
+        for (int cg : {2, 3, 6})
+            for (int rt : {2, 3, 6})
+                if (cg * ((nrt + rt - 1) / rt) <= 16) plds.push_back(cg * 16 + rt);
+    }
     auto persistent = [&]() {
         const bool f64 = which == TP_FP64;
         return (path_flags(p, f64, false, nrhs) & TP_PATH_PERSISTENT) ||
@@ -88,39 +97,44 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
         ms = (double)f / reps;
     };
     const int keep_pass = p->opt_spectrum_pass, keep_cols = p->opt_mfma_cols, keep_tile = p->opt_fft2_lds,
-              keep_multi = p->opt_multi_fused;
+              keep_multi = p->opt_multi_fused, keep_plds = p->opt_prod_lds;
     // every option at its default first
     p->opt_spectrum_pass = TP_PASS_AUTO;
     p->opt_mfma_cols = 0;
     p->opt_fft2_lds = 0;
     p->opt_multi_fused = 0;
+    p->opt_prod_lds = 0;
     double ms_def = 0.0;
     time_it(ms_def);
     double best = -1.0;
-    int bp = keep_pass, bc = keep_cols, bt = keep_tile, bm = keep_multi, n = 0;
+    int bp = keep_pass, bc = keep_cols, bt = keep_tile, bm = keep_multi, bl = keep_plds, n = 0;
     bool multi_seen = false;
     for (int pv : passes)
         for (int cv : cols)
             for (int tv : tiles)
-                for (int mv = 0; mv < 2; ++mv) {
-                    if (e != hipSuccess) break;
-                    p->opt_spectrum_pass = pv;
-                    p->opt_mfma_cols = cv;
-                    p->opt_fft2_lds = tv;
-                    p->opt_multi_fused = mv;
-                    if (mv == 1 && (cv != def_cols || !persistent())) continue;
-                    multi_seen |= mv == 1;
-                    double ms = 0.0;
-                    time_it(ms);
-                    ++n;
-                    if (e == hipSuccess && (best < 0.0 || ms < best)) {
-                        best = ms;
-                        bp = pv;
-                        bc = cv;
-                        bt = tv;
-                        bm = mv;
+                for (int mv = 0; mv < 2; ++mv)
+                    for (int lv : plds) {
+                        if (e != hipSuccess) break;
+                        p->opt_spectrum_pass = pv;
+                        p->opt_mfma_cols = cv;
+                        p->opt_fft2_lds = tv;
+                        p->opt_multi_fused = mv;
+                        p->opt_prod_lds = lv;
+                        if (mv == 1 && (cv != def_cols || lv != 0 || !persistent())) continue;
+                        if (lv != 0 && cv != def_cols) continue;
+                        multi_seen |= mv == 1;
+                        double ms = 0.0;
+                        time_it(ms);
+                        ++n;
+                        if (e == hipSuccess && (best < 0.0 || ms < best)) {
+                            best = ms;
+                            bp = pv;
+                            bc = cv;
+                            bt = tv;
+                            bm = mv;
+                            bl = lv;
+                        }
                     }
-                }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     solver_drop_graphs(p);      // captured graphs hold the launch shapes
@@ -129,16 +143,19 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
         p->opt_mfma_cols = keep_cols;
         p->opt_fft2_lds = keep_tile;
         p->opt_multi_fused = keep_multi;
+        p->opt_prod_lds = keep_plds;
         return hip_fail(e, "tune");
     }
     p->opt_spectrum_pass = bp;
     p->opt_mfma_cols = bc;
     p->opt_fft2_lds = bt;
     p->opt_multi_fused = bm;
+    p->opt_prod_lds = bl;
     res->spectrum_pass = pass_matters ? bp : TP_PASS_AUTO;
     res->mfma_cols = mfma_matters ? bc : 0;
     res->fft2_lds = fft2_matters ? bt : 0;
     res->multi_fused = multi_seen ? bm : 0;
+    res->prod_lds = bl;
     res->candidates = n;
     res->ms = best;
     res->ms_default = ms_def;

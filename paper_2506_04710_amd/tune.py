@@ -93,7 +93,7 @@ def tune(plan, which: str = "mixed", nrhs: int = 1, reps: int = 10, path: str | 
                                            ctypes.c_void_p(y.data_ptr()), plan.Nt, nrhs, reps,
                                            ctypes.c_void_p(stream.cuda_stream), ctypes.byref(r)))
         rec = dict(spectrum_pass=r.spectrum_pass, mfma_cols=r.mfma_cols, fft2_lds=r.fft2_lds,
-                   multi_fused=r.multi_fused, candidates=r.candidates,
+                   multi_fused=r.multi_fused, prod_lds=r.prod_lds, candidates=r.candidates,
                    ms=r.ms, ms_default=r.ms_default, nrhs=nrhs, source="measured")
         data.setdefault(dkey, {})[pkey] = rec
         _store(path, data)
@@ -107,4 +107,6 @@ def tune(plan, which: str = "mixed", nrhs: int = 1, reps: int = 10, path: str | 
             plan.set_option(_lib.TP_OPT_FFT2_LDS, rec["fft2_lds"])
         if rec.get("multi_fused"):
             plan.set_option(_lib.TP_OPT_MULTI_FUSED, rec["multi_fused"])
+        if rec.get("prod_lds"):
+            plan.set_option(_lib.TP_OPT_PROD_LDS, rec["prod_lds"])
     return rec
