@@ -50,7 +50,11 @@ typedef enum {
 typedef enum {
     TP_FP64 = 0,   /* complex128 spectrum and rim, FP64 arithmetic */
     TP_FP32 = 1,   /* complex64 spectrum and rim, FP32 arithmetic with FP32 accumulation */
-    TP_MIXED = 2   /* both copies (plans); for solves: FP32 operator inside FP64 refinement */
+    TP_MIXED = 2,  /* both copies (plans); for solves: FP32 operator inside FP64 refinement */
+    /* range markers, not precisions: every int is a value of the type, so an
+       out-of-range argument reaches the library's check (TP_E_INVAL) */
+    TP_PREC_RANGE_MIN_ = -2147483647 - 1,
+    TP_PREC_RANGE_MAX_ = 2147483647
 } tp_prec;
 
 /* Plan layout facts, filled by toeplitz_plan_info. */

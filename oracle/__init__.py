@@ -48,7 +48,8 @@ ETA0 = 376.730313668
 def _lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "_oracle.so")
+        # ORACLE_LIBRARY: another build of oracle.c (e.g. the sanitizer build)
+        path = os.environ.get("ORACLE_LIBRARY") or os.path.join(_HERE, "_oracle.so")
         if not os.path.exists(path):
             from . import build as _b
             _b.build()

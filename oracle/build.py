@@ -12,14 +12,19 @@ SRC = os.path.join(HERE, "oracle.c")
 OUT = os.path.join(HERE, "_oracle.so")
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-Wall",
-           "-fno-fast-math", "-ffp-contract=off", "-fcx-fortran-rules", SRC, "-o", OUT + ".tmp", "-lm"]
+def build(verbose: bool = False, sanitize: bool = False, out: str = OUT) -> str:
+    """Compile oracle.c into `out`; sanitize: AddressSanitizer and
+    UndefinedBehaviorSanitizer instrumentation (load with gcc's libasan
+    preloaded)."""
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"] \
+        if sanitize else []
+    cmd = ["gcc", "-O1" if sanitize else "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-Wall", *san,
+           "-fno-fast-math", "-ffp-contract=off", "-fcx-fortran-rules", SRC, "-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -19,8 +19,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include")]
 
 
-def _compile(src, verbose, extra):
-    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+def _compile(src, verbose, extra, objdir=None):
+    obj = os.path.join(objdir or OBJ, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -30,18 +30,19 @@ def _compile(src, verbose, extra):
     return obj
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    """Compile every source and link libtoeplitz.so; `extra` holds additional
-    hipcc flags (e.g. -DTP_MFMA_MIN_R=8 to move the matrix-core threshold)."""
-    os.makedirs(OBJ, exist_ok=True)
+def build(verbose: bool = False, extra=(), out: str = OUT, objdir: str = OBJ, link_extra=()) -> str:
+    """Compile every source and link libtoeplitz.so (or `out`); `extra` holds
+    additional hipcc flags (e.g. -DTP_MFMA_MIN_R=8 to move the matrix-core
+    threshold, or host-only sanitizer flags, each after -Xarch_host)."""
+    os.makedirs(objdir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose, list(extra)), SOURCES))
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", OUT + ".tmp"]
+        objs = list(ex.map(lambda s: _compile(s, verbose, list(extra), objdir), SOURCES))
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *link_extra, *objs, "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":
