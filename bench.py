@@ -32,8 +32,8 @@ METRIC = "solves/s at rel-residual 1e-8 (32x32,b=64) vs FP64 plain; matvec GB/s;
 # HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the same counters on a plain copy of known size),
 # valid only for the kernel source it was measured on.
-TRAFFIC = {"source_sha256": "05905eaa96f44caeaeb4fc83e68f291b7535bc1055187d6cac6694f86ed1ed6b",
-           "bytes": 211212425, "fetch_factor": 0.500009, "write_factor": 1.0}
+TRAFFIC = {"source_sha256": "5f94aa18bf0334a3853bbc1ca46d58a4a5f04c57ce39983195dc96689b958dbd",
+           "bytes": 105718525, "fetch_factor": 0.416678, "write_factor": 1.0}
 
 
 def parse():
@@ -171,17 +171,31 @@ def timed_solves(plan, v, K, W, tol=1e-8, **kw):
     return time.perf_counter() - t_start, np.array(lat), last
 
 
+def _whole_us(plan, x, which, n=20):
+    """Mean microseconds of n operator applications back to back between two events."""
+    import torch
+    plan.matvec(x, which=which)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(n):
+        plan.matvec(x, which=which)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n * 1e3
+
+
 def multi_rhs(dev, K=3):
     """81 port excitations of the 9 x 9, b = 96 array solved together, the
-    matrix-core product's rate, and the S-matrix post-step."""
+    matrix-core product's rate, the persistent launch, the placed-rim form and
+    the S-matrix post-step."""
     import numpy as np
     import torch
     import paper_2506_04710_amd as tp
+    from paper_2506_04710_amd import _lib, tune
     from synth import arrays as sa
     prob, V = sa.make_config(3)
     R = V.shape[0]
     plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=R, restart=40, device=dev).precond_create()
-    from paper_2506_04710_amd import tune
     tuned = tune.tune(plan, "mixed", R)
     v = torch.from_numpy(V).to(dev)
     total, lat, (x, inf) = timed_solves(plan, v, K, 1, mode="mixed", precond=True)
@@ -192,28 +206,48 @@ def multi_rhs(dev, K=3):
     Pa = (2 * prob.Nx - 1) * (2 * prob.Ny - 1)
     flops = 8.0 * Pa * prob.b ** 2 * R
     flops_rim = 16.0 * prob.Nr * prob.N * R + 8.0 * prob.Nr ** 2 * R
-    # the whole operator application, 20 back to back between two events
     xv = v.to(torch.complex64)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    plan.matvec(xv, which="fp32")
-    e0.record()
-    for _ in range(20):
-        plan.matvec(xv, which="fp32")
-    e1.record()
-    torch.cuda.synchronize()
-    whole_us = e0.elapsed_time(e1) / 20 * 1e3
+    path = sorted(plan.path("fp32", R))
+    whole_us = _whole_us(plan, xv, "fp32")
+    # the product launch alone (separate launches), and the persistent launch
+    keep_multi = plan.get_option(_lib.TP_OPT_MULTI_FUSED)
+    plan.set_option(_lib.TP_OPT_MULTI_FUSED, 0)
     prod_us = plan.stage_time(xv, 3, "fp32", reps=50) * 1e3
+    sep_us = _whole_us(plan, xv, "fp32")
+    keep_lds = plan.get_option(_lib.TP_OPT_PROD_LDS)
+    keep_cols = plan.get_option(_lib.TP_OPT_MFMA_COLS)
+    plan.set_option(_lib.TP_OPT_PROD_LDS, 0)
+    plan.set_option(_lib.TP_OPT_MFMA_COLS, 0)
+    plan.set_option(_lib.TP_OPT_MULTI_FUSED, 1)
+    persistent_us = _whole_us(plan, xv, "fp32") if "persistent" in plan.path("fp32", R) else None
+    plan.set_option(_lib.TP_OPT_MULTI_FUSED, keep_multi)
+    plan.set_option(_lib.TP_OPT_PROD_LDS, keep_lds)
+    plan.set_option(_lib.TP_OPT_MFMA_COLS, keep_cols)
     rows = np.nonzero(V)[1]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = tp.port_smatrix(x, rows, Z0=50.0)
     t_s = time.perf_counter() - t0
     S = S.cpu().numpy()
+    plan.close()
+    # the same ports with the rim placed as channels of the element cells
+    place, nrc = sa.rim_placement(prob)
+    pplan = tp.Plan.create(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, prec="mixed",
+                           max_rhs=R, restart=40, device=dev, rim_place=(place, nrc)).precond_create()
+    ptuned = tune.tune(pplan, "mixed", R)
+    ptotal, _, (px, pinf) = timed_solves(pplan, v, K, 1, mode="mixed", precond=True)
+    assert all(i["status"] == 0 and i["relres"] <= 1e-8 for i in pinf), pinf
+    pwhole = _whole_us(pplan, xv, "fp32")
+    bc = pplan.info()["bc"]
+    pflops = 8.0 * Pa * bc ** 2 * R
+    pplan.close()
     out = {"workload": "9x9 array, b=96, 72 rim functions, 81 port excitations (one per element feed), tol 1e-8, "
                        "mixed + preconditioner, one launch sequence for all columns",
            "solves_per_s": round(R * K / total, 1), "ms_per_81": round(1e3 * total / K, 2),
            "iters_max": max(i["iters"] for i in inf), "outer_max": max(i["outer_iters"] for i in inf),
            "fp32_matvec_stages_us": {k: round(t * 1e3, 2) for k, t in st.items()},
+           "tuned": {k: tuned[k] for k in ("mfma_cols", "multi_fused", "prod_lds", "fft2_lds", "candidates")},
+           "path": path,
            "prod_mfma": {"us": round(prod_us, 2), "tflops": round(flops / (prod_us * 1e-6) / 1e12, 1),
                          "peak_tflops_fp32_mfma": 157.3,
                          "frac": round(flops / (prod_us * 1e-6) / 1e12 / 157.3, 3),
@@ -221,10 +255,16 @@ def multi_rhs(dev, K=3):
                          "timing": "launch repeated back to back between two events"},
            "whole_matvec": {"us": round(whole_us, 2), "flops": flops + flops_rim,
                             "frac_fp32_mfma": round((flops + flops_rim) / (whole_us * 1e-6) / 1e12 / 157.3, 3),
+                            "separate_launches_us": round(sep_us, 2),
+                            "persistent_launch_us": None if persistent_us is None else round(persistent_us, 2),
                             "timing": "20 applications back to back between two events"},
-           "smatrix_ms": round(1e3 * t_s, 2), "smatrix_max_asymmetry": float(np.abs(S - S.T).max()),
-           "tuned_mfma_cols": tuned["mfma_cols"]}
-    plan.close()
+           "placed_rim": {"channels_per_cell": bc, "solves_per_s": round(R * K / ptotal, 1),
+                          "ms_per_81": round(1e3 * ptotal / K, 2),
+                          "iters_max": max(i["iters"] for i in pinf),
+                          "whole_matvec_us": round(pwhole, 2), "flops": pflops,
+                          "frac_fp32_mfma": round(pflops / (pwhole * 1e-6) / 1e12 / 157.3, 3),
+                          "tuned": {k: ptuned[k] for k in ("mfma_cols", "multi_fused", "prod_lds", "fft2_lds")}},
+           "smatrix_ms": round(1e3 * t_s, 2), "smatrix_max_asymmetry": float(np.abs(S - S.T).max())}
     return out
 
 
@@ -265,7 +305,7 @@ def progress(msg):
 
 def tune_only():
     """Tune the headline plan (placed rim, preconditioner, mixed, one column)
-    and print the record."""
+    and the multi-RHS plan, and print the records."""
     import torch
     import paper_2506_04710_amd as tp
     from paper_2506_04710_amd import tune
@@ -274,8 +314,14 @@ def tune_only():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     prob, _ = sa.make_config(2)
     plan = headline_plan(tp, prob, True).precond_create()
-    print(json.dumps({"tune": tune.tune(plan, "mixed", 1)}), flush=True)
+    rec = tune.tune(plan, "mixed", 1)
     plan.close()
+    # the multi-RHS plan of --apply-only multi (9 x 9, b = 96, 81 columns)
+    prob3, V3 = sa.make_config(3)
+    plan3 = tp.Plan.from_problem(prob3, prec="mixed", max_rhs=V3.shape[0], restart=4).precond_create()
+    rec3 = tune.tune(plan3, "mixed", V3.shape[0])
+    plan3.close()
+    print(json.dumps({"tune": rec, "tune_multi": rec3}), flush=True)
 
 
 def apply_only(which, placed, K=20):
@@ -288,8 +334,10 @@ def apply_only(which, placed, K=20):
     from synth import arrays as sa
     tp.load()
     if which == "multi":
+        from paper_2506_04710_amd import tune
         prob, V = sa.make_config(3)
-        plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=V.shape[0], restart=4)
+        plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=V.shape[0], restart=4).precond_create()
+        progress(f"tuning: {tune.tune(plan, 'mixed', V.shape[0])}")
         xv = torch.from_numpy(V).to("cuda:0").to(torch.complex64)
         for _ in range(K):
             plan.matvec(xv, which="fp32")
@@ -299,9 +347,10 @@ def apply_only(which, placed, K=20):
         plan = headline_plan(tp, prob, placed)
         dt = torch.complex64 if which == "fp32" else torch.complex128
         xv = torch.from_numpy(V).to("cuda:0").to(dt)
-        if which == "precond":
-            plan.precond_create()
+        # the headline plan's preconditioner and launch options (the same
+        # tuning key as the headline solve), so the operator runs its kernels
         if placed or which == "precond":
+            plan.precond_create()
             progress(f"tuning: {tune.tune(plan, 'mixed', 1)}")
         if which == "precond":
             for _ in range(K):
