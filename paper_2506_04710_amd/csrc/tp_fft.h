@@ -191,13 +191,13 @@ __device__ __forceinline__ int small_divmod(int n, int d, float rd, int &rem) {
     return q;
 }
 
-// One radix-R stage over nout transforms (transform o starts at o * so; point
-// n of it sits at n * sp), each over the CC contiguous channels.  Every
-// butterfly applies its twiddles (w^0 = 1 for j = 0), so the data and twiddle
-// reads of an item issue together.
+// One radix-R stage over nout transforms (transform o starts at o * so, or at
+// ofs[o] * so with a start table; point n of it sits at n * sp), each over the
+// CC contiguous channels.  Every butterfly applies its twiddles (w^0 = 1 for
+// j = 0), so the data and twiddle reads of an item issue together.
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void fft_stage_axis(cpx<T> *buf, int lgCC, int P, int L, int sp, int nout, int so,
-                                               const cpx<T> *twl) {
+                                               const cpx<T> *twl, const int *ofs = nullptr) {
     const int CC = 1 << lgCC;
     const int nb = P / R;
     const int stride = P / (L * R);
@@ -210,7 +210,7 @@ __device__ __forceinline__ void fft_stage_axis(cpx<T> *buf, int lgCC, int P, int
         const int o = small_divmod(rest, nb, rnb, bf);
         const int grp = small_divmod(bf, L, rL, j);
         const int base = grp * L * R + j;
-        cpx<T> *b0 = buf + o * so + ch;
+        cpx<T> *b0 = buf + (ofs ? ofs[o] : o) * so + ch;
         cpx<T> a[R], w[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) a[q] = b0[(base + q * L) * sp];
@@ -333,20 +333,21 @@ __device__ void lds_fft(cpx<T> *buf, int lgCC, const FFTDesc &d, const cpx<T> *t
 
 // Two-dimensional tiles: nout transforms of length P along one axis of an LDS
 // array whose point stride is sp and whose transforms start so apart (both in
-// values), each over the CC = 2^lgCC contiguous channels.  Input in
-// digit-reversed order along the axis, output natural.
+// values; with a start table ofs, transform o starts at ofs[o] * so), each
+// over the CC = 2^lgCC contiguous channels.  Input in digit-reversed order
+// along the axis, output natural.
 template <typename T, bool INV>
 __device__ void lds_fft_axis(cpx<T> *buf, int lgCC, const FFTDesc &d, int sp, int nout, int so,
-                             const cpx<T> *twl) {
+                             const cpx<T> *twl, const int *ofs = nullptr) {
     for (int s = 0; s < d.nst; ++s) {
         switch (d.radix[s]) {
-            case 2: fft_stage_axis<T, 2, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
-            case 3: fft_stage_axis<T, 3, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
-            case 4: fft_stage_axis<T, 4, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
-            case 5: fft_stage_axis<T, 5, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
-            case 7: fft_stage_axis<T, 7, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
-            case 8: fft_stage_axis<T, 8, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
-            case 9: fft_stage_axis<T, 9, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl); break;
+            case 2: fft_stage_axis<T, 2, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl, ofs); break;
+            case 3: fft_stage_axis<T, 3, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl, ofs); break;
+            case 4: fft_stage_axis<T, 4, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl, ofs); break;
+            case 5: fft_stage_axis<T, 5, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl, ofs); break;
+            case 7: fft_stage_axis<T, 7, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl, ofs); break;
+            case 8: fft_stage_axis<T, 8, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl, ofs); break;
+            case 9: fft_stage_axis<T, 9, INV>(buf, lgCC, d.P, d.L[s], sp, nout, so, twl, ofs); break;
             default: break;
         }
     }

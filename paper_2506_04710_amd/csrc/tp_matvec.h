@@ -1065,16 +1065,19 @@ __device__ __forceinline__ void fft2_fwd_tile(Cols<const In> x, int R, int Nx, i
         if (xc && p >= rm.be) {
             // a rim channel: the rim functions placed at this channel's cells
             const int es = kBlock >> lgCC, ne = Nx * Ny;
+            const float rNx = 1.0f / (float)Nx;
             for (int e = threadIdx.x >> lgCC; e < ne; e += es) {
                 const long j = cell_unknown(rm, e, p);
                 if (j >= 0) {
-                    const int iy = e / Nx, ix = e - iy * Nx;
+                    int ix;
+                    const int iy = small_divmod(e, Nx, rNx, ix);
                     buf[px[ix] * XS + (py[iy] << lgCC) + cl] = cvt<T>(ldg(xc + j));
                 }
             }
         } else if (xc) {
             xc += p;
             const int es = kBlock >> lgCC, ne = Nx * Ny;
+            const float rNx = 1.0f / (float)Nx;
             for (int eb = threadIdx.x >> lgCC; eb < ne; eb += 8 * es) {
                 In v[8];
 #pragma unroll
@@ -1085,7 +1088,8 @@ __device__ __forceinline__ void fft2_fwd_tile(Cols<const In> x, int R, int Nx, i
                 for (int u = 0; u < 8; ++u) {
                     const int e = eb + u * es;
                     if (e < ne) {
-                        const int iy = e / Nx, ix = e - iy * Nx;
+                        int ix;
+                    const int iy = small_divmod(e, Nx, rNx, ix);
                         buf[px[ix] * XS + (py[iy] << lgCC) + cl] = cvt<T>(v[u]);
                     }
                 }
@@ -1093,12 +1097,21 @@ __device__ __forceinline__ void fft2_fwd_tile(Cols<const In> x, int R, int Nx, i
         }
     }
     __syncthreads();
+    // x first, on the Ny rows that hold data (at their digit-reversed y
+    // positions), then y on every column
+    lds_fft_axis<T, false>(buf, lgCC, fx, XS, Ny, CC, twx, py);
     lds_fft_axis<T, false>(buf, lgCC, fy, CC, Px, XS, twy);
-    lds_fft_axis<T, false>(buf, lgCC, fx, XS, Py, CC, twx);
+    // frequency k = kx Py + ky of item i, stepped without a division per item
+    const int kst = kBlock >> lgCC, cl = threadIdx.x & (CC - 1), c = c0 + cl;
+    int kx = (threadIdx.x >> lgCC) / Py, ky = (threadIdx.x >> lgCC) - kx * Py;
     for (int i = threadIdx.x; i < Px * Py * CC; i += kBlock) {
-        const int k = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
-        const int kx = k / Py, ky = k - kx * Py;
+        const int k = i >> lgCC;
         if (c < C) out[(long)k * C + c] = buf[kx * XS + (ky << lgCC) + cl];
+        ky += kst;
+        while (ky >= Py) {
+            ky -= Py;
+            ++kx;
+        }
     }
 }
 
@@ -1139,11 +1152,13 @@ __device__ __forceinline__ void fft2_inv_tile(const cpx<T> *__restrict__ in, int
     load_twiddles<T>(twy, fy);
     for (int i = threadIdx.x; i < Px + Py; i += kBlock) px[i] = i < Px ? fx.perm[i] : fy.perm[i - Px];
     __syncthreads();
+    const float rPy = 1.0f / (float)Py;
     batched<8, cpx<T>>(
         Px * Py * CC, [&](int i) { return in[(long)(i >> lgCC) * C + min(c0 + (i & (CC - 1)), C - 1)]; },
         [&](int i, cpx<T> v) {
             const int k = i >> lgCC, cl = i & (CC - 1);
-            const int kx = k / Py, ky = k - kx * Py;
+            int ky;
+            const int kx = small_divmod(k, Py, rPy, ky);
             buf[px[kx] * XS + (py[ky] << lgCC) + cl] = c0 + cl < C ? v : mk<T>(0, 0);
         });
     __syncthreads();
@@ -1155,12 +1170,14 @@ __device__ __forceinline__ void fft2_inv_tile(const cpx<T> *__restrict__ in, int
     const int p = c % b;
     const Out *ac = accumulate ? acc.col(c / b) : nullptr;
     const int es = kBlock >> lgCC, ne = Nx * Ny;
+            const float rNx = 1.0f / (float)Nx;
     if (p >= rm.be) {
         // a rim channel: results of the rim functions placed at its cells
         for (int e = threadIdx.x >> lgCC; e < ne; e += es) {
             const long j = cell_unknown(rm, e, p);
             if (j >= 0) {
-                const int iy = e / Nx, ix = e - iy * Nx;
+                int ix;
+                    const int iy = small_divmod(e, Nx, rNx, ix);
                 Out v = cvt<typename Out::value_type>(buf[ix * XS + (iy << lgCC) + cl]);
                 if (ac) v = v + ldg(ac + j);
                 stg(yc + j, v);
@@ -1182,7 +1199,8 @@ __device__ __forceinline__ void fft2_inv_tile(const cpx<T> *__restrict__ in, int
         for (int u = 0; u < 8; ++u) {
             const int e = eb + u * es;
             if (e < ne) {
-                const int iy = e / Nx, ix = e - iy * Nx;
+                int ix;
+                    const int iy = small_divmod(e, Nx, rNx, ix);
                 Out v = cvt<typename Out::value_type>(buf[ix * XS + (iy << lgCC) + cl]);
                 if (ac) v = v + old[u];
                 stg(yc + (long)e * rm.be, v);
@@ -1337,13 +1355,14 @@ static int fft2_xstride(int Py, int lgCC, size_t elem) {
 #define TP_FFT2_MAXLG 4
 #endif
 static int fft2_lgcc(int Px, int Py, int C, size_t elem, size_t lds_cap = 48 * 1024) {
+    constexpr int minlg = 2;   // tiles of 1 or 2 channels lose to the separate passes (63 x 63: 54 vs 39 us)
     auto bytes = [&](int lg) {
         return ((size_t)Px * fft2_xstride(Py, lg, elem) + Px + Py) * elem + (size_t)(Px + Py) * sizeof(int);
     };
     int lg = TP_FFT2_MAXLG;
-    while (lg >= 2 && bytes(lg) > lds_cap) --lg;
-    if (lg < 2) return -1;
-    while (lg > 2 && (1 << (lg - 1)) >= C) --lg;
+    while (lg >= minlg && bytes(lg) > lds_cap) --lg;
+    if (lg < minlg) return -1;
+    while (lg > minlg && (1 << (lg - 1)) >= C) --lg;
     return lg;
 }
 
