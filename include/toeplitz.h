@@ -207,6 +207,11 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
  *     take tasks from a queue in dependency order (same results bit for bit);
  *     0 (default): one launch per stage.  Applies with even b, the default
  *     column tile, no separate B_er and TP_OPT_PROD_LDS off.
+ *   TP_OPT_RIM_OVERLAP  1 (default): where the dense rim runs on the matrix
+ *     cores and the transforms on 2-D tiles (16+ columns on small grids), the
+ *     rim's slabs and the forward tiles share one launch (independent work: the
+ *     rim's matrix work overlaps the transforms); 0: two launches.  Same
+ *     results bit for bit.
  *   TP_OPT_PROD_LDS  FP32 per-frequency product with the spectrum block staged
  *     in LDS and each wave's column tile of the transformed input held in
  *     registers: value 16 * CG + RT, CG column tiles of 16 per workgroup
@@ -224,6 +229,7 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
 #define TP_OPT_FFT2_LDS 4
 #define TP_OPT_MULTI_FUSED 5
 #define TP_OPT_PROD_LDS 6
+#define TP_OPT_RIM_OVERLAP 7
 #define TP_PASS_AUTO 0
 #define TP_PASS_FUSED 1
 #define TP_PASS_PAIRS 2
@@ -242,6 +248,8 @@ tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value);
  *   TP_PATH_RIM_MFMA    that rim pass on the matrix cores
  *   TP_PATH_TILES2D     both transform directions per launch on 2-D tiles
  *   TP_PATH_PERSISTENT  every stage in one persistent launch (TP_OPT_MULTI_FUSED)
+ *   TP_PATH_RIM_OVERLAP the rim's slabs and the forward tiles in one launch
+ *                       (TP_OPT_RIM_OVERLAP)
  * Launches nothing.  Errors: TP_E_INVAL (NULL plan or flags, bad precision,
  * nrhs outside [1, max_rhs], precond without a preconditioner),
  * TP_E_UNSUPPORTED (the plan lacks the copy `which` needs).
@@ -253,6 +261,7 @@ tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value);
 #define TP_PATH_RIM_MFMA 16
 #define TP_PATH_TILES2D 32
 #define TP_PATH_PERSISTENT 64
+#define TP_PATH_RIM_OVERLAP 128
 tp_status toeplitz_plan_path(tp_plan p, tp_prec which, int precond, int nrhs, int *flags);
 
 /* Result of toeplitz_tune: the options it set and the time they gave. */
@@ -262,6 +271,7 @@ typedef struct {
     int fft2_lds;        /* 0 (48 KB tiles) or 163840 (where larger tiles would change the path) */
     int multi_fused;     /* 1 where the persistent multi-column launch was timed and fastest, else 0 */
     int prod_lds;        /* TP_OPT_PROD_LDS value chosen (0: the streaming product) */
+    int rim_overlap;     /* TP_OPT_RIM_OVERLAP value chosen */
     int candidates;      /* option combinations timed */
     double ms;           /* mean milliseconds of the timed work with the chosen options */
     double ms_default;   /* the same with every option at its default */
@@ -276,7 +286,8 @@ typedef struct {
  * that a 48 KB one does not; the persistent multi-column launch where a
  * combination at the default column tile takes it; for FP32 operators from
  * the threshold on, the LDS-staged product in column-group and row-tile
- * shapes whose workgroup fits), each
+ * shapes whose workgroup fits; the rim and forward tiles in one launch or
+ * two where that applies), each
  * for reps applications after two untimed ones, with HIP events on
  * hip_stream, and set the fastest.  The timed work is what a solve applies:
  * the operator `which` (TP_FP64, TP_FP32 or TP_MIXED, as toeplitz_matvec) and,

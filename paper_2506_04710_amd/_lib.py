@@ -33,9 +33,10 @@ EXPORTS = ("toeplitz_plan_bytes", "toeplitz_plan_create", "toeplitz_plan_info", 
            "toeplitz_stage_time", "toeplitz_plan_path")
 TP_SYM_RIM, TP_SYM_GEN = 1, 2
 TP_OPT_SPECTRUM_PASS, TP_OPT_MFMA_COLS, TP_OPT_MFMA_MIN_R, TP_OPT_FFT2_LDS, TP_OPT_MULTI_FUSED = 1, 2, 3, 4, 5
-TP_OPT_PROD_LDS = 6
+TP_OPT_PROD_LDS, TP_OPT_RIM_OVERLAP = 6, 7
 TP_PASS_AUTO, TP_PASS_FUSED, TP_PASS_PAIRS = 0, 1, 2
-PATH_BITS = {"fused": 1, "pairs": 2, "mfma": 4, "dense_rim": 8, "rim_mfma": 16, "tiles2d": 32, "persistent": 64}
+PATH_BITS = {"fused": 1, "pairs": 2, "mfma": 4, "dense_rim": 8, "rim_mfma": 16, "tiles2d": 32, "persistent": 64,
+             "rim_overlap": 128}
 
 
 class PlanDesc(ctypes.Structure):
@@ -56,8 +57,8 @@ class SolveOpts(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("spectrum_pass", ctypes.c_int), ("mfma_cols", ctypes.c_int), ("fft2_lds", ctypes.c_int),
-                ("multi_fused", ctypes.c_int), ("prod_lds", ctypes.c_int), ("candidates", ctypes.c_int),
-                ("ms", ctypes.c_double),
+                ("multi_fused", ctypes.c_int), ("prod_lds", ctypes.c_int), ("rim_overlap", ctypes.c_int),
+                ("candidates", ctypes.c_int), ("ms", ctypes.c_double),
                 ("ms_default", ctypes.c_double)]
 
 

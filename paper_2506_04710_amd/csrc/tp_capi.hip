@@ -518,6 +518,11 @@ tp_status toeplitz_plan_set_option(tp_plan p, int option, int value) {
             solver_drop_graphs(p);
             p->opt_mfma_min_r = value;
             return TP_OK;
+        case TP_OPT_RIM_OVERLAP:
+            if (value != 0 && value != 1) return fail(TP_E_INVAL, "rim overlap must be 0 or 1");
+            solver_drop_graphs(p);
+            p->opt_rim_overlap = value;
+            return TP_OK;
         case TP_OPT_PROD_LDS: {
             const int cg = value >> 4, rt = value & 15;
             if (value != 0 && (cg < 1 || cg > 16 || (rt != 2 && rt != 3 && rt != 6)))
@@ -551,6 +556,7 @@ tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value) {
         case TP_OPT_FFT2_LDS: *value = p->opt_fft2_lds; return TP_OK;
         case TP_OPT_MULTI_FUSED: *value = p->opt_multi_fused; return TP_OK;
         case TP_OPT_PROD_LDS: *value = p->opt_prod_lds; return TP_OK;
+        case TP_OPT_RIM_OVERLAP: *value = p->opt_rim_overlap; return TP_OK;
         default: return fail(TP_E_INVAL, "unknown option");
     }
 }

@@ -324,6 +324,7 @@ struct tp_plan_s {
     int opt_fft2_lds = 0;         // LDS bytes the 2-D transform tiles may take (0 = 48 KB)
     int opt_multi_fused = 0;      // 1: many columns on the 2-D tiles in one persistent launch
     int opt_prod_lds = 0;         // FP32 product with the block in LDS: 16 * column tiles + row tiles (0: off)
+    int opt_rim_overlap = 1;      // 1: the dense rim's matrix-core slabs and the forward 2-D tiles in one launch
     int *fctr = nullptr;          // task queue and completion counters of that launch (workspace)
     // instrumentation only, on a copy of the record: launch this stage alone
     int only_stage = -1;

@@ -1240,6 +1240,26 @@ __global__ void __launch_bounds__(256) k_fft2_inv_fin(const cpx<T> *__restrict__
 // the device stops running the workgroups that hold earlier tasks).
 constexpr int kFusedCounters = 5;
 
+// The dense rim's slabs (matrix cores) and the forward 2-D tiles in one
+// launch: both only read x and they write disjoint buffers (the rim: y's
+// element rows and the slab partials; the tiles: the transform grid), so no
+// ordering is needed between them, and the rim's matrix-core work overlaps
+// the latency-bound transforms.  Rim workgroups come first.
+template <typename T, typename In, typename Out, bool NBE>
+__global__ void __launch_bounds__(256) k_rim_fft2_fwd(const cpx<T> *__restrict__ B, const cpx<T> *__restrict__ BE,
+                                                      Cols<const In> x, Cols<Out> y, int R, long N, int Nr,
+                                                      cpx<T> *__restrict__ part, int nslab, int nrim, int Nx, int Ny,
+                                                      int b, FFTDesc fx, FFTDesc fy, int lgCC, int XS,
+                                                      cpx<T> *__restrict__ out, RimMap rm) {
+    extern __shared__ char smem_raw[];
+    const int blk = blockIdx.x;
+    if (blk < nrim)
+        rim_mfma_tile<T, In, Out, rim_nt<T>(), rim_rch<T>(), NBE>(B, BE, x, y, R, N, Nr, part, blk % nslab,
+                                                                  blk / nslab, smem_raw);
+    else
+        fft2_fwd_tile<T, In>(x, R, Nx, Ny, b, fx, fy, lgCC, XS, out, rm, blk - nrim, smem_raw);
+}
+
 static __global__ void k_zero_ints(int *p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
@@ -1628,6 +1648,7 @@ struct Path {
     bool mfma;         // products (and a dense rim) on the matrix cores
     bool rim_mma;      // the dense rim on the matrix cores
     bool fusedm;       // every stage in one persistent launch
+    bool rimfwd;       // the dense rim's slabs and the forward 2-D tiles in one launch
     int lg2, xs2;      // 2-D tiles: log2 channels per tile (-1: separate x and y passes), row stride
     size_t sh_fused, sh2;
 };
@@ -1662,6 +1683,8 @@ static Path choose_path(tp_plan pl, int R) {
                (!P.rim || (P.rim_mma && OpPtrs<T>::BE(pl) == nullptr)) &&
                (pl->opt_mfma_cols == 0 || pl->opt_mfma_cols == (sizeof(T) == 4 ? 32 : 16)) &&
                fused_multi_lds<T>(b, P.sh2, P.rim) + 1024 <= kLdsLimit;
+    P.rimfwd = !P.fusedm && pl->opt_rim_overlap == 1 && P.rim_mma && P.lg2 >= 0 &&
+               std::max(P.sh2, rim_mfma_lds<T>(OpPtrs<T>::BE(pl) != nullptr)) + 1024 <= kLdsLimit;
     return P;
 }
 
@@ -1711,8 +1734,24 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         return hipGetLastError();
     }
 
+    // the dense rim and the forward 2-D tiles in one launch (plan option; a
+    // timing of one stage launches them apart)
+    const bool rimfwd = P.rimfwd && pl->only_stage < 0;
     mark(0);
-    if (rim && !fused && on(0)) {
+    if (rimfwd) {
+        const cpx<T> *Bp = OpPtrs<T>::B(pl), *BEp = OpPtrs<T>::BE(pl);
+        const int nrim = pl->rim_nslab * ((R + 16 * rim_nt<T>() - 1) / (16 * rim_nt<T>()));
+        const int nfwd = (C + (1 << lg2) - 1) >> lg2;
+        const size_t sh = std::max(sh2, rim_mfma_lds<T>(BEp != nullptr));
+        cpx<T> *partp = reinterpret_cast<cpx<T> *>(pl->rim_part);
+        if (BEp)
+            hipLaunchKernelGGL((k_rim_fft2_fwd<T, In, Out, true>), dim3(nrim + nfwd), blk, sh, st, Bp, BEp, x, y, R,
+                               pl->N, Nr, partp, pl->rim_nslab, nrim, Nx, Ny, b, pl->fx, pl->fy, lg2, xs2, gB, rm);
+        else
+            hipLaunchKernelGGL((k_rim_fft2_fwd<T, In, Out, false>), dim3(nrim + nfwd), blk, sh, st, Bp, Bp, x, y,
+                               R, pl->N, Nr, partp, pl->rim_nslab, nrim, Nx, Ny, b, pl->fx, pl->fy, lg2, xs2, gB,
+                               rm);
+    } else if (rim && !fused && on(0)) {
         if (rim_mma)
             rim_mfma<T, In, Out>(OpPtrs<T>::B(pl), OpPtrs<T>::BE(pl), x, y, R, pl->N, Nr, pl->rim_nslab,
                                  reinterpret_cast<cpx<T> *>(pl->rim_part), st);
@@ -1720,7 +1759,7 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
             launch_rim_general<T, In, Out>(pl, x, y, R, st);
     }
     mark(1);
-    if (!on(1)) {
+    if (!on(1) || rimfwd) {
     } else if (lg2 >= 0) {
         hipLaunchKernelGGL((k_fft2_fwd<T, In>), dim3((C + (1 << lg2) - 1) >> lg2), blk, sh2, st, x, R, Nx, Ny, b,
                            pl->fx, pl->fy, lg2, xs2, gB, rm);

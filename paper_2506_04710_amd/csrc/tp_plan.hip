@@ -226,7 +226,8 @@ static int path_bits(tp_plan pl, int R) {
     const Path P = choose_path<T, PRE>(pl, R);
     return (P.fused ? TP_PATH_FUSED : 0) | (P.pairs ? TP_PATH_PAIRS : 0) | (P.mfma ? TP_PATH_MFMA : 0) |
            (P.rim ? TP_PATH_DENSE_RIM : 0) | (P.rim_mma ? TP_PATH_RIM_MFMA : 0) |
-           (P.lg2 >= 0 ? TP_PATH_TILES2D : 0) | (P.fusedm ? TP_PATH_PERSISTENT : 0);
+           (P.lg2 >= 0 ? TP_PATH_TILES2D : 0) | (P.fusedm ? TP_PATH_PERSISTENT : 0) |
+           (P.rimfwd ? TP_PATH_RIM_OVERLAP : 0);
 }
 
 int path_flags(tp_plan pl, bool fp64, bool pre, int R) {

@@ -97,44 +97,55 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
         ms = (double)f / reps;
     };
     const int keep_pass = p->opt_spectrum_pass, keep_cols = p->opt_mfma_cols, keep_tile = p->opt_fft2_lds,
-              keep_multi = p->opt_multi_fused, keep_plds = p->opt_prod_lds;
+              keep_multi = p->opt_multi_fused, keep_plds = p->opt_prod_lds, keep_ro = p->opt_rim_overlap;
     // every option at its default first
     p->opt_spectrum_pass = TP_PASS_AUTO;
     p->opt_mfma_cols = 0;
     p->opt_fft2_lds = 0;
     p->opt_multi_fused = 0;
     p->opt_prod_lds = 0;
+    p->opt_rim_overlap = 1;
     double ms_def = 0.0;
     time_it(ms_def);
     double best = -1.0;
-    int bp = keep_pass, bc = keep_cols, bt = keep_tile, bm = keep_multi, bl = keep_plds, n = 0;
+    int bp = keep_pass, bc = keep_cols, bt = keep_tile, bm = keep_multi, bl = keep_plds, bro = keep_ro, n = 0;
+    // the rim and the forward tiles in one launch or two: timed both ways where it applies
+    auto overlap = [&]() {
+        const bool f64 = which == TP_FP64;
+        return (path_flags(p, f64, false, nrhs) & TP_PATH_RIM_OVERLAP) != 0;
+    };
     bool multi_seen = false;
     for (int pv : passes)
         for (int cv : cols)
             for (int tv : tiles)
                 for (int mv = 0; mv < 2; ++mv)
-                    for (int lv : plds) {
-                        if (e != hipSuccess) break;
-                        p->opt_spectrum_pass = pv;
-                        p->opt_mfma_cols = cv;
-                        p->opt_fft2_lds = tv;
-                        p->opt_multi_fused = mv;
-                        p->opt_prod_lds = lv;
-                        if (mv == 1 && (cv != def_cols || lv != 0 || !persistent())) continue;
-                        if (lv != 0 && cv != def_cols) continue;
-                        multi_seen |= mv == 1;
-                        double ms = 0.0;
-                        time_it(ms);
-                        ++n;
-                        if (e == hipSuccess && (best < 0.0 || ms < best)) {
-                            best = ms;
-                            bp = pv;
-                            bc = cv;
-                            bt = tv;
-                            bm = mv;
-                            bl = lv;
+                    for (int lv : plds)
+                        for (int ro = 1; ro >= 0; --ro) {
+                            if (e != hipSuccess) break;
+                            p->opt_spectrum_pass = pv;
+                            p->opt_mfma_cols = cv;
+                            p->opt_fft2_lds = tv;
+                            p->opt_multi_fused = mv;
+                            p->opt_prod_lds = lv;
+                            p->opt_rim_overlap = 1;
+                            if (mv == 1 && (cv != def_cols || lv != 0 || !persistent())) continue;
+                            if (lv != 0 && cv != def_cols) continue;
+                            if (ro == 0 && !overlap()) continue;   // the setting changes nothing here
+                            p->opt_rim_overlap = ro;
+                            multi_seen |= mv == 1;
+                            double ms = 0.0;
+                            time_it(ms);
+                            ++n;
+                            if (e == hipSuccess && (best < 0.0 || ms < best)) {
+                                best = ms;
+                                bp = pv;
+                                bc = cv;
+                                bt = tv;
+                                bm = mv;
+                                bl = lv;
+                                bro = ro;
+                            }
                         }
-                    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     solver_drop_graphs(p);      // captured graphs hold the launch shapes
@@ -144,6 +155,7 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
         p->opt_fft2_lds = keep_tile;
         p->opt_multi_fused = keep_multi;
         p->opt_prod_lds = keep_plds;
+        p->opt_rim_overlap = keep_ro;
         return hip_fail(e, "tune");
     }
     p->opt_spectrum_pass = bp;
@@ -151,11 +163,13 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
     p->opt_fft2_lds = bt;
     p->opt_multi_fused = bm;
     p->opt_prod_lds = bl;
+    p->opt_rim_overlap = bro;
     res->spectrum_pass = pass_matters ? bp : TP_PASS_AUTO;
     res->mfma_cols = mfma_matters ? bc : 0;
     res->fft2_lds = fft2_matters ? bt : 0;
     res->multi_fused = multi_seen ? bm : 0;
     res->prod_lds = bl;
+    res->rim_overlap = bro;
     res->candidates = n;
     res->ms = best;
     res->ms_default = ms_def;

@@ -93,7 +93,8 @@ def tune(plan, which: str = "mixed", nrhs: int = 1, reps: int = 10, path: str | 
                                            ctypes.c_void_p(y.data_ptr()), plan.Nt, nrhs, reps,
                                            ctypes.c_void_p(stream.cuda_stream), ctypes.byref(r)))
         rec = dict(spectrum_pass=r.spectrum_pass, mfma_cols=r.mfma_cols, fft2_lds=r.fft2_lds,
-                   multi_fused=r.multi_fused, prod_lds=r.prod_lds, candidates=r.candidates,
+                   multi_fused=r.multi_fused, prod_lds=r.prod_lds, rim_overlap=r.rim_overlap,
+                   candidates=r.candidates,
                    ms=r.ms, ms_default=r.ms_default, nrhs=nrhs, source="measured")
         data.setdefault(dkey, {})[pkey] = rec
         _store(path, data)
@@ -109,4 +110,6 @@ def tune(plan, which: str = "mixed", nrhs: int = 1, reps: int = 10, path: str | 
             plan.set_option(_lib.TP_OPT_MULTI_FUSED, rec["multi_fused"])
         if rec.get("prod_lds"):
             plan.set_option(_lib.TP_OPT_PROD_LDS, rec["prod_lds"])
+        if "rim_overlap" in rec:
+            plan.set_option(_lib.TP_OPT_RIM_OVERLAP, rec["rim_overlap"])
     return rec
