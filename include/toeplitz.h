@@ -195,7 +195,8 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
  *                    mirror frequency;
  *     TP_PASS_AUTO   (default) the fused launch.
  *   TP_OPT_MFMA_COLS  columns per workgroup of the matrix-core product (16,
- *     32 or 64, FP64 products take at most 32; 0 = default: 32 FP32, 16 FP64).
+ *     32 or 64, FP64 products take at most 32; 0 = default: 16 up to 16
+ *     columns, else 32 for FP32 and 16 for FP64).
  *   TP_OPT_MFMA_MIN_R  number of columns from which products and the dense rim
  *     pass run on the matrix cores (2..max_rhs; 0 = default 16).
  *   TP_OPT_FFT2_LDS  LDS bytes a workgroup of the 2-D transform tiles may take

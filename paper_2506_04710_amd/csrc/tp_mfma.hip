@@ -29,7 +29,9 @@ static void launch_prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, in
 template <typename T>
 hipError_t prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, int Px, int Py, int kxh, cpx<T> *out,
                      const void *const *act, hipStream_t st, int cols) {
-    if (cols == 0) cols = sizeof(T) == 4 ? 32 : 16;
+    // default tile: 16 columns up to 16 (a 32-column tile would compute as
+    // many padded columns as real ones), else 32 for FP32 and 16 for FP64
+    if (cols == 0) cols = (sizeof(T) == 4 && R > 16) ? 32 : 16;
     if (cols >= 64 && sizeof(T) == 4)
         launch_prod_mfma<T, 4>(G, in, b, R, Px, Py, kxh, out, act, st);
     else if (cols >= 32)
