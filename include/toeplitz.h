@@ -215,11 +215,14 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
  *     results bit for bit.
  *   TP_OPT_PROD_LDS  FP32 per-frequency product with the spectrum block staged
  *     in LDS and each wave's column tile of the transformed input held in
- *     registers: value 16 * CG + RT, CG column tiles of 16 per workgroup
- *     (1..16), RT row tiles of 16 per wave (2, 3 or 6); 0 (default): the
- *     product that streams the block from memory.  Same results bit for bit;
- *     applies from the matrix-core column threshold on, to b <= 128, where
- *     CG * ceil(ceil(b / 16) / RT) <= 16 (else the default product runs).
+ *     registers: value 16 * CG + RT (+ 256), CG column tiles of 16 per
+ *     workgroup (1..15), RT row tiles of 16 per wave (2, 3 or 6); + 256 (half
+ *     spectrum): one workgroup per stored block, applied to its frequency and
+ *     transposed to the mirror frequency, so each stored block is read once;
+ *     0 (default): the product that streams the block from memory.  Same
+ *     results bit for bit; applies from the matrix-core column threshold on,
+ *     to b <= 128, where CG * ceil(ceil(b / 16) / RT) <= 16 (else the
+ *     default product runs).
  * Setting an option drops the plan's captured solver graphs.  Errors:
  * TP_E_INVAL (unknown option or value, NULL pointers, a continuous batch is
  * active on the plan).

@@ -524,9 +524,11 @@ tp_status toeplitz_plan_set_option(tp_plan p, int option, int value) {
             p->opt_rim_overlap = value;
             return TP_OK;
         case TP_OPT_PROD_LDS: {
-            const int cg = value >> 4, rt = value & 15;
-            if (value != 0 && (cg < 1 || cg > 16 || (rt != 2 && rt != 3 && rt != 6)))
-                return fail(TP_E_INVAL, "LDS product: 16 * column tiles (1..16) + row tiles (2, 3 or 6), or 0");
+            const int cg = (value >> 4) & 15, rt = value & 15;
+            if (value != 0 && (value < 0 || value >= 512 || cg < 1 || (rt != 2 && rt != 3 && rt != 6)))
+                return fail(TP_E_INVAL,
+                            "LDS product: 16 * column tiles (1..15) + row tiles (2, 3 or 6), + 256 for the pair "
+                            "form, or 0");
             solver_drop_graphs(p);
             p->opt_prod_lds = value;
             return TP_OK;

@@ -67,7 +67,7 @@ bool solver_batch_active(tp_plan pl);
 // FP32 product with the spectrum block in LDS (b <= 128; LDS prod_lds_bytes(b))
 size_t prod_lds_bytes(int b);
 hipError_t prod_lds(const c64 *G, const c64 *in, int b, int R, int Px, int Py, int kxh, c64 *out,
-                    const void *const *act, hipStream_t st, int CG, int RT);
+                    const void *const *act, hipStream_t st, int CG, int RT, bool pair);
 template <typename T>
 hipError_t prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, int Px, int Py, int kxh, cpx<T> *out,
                      const void *const *act, hipStream_t st, int cols);   // cols: columns per workgroup, 0 = default

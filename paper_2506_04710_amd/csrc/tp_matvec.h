@@ -1634,7 +1634,7 @@ static void launch_rim_general(tp_plan pl, Cols<const In> x, Cols<Out> y, int R,
 template <typename T>
 static bool prod_lds_ok(tp_plan pl, int b) {
     if (sizeof(T) != 4 || pl->opt_prod_lds == 0 || b > 128 || prod_lds_bytes(b) > kLdsLimit) return false;
-    const int CG = pl->opt_prod_lds >> 4, RT = pl->opt_prod_lds & 15, nrt = (b + 15) >> 4;
+    const int CG = (pl->opt_prod_lds >> 4) & 15, RT = pl->opt_prod_lds & 15, nrt = (b + 15) >> 4;
     const int rt = RT <= 2 ? 2 : RT <= 3 ? 3 : 6;
     return CG >= 1 && CG * ((nrt + rt - 1) / rt) <= 16;
 }
@@ -1792,7 +1792,8 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
         launch_pair_prod<T>(pl, G, gB, gA, act, st);
     } else if (mfma && prod_lds_ok<T>(pl, b)) {
         prod_lds(reinterpret_cast<const c64 *>(G), reinterpret_cast<const c64 *>(gB), b, R, Px, Py, pl->kxh,
-                 reinterpret_cast<c64 *>(gA), act, st, pl->opt_prod_lds >> 4, pl->opt_prod_lds & 15);
+                 reinterpret_cast<c64 *>(gA), act, st, (pl->opt_prod_lds >> 4) & 15, pl->opt_prod_lds & 15,
+                 (pl->opt_prod_lds & 256) != 0 && pl->half);
     } else if (mfma) {
         prod_mfma<T>(G, gB, b, R, Px, Py, pl->kxh, gA, act, st, pl->opt_mfma_cols);
     } else {

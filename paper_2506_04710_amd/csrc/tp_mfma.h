@@ -253,7 +253,12 @@ __global__ void __launch_bounds__(1024) k_prod_mfma(const cpx<T> *__restrict__ G
 // group g, step h) is that of k_prod_mfma, so both give the same bits.
 // LDS row stride 8 KP + 2 values: the 16 rows a 16-lane phase reads fall in
 // distinct 16-byte bank groups.  KPM: pairs held in registers (KP <= KPM).
-template <typename T, int RT, int KPM, bool EVEN>
+// PAIR (half spectrum): workgroup = stored block s = kx Py + ky (kx < kxh);
+// the staged block serves its own frequency and, when the mirror frequency
+// (Px - kx, -ky) is not itself stored, the mirror too, with the block read
+// from LDS by columns (the transpose): each stored block is read from memory
+// once per column group instead of twice.
+template <typename T, int RT, int KPM, bool EVEN, bool PAIR>
 __global__ void __launch_bounds__(1024) k_prod_lds(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ in,
                                                    int b, int R, int Px, int Py, int kxh, int CG,
                                                    cpx<T> *__restrict__ out, const void *const *act) {
@@ -261,7 +266,7 @@ __global__ void __launch_bounds__(1024) k_prod_lds(const cpx<T> *__restrict__ G,
     cpx<T> *gs = reinterpret_cast<cpx<T> *>(smem_raw);
     const int KP = (b + 7) >> 3, W = 8 * KP, S = W + 2;
     const int ntc = (R + 15) >> 4, ncg = (ntc + CG - 1) / CG;
-    const long P = (long)Px * Py, nitem = P * ncg, per = (long)gridDim.x >> 3;
+    const long P = PAIR ? (long)kxh * Py : (long)Px * Py, nitem = P * ncg, per = (long)gridDim.x >> 3;
     const long item = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (item >= nitem) return;
     const long k = item / ncg;
@@ -273,13 +278,16 @@ __global__ void __launch_bounds__(1024) k_prod_lds(const cpx<T> *__restrict__ G,
     const int ct = w % CG, rg = w / CG;
     const int c0 = cfirst + ct * 16;
     const bool wlive = c0 <= clast && cols_live(act, c0, min(c0 + 15, clast));
+    // the mirror frequency of a stored block (PAIR), when it is not stored
+    const int kxs = (int)(k / Py), kys = (int)(k - (long)kxs * Py);
+    const bool mir = PAIR && kxs > 0 && Px - kxs >= kxh;
+    const long km = (long)(Px - kxs) * Py + (kys == 0 ? 0 : Py - kys);
     // this lane's column of the tile, its xhat values for every pair (zero
     // past row b and past column R)
-    cpair<T> xr[KPM];
-    {
+    auto load_x = [&](long kk, cpair<T>(&xr)[KPM]) {
         const int col = min(c0 + i, R - 1);
         const bool cok = c0 + i < R;
-        const cpx<T> *xc = in + k * C + (long)col * b;
+        const cpx<T> *xc = in + kk * C + (long)col * b;
 #pragma unroll
         for (int t = 0; t < KPM; ++t) {
             if (t < KP) {
@@ -294,10 +302,15 @@ __global__ void __launch_bounds__(1024) k_prod_lds(const cpx<T> *__restrict__ G,
                 xr[t].b = keep(xr[t].b, cok && q + 1 < b);
             }
         }
+    };
+    cpair<T> xr[KPM], xm[PAIR ? KPM : 1];
+    load_x(k, xr);
+    if constexpr (PAIR) {
+        if (mir) load_x(km, xm);
     }
     // the spectrum block, transposed for a mirrored frequency
     bool tr;
-    const cpx<T> *Gk = G + spec_src(k, Px, Py, kxh, tr) * (long)b * b;
+    const cpx<T> *Gk = G + (PAIR ? (tr = false, k) : spec_src(k, Px, Py, kxh, tr)) * (long)b * b;
     const int nthr = blockDim.x;
     if (tr) {
         // LDS[p][q] = stored[q][p]: read stored rows (contiguous in p)
@@ -328,7 +341,22 @@ __global__ void __launch_bounds__(1024) k_prod_lds(const cpx<T> *__restrict__ G,
     __syncthreads();
     if (!wlive) return;
     const int nrt = (b + 15) >> 4;
+    const int j = c0 + i;
     CAcc<T> acc[RT];
+    auto store = [&](long kk) {
+        if (j <= clast) {
+            cpx<T> *o = out + kk * C + (long)j * b;
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const int rt = rg * RT + r;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * rt + Mfma<T>::row(g, v);
+                    if (rt < nrt && row < b) o[row] = acc[r].get(v);
+                }
+            }
+        }
+    };
 #pragma unroll
     for (int r = 0; r < RT; ++r) acc[r].zero();
     // rows past b read the last row (results not stored)
@@ -353,18 +381,37 @@ __global__ void __launch_bounds__(1024) k_prod_lds(const cpx<T> *__restrict__ G,
             for (int r = 0; r < RT; ++r) acc[r].mac_b(a[r].b, xr[t].b);
         }
     }
-    const int j = c0 + i;
-    if (j <= clast) {
-        cpx<T> *o = out + k * C + (long)j * b;
+    store(k);
+    if constexpr (PAIR) {
+        if (!mir) return;
+        // the mirror: A[p][q] = block[q][p], LDS rows q (clamped to the last
+        // row; its xhat values are zero there) at column p
 #pragma unroll
-        for (int r = 0; r < RT; ++r) {
-            const int rt = rg * RT + r;
+        for (int r = 0; r < RT; ++r) acc[r].zero();
+        const cpx<T> *acol[RT];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * rt + Mfma<T>::row(g, v);
-                if (rt < nrt && row < b) o[row] = acc[r].get(v);
+        for (int r = 0; r < RT; ++r) acol[r] = gs + min(16 * (rg * RT + r) + i, b - 1);
+#pragma unroll
+        for (int t = 0; t < KPM; ++t) {
+            if (t < KP) {
+                const int q = 8 * t + 2 * g;
+                cpair<T> a[RT];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    a[r].a = acol[r][min(q, b - 1) * S];
+                    a[r].b = acol[r][min(q + 1, b - 1) * S];
+                }
+#pragma unroll
+                for (int r = 0; r < RT; ++r) acc[r].mac_a(a[r].a, xm[t].a);
+#pragma unroll
+                for (int r = 0; r < RT; ++r) acc[r].mac_b(a[r].a, xm[t].a);
+#pragma unroll
+                for (int r = 0; r < RT; ++r) acc[r].mac_a(a[r].b, xm[t].b);
+#pragma unroll
+                for (int r = 0; r < RT; ++r) acc[r].mac_b(a[r].b, xm[t].b);
             }
         }
+        store(km);
     }
 }
 

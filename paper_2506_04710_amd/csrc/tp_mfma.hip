@@ -53,30 +53,42 @@ size_t prod_lds_bytes(int b) {
 
 template <int RT, int KPM>
 static void launch_prod_lds(const c64 *G, const c64 *in, int b, int R, int Px, int Py, int kxh, c64 *out,
-                            const void *const *act, hipStream_t st, int CG) {
+                            const void *const *act, hipStream_t st, int CG, bool pair) {
     const int nrt = (b + 15) >> 4, RG = (nrt + RT - 1) / RT;
     const int ntc = (R + 15) >> 4, ncg = (ntc + CG - 1) / CG;
-    const long nitem = (long)Px * Py * ncg;
+    const long nitem = (long)(pair ? kxh : Px) * Py * ncg;
     dim3 grid((unsigned)(((nitem + 7) / 8) * 8));
+    const dim3 blk(64 * CG * RG);
     const size_t sh = prod_lds_bytes(b);
-    if (b % 2 == 0)
-        hipLaunchKernelGGL((k_prod_lds<float, RT, KPM, true>), grid, dim3(64 * CG * RG), sh, st, G, in, b, R, Px,
-                           Py, kxh, CG, out, act);
-    else
-        hipLaunchKernelGGL((k_prod_lds<float, RT, KPM, false>), grid, dim3(64 * CG * RG), sh, st, G, in, b, R, Px,
-                           Py, kxh, CG, out, act);
+    if (b % 2 == 0) {
+        if (pair)
+            hipLaunchKernelGGL((k_prod_lds<float, RT, KPM, true, true>), grid, blk, sh, st, G, in, b, R, Px, Py, kxh,
+                               CG, out, act);
+        else
+            hipLaunchKernelGGL((k_prod_lds<float, RT, KPM, true, false>), grid, blk, sh, st, G, in, b, R, Px, Py,
+                               kxh, CG, out, act);
+    } else {
+        if (pair)
+            hipLaunchKernelGGL((k_prod_lds<float, RT, KPM, false, true>), grid, blk, sh, st, G, in, b, R, Px, Py,
+                               kxh, CG, out, act);
+        else
+            hipLaunchKernelGGL((k_prod_lds<float, RT, KPM, false, false>), grid, blk, sh, st, G, in, b, R, Px, Py,
+                               kxh, CG, out, act);
+    }
 }
 
 // FP32 product with the spectrum block in LDS (b <= 128): RT row tiles per
-// wave, CG column tiles per workgroup (CG x ceil(ceil(b / 16) / RT) waves).
+// wave, CG column tiles per workgroup (CG x ceil(ceil(b / 16) / RT) waves);
+// pair: one workgroup per stored block of a half spectrum, applied to its
+// frequency and to the mirror.
 hipError_t prod_lds(const c64 *G, const c64 *in, int b, int R, int Px, int Py, int kxh, c64 *out,
-                    const void *const *act, hipStream_t st, int CG, int RT) {
+                    const void *const *act, hipStream_t st, int CG, int RT, bool pair) {
     const int KP = (b + 7) >> 3;
     auto go = [&](auto rt) {
         constexpr int RTc = decltype(rt)::value;
-        if (KP <= 8) launch_prod_lds<RTc, 8>(G, in, b, R, Px, Py, kxh, out, act, st, CG);
-        else if (KP <= 12) launch_prod_lds<RTc, 12>(G, in, b, R, Px, Py, kxh, out, act, st, CG);
-        else launch_prod_lds<RTc, 16>(G, in, b, R, Px, Py, kxh, out, act, st, CG);
+        if (KP <= 8) launch_prod_lds<RTc, 8>(G, in, b, R, Px, Py, kxh, out, act, st, CG, pair);
+        else if (KP <= 12) launch_prod_lds<RTc, 12>(G, in, b, R, Px, Py, kxh, out, act, st, CG, pair);
+        else launch_prod_lds<RTc, 16>(G, in, b, R, Px, Py, kxh, out, act, st, CG, pair);
     };
     if (RT <= 2) go(std::integral_constant<int, 2>());
     else if (RT <= 3) go(std::integral_constant<int, 3>());

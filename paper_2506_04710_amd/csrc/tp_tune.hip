@@ -70,9 +70,10 @@ tp_status toeplitz_tune(tp_plan p, tp_prec which, const void *x, long ldx, void 
     std::vector<int> plds{0};
     if (mfma_matters && which != TP_FP64 && p->bc <= 128) {
         const int nrt = (p->bc + 15) / 16;
-        for (int cg : {2, 3, 6})
-            for (int rt : {2, 3, 6})
-                if (cg * ((nrt + rt - 1) / rt) <= 16) plds.push_back(cg * 16 + rt);
+        for (int pr : {0, 256})
+            for (int cg : {2, 3, 6})
+                for (int rt : {2, 3, 6})
+                    if (cg * ((nrt + rt - 1) / rt) <= 16 && (pr == 0 || p->half)) plds.push_back(pr + cg * 16 + rt);
     }
     auto persistent = [&]() {
         const bool f64 = which == TP_FP64;

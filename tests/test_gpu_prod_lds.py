@@ -1,7 +1,9 @@
-"""The FP32 product with the spectrum block staged in LDS (TP_OPT_PROD_LDS)
-against the streaming product bit for bit, over row and column shapes, odd b,
-half and full spectra, placed rims and solver-idle columns; the option's
-checks and its fallback where the workgroup would not fit."""
+"""The FP32 product with the spectrum block staged in LDS (TP_OPT_PROD_LDS),
+per frequency and in the pair form (one workgroup per stored block of a half
+spectrum, applied to its frequency and transposed to the mirror), against the
+streaming product bit for bit, over row and column shapes, odd b, half and
+full spectra, placed rims and solver-idle columns; the option's checks and
+its fallback where the workgroup would not fit."""
 import numpy as np
 import pytest
 
@@ -54,13 +56,14 @@ def test_prod_lds_bitwise(tp, case, which):
     y0 = plan.matvec(x, which=which).cpu().numpy()
     nrt = (b + 15) // 16
     ran = 0
-    for cg in (1, 2, 3, 6, 16):
-        for rt in (2, 3, 6):
-            plan.set_option(_lib.TP_OPT_PROD_LDS, cg * 16 + rt)
-            y1 = plan.matvec(x, which=which).cpu().numpy()
-            assert np.array_equal(_bits(y0), _bits(y1)), (cg, rt)
-            ran += cg * -(-nrt // rt) <= 16
-    assert ran >= 9
+    for pair in (0, 256):
+        for cg in (1, 2, 3, 6, 15):
+            for rt in (2, 3, 6):
+                plan.set_option(_lib.TP_OPT_PROD_LDS, pair + cg * 16 + rt)
+                y1 = plan.matvec(x, which=which).cpu().numpy()
+                assert np.array_equal(_bits(y0), _bits(y1)), (pair, cg, rt)
+                ran += cg * -(-nrt // rt) <= 16
+    assert ran >= 18
     op = oracle.Operator(Nx, Ny, b, Nr, gen, prob.rim_re, prob.rim_rr)
     assert_parity(y1.astype(np.complex128).reshape(X.shape), oracle.matvec(op, X), 1e-5, N=prob.N, what=which)
     plan.close()
@@ -74,7 +77,7 @@ def test_prod_lds_placed_and_idle_columns(tp):
     prob = sa.make_problem(6, 5, 40, 30, 9390)
     plan = tp.Plan.create(6, 5, 40, 30, prob.gen, prob.rim_re, prob.rim_rr, prec="mixed", max_rhs=24, restart=30,
                           rim_place=sa.rim_placement(prob))
-    plan.set_option(_lib.TP_OPT_PROD_LDS, 3 * 16 + 2)
+    plan.set_option(_lib.TP_OPT_PROD_LDS, 256 + 3 * 16 + 2)       # the pair form (half spectrum)
     plan.precond_create()
     V = sa.rhs_random(prob, 24, rng=np.random.default_rng(5))
     V[::3] *= 1e-3                      # a spread of norms: columns finish at different steps
@@ -90,7 +93,7 @@ def test_prod_lds_option_checks(tp):
     prob = sa.make_problem(3, 3, 8, 0, 9391)
     plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=16, restart=4)
     assert plan.get_option(_lib.TP_OPT_PROD_LDS) == 0
-    for bad in (16 * 3 + 4, 16 * 0 + 2, 16 * 17 + 2, -1):
+    for bad in (16 * 3 + 4, 16 * 0 + 2, 256 + 2, 512 + 16 + 2, -1):
         with pytest.raises(tp.ToeplitzError):
             plan.set_option(_lib.TP_OPT_PROD_LDS, bad)
     plan.set_option(_lib.TP_OPT_PROD_LDS, 16 * 2 + 3)

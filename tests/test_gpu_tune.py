@@ -71,11 +71,12 @@ def test_tune_many_columns(tp, tmp_path):
     prob = sa.make_problem(4, 4, 16, 24, 9802)
     plan = tp.Plan.from_problem(prob, prec="mixed", max_rhs=20, restart=4)
     rec = tune.tune(plan, "fp32", 20, reps=5, path=str(tmp_path / "t.json"))
-    # three column tiles and nine shapes of the LDS product (one row tile:
-    # every column group 2, 3, 6 fits), each with the rim and the forward
-    # tiles in one launch and in two, and the persistent launch at the default
-    # tile (a small grid on 2-D tiles, even b, reciprocal dense rim)
-    assert rec["mfma_cols"] in (16, 32, 64) and rec["candidates"] == 25 and rec["spectrum_pass"] == 0
+    # three column tiles and eighteen shapes of the LDS product (one row tile:
+    # every column group 2, 3, 6 fits; per frequency and in pairs over the half
+    # spectrum), each with the rim and the forward tiles in one launch and in
+    # two, and the persistent launch at the default tile (a small grid on 2-D
+    # tiles, even b, reciprocal dense rim)
+    assert rec["mfma_cols"] in (16, 32, 64) and rec["candidates"] == 43 and rec["spectrum_pass"] == 0
     from paper_2506_04710_amd import _lib
     assert plan.get_option(_lib.TP_OPT_RIM_OVERLAP) == rec["rim_overlap"]
     assert rec["multi_fused"] in (0, 1)
