@@ -213,6 +213,12 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
  *     rim's slabs and the forward tiles share one launch (independent work: the
  *     rim's matrix work overlaps the transforms); 0: two launches.  Same
  *     results bit for bit.
+ *   TP_OPT_DUAL_LAUNCH  1 (default): a one-column mixed solve (TP_MIXED)
+ *     applies its FP32 operator (Arnoldi steps) and its FP64 operator
+ *     (residual steps) in shared launches, one per stage, where both take the
+ *     pair-stream path with separate x and y passes (the idle one costs no
+ *     launch of its own); 0: one launch sequence per precision.  Same results
+ *     bit for bit.
  *   TP_OPT_PROD_LDS  FP32 per-frequency product with the spectrum block staged
  *     in LDS and each wave's column tile of the transformed input held in
  *     registers: value 16 * CG + RT (+ 256), CG column tiles of 16 per
@@ -234,6 +240,7 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
 #define TP_OPT_MULTI_FUSED 5
 #define TP_OPT_PROD_LDS 6
 #define TP_OPT_RIM_OVERLAP 7
+#define TP_OPT_DUAL_LAUNCH 8
 #define TP_PASS_AUTO 0
 #define TP_PASS_FUSED 1
 #define TP_PASS_PAIRS 2

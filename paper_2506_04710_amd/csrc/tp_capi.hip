@@ -86,7 +86,7 @@ struct Layout {
     size_t G64, G32, B64, BE64, C64, B32, BE32, C32;   // offsets (SIZE_MAX = absent)
     size_t tab, ws, total;
     size_t spec1, rim1;      // bytes per copy (complex128)
-    size_t grid_bytes, rimpart_bytes, ypart_bytes, solver_bytes, scratch_bytes, ws_bytes;
+    size_t grid_bytes, rimpart_bytes, ypart_bytes, dual_bytes, solver_bytes, scratch_bytes, ws_bytes;
     int rim_te, rim_nslab;
     int kxh;                 // stored spectrum columns
 };
@@ -154,13 +154,16 @@ static tp_status make_layout(int Nx, int Ny, int b, int Nr, int nrc, int sym, tp
     L->rimpart_bytes = dense_rim ? al((size_t)L->rim_nslab * Nr * max_rhs * 16) : al(16);
     // single-column half-spectrum path: mirror parts per row chunk of 8
     L->ypart_bytes = half ? al((size_t)((bc + 7) / 8) * Ny * (L->Px - L->kxh) * bc * 16) : 0;
+    // FP32 grids of one column for the mixed solver's shared launches
+    L->dual_bytes = (f32 && f64) ? al(gpts * (size_t)bc * 8) : 0;
     L->solver_bytes = al(solver_ws_bytes((long)Nt, restart, max_rhs));
     // plan-time scratch: device copy of the generators + the x-transformed rows
     // (+ a staging copy of one dense rim block)
     L->scratch_bytes = al((size_t)(2 * Ny - 1) * (2 * Nx - 1) * bb * 16) + al((size_t)(2 * Ny - 1) * L->Px * bb * 16) +
                        (dense_rim ? al((size_t)Nr * std::max(N, (size_t)Nr) * 16) : 0);
-    L->ws_bytes =
-        std::max(2 * L->grid_bytes + L->rimpart_bytes + L->ypart_bytes + 256 + L->solver_bytes, L->scratch_bytes);
+    L->ws_bytes = std::max(2 * L->grid_bytes + L->rimpart_bytes + L->ypart_bytes + 256 + 2 * L->dual_bytes +
+                               L->solver_bytes,
+                           L->scratch_bytes);
     L->ws = take(true, L->ws_bytes);
     L->total = off;
     return TP_OK;
@@ -365,7 +368,10 @@ static tp_status create_plan(int Nx, int Ny, int b, int Nr, int nrc, const doubl
     pl->ypart = L.ypart_bytes ? pl->ws + 2 * L.grid_bytes + L.rimpart_bytes : nullptr;
     // the persistent multi-column launch's queue and counters (256 bytes)
     pl->fctr = (int *)(pl->ws + 2 * L.grid_bytes + L.rimpart_bytes + L.ypart_bytes);
-    pl->solver_ws = pl->ws + 2 * L.grid_bytes + L.rimpart_bytes + L.ypart_bytes + 256;
+    char *dual = pl->ws + 2 * L.grid_bytes + L.rimpart_bytes + L.ypart_bytes + 256;
+    pl->gridA32 = L.dual_bytes ? dual : nullptr;
+    pl->gridB32 = L.dual_bytes ? dual + L.dual_bytes : nullptr;
+    pl->solver_ws = dual + 2 * L.dual_bytes;
     pl->rim_te = L.rim_te; pl->rim_nslab = L.rim_nslab;
 
     // transform tables
@@ -518,6 +524,11 @@ tp_status toeplitz_plan_set_option(tp_plan p, int option, int value) {
             solver_drop_graphs(p);
             p->opt_mfma_min_r = value;
             return TP_OK;
+        case TP_OPT_DUAL_LAUNCH:
+            if (value != 0 && value != 1) return fail(TP_E_INVAL, "shared launches must be 0 or 1");
+            solver_drop_graphs(p);
+            p->opt_dual_launch = value;
+            return TP_OK;
         case TP_OPT_RIM_OVERLAP:
             if (value != 0 && value != 1) return fail(TP_E_INVAL, "rim overlap must be 0 or 1");
             solver_drop_graphs(p);
@@ -559,6 +570,7 @@ tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value) {
         case TP_OPT_MULTI_FUSED: *value = p->opt_multi_fused; return TP_OK;
         case TP_OPT_PROD_LDS: *value = p->opt_prod_lds; return TP_OK;
         case TP_OPT_RIM_OVERLAP: *value = p->opt_rim_overlap; return TP_OK;
+        case TP_OPT_DUAL_LAUNCH: *value = p->opt_dual_launch; return TP_OK;
         default: return fail(TP_E_INVAL, "unknown option");
     }
 }

@@ -308,6 +308,9 @@ struct tp_plan_s {
     tp::FFTDesc fx, fy;
     // matvec workspace
     void *gridA, *gridB;          // [max(Ny*Px, Px*Py)][b*max_rhs] complex128-sized each
+    // one column of FP32 grids of their own (plans with both copies): the mixed
+    // solver's FP32 and FP64 operator instances then share each launch
+    void *gridA32 = nullptr, *gridB32 = nullptr;
     void *rim_part;               // [nslab][Nr][max_rhs] complex128-sized
     void *ypart;                  // half spectrum, one column: mirror parts [nchunk][Ny][Px - kxh][b]
     char *solver_ws;              // Krylov workspace
@@ -325,6 +328,7 @@ struct tp_plan_s {
     int opt_multi_fused = 0;      // 1: many columns on the 2-D tiles in one persistent launch
     int opt_prod_lds = 0;         // FP32 product with the block in LDS: 16 * column tiles + row tiles (0: off)
     int opt_rim_overlap = 1;      // 1: the dense rim's matrix-core slabs and the forward 2-D tiles in one launch
+    int opt_dual_launch = 1;      // 1: the mixed solver's FP32 and FP64 operators share launches where they can
     int *fctr = nullptr;          // task queue and completion counters of that launch (workspace)
     // instrumentation only, on a copy of the record: launch this stage alone
     int only_stage = -1;

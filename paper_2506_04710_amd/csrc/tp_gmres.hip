@@ -599,9 +599,8 @@ static hipError_t super_step(tp_plan pl, const Eng &E, int par, hipStream_t st) 
         if (e) return e;
     }
     if (E.mixed) {
-        e = matvec_fp32_wide(pl, Cols<const c128>{nullptr, 0, E.tin}, Cols<c128>{nullptr, 0, E.tout}, E.nslots, st);
-        if (e) return e;
-        e = matvec_fp64(pl, Cols<const c128>{nullptr, 0, E.rin}, Cols<c128>{nullptr, 0, E.rout}, E.nslots, st);
+        e = matvec_mixed_both(pl, Cols<const c128>{nullptr, 0, E.tin}, Cols<c128>{nullptr, 0, E.tout},
+                              Cols<const c128>{nullptr, 0, E.rin}, Cols<c128>{nullptr, 0, E.rout}, E.nslots, st);
     } else {
         e = matvec_fp64(pl, Cols<const c128>{nullptr, 0, E.tin}, Cols<c128>{nullptr, 0, E.tout}, E.nslots, st);
     }

@@ -22,6 +22,9 @@ hipError_t matvec_fp64(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipS
 hipError_t matvec_fp32(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStream_t st);
 // FP32 operator on complex128 vectors (inner solves of the mixed scheme)
 hipError_t matvec_fp32_wide(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st);
+// the mixed solver's FP32 (x32 -> y32) and FP64 (x64 -> y64) operator instances
+hipError_t matvec_mixed_both(tp_plan pl, Cols<const c128> x32, Cols<c128> y32, Cols<const c128> x64,
+                             Cols<c128> y64, int R, hipStream_t st);
 constexpr int kMatvecStages = 7;   // rim pass, x DFT, y DFT, product, inverse y, inverse x, rim finish
 hipError_t matvec_fp64_timed(tp_plan pl, Cols<const c128> x, Cols<c128> y, int R, hipStream_t st, hipEvent_t *ev);
 hipError_t matvec_fp32_timed(tp_plan pl, Cols<const c64> x, Cols<c64> y, int R, hipStream_t st, hipEvent_t *ev);

@@ -46,13 +46,13 @@ __device__ __forceinline__ void zero_lds(cpx<T> *buf, int n, int nt = kBlock) {
 
 // ------------------------------------------------------------ FFT passes
 template <typename T, typename In>
-__global__ void __launch_bounds__(256) k_fwd_x(Cols<const In> x, int R, int Nx, int b, FFTDesc fx,
-                                               int lgCC, cpx<T> *__restrict__ out, RimMap rm) {
-    extern __shared__ char smem_raw[];
+__device__ __forceinline__ void fwd_x_body(Cols<const In> x, int R, int Nx, int b, const FFTDesc &fx, int lgCC,
+                                           cpx<T> *__restrict__ out, const RimMap &rm, int bx, int by,
+                                           char *smem_raw) {
     cpx<T> *twl = reinterpret_cast<cpx<T> *>(smem_raw);
     cpx<T> *buf = twl + fx.P;
     const int CC = 1 << lgCC, C = b * R, P = fx.P;
-    const int c0 = blockIdx.x * CC, iy = blockIdx.y;
+    const int c0 = bx * CC, iy = by;
     if (!cols_live((const void *const *)x.tab, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
     auto fetch = [&](int i, bool &ok) {
         const int ix = i >> lgCC, c = c0 + (i & (CC - 1));
@@ -89,15 +89,21 @@ __global__ void __launch_bounds__(256) k_fwd_x(Cols<const In> x, int R, int Nx, 
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_fwd_y(const cpx<T> *__restrict__ in, int C, int Ny, int Px,
-                                               FFTDesc fy, int lgCC, cpx<T> *__restrict__ out,
-                                               const void *const *act, int b) {
+template <typename T, typename In>
+__global__ void __launch_bounds__(256) k_fwd_x(Cols<const In> x, int R, int Nx, int b, FFTDesc fx,
+                                               int lgCC, cpx<T> *__restrict__ out, RimMap rm) {
     extern __shared__ char smem_raw[];
+    fwd_x_body<T, In>(x, R, Nx, b, fx, lgCC, out, rm, blockIdx.x, blockIdx.y, smem_raw);
+}
+
+template <typename T>
+__device__ __forceinline__ void fwd_y_body(const cpx<T> *__restrict__ in, int C, int Ny, int Px, const FFTDesc &fy,
+                                           int lgCC, cpx<T> *__restrict__ out, const void *const *act, int b,
+                                           int bx, int by, char *smem_raw) {
     cpx<T> *twl = reinterpret_cast<cpx<T> *>(smem_raw);
     cpx<T> *buf = twl + fy.P;
     const int CC = 1 << lgCC, P = fy.P;
-    const int c0 = blockIdx.x * CC, kx = blockIdx.y;
+    const int c0 = bx * CC, kx = by;
     if (!cols_live(act, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
     load_twiddles<T>(twl, fy);
     zero_lds<T>(buf, P * CC);
@@ -115,14 +121,21 @@ __global__ void __launch_bounds__(256) k_fwd_y(const cpx<T> *__restrict__ in, in
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_inv_y(const cpx<T> *__restrict__ in, int C, int Ny, int Px,
+__global__ void __launch_bounds__(256) k_fwd_y(const cpx<T> *__restrict__ in, int C, int Ny, int Px,
                                                FFTDesc fy, int lgCC, cpx<T> *__restrict__ out,
                                                const void *const *act, int b) {
     extern __shared__ char smem_raw[];
+    fwd_y_body<T>(in, C, Ny, Px, fy, lgCC, out, act, b, blockIdx.x, blockIdx.y, smem_raw);
+}
+
+template <typename T>
+__device__ __forceinline__ void inv_y_body(const cpx<T> *__restrict__ in, int C, int Ny, int Px, const FFTDesc &fy,
+                                           int lgCC, cpx<T> *__restrict__ out, const void *const *act, int b,
+                                           int bx, int by, char *smem_raw) {
     cpx<T> *twl = reinterpret_cast<cpx<T> *>(smem_raw);
     cpx<T> *buf = twl + fy.P;
     const int CC = 1 << lgCC, P = fy.P;
-    const int c0 = blockIdx.x * CC, kx = blockIdx.y;
+    const int c0 = bx * CC, kx = by;
     if (!cols_live(act, c0 / b, (min(c0 + CC, C) - 1) / b)) return;
     load_twiddles<T>(twl, fy);
     for (int i = threadIdx.x; i < P * CC; i += kBlock) {
@@ -135,6 +148,14 @@ __global__ void __launch_bounds__(256) k_inv_y(const cpx<T> *__restrict__ in, in
         const int iy = i >> lgCC, cl = i & (CC - 1), c = c0 + cl;
         if (c < C) out[((long)iy * Px + kx) * C + c] = buf[i];
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_inv_y(const cpx<T> *__restrict__ in, int C, int Ny, int Px,
+                                               FFTDesc fy, int lgCC, cpx<T> *__restrict__ out,
+                                               const void *const *act, int b) {
+    extern __shared__ char smem_raw[];
+    inv_y_body<T>(in, C, Ny, Px, fy, lgCC, out, act, b, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 // ---------------------------------------------------- per-frequency product
@@ -510,17 +531,16 @@ constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 
 // keeps the stream balanced over the compute units whatever the block width;
 // every block's loads issue before anything else.
 template <typename T, int VPL>
-__global__ void __launch_bounds__(1024) k_pair_prod(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ in,
-                                                    int b, int Px, int Py, int kxh, cpx<T> *__restrict__ out,
-                                                    const void *const *act) {
+__device__ __forceinline__ void pair_prod_body(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ in, int b,
+                                               int Px, int Py, int kxh, cpx<T> *__restrict__ out,
+                                               const void *const *act, int bx, char *smem_raw) {
     constexpr int VP = pow2_at_least(VPL), S = RS8<VP>::S, NV = RS8<VP>::NV;
-    extern __shared__ char smem_raw[];
     if (!cols_live(act, 0, 0)) return;                 // an idle column (solver phases)
     const int nw = blockDim.x >> 6;
     cpx<T> *xk = reinterpret_cast<cpx<T> *>(smem_raw);   // [b] xhat(k)
     cpx<T> *xm = xk + b;                                   // [b] xhat(-k)
     cpx<T> *zp = xm + b;                                   // [nw][b] column sums per wave
-    const int s = blockIdx.x;
+    const int s = bx;
     const int kx = s / Py, ky = s - kx * Py;
     const bool mir = kx > 0 && Px - kx >= kxh;
     const long k = (long)kx * Py + ky;
@@ -564,6 +584,14 @@ __global__ void __launch_bounds__(1024) k_pair_prod(const cpx<T> *__restrict__ G
         for (int u = 1; u < nw; ++u) t = t + zp[u * b + q];
         out[km * b + q] = t;
     }
+}
+
+template <typename T, int VPL>
+__global__ void __launch_bounds__(1024) k_pair_prod(const cpx<T> *__restrict__ G, const cpx<T> *__restrict__ in,
+                                                    int b, int Px, int Py, int kxh, cpx<T> *__restrict__ out,
+                                                    const void *const *act) {
+    extern __shared__ char smem_raw[];
+    pair_prod_body<T, VPL>(G, in, b, Px, Py, kxh, out, act, blockIdx.x, smem_raw);
 }
 
 
@@ -950,14 +978,12 @@ struct MirrorParts {
 };
 
 template <typename T, typename In, typename Out>
-__global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in, int R, int Nx, int b, FFTDesc fx,
-                                                   int lgCC, int nchunk, Cols<Out> y, int accumulate,
-                                                   Cols<const Out> acc, int ninv, const cpx<T> *__restrict__ part,
-                                                   const cpx<T> *__restrict__ Cm, const cpx<T> *__restrict__ D,
-                                                   Cols<const In> x, long N, int Nr, int nslab, MirrorParts<T> mp,
-                                                   RimMap rm) {
-    extern __shared__ char smem_raw[];
-    const int blk = blockIdx.x;
+__device__ __forceinline__ void inv_x_fin_body(const cpx<T> *__restrict__ in, int R, int Nx, int b,
+                                               const FFTDesc &fx, int lgCC, int nchunk, Cols<Out> y, int accumulate,
+                                               Cols<const Out> acc, int ninv, const cpx<T> *__restrict__ part,
+                                               const cpx<T> *__restrict__ Cm, const cpx<T> *__restrict__ D,
+                                               Cols<const In> x, long N, int Nr, int nslab, const MirrorParts<T> &mp,
+                                               const RimMap &rm, int blk, char *smem_raw) {
     if (blk >= ninv) {
         const int f = blk - ninv, w = threadIdx.x >> 6;
         const int nrowblk = (Nr + 3) >> 2;
@@ -1029,6 +1055,18 @@ __global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in
             yc[e] = v;
         }
     }
+}
+
+template <typename T, typename In, typename Out>
+__global__ void __launch_bounds__(256) k_inv_x_fin(const cpx<T> *__restrict__ in, int R, int Nx, int b, FFTDesc fx,
+                                                   int lgCC, int nchunk, Cols<Out> y, int accumulate,
+                                                   Cols<const Out> acc, int ninv, const cpx<T> *__restrict__ part,
+                                                   const cpx<T> *__restrict__ Cm, const cpx<T> *__restrict__ D,
+                                                   Cols<const In> x, long N, int Nr, int nslab, MirrorParts<T> mp,
+                                                   RimMap rm) {
+    extern __shared__ char smem_raw[];
+    inv_x_fin_body<T, In, Out>(in, R, Nx, b, fx, lgCC, nchunk, y, accumulate, acc, ninv, part, Cm, D, x, N, Nr,
+                               nslab, mp, rm, blockIdx.x, smem_raw);
 }
 
 // ------------------------------------------------- small grids: 2-D tiles
@@ -1849,6 +1887,131 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     mark(6);
     mark(7);
     return hipGetLastError();
+}
+
+// --------------------------------------------- both precisions per launch
+// The mixed solver applies, in every super-step, the FP32 operator to the
+// columns in an Arnoldi step and the FP64 operator to the columns in a
+// residual step; one of the two usually has no live column (one right-hand
+// side: always).  Here each stage of the one-column pair-stream path runs once
+// for both: workgroups with blockIdx.z = 0 take the FP32 instance, z = 1 the
+// FP64 one (each with its own grids), and an instance without live columns
+// exits at once, so the idle instance costs no launch of its own.
+template <typename In>
+__global__ void __launch_bounds__(256) k_fwd_x_dual(Cols<const In> x32, Cols<const In> x64, int R, int Nx, int b,
+                                                    FFTDesc fx, int lg32, int lg64, int g32, int g64, c64 *o32,
+                                                    c128 *o64, RimMap rm) {
+    extern __shared__ char smem_raw[];
+    if (blockIdx.z == 0) {
+        if ((int)blockIdx.x < g32)
+            fwd_x_body<float, In>(x32, R, Nx, b, fx, lg32, o32, rm, blockIdx.x, blockIdx.y, smem_raw);
+    } else if ((int)blockIdx.x < g64) {
+        fwd_x_body<double, In>(x64, R, Nx, b, fx, lg64, o64, rm, blockIdx.x, blockIdx.y, smem_raw);
+    }
+}
+
+template <bool INV>
+__global__ void __launch_bounds__(256) k_y_dual(const c64 *i32, const c128 *i64, int C, int Ny, int Px, FFTDesc fy,
+                                                int lg32, int lg64, int g32, int g64, c64 *o32, c128 *o64,
+                                                const void *const *a32, const void *const *a64, int b) {
+    extern __shared__ char smem_raw[];
+    if (blockIdx.z == 0) {
+        if ((int)blockIdx.x >= g32) return;
+        if (INV) inv_y_body<float>(i32, C, Ny, Px, fy, lg32, o32, a32, b, blockIdx.x, blockIdx.y, smem_raw);
+        else fwd_y_body<float>(i32, C, Ny, Px, fy, lg32, o32, a32, b, blockIdx.x, blockIdx.y, smem_raw);
+    } else {
+        if ((int)blockIdx.x >= g64) return;
+        if (INV) inv_y_body<double>(i64, C, Ny, Px, fy, lg64, o64, a64, b, blockIdx.x, blockIdx.y, smem_raw);
+        else fwd_y_body<double>(i64, C, Ny, Px, fy, lg64, o64, a64, b, blockIdx.x, blockIdx.y, smem_raw);
+    }
+}
+
+template <int VPL>
+__global__ void __launch_bounds__(1024) k_pair_prod_dual(const c64 *G32, const c128 *G64, const c64 *i32,
+                                                         const c128 *i64, int b, int Px, int Py, int kxh, c64 *o32,
+                                                         c128 *o64, const void *const *a32,
+                                                         const void *const *a64) {
+    extern __shared__ char smem_raw[];
+    if (blockIdx.z == 0) pair_prod_body<float, VPL>(G32, i32, b, Px, Py, kxh, o32, a32, blockIdx.x, smem_raw);
+    else pair_prod_body<double, VPL>(G64, i64, b, Px, Py, kxh, o64, a64, blockIdx.x, smem_raw);
+}
+
+template <typename In, typename Out>
+__global__ void __launch_bounds__(256) k_inv_x_dual(const c64 *i32, const c128 *i64, int R, int Nx, int b, FFTDesc fx,
+                                                    int lg32, int lg64, int nc32, int nc64, Cols<Out> y32,
+                                                    Cols<Out> y64, int g32, int g64, long N, int Nr, RimMap rm) {
+    extern __shared__ char smem_raw[];
+    // the operator of a plan without a dense rim pass: no accumulation, no
+    // rim rows to finish (a placed rim's rows come out of the crop)
+    if (blockIdx.z == 0) {
+        if ((int)blockIdx.x >= g32) return;
+        inv_x_fin_body<float, In, Out>(i32, R, Nx, b, fx, lg32, nc32, y32, 0, Cols<const Out>{y32.base, y32.ld, y32.tab},
+                                       g32, nullptr, nullptr, nullptr, Cols<const In>{nullptr, 0, nullptr}, N, Nr, 0,
+                                       MirrorParts<float>{nullptr, 0, 0, 0, 0}, rm, blockIdx.x, smem_raw);
+    } else {
+        if ((int)blockIdx.x >= g64) return;
+        inv_x_fin_body<double, In, Out>(i64, R, Nx, b, fx, lg64, nc64, y64, 0,
+                                        Cols<const Out>{y64.base, y64.ld, y64.tab}, g64, nullptr, nullptr, nullptr,
+                                        Cols<const In>{nullptr, 0, nullptr}, N, Nr, 0,
+                                        MirrorParts<double>{nullptr, 0, 0, 0, 0}, rm, blockIdx.x, smem_raw);
+    }
+}
+
+// The FP32 operator on (x32 -> y32) and the FP64 operator on (x64 -> y64),
+// one column each, in five launches instead of ten, where both precisions take
+// the pair-stream path with separate x and y passes and the plan has grids
+// for the FP32 instance; otherwise returns false and launches nothing.
+template <typename In, typename Out>
+bool matvec_dual_launch(tp_plan pl, Cols<const In> x32, Cols<Out> y32, Cols<const In> x64, Cols<Out> y64,
+                        hipStream_t st) {
+    const int R = 1;
+    if (!pl->gridA32 || !pl->G32 || !pl->G64) return false;
+    const Path p32 = choose_path<float, false>(pl, R), p64 = choose_path<double, false>(pl, R);
+    if (!p32.pairs || !p64.pairs || p32.rim || p64.rim || p32.lg2 >= 0 || p64.lg2 >= 0) return false;
+    const int Nx = pl->Nx, Ny = pl->Ny, b = pl->bc, Px = pl->Px, Py = pl->Py, C = b * R;
+    const RimMap rm{pl->rim_map, pl->b, pl->nrc, pl->N};
+    c64 *A32 = reinterpret_cast<c64 *>(pl->gridA32), *B32 = reinterpret_cast<c64 *>(pl->gridB32);
+    c128 *A64 = reinterpret_cast<c128 *>(pl->gridA), *B64 = reinterpret_cast<c128 *>(pl->gridB);
+    const void *const *a32 = (const void *const *)x32.tab;
+    const void *const *a64 = (const void *const *)x64.tab;
+    const dim3 blk(256);
+    // x passes
+    const int lx32 = fft_lgcc(Px, C, 8, fftx_maxcc(C, Ny)), lx64 = fft_lgcc(Px, C, 16, fftx_maxcc(C, Ny));
+    const int gx32 = (C + (1 << lx32) - 1) >> lx32, gx64 = (C + (1 << lx64) - 1) >> lx64;
+    const size_t shx = std::max(((size_t)Px * (1 << lx32) + Px) * 8, ((size_t)Px * (1 << lx64) + Px) * 16);
+    hipLaunchKernelGGL((k_fwd_x_dual<In>), dim3(std::max(gx32, gx64), Ny, 2), blk, shx, st, x32, x64, R, Nx, b,
+                       pl->fx, lx32, lx64, gx32, gx64, A32, A64, rm);
+    // y passes
+    const int ly32 = fft_lgcc(Py, C, 8, TP_FFTY_MAXCC), ly64 = fft_lgcc(Py, C, 16, TP_FFTY_MAXCC);
+    const int gy32 = (C + (1 << ly32) - 1) >> ly32, gy64 = (C + (1 << ly64) - 1) >> ly64;
+    const size_t shy = std::max(((size_t)Py * (1 << ly32) + Py) * 8, ((size_t)Py * (1 << ly64) + Py) * 16);
+    hipLaunchKernelGGL((k_y_dual<false>), dim3(std::max(gy32, gy64), Px, 2), blk, shy, st, A32, A64, C, Ny, Px,
+                       pl->fy, ly32, ly64, gy32, gy64, B32, B64, a32, a64, b);
+    // pair-stream products
+    {
+        const int nw = (b + 7) / 8, vpl = (b + 7) / 8;
+        const size_t sh = (size_t)(2 + nw) * b * sizeof(c128);
+        const dim3 grid((unsigned)(pl->kxh * Py), 1, 2), pblk((unsigned)(64 * nw));
+        const int kxh = pl->kxh;
+#define TP_PAIR_DUAL(V)                                                                                         \
+    hipLaunchKernelGGL((k_pair_prod_dual<V>), grid, pblk, sh, st, pl->G32, pl->G64, B32, B64, b, Px, Py, kxh, A32, \
+                       A64, a32, a64)
+        if (vpl <= 2) TP_PAIR_DUAL(2);
+        else if (vpl <= 4) TP_PAIR_DUAL(4);
+        else if (vpl <= 6) TP_PAIR_DUAL(6);
+        else if (vpl <= 8) TP_PAIR_DUAL(8);
+        else if (vpl <= 9) TP_PAIR_DUAL(9);
+        else if (vpl <= 12) TP_PAIR_DUAL(12);
+        else TP_PAIR_DUAL(16);
+#undef TP_PAIR_DUAL
+    }
+    hipLaunchKernelGGL((k_y_dual<true>), dim3(std::max(gy32, gy64), Px, 2), blk, shy, st, A32, A64, C, Ny, Px,
+                       pl->fy, ly32, ly64, gy32, gy64, B32, B64, a32, a64, b);
+    // inverse x passes, crop
+    const int nc32 = gx32, nc64 = gx64;
+    hipLaunchKernelGGL((k_inv_x_dual<In, Out>), dim3(std::max(nc32, nc64) * Ny, 1, 2), blk, shx, st, B32, B64, R,
+                       Nx, b, pl->fx, lx32, lx64, nc32, nc64, y32, y64, nc32 * Ny, nc64 * Ny, pl->N, pl->Nr, rm);
+    return true;
 }
 
 }  // namespace tp

@@ -222,3 +222,28 @@ def test_solve_nonfinite_rhs_stops():
     assert info[2].status == _lib.TP_E_INVAL and info[2].iters == 0
     assert oracle.relres(prob, x[:1].cpu().numpy(), V)[0] <= 1e-8
     plan.close()
+
+
+def test_mixed_solve_shared_launches_bitwise(tp):
+    """A one-column mixed solve whose FP32 and FP64 operators share each stage's
+    launch (TP_OPT_DUAL_LAUNCH, placed rim, pair-stream pass) gives the same
+    bits as the solve with one launch sequence per precision."""
+    from paper_2506_04710_amd import _lib
+    banner("mixed solve, shared FP32/FP64 launches")
+    prob = sa.make_problem(12, 10, 24, 40, 9555)
+    V = sa.rhs_random(prob, 1, rng=np.random.default_rng(4))
+    out = {}
+    for dual in (1, 0):
+        plan = tp.Plan.create(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, prec="mixed",
+                              max_rhs=1, restart=30, rim_place=sa.rim_placement(prob))
+        plan.set_option(_lib.TP_OPT_SPECTRUM_PASS, _lib.TP_PASS_PAIRS)
+        assert plan.get_option(_lib.TP_OPT_DUAL_LAUNCH) == 1
+        plan.set_option(_lib.TP_OPT_DUAL_LAUNCH, dual)
+        plan.precond_create()
+        x, info = plan.solve(to_dev(V), mode="mixed", tol=1e-8, precond=True)
+        out[dual] = (x.cpu().numpy().reshape(1, -1), info[0])
+        plan.close()
+    (x1, i1), (x0, i0) = out[1], out[0]
+    assert i1["status"] == 0 and i1["iters"] == i0["iters"] and i1["outer_iters"] == i0["outer_iters"]
+    assert np.array_equal(x1.view(np.uint64), x0.view(np.uint64))
+    assert oracle.relres(prob, x1, V)[0] <= 1e-8
