@@ -213,12 +213,15 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
  *     rim's slabs and the forward tiles share one launch (independent work: the
  *     rim's matrix work overlaps the transforms); 0: two launches.  Same
  *     results bit for bit.
- *   TP_OPT_DUAL_LAUNCH  1 (default): a one-column mixed solve (TP_MIXED)
- *     applies its FP32 operator (Arnoldi steps) and its FP64 operator
- *     (residual steps) in shared launches, one per stage, where both take the
- *     pair-stream path with separate x and y passes (the idle one costs no
- *     launch of its own); 0: one launch sequence per precision.  Same results
- *     bit for bit.
+ *   TP_OPT_DUAL_LAUNCH  1 (default): a mixed solve (TP_MIXED) applies its
+ *     FP32 operator (Arnoldi steps) and its FP64 operator (residual steps) in
+ *     shared launches, one per stage, where both precisions take the same
+ *     launch shape: one column on the pair-stream path with separate x and y
+ *     passes, or many columns with the matrix-core product at its default
+ *     column tiles (TP_OPT_MFMA_COLS 0, TP_OPT_PROD_LDS 0, no persistent
+ *     launch) on separate passes or on 2-D tiles, without a dense rim pass
+ *     (the idle instance costs no launch of its own); 0: one launch sequence
+ *     per precision.  Same results bit for bit.
  *   TP_OPT_PROD_LDS  FP32 per-frequency product with the spectrum block staged
  *     in LDS and each wave's column tile of the transformed input held in
  *     registers: value 16 * CG + RT (+ 256), CG column tiles of 16 per

@@ -18,7 +18,7 @@ hipError_t matvec_fp32_wide_timed(tp_plan pl, Cols<const c128> x, Cols<c128> y, 
 // path allows it, else the two applications in turn.
 hipError_t matvec_mixed_both(tp_plan pl, Cols<const c128> x32, Cols<c128> y32, Cols<const c128> x64,
                              Cols<c128> y64, int R, hipStream_t st) {
-    if (R == 1 && pl->opt_dual_launch && matvec_dual_launch<c128, c128>(pl, x32, y32, x64, y64, st))
+    if (pl->opt_dual_launch && matvec_dual_launch<c128, c128>(pl, x32, y32, x64, y64, R, st))
         return hipGetLastError();
     hipError_t e = matvec_launch<float, c128, c128>(pl, x32, y32, R, st);
     if (e) return e;

@@ -154,8 +154,8 @@ static tp_status make_layout(int Nx, int Ny, int b, int Nr, int nrc, int sym, tp
     L->rimpart_bytes = dense_rim ? al((size_t)L->rim_nslab * Nr * max_rhs * 16) : al(16);
     // single-column half-spectrum path: mirror parts per row chunk of 8
     L->ypart_bytes = half ? al((size_t)((bc + 7) / 8) * Ny * (L->Px - L->kxh) * bc * 16) : 0;
-    // FP32 grids of one column for the mixed solver's shared launches
-    L->dual_bytes = (f32 && f64) ? al(gpts * (size_t)bc * 8) : 0;
+    // FP32 grids for the mixed solver's shared launches
+    L->dual_bytes = (f32 && f64) ? al(gpts * (size_t)bc * max_rhs * 8) : 0;
     L->solver_bytes = al(solver_ws_bytes((long)Nt, restart, max_rhs));
     // plan-time scratch: device copy of the generators + the x-transformed rows
     // (+ a staging copy of one dense rim block)

@@ -308,8 +308,8 @@ struct tp_plan_s {
     tp::FFTDesc fx, fy;
     // matvec workspace
     void *gridA, *gridB;          // [max(Ny*Px, Px*Py)][b*max_rhs] complex128-sized each
-    // one column of FP32 grids of their own (plans with both copies): the mixed
-    // solver's FP32 and FP64 operator instances then share each launch
+    // FP32 grids of their own, max_rhs columns (plans with both copies): the
+    // mixed solver's FP32 and FP64 operator instances then share each launch
     void *gridA32 = nullptr, *gridB32 = nullptr;
     void *rim_part;               // [nslab][Nr][max_rhs] complex128-sized
     void *ypart;                  // half spectrum, one column: mirror parts [nchunk][Ny][Px - kxh][b]

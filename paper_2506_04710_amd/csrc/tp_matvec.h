@@ -1957,17 +1957,85 @@ __global__ void __launch_bounds__(256) k_inv_x_dual(const c64 *i32, const c128 *
     }
 }
 
-// The FP32 operator on (x32 -> y32) and the FP64 operator on (x64 -> y64),
-// one column each, in five launches instead of ten, where both precisions take
-// the pair-stream path with separate x and y passes and the plan has grids
-// for the FP32 instance; otherwise returns false and launches nothing.
+// Many columns: the matrix-core product of both instances in one launch
+// (default column tiles: NT32 for FP32, one tile of 16 for FP64).  Each
+// instance deals its own items to the XCDs as k_prod_mfma does (a contiguous
+// range per XCD, sized from the instance's own item count, so an instance
+// with fewer items than the launch still spreads over all eight).
+template <int NT32, bool EVEN>
+__global__ void __launch_bounds__(1024) k_prod_mfma_dual(const c64 *G32, const c128 *G64, const c64 *i32,
+                                                         const c128 *i64, int b, int R, int Px, int Py, int kxh,
+                                                         c64 *o32, c128 *o64, const void *const *a32,
+                                                         const void *const *a64) {
+    extern __shared__ char smem_raw[];
+    const long P = (long)Px * Py;
+    const int ncb = blockIdx.z == 0 ? (R + 16 * NT32 - 1) / (16 * NT32) : (R + 15) / 16;
+    const long nitem = P * ncb, per = (nitem + 7) >> 3;
+    if ((long)(blockIdx.x >> 3) >= per) return;
+    const long item = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (item >= nitem) return;
+    const long k = item / ncb;
+    if (blockIdx.z == 0)
+        prod_mfma_item<float, NT32, TP_PROD_KC, EVEN>(G32, i32, b, R, Px, Py, kxh, o32, a32, k,
+                                                      (int)(item - k * ncb), smem_raw);
+    else
+        prod_mfma_item<double, 1, TP_PROD_KC, EVEN>(G64, i64, b, R, Px, Py, kxh, o64, a64, k, (int)(item - k * ncb),
+                                                    smem_raw);
+}
+
+// Many columns on small grids: the 2-D tiles of both instances per launch
+// (no rim: the operator of a plan without a dense rim pass).
+template <typename In>
+__global__ void __launch_bounds__(256) k_fft2_fwd_dual(Cols<const In> x32, Cols<const In> x64, int R, int Nx, int Ny,
+                                                       int b, FFTDesc fx, FFTDesc fy, int lg32, int lg64, int xs32,
+                                                       int xs64, int g32, int g64, c64 *o32, c128 *o64, RimMap rm) {
+    extern __shared__ char smem_raw[];
+    if (blockIdx.z == 0) {
+        if ((int)blockIdx.x < g32)
+            fft2_fwd_tile<float, In>(x32, R, Nx, Ny, b, fx, fy, lg32, xs32, o32, rm, blockIdx.x, smem_raw);
+    } else if ((int)blockIdx.x < g64) {
+        fft2_fwd_tile<double, In>(x64, R, Nx, Ny, b, fx, fy, lg64, xs64, o64, rm, blockIdx.x, smem_raw);
+    }
+}
+
 template <typename In, typename Out>
-bool matvec_dual_launch(tp_plan pl, Cols<const In> x32, Cols<Out> y32, Cols<const In> x64, Cols<Out> y64,
+__global__ void __launch_bounds__(256) k_fft2_inv_dual(const c64 *i32, const c128 *i64, int R, int Nx, int Ny, int b,
+                                                       FFTDesc fx, FFTDesc fy, int lg32, int lg64, int xs32, int xs64,
+                                                       int g32, int g64, Cols<Out> y32, Cols<Out> y64, long N,
+                                                       int Nr, RimMap rm) {
+    extern __shared__ char smem_raw[];
+    const Cols<const In> nox{nullptr, 0, nullptr};
+    if (blockIdx.z == 0) {
+        if ((int)blockIdx.x < g32)
+            fft2_inv_tile<float, In, Out>(i32, R, Nx, Ny, b, fx, fy, lg32, xs32, y32, 0,
+                                          Cols<const Out>{y32.base, y32.ld, y32.tab}, g32, nullptr, nullptr, nullptr,
+                                          nox, N, Nr, 0, rm, blockIdx.x, smem_raw);
+    } else if ((int)blockIdx.x < g64) {
+        fft2_inv_tile<double, In, Out>(i64, R, Nx, Ny, b, fx, fy, lg64, xs64, y64, 0,
+                                       Cols<const Out>{y64.base, y64.ld, y64.tab}, g64, nullptr, nullptr, nullptr,
+                                       nox, N, Nr, 0, rm, blockIdx.x, smem_raw);
+    }
+}
+
+// The FP32 operator on (x32 -> y32) and the FP64 operator on (x64 -> y64) in
+// one launch per stage, where both precisions take the same launch shape and
+// the plan has FP32 grids of its own: one column on the pair-stream path with
+// separate x and y passes, or many columns (up to the plan's max_rhs) with the
+// matrix-core product at its default column tiles, on separate passes or on
+// 2-D tiles, without a dense rim pass.  Otherwise returns false and launches
+// nothing.
+template <typename In, typename Out>
+bool matvec_dual_launch(tp_plan pl, Cols<const In> x32, Cols<Out> y32, Cols<const In> x64, Cols<Out> y64, int R,
                         hipStream_t st) {
-    const int R = 1;
     if (!pl->gridA32 || !pl->G32 || !pl->G64) return false;
     const Path p32 = choose_path<float, false>(pl, R), p64 = choose_path<double, false>(pl, R);
-    if (!p32.pairs || !p64.pairs || p32.rim || p64.rim || p32.lg2 >= 0 || p64.lg2 >= 0) return false;
+    if (p32.rim || p64.rim || p32.fused || p64.fused || p32.fusedm || p64.fusedm) return false;
+    const bool pairs = p32.pairs && p64.pairs;
+    const bool mfma = p32.mfma && p64.mfma && pl->opt_mfma_cols == 0 && pl->opt_prod_lds == 0;
+    if (!pairs && !mfma) return false;
+    const bool tiles = p32.lg2 >= 0 && p64.lg2 >= 0;
+    if (!tiles && (p32.lg2 >= 0 || p64.lg2 >= 0)) return false;
+    if (pairs && tiles) return false;
     const int Nx = pl->Nx, Ny = pl->Ny, b = pl->bc, Px = pl->Px, Py = pl->Py, C = b * R;
     const RimMap rm{pl->rim_map, pl->b, pl->nrc, pl->N};
     c64 *A32 = reinterpret_cast<c64 *>(pl->gridA32), *B32 = reinterpret_cast<c64 *>(pl->gridB32);
@@ -1975,20 +2043,28 @@ bool matvec_dual_launch(tp_plan pl, Cols<const In> x32, Cols<Out> y32, Cols<cons
     const void *const *a32 = (const void *const *)x32.tab;
     const void *const *a64 = (const void *const *)x64.tab;
     const dim3 blk(256);
-    // x passes
-    const int lx32 = fft_lgcc(Px, C, 8, fftx_maxcc(C, Ny)), lx64 = fft_lgcc(Px, C, 16, fftx_maxcc(C, Ny));
-    const int gx32 = (C + (1 << lx32) - 1) >> lx32, gx64 = (C + (1 << lx64) - 1) >> lx64;
-    const size_t shx = std::max(((size_t)Px * (1 << lx32) + Px) * 8, ((size_t)Px * (1 << lx64) + Px) * 16);
-    hipLaunchKernelGGL((k_fwd_x_dual<In>), dim3(std::max(gx32, gx64), Ny, 2), blk, shx, st, x32, x64, R, Nx, b,
-                       pl->fx, lx32, lx64, gx32, gx64, A32, A64, rm);
-    // y passes
-    const int ly32 = fft_lgcc(Py, C, 8, TP_FFTY_MAXCC), ly64 = fft_lgcc(Py, C, 16, TP_FFTY_MAXCC);
-    const int gy32 = (C + (1 << ly32) - 1) >> ly32, gy64 = (C + (1 << ly64) - 1) >> ly64;
-    const size_t shy = std::max(((size_t)Py * (1 << ly32) + Py) * 8, ((size_t)Py * (1 << ly64) + Py) * 16);
-    hipLaunchKernelGGL((k_y_dual<false>), dim3(std::max(gy32, gy64), Px, 2), blk, shy, st, A32, A64, C, Ny, Px,
-                       pl->fy, ly32, ly64, gy32, gy64, B32, B64, a32, a64, b);
-    // pair-stream products
-    {
+    if (tiles) {
+        // 2-D tiles: forward (-> B), products (B -> A), inverse (A -> y)
+        const int g32 = (C + (1 << p32.lg2) - 1) >> p32.lg2, g64 = (C + (1 << p64.lg2) - 1) >> p64.lg2;
+        const size_t sh = std::max(p32.sh2, p64.sh2);
+        hipLaunchKernelGGL((k_fft2_fwd_dual<In>), dim3(std::max(g32, g64), 1, 2), blk, sh, st, x32, x64, R, Nx, Ny, b,
+                           pl->fx, pl->fy, p32.lg2, p64.lg2, p32.xs2, p64.xs2, g32, g64, B32, B64, rm);
+    } else {
+        // x passes (-> A)
+        const int lx32 = fft_lgcc(Px, C, 8, fftx_maxcc(C, Ny)), lx64 = fft_lgcc(Px, C, 16, fftx_maxcc(C, Ny));
+        const int gx32 = (C + (1 << lx32) - 1) >> lx32, gx64 = (C + (1 << lx64) - 1) >> lx64;
+        const size_t shx = std::max(((size_t)Px * (1 << lx32) + Px) * 8, ((size_t)Px * (1 << lx64) + Px) * 16);
+        hipLaunchKernelGGL((k_fwd_x_dual<In>), dim3(std::max(gx32, gx64), Ny, 2), blk, shx, st, x32, x64, R, Nx, b,
+                           pl->fx, lx32, lx64, gx32, gx64, A32, A64, rm);
+        // y passes (A -> B)
+        const int ly32 = fft_lgcc(Py, C, 8, TP_FFTY_MAXCC), ly64 = fft_lgcc(Py, C, 16, TP_FFTY_MAXCC);
+        const int gy32 = (C + (1 << ly32) - 1) >> ly32, gy64 = (C + (1 << ly64) - 1) >> ly64;
+        const size_t shy = std::max(((size_t)Py * (1 << ly32) + Py) * 8, ((size_t)Py * (1 << ly64) + Py) * 16);
+        hipLaunchKernelGGL((k_y_dual<false>), dim3(std::max(gy32, gy64), Px, 2), blk, shy, st, A32, A64, C, Ny, Px,
+                           pl->fy, ly32, ly64, gy32, gy64, B32, B64, a32, a64, b);
+    }
+    // products (B -> A)
+    if (pairs) {
         const int nw = (b + 7) / 8, vpl = (b + 7) / 8;
         const size_t sh = (size_t)(2 + nw) * b * sizeof(c128);
         const dim3 grid((unsigned)(pl->kxh * Py), 1, 2), pblk((unsigned)(64 * nw));
@@ -2004,11 +2080,48 @@ bool matvec_dual_launch(tp_plan pl, Cols<const In> x32, Cols<Out> y32, Cols<cons
         else if (vpl <= 12) TP_PAIR_DUAL(12);
         else TP_PAIR_DUAL(16);
 #undef TP_PAIR_DUAL
+    } else {
+        // default column tiles: FP32 16 up to 16 columns, else 32; FP64 16
+        const int nt32 = R > 16 ? 2 : 1, KP = (b + 7) >> 3;
+        const size_t sh = std::max((size_t)16 * nt32 * (8 * KP + 2) * 8, (size_t)16 * (8 * KP + 2) * 16);
+        const long P = (long)Px * Py;
+        const long n32 = P * ((R + 16 * nt32 - 1) / (16 * nt32)), n64 = P * ((R + 15) / 16);
+        const long nitem = std::max(n32, n64);
+        const dim3 grid((unsigned)(((nitem + 7) / 8) * 8), 1, 2), mblk((unsigned)(64 * ((b + 15) / 16)));
+        const int kxh = pl->kxh;
+        if (b % 2 == 0) {
+            if (nt32 == 2)
+                hipLaunchKernelGGL((k_prod_mfma_dual<2, true>), grid, mblk, sh, st, pl->G32, pl->G64, B32, B64, b, R,
+                                   Px, Py, kxh, A32, A64, a32, a64);
+            else
+                hipLaunchKernelGGL((k_prod_mfma_dual<1, true>), grid, mblk, sh, st, pl->G32, pl->G64, B32, B64, b, R,
+                                   Px, Py, kxh, A32, A64, a32, a64);
+        } else {
+            if (nt32 == 2)
+                hipLaunchKernelGGL((k_prod_mfma_dual<2, false>), grid, mblk, sh, st, pl->G32, pl->G64, B32, B64, b,
+                                   R, Px, Py, kxh, A32, A64, a32, a64);
+            else
+                hipLaunchKernelGGL((k_prod_mfma_dual<1, false>), grid, mblk, sh, st, pl->G32, pl->G64, B32, B64, b,
+                                   R, Px, Py, kxh, A32, A64, a32, a64);
+        }
     }
+    if (tiles) {
+        const int g32 = (C + (1 << p32.lg2) - 1) >> p32.lg2, g64 = (C + (1 << p64.lg2) - 1) >> p64.lg2;
+        const size_t sh = std::max(p32.sh2, p64.sh2);
+        hipLaunchKernelGGL((k_fft2_inv_dual<In, Out>), dim3(std::max(g32, g64), 1, 2), blk, sh, st, A32, A64, R, Nx,
+                           Ny, b, pl->fx, pl->fy, p32.lg2, p64.lg2, p32.xs2, p64.xs2, g32, g64, y32, y64, pl->N,
+                           pl->Nr, rm);
+        return true;
+    }
+    // inverse y passes (A -> B), inverse x passes and crop (B -> y)
+    const int ly32 = fft_lgcc(Py, C, 8, TP_FFTY_MAXCC), ly64 = fft_lgcc(Py, C, 16, TP_FFTY_MAXCC);
+    const int gy32 = (C + (1 << ly32) - 1) >> ly32, gy64 = (C + (1 << ly64) - 1) >> ly64;
+    const size_t shy = std::max(((size_t)Py * (1 << ly32) + Py) * 8, ((size_t)Py * (1 << ly64) + Py) * 16);
     hipLaunchKernelGGL((k_y_dual<true>), dim3(std::max(gy32, gy64), Px, 2), blk, shy, st, A32, A64, C, Ny, Px,
                        pl->fy, ly32, ly64, gy32, gy64, B32, B64, a32, a64, b);
-    // inverse x passes, crop
-    const int nc32 = gx32, nc64 = gx64;
+    const int lx32 = fft_lgcc(Px, C, 8, fftx_maxcc(C, Ny)), lx64 = fft_lgcc(Px, C, 16, fftx_maxcc(C, Ny));
+    const int nc32 = (C + (1 << lx32) - 1) >> lx32, nc64 = (C + (1 << lx64) - 1) >> lx64;
+    const size_t shx = std::max(((size_t)Px * (1 << lx32) + Px) * 8, ((size_t)Px * (1 << lx64) + Px) * 16);
     hipLaunchKernelGGL((k_inv_x_dual<In, Out>), dim3(std::max(nc32, nc64) * Ny, 1, 2), blk, shx, st, B32, B64, R,
                        Nx, b, pl->fx, lx32, lx64, nc32, nc64, y32, y64, nc32 * Ny, nc64 * Ny, pl->N, pl->Nr, rm);
     return true;

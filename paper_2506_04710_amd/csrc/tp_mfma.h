@@ -13,6 +13,11 @@
 // run of memory.
 #include "tp_internal.h"
 
+// pairs of contraction steps per prefetched chunk of the product
+#ifndef TP_PROD_KC
+#define TP_PROD_KC 4
+#endif
+
 namespace tp {
 
 

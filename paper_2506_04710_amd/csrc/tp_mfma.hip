@@ -5,11 +5,6 @@
 
 namespace tp {
 
-// pairs of contraction steps per prefetched chunk of the product
-#ifndef TP_PROD_KC
-#define TP_PROD_KC 4
-#endif
-
 template <typename T, int NT>
 static void launch_prod_mfma(const cpx<T> *G, const cpx<T> *in, int b, int R, int Px, int Py, int kxh, cpx<T> *out,
                              const void *const *act, hipStream_t st) {

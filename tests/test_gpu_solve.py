@@ -247,3 +247,36 @@ def test_mixed_solve_shared_launches_bitwise(tp):
     assert i1["status"] == 0 and i1["iters"] == i0["iters"] and i1["outer_iters"] == i0["outer_iters"]
     assert np.array_equal(x1.view(np.uint64), x0.view(np.uint64))
     assert oracle.relres(prob, x1, V)[0] <= 1e-8
+
+
+@pytest.mark.parametrize("shape,R,placed", [((12, 10, 24, 40), 16, True), ((12, 10, 24, 40), 40, True),
+                                            ((40, 36, 16, 24), 20, True), ((40, 36, 16, 0), 33, False)])
+def test_mixed_solve_shared_launches_multi_bitwise(tp, shape, R, placed):
+    """Many columns: the shared FP32/FP64 launches (matrix-core product at its
+    default column tiles, on 2-D tiles for the small grid and on separate
+    passes for the larger one; ragged column blocks) give the same bits,
+    iteration counts and statuses as one launch sequence per precision."""
+    from paper_2506_04710_amd import _lib
+    Nx, Ny, b, Nr = shape
+    banner(f"mixed solve, shared launches, {Nx}x{Ny} b{b} Nr{Nr} R{R} placed={placed}")
+    prob = sa.make_problem(Nx, Ny, b, Nr, 9556 + R)
+    V = sa.rhs_random(prob, R, rng=np.random.default_rng(R))
+    out = {}
+    for dual in (1, 0):
+        kw = {"rim_place": sa.rim_placement(prob)} if placed and Nr else {}
+        plan = tp.Plan.create(prob.Nx, prob.Ny, prob.b, prob.Nr, prob.gen, prob.rim_re, prob.rim_rr, prec="mixed",
+                              max_rhs=R, restart=30, **kw)
+        plan.set_option(_lib.TP_OPT_DUAL_LAUNCH, dual)
+        p32, p64 = plan.path("fp32", nrhs=R), plan.path("fp64", nrhs=R)
+        assert "mfma" in p32 and "mfma" in p64 and not (p32 | p64) & {"dense_rim", "persistent"}
+        assert ("tiles2d" in p32) == ("tiles2d" in p64) == (Nx < 20)
+        x, info = plan.solve(to_dev(V), mode="mixed", tol=1e-8)
+        out[dual] = (x.cpu().numpy().reshape(R, -1), info)
+        plan.close()
+    (x1, i1), (x0, i0) = out[1], out[0]
+    for a, c in zip(i1, i0):
+        assert a["status"] == c["status"] == 0 and a["iters"] == c["iters"] and a["outer_iters"] == c["outer_iters"]
+    assert np.array_equal(x1.view(np.uint64), x0.view(np.uint64))
+    rr = oracle.relres(prob, x1, V)
+    assert max(rr) <= 1e-8, rr
+    print(f"R={R}: iters {[a['iters'] for a in i1][:4]} max relres {max(rr):.2e}")
