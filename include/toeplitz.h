@@ -220,8 +220,10 @@ tp_status toeplitz_plan_create_placed(int Nx, int Ny, int b, int Nr, const doubl
  *     passes, or many columns with the matrix-core product at its default
  *     column tiles (TP_OPT_MFMA_COLS 0, TP_OPT_PROD_LDS 0, no persistent
  *     launch) on separate passes or on 2-D tiles, without a dense rim pass
- *     (the idle instance costs no launch of its own); 0: one launch sequence
- *     per precision.  Same results bit for bit.
+ *     (the idle instance costs no launch of its own); with the
+ *     preconditioner on one column, its last pass (inverse x transforms) and
+ *     the operator's first (forward x transforms) also share one launch; 0:
+ *     one launch sequence per precision.  Same results bit for bit.
  *   TP_OPT_PROD_LDS  FP32 per-frequency product with the spectrum block staged
  *     in LDS and each wave's column tile of the transformed input held in
  *     registers: value 16 * CG + RT (+ 256), CG column tiles of 16 per

@@ -592,13 +592,18 @@ static hipError_t super_step(tp_plan pl, const Eng &E, int par, hipStream_t st) 
     const dim3 gv(E.nb, E.nslots), blk(kThreads);
     hipLaunchKernelGGL(k_commit, gv, blk, 0, st, E, par);
     hipError_t e;
-    if (E.prec) {
+    if (E.prec && E.mixed) {
         const Cols<const c128> pi{nullptr, 0, E.pin}, pb{nullptr, 0, E.pbase};
         const Cols<c128> po{nullptr, 0, E.pout};
-        e = E.mixed ? precond_fp32_wide(pl, pi, po, pb, E.nslots, st) : precond_fp64(pl, pi, po, pb, E.nslots, st);
+        e = precond_op_mixed(pl, pi, po, pb, Cols<const c128>{nullptr, 0, E.tin}, Cols<c128>{nullptr, 0, E.tout},
+                             Cols<const c128>{nullptr, 0, E.rin}, Cols<c128>{nullptr, 0, E.rout}, E.nslots, st);
+    } else if (E.prec) {
+        const Cols<const c128> pi{nullptr, 0, E.pin}, pb{nullptr, 0, E.pbase};
+        const Cols<c128> po{nullptr, 0, E.pout};
+        e = precond_fp64(pl, pi, po, pb, E.nslots, st);
         if (e) return e;
-    }
-    if (E.mixed) {
+        e = matvec_fp64(pl, Cols<const c128>{nullptr, 0, E.tin}, Cols<c128>{nullptr, 0, E.tout}, E.nslots, st);
+    } else if (E.mixed) {
         e = matvec_mixed_both(pl, Cols<const c128>{nullptr, 0, E.tin}, Cols<c128>{nullptr, 0, E.tout},
                               Cols<const c128>{nullptr, 0, E.rin}, Cols<c128>{nullptr, 0, E.rout}, E.nslots, st);
     } else {

@@ -1734,7 +1734,8 @@ static Path choose_path(tp_plan pl, int R) {
 
 template <typename T, typename In, typename Out, bool PRE = false>
 hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipStream_t st,
-                         hipEvent_t *ev = nullptr, Cols<const Out> base = Cols<const Out>{nullptr, 0, nullptr}) {
+                         hipEvent_t *ev = nullptr, Cols<const Out> base = Cols<const Out>{nullptr, 0, nullptr},
+                         int last_stage = 7) {
     // b: channels per cell (element basis functions, plus the rim channels of
     // a placed rim); the embedding and crop map channels to unknowns
     const int Nx = pl->Nx, Ny = pl->Ny, b = pl->bc, Nr = pl->Nr;
@@ -1750,7 +1751,8 @@ hipError_t matvec_launch(tp_plan pl, Cols<const In> x, Cols<Out> y, int R, hipSt
     };
     // instrumentation (a copy of the plan record with only_stage set): launch
     // one stage alone, on the workspace a full application left behind
-    auto on = [&](int stage) { return pl->only_stage < 0 || pl->only_stage == stage; };
+    // (last_stage < 7: the stages after it are left to the caller)
+    auto on = [&](int stage) { return stage <= last_stage && (pl->only_stage < 0 || pl->only_stage == stage); };
     const cpx<T> *G = PRE ? OpPtrs<T>::S(pl) : OpPtrs<T>::G(pl);
     const Path P = choose_path<T, PRE>(pl, R);
     const bool rim = P.rim, pairs = P.pairs, fused = P.fused, mfma = P.mfma, rim_mma = P.rim_mma;
@@ -2026,7 +2028,7 @@ __global__ void __launch_bounds__(256) k_fft2_inv_dual(const c64 *i32, const c12
 // nothing.
 template <typename In, typename Out>
 bool matvec_dual_launch(tp_plan pl, Cols<const In> x32, Cols<Out> y32, Cols<const In> x64, Cols<Out> y64, int R,
-                        hipStream_t st) {
+                        hipStream_t st, bool skip_fwd_x = false) {
     if (!pl->gridA32 || !pl->G32 || !pl->G64) return false;
     const Path p32 = choose_path<float, false>(pl, R), p64 = choose_path<double, false>(pl, R);
     if (p32.rim || p64.rim || p32.fused || p64.fused || p32.fusedm || p64.fusedm) return false;
@@ -2036,6 +2038,7 @@ bool matvec_dual_launch(tp_plan pl, Cols<const In> x32, Cols<Out> y32, Cols<cons
     const bool tiles = p32.lg2 >= 0 && p64.lg2 >= 0;
     if (!tiles && (p32.lg2 >= 0 || p64.lg2 >= 0)) return false;
     if (pairs && tiles) return false;
+    if (skip_fwd_x && (tiles || !pairs)) return false;
     const int Nx = pl->Nx, Ny = pl->Ny, b = pl->bc, Px = pl->Px, Py = pl->Py, C = b * R;
     const RimMap rm{pl->rim_map, pl->b, pl->nrc, pl->N};
     c64 *A32 = reinterpret_cast<c64 *>(pl->gridA32), *B32 = reinterpret_cast<c64 *>(pl->gridB32);
@@ -2054,8 +2057,9 @@ bool matvec_dual_launch(tp_plan pl, Cols<const In> x32, Cols<Out> y32, Cols<cons
         const int lx32 = fft_lgcc(Px, C, 8, fftx_maxcc(C, Ny)), lx64 = fft_lgcc(Px, C, 16, fftx_maxcc(C, Ny));
         const int gx32 = (C + (1 << lx32) - 1) >> lx32, gx64 = (C + (1 << lx64) - 1) >> lx64;
         const size_t shx = std::max(((size_t)Px * (1 << lx32) + Px) * 8, ((size_t)Px * (1 << lx64) + Px) * 16);
-        hipLaunchKernelGGL((k_fwd_x_dual<In>), dim3(std::max(gx32, gx64), Ny, 2), blk, shx, st, x32, x64, R, Nx, b,
-                           pl->fx, lx32, lx64, gx32, gx64, A32, A64, rm);
+        if (!skip_fwd_x)
+            hipLaunchKernelGGL((k_fwd_x_dual<In>), dim3(std::max(gx32, gx64), Ny, 2), blk, shx, st, x32, x64, R, Nx,
+                               b, pl->fx, lx32, lx64, gx32, gx64, A32, A64, rm);
         // y passes (A -> B)
         const int ly32 = fft_lgcc(Py, C, 8, TP_FFTY_MAXCC), ly64 = fft_lgcc(Py, C, 16, TP_FFTY_MAXCC);
         const int gy32 = (C + (1 << ly32) - 1) >> ly32, gy64 = (C + (1 << ly64) - 1) >> ly64;
