@@ -32,8 +32,8 @@ METRIC = "solves/s at rel-residual 1e-8 (32x32,b=64) vs FP64 plain; matvec GB/s;
 # HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the same counters on a plain copy of known size),
 # valid only for the kernel source it was measured on.
-TRAFFIC = {"source_sha256": "540147bb5cd6aaaa3ca27f48fd4d70262c6d4af6d483dd546d38d522027e7ac9",
-           "bytes": 105737037, "fetch_factor": 0.416678, "write_factor": 1.0}
+TRAFFIC = {"source_sha256": "78202dab81867be606c19762180f122cb00569385868bf97884cf975968218cd",
+           "bytes": 105737075, "fetch_factor": 0.416678, "write_factor": 1.0}
 
 
 def parse():

@@ -266,6 +266,9 @@ tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value);
  *   TP_PATH_PERSISTENT  every stage in one persistent launch (TP_OPT_MULTI_FUSED)
  *   TP_PATH_RIM_OVERLAP the rim's slabs and the forward tiles in one launch
  *                       (TP_OPT_RIM_OVERLAP)
+ *   TP_PATH_JOINED      (which = TP_MIXED, precond = 1, nrhs = 1) a mixed
+ *                       solve's preconditioner inverse x pass and operator
+ *                       forward x pass share one launch (TP_OPT_DUAL_LAUNCH)
  * Launches nothing.  Errors: TP_E_INVAL (NULL plan or flags, bad precision,
  * nrhs outside [1, max_rhs], precond without a preconditioner),
  * TP_E_UNSUPPORTED (the plan lacks the copy `which` needs).
@@ -278,6 +281,7 @@ tp_status toeplitz_plan_get_option(tp_plan p, int option, int *value);
 #define TP_PATH_TILES2D 32
 #define TP_PATH_PERSISTENT 64
 #define TP_PATH_RIM_OVERLAP 128
+#define TP_PATH_JOINED 256
 tp_status toeplitz_plan_path(tp_plan p, tp_prec which, int precond, int nrhs, int *flags);
 
 /* Result of toeplitz_tune: the options it set and the time they gave. */

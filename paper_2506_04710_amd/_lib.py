@@ -36,7 +36,7 @@ TP_OPT_SPECTRUM_PASS, TP_OPT_MFMA_COLS, TP_OPT_MFMA_MIN_R, TP_OPT_FFT2_LDS, TP_O
 TP_OPT_PROD_LDS, TP_OPT_RIM_OVERLAP, TP_OPT_DUAL_LAUNCH = 6, 7, 8
 TP_PASS_AUTO, TP_PASS_FUSED, TP_PASS_PAIRS = 0, 1, 2
 PATH_BITS = {"fused": 1, "pairs": 2, "mfma": 4, "dense_rim": 8, "rim_mfma": 16, "tiles2d": 32, "persistent": 64,
-             "rim_overlap": 128}
+             "rim_overlap": 128, "joined": 256}
 
 
 class PlanDesc(ctypes.Structure):

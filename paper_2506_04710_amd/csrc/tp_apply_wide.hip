@@ -58,22 +58,32 @@ __global__ void __launch_bounds__(256) k_pre_inv_x_op_fwd_x(const c64 *pin, int 
 // the preconditioner and the operator take the pair-stream path with separate
 // x and y passes (no dense rim pass) and the same channel chunks; otherwise
 // returns false and launches nothing.
+// Whether the joined pass applies to the plan as its options stand (one
+// column); *lg receives the channel chunk of both passes.
+bool precond_op_joined_ok(tp_plan pl, int *lg) {
+    const int R = 1;
+    if (!pl->opt_dual_launch || !pl->gridA32 || !pl->G32 || !pl->G64 || !pl->S32 || !pl->has_precond)
+        return false;
+    if (pl->Nr > 0 && pl->nrc == 0) return false;            // a dense rim: rows finished apart
+    const Path pp = choose_path<float, true>(pl, R);
+    const Path p32 = choose_path<float, false>(pl, R), p64 = choose_path<double, false>(pl, R);
+    // (these include the conditions of the shared launches on one column)
+    if (!pp.pairs || pp.lg2 >= 0 || !p32.pairs || !p64.pairs || p32.rim || p64.rim || p32.lg2 >= 0 ||
+        p64.lg2 >= 0)
+        return false;
+    const int C = pl->bc, l = fft_lgcc(pl->Px, C, 8, fftx_maxcc(C, pl->Ny));
+    if (fft_lgcc(pl->Px, C, 16, fftx_maxcc(C, pl->Ny)) != l) return false;
+    *lg = l;
+    return true;
+}
+
 static bool precond_op_mixed_launch(tp_plan pl, Cols<const c128> pin, Cols<c128> pout, Cols<const c128> pbase,
                                     Cols<const c128> x32, Cols<c128> y32, Cols<const c128> x64, Cols<c128> y64,
                                     hipStream_t st) {
     const int R = 1;
-    if (!pl->gridA32 || !pl->G32 || !pl->G64 || !pl->S32 || pl->only_stage >= 0) return false;
-    if (pl->Nr > 0 && pl->nrc == 0) return false;            // a dense rim: rows finished apart
-    const Path pp = choose_path<float, true>(pl, R);
-    const Path p32 = choose_path<float, false>(pl, R), p64 = choose_path<double, false>(pl, R);
-    // (these are the conditions of the shared launches below on one column:
-    // nothing is launched unless all of them hold)
-    if (!pp.pairs || pp.lg2 >= 0 || !p32.pairs || !p64.pairs || p32.rim || p64.rim || p32.lg2 >= 0 ||
-        p64.lg2 >= 0)
-        return false;
+    int lg = 0;
+    if (pl->only_stage >= 0 || !precond_op_joined_ok(pl, &lg)) return false;   // nothing launched
     const int Nx = pl->Nx, Ny = pl->Ny, b = pl->bc, Px = pl->Px, C = b;
-    const int lg = fft_lgcc(Px, C, 8, fftx_maxcc(C, Ny));
-    if (fft_lgcc(Px, C, 16, fftx_maxcc(C, Ny)) != lg) return false;
     // the preconditioner's transforms and product, up to its inverse y pass
     // (launch errors surface through hipGetLastError in the caller)
     matvec_launch<float, c128, c128, true>(pl, pin, pout, R, st, nullptr, pbase, 4);
@@ -101,7 +111,7 @@ hipError_t precond_fp32_wide(tp_plan pl, Cols<const c128> x, Cols<c128> y, Cols<
 hipError_t precond_op_mixed(tp_plan pl, Cols<const c128> pin, Cols<c128> pout, Cols<const c128> pbase,
                             Cols<const c128> x32, Cols<c128> y32, Cols<const c128> x64, Cols<c128> y64, int R,
                             hipStream_t st) {
-    if (R == 1 && pl->opt_dual_launch && precond_op_mixed_launch(pl, pin, pout, pbase, x32, y32, x64, y64, st))
+    if (R == 1 && precond_op_mixed_launch(pl, pin, pout, pbase, x32, y32, x64, y64, st))
         return hipGetLastError();
     hipError_t e = precond_fp32_wide(pl, pin, pout, pbase, R, st);
     if (e) return e;

@@ -584,6 +584,8 @@ tp_status toeplitz_plan_path(tp_plan p, tp_prec which, int precond, int nrhs, in
     if (which != TP_FP64 && !p->G32) return fail(TP_E_UNSUPPORTED, "plan holds no FP32 operator");
     if (which == TP_FP64 && !p->G64) return fail(TP_E_UNSUPPORTED, "plan holds no FP64 operator");
     *flags = tp::path_flags(p, which == TP_FP64, precond != 0, nrhs);
+    int lg;
+    if (which == TP_MIXED && precond && nrhs == 1 && tp::precond_op_joined_ok(p, &lg)) *flags |= TP_PATH_JOINED;
     return TP_OK;
 }
 

@@ -36,6 +36,7 @@ hipError_t precond_fp64(tp_plan pl, Cols<const c128> x, Cols<c128> y, Cols<const
 hipError_t precond_fp32(tp_plan pl, Cols<const c64> x, Cols<c64> y, Cols<const c64> base, int R, hipStream_t st);
 hipError_t precond_fp32_wide(tp_plan pl, Cols<const c128> x, Cols<c128> y, Cols<const c128> base, int R,
                              hipStream_t st);
+bool precond_op_joined_ok(tp_plan pl, int *lg);
 hipError_t precond_op_mixed(tp_plan pl, Cols<const c128> pin, Cols<c128> pout, Cols<const c128> pbase,
                             Cols<const c128> x32, Cols<c128> y32, Cols<const c128> x64, Cols<c128> y64, int R,
                             hipStream_t st);

@@ -224,13 +224,16 @@ def test_solve_nonfinite_rhs_stops():
     plan.close()
 
 
-def test_mixed_solve_shared_launches_bitwise(tp):
+@pytest.mark.parametrize("shape", [(12, 10, 24, 40), (40, 36, 16, 24)])
+def test_mixed_solve_shared_launches_bitwise(tp, shape):
     """A one-column mixed solve whose FP32 and FP64 operators share each stage's
-    launch (TP_OPT_DUAL_LAUNCH, placed rim, pair-stream pass) gives the same
-    bits as the solve with one launch sequence per precision."""
+    launch, and whose preconditioner's last pass shares a launch with the
+    operator's first (TP_OPT_DUAL_LAUNCH, placed rim, pair-stream pass), gives
+    the same bits as the solve with one launch sequence per precision."""
     from paper_2506_04710_amd import _lib
-    banner("mixed solve, shared FP32/FP64 launches")
-    prob = sa.make_problem(12, 10, 24, 40, 9555)
+    Nx, Ny, b, Nr = shape
+    banner(f"mixed solve, shared FP32/FP64 launches, {Nx}x{Ny} b{b} Nr{Nr}")
+    prob = sa.make_problem(Nx, Ny, b, Nr, 9555)
     V = sa.rhs_random(prob, 1, rng=np.random.default_rng(4))
     out = {}
     for dual in (1, 0):
@@ -240,6 +243,10 @@ def test_mixed_solve_shared_launches_bitwise(tp):
         assert plan.get_option(_lib.TP_OPT_DUAL_LAUNCH) == 1
         plan.set_option(_lib.TP_OPT_DUAL_LAUNCH, dual)
         plan.precond_create()
+        # on the larger grid (separate x and y passes) the preconditioner's last
+        # pass and the operator's first share a launch; the small grid's
+        # preconditioner runs on 2-D tiles
+        assert ("joined" in plan.path("mixed", nrhs=1, precond=True)) == (bool(dual) and Nx >= 20)
         x, info = plan.solve(to_dev(V), mode="mixed", tol=1e-8, precond=True)
         out[dual] = (x.cpu().numpy().reshape(1, -1), info[0])
         plan.close()
